@@ -1,0 +1,255 @@
+"""CPU oracle for the radar ray-tracing hot path (TEST INFRASTRUCTURE).
+
+A plain single-threaded FP64 implementation in C (`oracle.c`) wrapped with
+ctypes, plus an FP64 numpy implementation of the proposal network
+(`oracle.mlp`).  Only the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import this package.  It shares no code with the GPU
+library and never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+KMAX = 8
+
+PATH_DTYPE = np.dtype([
+    ("src", np.int32), ("K", np.int32), ("ray", np.int64),
+    ("tri", np.int32, (KMAX,)), ("vid", np.int32, (KMAX,)),
+    ("p", np.float64, (KMAX, 3)), ("L", np.float64), ("amp", np.float64),
+], align=True)
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                               "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Scene(C.Structure):
+    _fields_ = [("verts", C.c_void_p), ("nv", C.c_int64), ("tris", C.c_void_p),
+                ("tri_obj", C.c_void_p), ("nt", C.c_int64), ("obj_alpha", C.c_void_p),
+                ("obj_vel", C.c_void_p), ("nobj", C.c_int32), ("pt_pos", C.c_void_p),
+                ("pt_vel", C.c_void_p), ("pt_ap", C.c_void_p), ("npts", C.c_int32)]
+
+
+class _Array(C.Structure):
+    _fields_ = [("tx", C.c_void_p), ("ntx", C.c_int32), ("rx", C.c_void_p), ("nrx", C.c_int32),
+                ("rx_radius", C.c_double), ("shared", C.c_int32)]
+
+
+class _Chirp(C.Structure):
+    _fields_ = [("f0", C.c_double), ("bandwidth", C.c_double), ("t_chirp", C.c_double),
+                ("t_rep", C.c_double), ("n_samples", C.c_int32), ("n_chirps", C.c_int32)]
+
+
+class _Trace(C.Structure):
+    _fields_ = [("n_rays", C.c_int64), ("max_bounces", C.c_int32), ("seed", C.c_uint64),
+                ("az_min", C.c_double), ("az_max", C.c_double), ("el_min", C.c_double),
+                ("el_max", C.c_double), ("cdf", C.c_void_p), ("n_az", C.c_int32),
+                ("n_el", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        L.orc_philox4x64.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_sincos_turn.argtypes = [C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_closest.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
+                                  C.POINTER(C.c_double)]
+        L.orc_closest.restype = C.c_int64
+        L.orc_bounce.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                 C.c_void_p]
+        L.orc_launch_dir.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                     C.c_void_p]
+        L.orc_trace.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                C.POINTER(C.c_int64)]
+        L.orc_synth.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_int, C.c_void_p, C.c_int64, C.c_void_p]
+        L.orc_release.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+class _Keep:
+    """Holds the numpy buffers a ctypes struct points into."""
+
+    def __init__(self):
+        self.bufs = []
+
+    def add(self, a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.bufs.append(a)
+        return a
+
+
+def _scene(s, keep):
+    v = keep.add(s.verts, np.float32)
+    t = keep.add(s.tris, np.int32)
+    o = keep.add(s.tri_obj, np.int32)
+    a = keep.add(s.obj_alpha, np.float32)
+    ov = keep.add(s.obj_vel, np.float64)
+    pp = keep.add(s.pt_pos, np.float64)
+    pv = keep.add(s.pt_vel, np.float64)
+    pa = keep.add(s.pt_aperture, np.float64)
+    st = _Scene(_p(v), v.shape[0], _p(t), _p(o), t.shape[0], _p(a), _p(ov), a.shape[0],
+                _p(pp), _p(pv), _p(pa), pp.shape[0])
+    keep.bufs.append(st)
+    return st
+
+
+def _array(a, keep):
+    tx = keep.add(a.tx, np.float64)
+    rx = keep.add(a.rx, np.float64)
+    st = _Array(_p(tx), tx.shape[0], _p(rx), rx.shape[0], float(a.rx_radius), int(a.mode))
+    keep.bufs.append(st)
+    return st
+
+
+def _trace(tp, keep, cdf=None, n_az=0, n_el=0):
+    c = None if cdf is None else keep.add(cdf, np.float64)
+    st = _Trace(int(tp.n_rays), int(tp.max_bounces), int(tp.seed) & (2**64 - 1), tp.az_min,
+                tp.az_max, tp.el_min, tp.el_max, _p(c), n_az, n_el)
+    keep.bufs.append(st)
+    return st
+
+
+def _chirp(ch):
+    return _Chirp(ch.f0, ch.bandwidth, ch.t_chirp, ch.t_rep, ch.n_samples, ch.n_chirps)
+
+
+# ----------------------------------------------------------------------------
+# primitives
+# ----------------------------------------------------------------------------
+
+def philox4x64(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+def sincos_turn(u: float) -> tuple[float, float]:
+    s, c = C.c_double(), C.c_double()
+    lib().orc_sincos_turn(float(u), C.byref(s), C.byref(c))
+    return s.value, c.value
+
+
+def closest(scene, o, d, skip=-1, use_bvh=False):
+    keep = _Keep()
+    sc = _scene(scene, keep)
+    o = keep.add(o, np.float64)
+    d = keep.add(d, np.float64)
+    t = C.c_double()
+    h = lib().orc_closest(C.addressof(sc), o.ctypes.data, d.ctypes.data, int(skip), int(use_bvh),
+                          C.byref(t))
+    lib().orc_release()
+    return int(h), t.value
+
+
+def bounce(d, n, alpha, u0, u1) -> np.ndarray:
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_bounce(d.ctypes.data, n.ctypes.data, float(alpha), float(u0), float(u1),
+                     out.ctypes.data)
+    return out
+
+
+def launch_dir(scene, array, tp, i, t, cdf=None, n_az=0, n_el=0) -> np.ndarray:
+    keep = _Keep()
+    out = np.zeros(4)
+    lib().orc_launch_dir(C.addressof(_scene(scene, keep)), C.addressof(_array(array, keep)),
+                         C.addressof(_trace(tp, keep, cdf, n_az, n_el)), int(i), int(t),
+                         out.ctypes.data)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# trace and synthesis
+# ----------------------------------------------------------------------------
+
+def n_per_src(scene, array, tp) -> int:
+    return int(tp.n_rays) if array.mode == 1 else int(tp.n_rays) // array.n_tx
+
+
+def n_src(array) -> int:
+    return 1 if array.mode == 1 else array.n_tx
+
+
+def n_virtual(scene, array, tp) -> int:
+    return n_src(array) * (n_per_src(scene, array, tp) + scene.n_pts)
+
+
+def trace(scene, array, tp, vids=None, use_bvh=None, cdf=None, n_az=0, n_el=0,
+          want_hits=True, cap=None):
+    """Trace virtual rays `vids` (all when None).  Returns (hits, paths):
+    hits int32 [n][max_bounces+1] (or None), paths: structured PATH_DTYPE array
+    in (virtual ray, bounce) order."""
+    if use_bvh is None:
+        use_bvh = scene.n_tris > 1000
+    keep = _Keep()
+    sc = _scene(scene, keep)
+    ar = _array(array, keep)
+    tr = _trace(tp, keep, cdf, n_az, n_el)
+    v = None if vids is None else keep.add(vids, np.int64)
+    n = n_virtual(scene, array, tp) if vids is None else v.shape[0]
+    hits = np.full((n, tp.max_bounces + 1), -1, dtype=np.int32) if want_hits else None
+    if cap is None:
+        cap = max(1024, n // 16)
+    while True:
+        paths = np.zeros(cap, dtype=PATH_DTYPE)
+        npaths = C.c_int64()
+        rc = lib().orc_trace(C.addressof(sc), C.addressof(ar), C.addressof(tr), int(use_bvh),
+                             _p(v), n, _p(hits), paths.ctypes.data, cap, C.byref(npaths))
+        if rc != 0:
+            raise RuntimeError(f"orc_trace failed: {rc}")
+        if npaths.value <= cap:
+            break
+        cap = npaths.value
+    lib().orc_release()
+    return hits, paths[: npaths.value].copy()
+
+
+def synth(paths, scene, array, chirp, model=0, idx=None) -> np.ndarray:
+    """Cube entries (complex128) for model 0 (exact) or 1 (separable).  With
+    idx None: the full cube [C][M][K]; else the flat entries idx."""
+    keep = _Keep()
+    paths = np.ascontiguousarray(paths, dtype=PATH_DTYPE)
+    sc = _scene(scene, keep)
+    ar = _array(array, keep)
+    ch = _chirp(chirp)
+    ix = None if idx is None else keep.add(idx, np.int64)
+    n = array.n_ch * chirp.n_chirps * chirp.n_samples if ix is None else ix.shape[0]
+    out = np.zeros((n, 2))
+    rc = lib().orc_synth(paths.ctypes.data if paths.size else None, paths.shape[0],
+                         C.addressof(sc), C.addressof(ar), C.byref(ch), int(model), _p(ix), n,
+                         out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_synth failed: {rc}")
+    z = out[:, 0] + 1j * out[:, 1]
+    if ix is None:
+        z = z.reshape(array.n_ch, chirp.n_chirps, chirp.n_samples)
+    return z
