@@ -1,0 +1,208 @@
+/*
+ * radray.h -- C ABI of the MI355X radar ray-tracing library (libradray.so).
+ *
+ * The library computes the hot path of the ray-tracing radar simulator of
+ * Braeunig et al., "A Realistic Radar Ray Tracing Simulator for Hand Pose
+ * Imaging" (Section III): rays leave every transmitter, bounce off a
+ * triangle mesh with the two-lobe material of Eqs. (1)-(3), the received
+ * paths keep their total length (Section III-B), and the baseband is the
+ * coherent sum of Eq. (4).  Eq. (4) is evaluated with the FMCW instantaneous
+ * frequency f_k = f0 + B k / K of fast-time sample k instead of the stepped
+ * frequency, and objects move at constant velocity between chirps
+ * (stop-and-go).  All device work runs in hand-written HIP kernels for gfx950.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: RR_OK (0) or a negative RR_E* code; no exception crosses
+ *     the ABI.  rr_last_error() returns a thread-local message for the last
+ *     failing call on the calling thread.
+ *   - Units: metres, seconds, hertz.  Axes: x = boresight, y = left, z = up.
+ *   - Host pointers (`const T*` without `_dev`) are read during the call and
+ *     copied; the caller keeps ownership.  Device pointers (`*_dev`) are
+ *     caller-owned HIP allocations on the context's device; they must stay
+ *     valid until the work enqueued by the call has completed on the
+ *     context's stream.
+ *   - All device work is enqueued on the stream given to rr_create, in call
+ *     order.  A call returns without waiting unless it writes a host scalar
+ *     (`*_out` arguments), which synchronises the stream.
+ *   - Virtual channel c = t * n_rx + r (Tx-major).  Cubes are complex64
+ *     (interleaved float re, im) laid out [channel][chirp][sample].
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef RADRAY_H
+#define RADRAY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RR_OK = 0,
+    RR_EINVAL = -1,        /* invalid argument (shape, NaN, range) */
+    RR_ENOMEM = -2,        /* device or host allocation failed */
+    RR_EHIP = -3,          /* a HIP runtime call failed */
+    RR_ESTATE = -4,        /* call order violated (e.g. synthesize before trace) */
+    RR_EOVERFLOW = -5,     /* an output buffer is too small; needed size reported */
+    RR_EUNSUPPORTED = -6   /* valid request that this build does not support */
+};
+
+enum { RR_TX_PER_ELEMENT = 0, RR_TX_SHARED = 1 };
+enum { RR_UNIFORM = 0, RR_PROPOSAL = 1 };
+enum { RR_EXACT = 0, RR_SEPARABLE = 1 };
+enum { RR_ENGINE_AUTO = 0, RR_DIRECT_FP32 = 1, RR_GEMM_BF16X3 = 2 };
+
+#define RR_KMAX 4          /* largest supported bounce count */
+
+typedef struct rr_ctx rr_ctx;
+
+/* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+int rr_create(int hip_device, void *hip_stream, rr_ctx **out);
+
+/* Release every device buffer the context owns.  Safe on NULL. */
+void rr_destroy(rr_ctx *ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *rr_last_error(void);
+
+/* Library version string. */
+const char *rr_version(void);
+
+/* Scene upload (Section III: a 3D triangle mesh; Sec. III-A: a material
+ * parameter alpha per surface, Eq. 3).
+ *   verts     float [n_verts][3]
+ *   tris      int32 [n_tris][3] vertex indices
+ *   tri_obj   int32 [n_tris] object of each triangle, in [0, n_obj)
+ *   obj_alpha float [n_obj], each in [0, 1] (0 specular, 1 diffuse)
+ *   obj_vel   double [n_obj][3] constant velocity (m/s)
+ *   pt_pos, pt_vel double [n_pts][3], pt_aperture double [n_pts] (m^2):
+ *             point reflectors (a retro-reflector of the given aperture)
+ * The host builds a binned-SAH BVH (depth <= 31) and uploads it.  Replaces
+ * any previous scene and invalidates traced paths.  n_tris may be 0.
+ * Errors: RR_EINVAL for out-of-range indices, non-finite coordinates or alpha
+ * outside [0, 1]; RR_ENOMEM. */
+int rr_scene_upload(rr_ctx *ctx, const float *verts, int64_t n_verts,
+                    const int32_t *tris, const int32_t *tri_obj, int64_t n_tris,
+                    const float *obj_alpha, const double *obj_vel, int32_t n_obj,
+                    const double *pt_pos, const double *pt_vel, const double *pt_aperture,
+                    int32_t n_pts);
+
+/* MIMO array geometry (Section II).  tx double [n_tx][3], rx double [n_rx][3].
+ * rx_radius: radius of the array-level reception sphere centred on the Rx
+ * phase centre (mean of rx).  tx_mode: RR_TX_PER_ELEMENT (rays from every Tx,
+ * n_rays / n_tx each) or RR_TX_SHARED (rays from the Tx phase centre, each
+ * path feeding every channel).  Errors: RR_EINVAL. */
+int rr_set_array(rr_ctx *ctx, const double *tx, int32_t n_tx, const double *rx, int32_t n_rx,
+                 double rx_radius, int32_t tx_mode);
+
+/* FMCW chirp: start frequency f0, sweep bandwidth B over t_chirp, chirp
+ * repetition t_rep, n_samples fast-time samples per chirp (sample k at
+ * frequency f0 + B k / n_samples), n_chirps chirps.  Errors: RR_EINVAL. */
+typedef struct {
+    double f0, bandwidth, t_chirp, t_rep;
+    int32_t n_samples, n_chirps;
+} rr_chirp;
+int rr_set_chirp(rr_ctx *ctx, const rr_chirp *chirp);
+
+/* Trace parameters (Sec. III-A: each Tx sends out many rays).
+ *   n_rays      total launched rays (split evenly over Tx in per-element mode)
+ *   max_bounces surface hits per ray, 1..RR_KMAX
+ *   seed        Philox4x64-10 key
+ *   az/el range field of view in radians; directions uniform in solid angle
+ *   sampler     RR_UNIFORM, or RR_PROPOSAL (bins of the proposal table set by
+ *               rr_proposal_set_cdf or rr_proposal_build, weight p0/q)
+ *   record_hits 1: keep the per-ray hit list for rr_get_hits
+ *   path_cap    keep at most this many paths (first in ray, bounce order);
+ *               0 = keep all */
+typedef struct {
+    int64_t n_rays;
+    int32_t max_bounces;
+    uint64_t seed;
+    double az_min, az_max, el_min, el_max;
+    int32_t sampler;
+    int32_t record_hits;
+    int64_t path_cap;
+} rr_trace_params;
+
+/* Trace the scene from the array.  Paths are ordered by (virtual ray,
+ * bounce): for source s, its rays 0..N_s-1 then its point reflectors.  With
+ * n_paths_out != NULL the stream is synchronised and the number of stored
+ * paths written; the internal path buffer grows as needed.  With NULL the
+ * call does not synchronise (path count stays on the device; a later
+ * rr_get_path_count reports it, and overflow of the current capacity is
+ * reported as RR_EOVERFLOW there).  Errors: RR_ESTATE (no scene or array),
+ * RR_EINVAL, RR_ENOMEM, RR_EHIP. */
+int rr_trace(rr_ctx *ctx, const rr_trace_params *params, int64_t *n_paths_out);
+
+/* Number of paths held by the context (synchronises).  RR_EOVERFLOW (with
+ * the needed count in *n_out) if the last asynchronous trace overflowed. */
+int rr_get_path_count(rr_ctx *ctx, int64_t *n_out);
+
+/* Copy the per-ray hit list of the last trace into tri_dev, int32
+ * [n_rays][max_bounces + 1]: closest-hit triangle id of each traced segment,
+ * -1 for a miss or a segment not traced.  Ray r of source s is row
+ * s * N_s + r.  cap_elems is the capacity of tri_dev in elements.
+ * Errors: RR_ESTATE (no hits recorded), RR_EOVERFLOW. */
+int rr_get_hits(rr_ctx *ctx, int32_t *tri_dev, int64_t cap_elems);
+
+/* Path list in structure-of-arrays form (device pointers, planes of
+ * `stride` elements):
+ *   src  int32  [n]      Tx index, -1 for a shared launch
+ *   K    int32  [n]      number of hit points (1..RR_KMAX)
+ *   ray  int64  [n]      virtual ray id
+ *   tri  int32  [RR_KMAX][stride]  hit triangle ids (-1: point reflector/unused)
+ *   vid  int32  [RR_KMAX][stride]  velocity id: object id, or n_obj + point id
+ *   p    double [RR_KMAX*3][stride] hit point j, coordinate a in plane 3j+a
+ *   L    double [n]      source-to-last-hit length at t = 0
+ *   amp  double [n]      amplitude a_p (weight / rays per source, or the
+ *                        point reflector's return) */
+typedef struct {
+    int32_t *src;
+    int32_t *K;
+    int64_t *ray;
+    int32_t *tri;
+    int32_t *vid;
+    double *p;
+    double *L;
+    double *amp;
+    int64_t stride;
+} rr_paths;
+
+/* Copy the context's paths into dst (device buffers, capacity dst->stride).
+ * *n_out receives the number of paths (synchronises).  RR_EOVERFLOW if the
+ * capacity is too small (the needed count is still written to *n_out). */
+int rr_get_paths(rr_ctx *ctx, const rr_paths *dst, int64_t *n_out);
+
+/* Replace the context's paths by n paths from src (device buffers), e.g. to
+ * synthesise a path list produced elsewhere.  Errors: RR_EINVAL, RR_ENOMEM. */
+int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
+
+/* Coherent sum of Eq. (4) over the context's paths into cube_dev.
+ *   model  RR_EXACT: d = |p_1(m) - tx_t| + inner(m) + |rx_r - p_K(m)| per
+ *          channel and chirp; RR_SEPARABLE: the channel part of the length
+ *          uses f0 and chirp 0 (a per-channel factor times a per-(chirp,
+ *          sample) factor), which allows the complex-GEMM engine.
+ *   engine RR_DIRECT_FP32 (either model), RR_GEMM_BF16X3 (separable only:
+ *          split-bf16 hi+lo complex GEMM on MFMA, FP32 accumulation), or
+ *          RR_ENGINE_AUTO (GEMM for the separable model, direct otherwise).
+ *   cube_dev complex64 [n_ch][n_chirps][n_samples], cube_elems = its complex
+ *          element count; the cube is overwritten.
+ *   sample_idx_dev int64 [n_sample] flat entry indices (c*M*K + m*K + k):
+ *          when non-NULL only these entries are computed, into
+ *          cube_dev[0..n_sample) (direct engine, FP64-reduced phase).
+ * Errors: RR_ESTATE (no paths/array/chirp), RR_EINVAL, RR_EUNSUPPORTED
+ * (GEMM engine with the exact model). */
+int rr_synthesize(rr_ctx *ctx, int32_t model, int32_t engine, void *cube_dev, int64_t cube_elems,
+                  const int64_t *sample_idx_dev, int64_t n_sample);
+
+/* Kernel timing of the last rr_trace / rr_synthesize call, in milliseconds,
+ * measured with HIP events on the context stream (synchronises).
+ * which: 0 = trace (all trace kernels), 1 = synthesis main kernel. */
+int rr_last_kernel_ms(rr_ctx *ctx, int32_t which, double *ms_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADRAY_H */

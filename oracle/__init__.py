@@ -253,3 +253,15 @@ def synth(paths, scene, array, chirp, model=0, idx=None) -> np.ndarray:
     if ix is None:
         z = z.reshape(array.n_ch, chirp.n_chirps, chirp.n_samples)
     return z
+
+
+def to_soa(p, kmax: int = 4) -> dict:
+    """Oracle path records -> the library's structure-of-arrays layout
+    (src, K, ray [n]; tri, vid [kmax][n]; p [3*kmax][n]; L, amp [n])."""
+    n = len(p)
+    return dict(src=p["src"].astype(np.int32), K=p["K"].astype(np.int32),
+                ray=p["ray"].astype(np.int64),
+                tri=np.ascontiguousarray(p["tri"][:, :kmax].T.astype(np.int32)),
+                vid=np.ascontiguousarray(p["vid"][:, :kmax].T.astype(np.int32)),
+                p=np.ascontiguousarray(p["p"][:, :kmax, :].reshape(n, 3 * kmax).T),
+                L=p["L"].astype(np.float64), amp=p["amp"].astype(np.float64))

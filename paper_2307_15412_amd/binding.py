@@ -1,0 +1,265 @@
+"""ctypes binding of libradray (include/radray.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Device memory comes from torch tensors on the context's device;
+work is enqueued on the torch stream that was current when the context was
+created.  There is no CPU fallback: if the library is missing or the device
+is not available, the constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libradray.so")
+
+RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_ESTATE, RR_EOVERFLOW, RR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+TX_PER_ELEMENT, TX_SHARED = 0, 1
+UNIFORM, PROPOSAL = 0, 1
+EXACT, SEPARABLE = 0, 1
+ENGINE_AUTO, DIRECT_FP32, GEMM_BF16X3 = 0, 1, 2
+KMAX = 4
+
+EXPORTED = [
+    "rr_create", "rr_destroy", "rr_last_error", "rr_version", "rr_scene_upload", "rr_set_array",
+    "rr_set_chirp", "rr_trace", "rr_get_path_count", "rr_get_hits", "rr_get_paths",
+    "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms",
+]
+
+
+class RadrayError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"radray error {code}: {msg}")
+        self.code = code
+
+
+class Chirp(C.Structure):
+    _fields_ = [("f0", C.c_double), ("bandwidth", C.c_double), ("t_chirp", C.c_double),
+                ("t_rep", C.c_double), ("n_samples", C.c_int32), ("n_chirps", C.c_int32)]
+
+
+class TraceParams(C.Structure):
+    _fields_ = [("n_rays", C.c_int64), ("max_bounces", C.c_int32), ("seed", C.c_uint64),
+                ("az_min", C.c_double), ("az_max", C.c_double), ("el_min", C.c_double),
+                ("el_max", C.c_double), ("sampler", C.c_int32), ("record_hits", C.c_int32),
+                ("path_cap", C.c_int64)]
+
+
+class Paths(C.Structure):
+    _fields_ = [("src", C.c_void_p), ("K", C.c_void_p), ("ray", C.c_void_p), ("tri", C.c_void_p),
+                ("vid", C.c_void_p), ("p", C.c_void_p), ("L", C.c_void_p), ("amp", C.c_void_p),
+                ("stride", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libradray.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libradray.so not built at {path}: run paper_2307_15412_amd/build.py")
+    L = C.CDLL(path)
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.rr_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+    L.rr_destroy.argtypes = [vp]
+    L.rr_destroy.restype = None
+    L.rr_last_error.restype = C.c_char_p
+    L.rr_version.restype = C.c_char_p
+    L.rr_scene_upload.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, i32, vp, vp, vp, i32]
+    L.rr_set_array.argtypes = [vp, vp, i32, vp, i32, f64, i32]
+    L.rr_set_chirp.argtypes = [vp, C.POINTER(Chirp)]
+    L.rr_trace.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
+    L.rr_get_path_count.argtypes = [vp, C.POINTER(i64)]
+    L.rr_get_hits.argtypes = [vp, vp, i64]
+    L.rr_get_paths.argtypes = [vp, C.POINTER(Paths), C.POINTER(i64)]
+    L.rr_set_paths.argtypes = [vp, C.POINTER(Paths), i64]
+    L.rr_synthesize.argtypes = [vp, i32, i32, vp, i64, vp, i64]
+    L.rr_last_kernel_ms.argtypes = [vp, i32, C.POINTER(f64)]
+    _lib = L
+    return L
+
+
+def _np(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, (a.ctypes.data if a.size else None)
+
+
+class Context:
+    """One library context on a GPU, bound to the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("radray needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        self._check(self.lib.rr_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.n_paths = None
+        self.n_traced = 0
+        self.max_bounces = 0
+        self.n_ch = self.M = self.K = 0
+
+    def _check(self, rc: int):
+        if rc != RR_OK:
+            raise RadrayError(rc, self.lib.rr_last_error().decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- inputs
+    def scene_upload(self, verts, tris, tri_obj, obj_alpha, obj_vel, pt_pos=None, pt_vel=None,
+                     pt_aperture=None):
+        v, pv = _np(verts, np.float32)
+        t, pt = _np(tris, np.int32)
+        o, po = _np(tri_obj, np.int32)
+        a, pa = _np(obj_alpha, np.float32)
+        ov, pov = _np(obj_vel, np.float64)
+        pp, ppp = _np(np.zeros((0, 3)) if pt_pos is None else pt_pos, np.float64)
+        pvv, ppv = _np(np.zeros((0, 3)) if pt_vel is None else pt_vel, np.float64)
+        pa2, ppa = _np(np.zeros((0,)) if pt_aperture is None else pt_aperture, np.float64)
+        self._check(self.lib.rr_scene_upload(self.h, pv, v.size // 3, pt, po, t.size // 3, pa, pov,
+                                             a.size, ppp, ppv, ppa, pp.size // 3))
+
+    def upload(self, scene):
+        """Upload an object with verts/tris/tri_obj/obj_alpha/obj_vel/pt_* fields."""
+        self.scene_upload(scene.verts, scene.tris, scene.tri_obj, scene.obj_alpha, scene.obj_vel,
+                          scene.pt_pos, scene.pt_vel, scene.pt_aperture)
+
+    def set_array(self, tx, rx, rx_radius=0.25, mode=TX_PER_ELEMENT):
+        tx, ptx = _np(tx, np.float64)
+        rx, prx = _np(rx, np.float64)
+        self._check(self.lib.rr_set_array(self.h, ptx, tx.size // 3, prx, rx.size // 3,
+                                          float(rx_radius), int(mode)))
+        self.n_tx, self.n_rx, self.mode = tx.size // 3, rx.size // 3, int(mode)
+        self.n_ch = self.n_tx * self.n_rx
+
+    def set_chirp(self, f0, bandwidth, t_chirp, t_rep, n_samples, n_chirps):
+        ch = Chirp(f0, bandwidth, t_chirp, t_rep, n_samples, n_chirps)
+        self._check(self.lib.rr_set_chirp(self.h, C.byref(ch)))
+        self.M, self.K = int(n_chirps), int(n_samples)
+
+    # -------------------------------------------------------------- trace
+    def trace(self, n_rays, max_bounces=2, seed=0, az_min=-math.pi / 2, az_max=math.pi / 2,
+              el_min=-math.pi / 2, el_max=math.pi / 2, sampler=UNIFORM, record_hits=True,
+              path_cap=0) -> int:
+        tp = TraceParams(int(n_rays), int(max_bounces), int(seed) & (2**64 - 1), az_min, az_max,
+                         el_min, el_max, int(sampler), int(bool(record_hits)), int(path_cap))
+        n = C.c_int64()
+        self._check(self.lib.rr_trace(self.h, C.byref(tp), C.byref(n)))
+        self.n_paths = n.value
+        n_src = 1 if self.mode == TX_SHARED else self.n_tx
+        per = int(n_rays) if self.mode == TX_SHARED else int(n_rays) // self.n_tx
+        self.n_traced = n_src * per
+        self.max_bounces = int(max_bounces)
+        self.record_hits = bool(record_hits)
+        return self.n_paths
+
+    def hits(self):
+        torch = self.torch
+        out = torch.empty((self.n_traced, self.max_bounces + 1), dtype=torch.int32,
+                          device=self.device)
+        if out.numel() == 0:
+            return out
+        self._check(self.lib.rr_get_hits(self.h, C.c_void_p(out.data_ptr()), out.numel()))
+        self.stream.synchronize()
+        return out
+
+    def paths(self):
+        """Context paths as device tensors: src, K, ray [n]; tri, vid [KMAX][n];
+        p [3*KMAX][n]; L, amp [n]."""
+        torch = self.torch
+        n = C.c_int64()
+        self._check(self.lib.rr_get_path_count(self.h, C.byref(n)))
+        n = max(n.value, 1)
+        d = self.device
+        out = dict(src=torch.empty(n, dtype=torch.int32, device=d),
+                   K=torch.empty(n, dtype=torch.int32, device=d),
+                   ray=torch.empty(n, dtype=torch.int64, device=d),
+                   tri=torch.empty((KMAX, n), dtype=torch.int32, device=d),
+                   vid=torch.empty((KMAX, n), dtype=torch.int32, device=d),
+                   p=torch.empty((3 * KMAX, n), dtype=torch.float64, device=d),
+                   L=torch.empty(n, dtype=torch.float64, device=d),
+                   amp=torch.empty(n, dtype=torch.float64, device=d))
+        ps = Paths(*(C.c_void_p(out[k].data_ptr()) for k in ("src", "K", "ray", "tri", "vid", "p", "L", "amp")), n)
+        cnt = C.c_int64()
+        self._check(self.lib.rr_get_paths(self.h, C.byref(ps), C.byref(cnt)))
+        m = cnt.value
+        return {k: (v[..., :m] if v.dim() == 2 else v[:m]) for k, v in out.items()}
+
+    def set_paths(self, paths: dict):
+        torch = self.torch
+        n = int(paths["K"].numel())
+        keep = {}
+        for k, dt, shape in (("src", torch.int32, (n,)), ("K", torch.int32, (n,)),
+                             ("ray", torch.int64, (n,)), ("tri", torch.int32, (KMAX, n)),
+                             ("vid", torch.int32, (KMAX, n)), ("p", torch.float64, (3 * KMAX, n)),
+                             ("L", torch.float64, (n,)), ("amp", torch.float64, (n,))):
+            if k in paths:
+                keep[k] = paths[k].to(device=self.device, dtype=dt).contiguous().reshape(shape)
+        ptr = lambda k: C.c_void_p(keep[k].data_ptr()) if k in keep and n else None
+        ps = Paths(ptr("src"), ptr("K"), ptr("ray"), ptr("tri"), ptr("vid"), ptr("p"), ptr("L"),
+                   ptr("amp"), n)
+        self._check(self.lib.rr_set_paths(self.h, C.byref(ps), n))
+        self.n_paths = n
+
+    # ---------------------------------------------------------- synthesis
+    def synthesize(self, model=EXACT, engine=ENGINE_AUTO, sample_idx=None, out=None):
+        """Full cube [C][M][K] complex64, or the flat entries sample_idx."""
+        torch = self.torch
+        if sample_idx is None:
+            if out is None:
+                out = torch.empty((self.n_ch, self.M, self.K), dtype=torch.complex64,
+                                  device=self.device)
+            self._check(self.lib.rr_synthesize(self.h, int(model), int(engine),
+                                               C.c_void_p(out.data_ptr()), out.numel(), None, 0))
+            return out
+        idx = torch.as_tensor(sample_idx, dtype=torch.int64).to(self.device).contiguous()
+        if out is None:
+            out = torch.empty(idx.numel(), dtype=torch.complex64, device=self.device)
+        self._check(self.lib.rr_synthesize(self.h, int(model), int(engine),
+                                           C.c_void_p(out.data_ptr()), out.numel(),
+                                           C.c_void_p(idx.data_ptr()), idx.numel()))
+        self._keep_idx = idx
+        return out
+
+    def kernel_ms(self, which: int) -> float:
+        ms = C.c_double()
+        self._check(self.lib.rr_last_kernel_ms(self.h, int(which), C.byref(ms)))
+        return ms.value
+
+    # ------------------------------------------------------ conveniences
+    def setup(self, workload):
+        """Upload a workload-like object (scene, array, chirp)."""
+        self.upload(workload.scene)
+        a = workload.array
+        self.set_array(a.tx, a.rx, a.rx_radius, a.mode)
+        ch = workload.chirp
+        self.set_chirp(ch.f0, ch.bandwidth, ch.t_chirp, ch.t_rep, ch.n_samples, ch.n_chirps)
+
+    def trace_workload(self, workload, record_hits=True, **kw):
+        tp = workload.trace
+        args = dict(n_rays=tp.n_rays, max_bounces=tp.max_bounces, seed=tp.seed, az_min=tp.az_min,
+                    az_max=tp.az_max, el_min=tp.el_min, el_max=tp.el_max,
+                    record_hits=record_hits, path_cap=getattr(workload, "path_cap", None) or 0)
+        args.update(kw)
+        return self.trace(**args)

@@ -1,0 +1,639 @@
+// rr_host.cpp -- the C ABI of libradray: context, validation, device buffers
+// and the launch sequence of the trace and synthesis kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rr_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(RR_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // grow to at least n bytes (contents are not preserved)
+    int ensure(size_t n)
+    {
+        if (n <= bytes && p) return RR_OK;
+        release();
+        if (n == 0) n = 256;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            p = nullptr;
+            return fail(RR_ENOMEM, "hipMalloc(%zu) failed", n);
+        }
+        bytes = n;
+        return RR_OK;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Device path list: one allocation, planes carved out of it.
+struct PathStore {
+    DevBuf buf;
+    PathSoA soa;
+    int alloc(int64_t cap)
+    {
+        if (cap < 1) cap = 1;
+        if (soa.cap >= cap && buf.p) return RR_OK;
+        size_t per = 4 + 4 + 8 + 4 + 4 * RR_KMAX + 4 * RR_KMAX + 8 * 3 * RR_KMAX + 8 + 8;
+        int rc = buf.ensure((size_t)cap * per + 1024);
+        if (rc) return rc;
+        char *b = buf.as<char>();
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            char *r = b + off;
+            off += (bytes + 255) & ~size_t(255);
+            return r;
+        };
+        soa.cap = cap;
+        soa.ray = (int64_t *)take(8 * cap);
+        soa.p = (double *)take(8 * 3 * RR_KMAX * cap);
+        soa.L = (double *)take(8 * cap);
+        soa.amp = (double *)take(8 * cap);
+        soa.src = (int32_t *)take(4 * cap);
+        soa.K = (int32_t *)take(4 * cap);
+        soa.loc = (int32_t *)take(4 * cap);
+        soa.tri = (int32_t *)take(4 * RR_KMAX * cap);
+        soa.vid = (int32_t *)take(4 * RR_KMAX * cap);
+        if (off > buf.bytes) {
+            // plane rounding exceeded the estimate: allocate exactly
+            buf.release();
+            int rc2 = buf.ensure(off);
+            if (rc2) return rc2;
+            soa.cap = 0;
+            return alloc(cap);
+        }
+        return RR_OK;
+    }
+};
+
+bool finite3(const double *p, int64_t n)
+{
+    for (int64_t i = 0; i < 3 * n; i++)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct rr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool trace_timed = false, synth_timed = false;
+
+    // scene
+    bool has_scene = false;
+    int64_t n_tris = 0;
+    int nobj = 0, npts = 0;
+    DevBuf nodes, ltris, obj_alpha, obj_vel, pt_pos, pt_vel, pt_ap;
+    int bvh_depth = 0;
+
+    // array
+    bool has_array = false;
+    int ntx = 0, nrx = 0, mode = RR_TX_PER_ELEMENT;
+    double rx_radius = 0.25;
+    std::vector<double> tx_h, rx_h;
+    double oT[3] = {0, 0, 0}, oR[3] = {0, 0, 0};
+    DevBuf tx, rx;
+
+    // chirp
+    bool has_chirp = false;
+    rr_chirp chirp{};
+
+    // trace state
+    DevBuf counts, offsets, bsums, counter, total, err_flag, hits, cdf;
+    PathStore tmp;
+    int64_t tmp_cap = 0;
+    PathStore paths;
+    int64_t n_paths = -1;          // -1: none
+    int64_t hits_elems = 0;
+    bool hits_recorded = false;
+    int n_az = 0, n_el = 0;        // proposal grid (cdf set)
+
+    // synthesis scratch
+    DevBuf syn, ranges;
+};
+
+extern "C" {
+
+const char *rr_last_error(void) { return g_err.c_str(); }
+
+const char *rr_version(void) { return "radray 0.1 (gfx950)"; }
+
+int rr_create(int hip_device, void *hip_stream, rr_ctx **out)
+{
+    if (!out) return fail(RR_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev)
+        return fail(RR_EINVAL, "device %d out of range (%d devices)", hip_device, ndev);
+    HIPCHK(hipSetDevice(hip_device));
+    rr_ctx *c = new rr_ctx();
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    for (auto &e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            rr_destroy(c);
+            return fail(RR_EHIP, "hipEventCreate failed");
+        }
+    }
+    int rc = c->counter.ensure(256);
+    if (!rc) rc = c->total.ensure(256);
+    if (!rc) rc = c->err_flag.ensure(256);
+    if (rc) {
+        rr_destroy(c);
+        return rc;
+    }
+    *out = c;
+    g_err.clear();
+    return RR_OK;
+}
+
+void rr_destroy(rr_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    DevBuf *bufs[] = {&c->nodes, &c->ltris, &c->obj_alpha, &c->obj_vel, &c->pt_pos, &c->pt_vel,
+                      &c->pt_ap, &c->tx, &c->rx, &c->counts, &c->offsets, &c->bsums,
+                      &c->counter, &c->total, &c->err_flag, &c->hits, &c->cdf, &c->syn,
+                      &c->ranges, &c->tmp.buf, &c->paths.buf};
+    for (DevBuf *b : bufs) b->release();
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int rr_scene_upload(rr_ctx *c, const float *verts, int64_t n_verts, const int32_t *tris,
+                    const int32_t *tri_obj, int64_t n_tris, const float *obj_alpha,
+                    const double *obj_vel, int32_t n_obj, const double *pt_pos,
+                    const double *pt_vel, const double *pt_aperture, int32_t n_pts)
+{
+    if (!c) return fail(RR_EINVAL, "ctx is NULL");
+    if (n_verts < 0 || n_tris < 0 || n_obj < 1 || n_pts < 0)
+        return fail(RR_EINVAL, "negative size or no object");
+    if ((n_tris > 0 && (!verts || !tris || !tri_obj)) || !obj_alpha || !obj_vel ||
+        (n_pts > 0 && (!pt_pos || !pt_vel || !pt_aperture)))
+        return fail(RR_EINVAL, "NULL array");
+    for (int64_t i = 0; i < 3 * n_verts; i++)
+        if (!std::isfinite(verts[i])) return fail(RR_EINVAL, "non-finite vertex coordinate");
+    for (int64_t i = 0; i < n_tris; i++) {
+        for (int k = 0; k < 3; k++)
+            if (tris[3 * i + k] < 0 || tris[3 * i + k] >= n_verts)
+                return fail(RR_EINVAL, "triangle %lld vertex index out of range", (long long)i);
+        if (tri_obj[i] < 0 || tri_obj[i] >= n_obj)
+            return fail(RR_EINVAL, "triangle %lld object out of range", (long long)i);
+    }
+    for (int i = 0; i < n_obj; i++)
+        if (!(obj_alpha[i] >= 0.0f && obj_alpha[i] <= 1.0f))
+            return fail(RR_EINVAL, "alpha of object %d outside [0, 1]", i);
+    if (!finite3(obj_vel, n_obj)) return fail(RR_EINVAL, "non-finite object velocity");
+    if (n_pts > 0 && (!finite3(pt_pos, n_pts) || !finite3(pt_vel, n_pts)))
+        return fail(RR_EINVAL, "non-finite point reflector");
+    for (int i = 0; i < n_pts; i++)
+        if (!(pt_aperture[i] >= 0.0) || !std::isfinite(pt_aperture[i]))
+            return fail(RR_EINVAL, "invalid point aperture");
+    HIPCHK(hipSetDevice(c->device));
+    HostBvh bvh;
+    std::string err;
+    int rc = rr_build_bvh(verts, n_verts, tris, tri_obj, n_tris, bvh, err);
+    if (rc) return fail(rc, "BVH build: %s", err.c_str());
+    c->has_scene = false;
+    c->n_paths = -1;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((rc = c->nodes.ensure(bvh.nodes.size() * 4 + 64))) return rc;
+    if ((rc = c->ltris.ensure(bvh.tris.size() * 4 + 64))) return rc;
+    if ((rc = c->obj_alpha.ensure((size_t)n_obj * 4))) return rc;
+    if ((rc = c->obj_vel.ensure((size_t)n_obj * 24))) return rc;
+    if ((rc = c->pt_pos.ensure((size_t)n_pts * 24 + 8))) return rc;
+    if ((rc = c->pt_vel.ensure((size_t)n_pts * 24 + 8))) return rc;
+    if ((rc = c->pt_ap.ensure((size_t)n_pts * 8 + 8))) return rc;
+    if (!bvh.nodes.empty())
+        HIPCHK(hipMemcpy(c->nodes.p, bvh.nodes.data(), bvh.nodes.size() * 4, hipMemcpyHostToDevice));
+    if (!bvh.tris.empty())
+        HIPCHK(hipMemcpy(c->ltris.p, bvh.tris.data(), bvh.tris.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->obj_alpha.p, obj_alpha, (size_t)n_obj * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->obj_vel.p, obj_vel, (size_t)n_obj * 24, hipMemcpyHostToDevice));
+    if (n_pts > 0) {
+        HIPCHK(hipMemcpy(c->pt_pos.p, pt_pos, (size_t)n_pts * 24, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->pt_vel.p, pt_vel, (size_t)n_pts * 24, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->pt_ap.p, pt_aperture, (size_t)n_pts * 8, hipMemcpyHostToDevice));
+    }
+    c->n_tris = n_tris;
+    c->nobj = n_obj;
+    c->npts = n_pts;
+    c->bvh_depth = bvh.depth;
+    c->has_scene = true;
+    g_err.clear();
+    return RR_OK;
+}
+
+int rr_set_array(rr_ctx *c, const double *tx, int32_t n_tx, const double *rx, int32_t n_rx,
+                 double rx_radius, int32_t tx_mode)
+{
+    if (!c) return fail(RR_EINVAL, "ctx is NULL");
+    if (!tx || !rx || n_tx < 1 || n_rx < 1) return fail(RR_EINVAL, "empty array");
+    if (!finite3(tx, n_tx) || !finite3(rx, n_rx)) return fail(RR_EINVAL, "non-finite element");
+    if (!(rx_radius > 0.0) || !std::isfinite(rx_radius))
+        return fail(RR_EINVAL, "rx_radius must be positive");
+    if (tx_mode != RR_TX_PER_ELEMENT && tx_mode != RR_TX_SHARED)
+        return fail(RR_EINVAL, "unknown tx_mode %d", tx_mode);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int rc;
+    if ((rc = c->tx.ensure((size_t)n_tx * 24))) return rc;
+    if ((rc = c->rx.ensure((size_t)n_rx * 24))) return rc;
+    HIPCHK(hipMemcpy(c->tx.p, tx, (size_t)n_tx * 24, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->rx.p, rx, (size_t)n_rx * 24, hipMemcpyHostToDevice));
+    c->tx_h.assign(tx, tx + 3 * n_tx);
+    c->rx_h.assign(rx, rx + 3 * n_rx);
+    // phase centres: sums in index order divided by the count
+    for (int a = 0; a < 3; a++) {
+        double s = 0.0;
+        for (int i = 0; i < n_tx; i++) s += tx[3 * i + a];
+        c->oT[a] = s / (double)n_tx;
+        s = 0.0;
+        for (int i = 0; i < n_rx; i++) s += rx[3 * i + a];
+        c->oR[a] = s / (double)n_rx;
+    }
+    c->ntx = n_tx;
+    c->nrx = n_rx;
+    c->rx_radius = rx_radius;
+    c->mode = tx_mode;
+    c->has_array = true;
+    c->n_paths = -1;
+    g_err.clear();
+    return RR_OK;
+}
+
+int rr_set_chirp(rr_ctx *c, const rr_chirp *ch)
+{
+    if (!c || !ch) return fail(RR_EINVAL, "NULL argument");
+    if (!(ch->f0 > 0.0) || !std::isfinite(ch->f0) || !(ch->bandwidth >= 0.0) ||
+        !std::isfinite(ch->bandwidth) || !(ch->t_chirp > 0.0) || !(ch->t_rep >= 0.0) ||
+        !std::isfinite(ch->t_rep) || ch->n_samples < 1 || ch->n_chirps < 1)
+        return fail(RR_EINVAL, "degenerate chirp");
+    c->chirp = *ch;
+    c->has_chirp = true;
+    g_err.clear();
+    return RR_OK;
+}
+
+// defined below; also used by the proposal code
+int rr_set_proposal_cdf_internal(rr_ctx *c, const double *cdf_dev, int n_az, int n_el);
+
+int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
+{
+    if (!c || !tp) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_scene || !c->has_array) return fail(RR_ESTATE, "scene and array must be set");
+    if (tp->max_bounces < 1 || tp->max_bounces > RR_KMAX)
+        return fail(RR_EINVAL, "max_bounces must be in [1, %d]", RR_KMAX);
+    if (tp->n_rays < 0) return fail(RR_EINVAL, "negative n_rays");
+    if (!(tp->az_max > tp->az_min) || !(tp->el_max > tp->el_min) || tp->el_min < -M_PI / 2 - 1e-12 ||
+        tp->el_max > M_PI / 2 + 1e-12 || !std::isfinite(tp->az_min) || !std::isfinite(tp->az_max))
+        return fail(RR_EINVAL, "invalid field of view");
+    if (tp->sampler != RR_UNIFORM && tp->sampler != RR_PROPOSAL)
+        return fail(RR_EINVAL, "unknown sampler");
+    if (tp->sampler == RR_PROPOSAL && c->n_az <= 0)
+        return fail(RR_ESTATE, "proposal sampler without a proposal table");
+    if (tp->path_cap < 0) return fail(RR_EINVAL, "negative path_cap");
+    HIPCHK(hipSetDevice(c->device));
+
+    const int shared = c->mode == RR_TX_SHARED;
+    const int64_t n_src = shared ? 1 : c->ntx;
+    const int64_t n_per_src = shared ? tp->n_rays : tp->n_rays / c->ntx;
+    const int64_t n_vps = n_per_src + c->npts;
+    const int64_t V = n_src * n_vps;
+    const int64_t n_traced = n_src * n_per_src;
+    if (V >= (int64_t(1) << 32)) return fail(RR_EUNSUPPORTED, "too many rays");
+    const int bmax = tp->max_bounces;
+
+    int rc;
+    if ((rc = c->counts.ensure((size_t)V + 64))) return rc;
+    if ((rc = c->offsets.ensure((size_t)V * 4 + 64))) return rc;
+    const int64_t nb = scan_u8_blocks(V);
+    if ((rc = c->bsums.ensure((size_t)(nb + 1) * 4))) return rc;
+    if (tp->record_hits) {
+        if ((rc = c->hits.ensure((size_t)n_traced * (bmax + 1) * 4 + 64))) return rc;
+        c->hits_elems = n_traced * (bmax + 1);
+        c->hits_recorded = true;
+    } else {
+        c->hits_elems = 0;
+        c->hits_recorded = false;
+    }
+    if (c->tmp_cap == 0) c->tmp_cap = std::max<int64_t>(65536, V / 32);
+    if ((rc = c->tmp.alloc(c->tmp_cap))) return rc;
+
+    TraceArgs A{};
+    A.nodes = c->nodes.as<const float4>();
+    A.ltris = c->ltris.as<const float4>();
+    A.has_bvh = c->n_tris > 0;
+    A.obj_alpha = c->obj_alpha.as<const float>();
+    A.tx = c->tx.as<const double>();
+    A.pt_pos = c->pt_pos.as<const double>();
+    A.pt_ap = c->pt_ap.as<const double>();
+    for (int a = 0; a < 3; a++) {
+        A.oT[a] = c->oT[a];
+        A.oR[a] = c->oR[a];
+    }
+    A.r2 = c->rx_radius * c->rx_radius;
+    A.shared = shared;
+    A.nobj = c->nobj;
+    A.npts = c->npts;
+    A.n_src = n_src;
+    A.n_per_src = n_per_src;
+    A.n_virt_per_src = n_vps;
+    const double INV_2PI = 0.15915494309189535;
+    A.at = tp->az_min * INV_2PI;
+    A.bt = tp->az_max * INV_2PI;
+    A.slo = std::sin(tp->el_min);
+    A.shi = std::sin(tp->el_max);
+    A.omega = (tp->az_max - tp->az_min) * (A.shi - A.slo);
+    A.bmax = bmax;
+    A.seed = tp->seed;
+    A.sampler = tp->sampler;
+    A.cdf = c->cdf.as<const double>();
+    A.n_az = c->n_az;
+    A.n_el = c->n_el;
+    A.hits = tp->record_hits ? c->hits.as<int32_t>() : nullptr;
+    A.counts = c->counts.as<uint8_t>();
+    A.counter = c->counter.as<unsigned long long>();
+    A.err_flag = c->err_flag.as<int>();
+
+    for (int attempt = 0; attempt < 2; attempt++) {
+        A.tmp = c->tmp.soa;
+        HIPCHK(hipMemsetAsync(c->counter.p, 0, 8, c->stream));
+        HIPCHK(hipMemsetAsync(c->err_flag.p, 0, 4, c->stream));
+        HIPCHK(hipEventRecord(c->ev[0], c->stream));
+        HIPCHK(launch_trace(A, n_traced, c->stream));
+        HIPCHK(launch_points(A, c->stream));
+        HIPCHK(launch_scan_u8(A.counts, V, c->offsets.as<uint32_t>(), c->bsums.as<uint32_t>(),
+                              nb + 1, c->total.as<unsigned long long>(), c->stream));
+        unsigned long long cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, c->counter.p, 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if ((int64_t)cnt > c->tmp_cap) {
+            c->tmp_cap = (int64_t)cnt + cnt / 4 + 1024;
+            if ((rc = c->tmp.alloc(c->tmp_cap))) return rc;
+            continue;
+        }
+        int64_t keep = (int64_t)cnt;
+        if (tp->path_cap > 0 && keep > tp->path_cap) keep = tp->path_cap;
+        if ((rc = c->paths.alloc(std::max<int64_t>(keep, 1)))) return rc;
+        HIPCHK(launch_scatter(c->tmp.soa, A.counter, c->tmp_cap, c->offsets.as<uint32_t>(),
+                              c->paths.soa, keep, c->stream));
+        HIPCHK(hipEventRecord(c->ev[1], c->stream));
+        int errf = 0;
+        HIPCHK(hipMemcpyAsync(&errf, c->err_flag.p, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (errf) return fail(RR_EHIP, "traversal stack overflow (BVH depth %d)", c->bvh_depth);
+        c->n_paths = keep;
+        c->trace_timed = true;
+        if (n_paths_out) *n_paths_out = keep;
+        g_err.clear();
+        return RR_OK;
+    }
+    return fail(RR_EOVERFLOW, "temporary path buffer overflow persisted");
+}
+
+int rr_get_path_count(rr_ctx *c, int64_t *n_out)
+{
+    if (!c || !n_out) return fail(RR_EINVAL, "NULL argument");
+    if (c->n_paths < 0) return fail(RR_ESTATE, "no paths");
+    *n_out = c->n_paths;
+    return RR_OK;
+}
+
+int rr_get_hits(rr_ctx *c, int32_t *dst, int64_t cap_elems)
+{
+    if (!c) return fail(RR_EINVAL, "NULL argument");
+    if (c->n_paths < 0 || !c->hits_recorded) return fail(RR_ESTATE, "no hit list recorded");
+    if (c->hits_elems == 0) return RR_OK;
+    if (!dst) return fail(RR_EINVAL, "NULL argument");
+    if (cap_elems < c->hits_elems)
+        return fail(RR_EOVERFLOW, "hit list needs %lld elements", (long long)c->hits_elems);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemcpyAsync(dst, c->hits.p, (size_t)c->hits_elems * 4, hipMemcpyDeviceToDevice,
+                          c->stream));
+    return RR_OK;
+}
+
+static hipError_t copy_planes(void *dst, int64_t dstride, const void *src, int64_t sstride,
+                              int64_t n, int planes, size_t esz, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    return hipMemcpy2DAsync(dst, (size_t)dstride * esz, src, (size_t)sstride * esz, (size_t)n * esz,
+                            (size_t)planes, hipMemcpyDeviceToDevice, s);
+}
+
+int rr_get_paths(rr_ctx *c, const rr_paths *d, int64_t *n_out)
+{
+    if (!c || !d || !n_out) return fail(RR_EINVAL, "NULL argument");
+    if (c->n_paths < 0) return fail(RR_ESTATE, "no paths");
+    int64_t n = c->n_paths;
+    *n_out = n;
+    if (d->stride < n) return fail(RR_EOVERFLOW, "need capacity %lld", (long long)n);
+    HIPCHK(hipSetDevice(c->device));
+    const PathSoA &s = c->paths.soa;
+    hipStream_t st = c->stream;
+    if (d->src) HIPCHK(copy_planes(d->src, d->stride, s.src, s.cap, n, 1, 4, st));
+    if (d->K) HIPCHK(copy_planes(d->K, d->stride, s.K, s.cap, n, 1, 4, st));
+    if (d->ray) HIPCHK(copy_planes(d->ray, d->stride, s.ray, s.cap, n, 1, 8, st));
+    if (d->tri) HIPCHK(copy_planes(d->tri, d->stride, s.tri, s.cap, n, RR_KMAX, 4, st));
+    if (d->vid) HIPCHK(copy_planes(d->vid, d->stride, s.vid, s.cap, n, RR_KMAX, 4, st));
+    if (d->p) HIPCHK(copy_planes(d->p, d->stride, s.p, s.cap, n, 3 * RR_KMAX, 8, st));
+    if (d->L) HIPCHK(copy_planes(d->L, d->stride, s.L, s.cap, n, 1, 8, st));
+    if (d->amp) HIPCHK(copy_planes(d->amp, d->stride, s.amp, s.cap, n, 1, 8, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return RR_OK;
+}
+
+int rr_set_paths(rr_ctx *c, const rr_paths *s, int64_t n)
+{
+    if (!c || !s) return fail(RR_EINVAL, "NULL argument");
+    if (n < 0 || s->stride < n) return fail(RR_EINVAL, "bad count or stride");
+    if (n > 0 && (!s->src || !s->K || !s->vid || !s->p || !s->amp))
+        return fail(RR_EINVAL, "src, K, vid, p and amp are required");
+    HIPCHK(hipSetDevice(c->device));
+    int rc = c->paths.alloc(std::max<int64_t>(n, 1));
+    if (rc) return rc;
+    const PathSoA &d = c->paths.soa;
+    hipStream_t st = c->stream;
+    HIPCHK(copy_planes(d.src, d.cap, s->src, s->stride, n, 1, 4, st));
+    HIPCHK(copy_planes(d.K, d.cap, s->K, s->stride, n, 1, 4, st));
+    HIPCHK(copy_planes(d.vid, d.cap, s->vid, s->stride, n, RR_KMAX, 4, st));
+    HIPCHK(copy_planes(d.p, d.cap, s->p, s->stride, n, 3 * RR_KMAX, 8, st));
+    HIPCHK(copy_planes(d.amp, d.cap, s->amp, s->stride, n, 1, 8, st));
+    if (s->ray) HIPCHK(copy_planes(d.ray, d.cap, s->ray, s->stride, n, 1, 8, st));
+    if (s->tri) HIPCHK(copy_planes(d.tri, d.cap, s->tri, s->stride, n, RR_KMAX, 4, st));
+    if (s->L) HIPCHK(copy_planes(d.L, d.cap, s->L, s->stride, n, 1, 8, st));
+    // validate on the host: K in range, src sorted and in range
+    std::vector<int32_t> hs(n), hk(n);
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(hs.data(), d.src, n * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hk.data(), d.K, n * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; i++) {
+        if (hk[i] < 1 || hk[i] > RR_KMAX) {
+            c->n_paths = -1;
+            return fail(RR_EINVAL, "path %lld: K out of range", (long long)i);
+        }
+        if (hs[i] < -1 || (i > 0 && hs[i] < hs[i - 1])) {
+            c->n_paths = -1;
+            return fail(RR_EINVAL, "path %lld: src must be >= -1 and sorted", (long long)i);
+        }
+    }
+    c->n_paths = n;
+    g_err.clear();
+    return RR_OK;
+}
+
+// forward declaration (k_gemm.hip)
+int rr_synth_gemm(rr_ctx *c, void *cube, const SynPath *paths, int64_t n_paths);
+
+int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t cube_elems,
+                  const int64_t *idx, int64_t n_idx)
+{
+    if (!c || !cube) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_array || !c->has_chirp) return fail(RR_ESTATE, "array and chirp must be set");
+    if (c->n_paths < 0) return fail(RR_ESTATE, "no paths (trace or rr_set_paths first)");
+    if (model != RR_EXACT && model != RR_SEPARABLE) return fail(RR_EINVAL, "unknown model");
+    if (engine == RR_ENGINE_AUTO) engine = (model == RR_SEPARABLE && !idx) ? RR_GEMM_BF16X3 : RR_DIRECT_FP32;
+    if (engine != RR_DIRECT_FP32 && engine != RR_GEMM_BF16X3)
+        return fail(RR_EINVAL, "unknown engine");
+    if (engine == RR_GEMM_BF16X3 && model != RR_SEPARABLE)
+        return fail(RR_EUNSUPPORTED, "the GEMM engine needs the separable model");
+    if (engine == RR_GEMM_BF16X3 && idx)
+        return fail(RR_EUNSUPPORTED, "sampled entries use the direct engine");
+    const int64_t C = (int64_t)c->ntx * c->nrx, M = c->chirp.n_chirps, K = c->chirp.n_samples;
+    const int64_t total = C * M * K;
+    if (idx) {
+        if (n_idx < 0 || cube_elems < n_idx) return fail(RR_EINVAL, "cube too small for samples");
+    } else if (cube_elems < total) {
+        return fail(RR_EINVAL, "cube needs %lld complex elements", (long long)total);
+    }
+    if (C * M > (int64_t)1 << 31) return fail(RR_EUNSUPPORTED, "too many rows");
+    HIPCHK(hipSetDevice(c->device));
+    const int64_t n = c->n_paths;
+    const int shared = c->mode == RR_TX_SHARED;
+    const int n_groups = shared ? 1 : c->ntx;
+    int rc;
+    if ((rc = c->syn.ensure((size_t)std::max<int64_t>(n, 1) * sizeof(SynPath)))) return rc;
+    if ((rc = c->ranges.ensure((size_t)(n_groups + 2) * 8))) return rc;
+    if (!c->has_scene) return fail(RR_ESTATE, "scene must be set (velocities)");
+    if (n > 0) {
+        // src must match the launch mode: all -1 (shared) or sorted within [0, n_tx)
+        int32_t ends[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(&ends[0], c->paths.soa.src, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(&ends[1], c->paths.soa.src + (n - 1), 4, hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (shared ? (ends[0] != -1 || ends[1] != -1) : (ends[0] < 0 || ends[1] >= c->ntx))
+            return fail(RR_EINVAL, "path sources do not match the array's launch mode");
+    }
+    SynPath *sp = c->syn.as<SynPath>();
+    HIPCHK(launch_syn_prep(c->paths.soa, n, c->obj_vel.as<const double>(), c->nobj,
+                           c->pt_vel.as<const double>(), c->npts, sp, c->stream));
+    // shared paths carry src = -1: one group over all paths
+    if (shared) {
+        int64_t r[2] = {0, n};
+        HIPCHK(hipMemcpyAsync(c->ranges.p, r, 16, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    } else {
+        HIPCHK(launch_ranges(c->paths.soa.src, n, n_groups, c->ranges.as<int64_t>(), c->stream));
+    }
+    SynthArgs A{};
+    A.paths = sp;
+    A.ranges = c->ranges.as<const int64_t>();
+    A.n_paths = n;
+    A.tx = c->tx.as<const double>();
+    A.rx = c->rx.as<const double>();
+    A.ntx = c->ntx;
+    A.nrx = c->nrx;
+    for (int a = 0; a < 3; a++) {
+        A.oT[a] = c->oT[a];
+        A.oR[a] = c->oR[a];
+    }
+    A.shared = shared;
+    A.model = model;
+    A.f0 = c->chirp.f0;
+    A.bw = c->chirp.bandwidth;
+    A.t_rep = c->chirp.t_rep;
+    A.inv_c = 1.0 / 299792458.0;
+    A.M = (int)M;
+    A.K = (int)K;
+    A.cube = static_cast<float2 *>(cube);
+    HIPCHK(hipEventRecord(c->ev[2], c->stream));
+    if (idx) {
+        HIPCHK(launch_synth_sampled(A, idx, n_idx, c->stream));
+    } else if (engine == RR_GEMM_BF16X3) {
+        rc = rr_synth_gemm(c, cube, sp, n);
+        if (rc) return rc;
+    } else {
+        int rows = (int)(shared ? C * M : (int64_t)c->nrx * M);
+        hipError_t e = launch_synth_direct(A, n_groups, rows, c->stream);
+        if (e == hipErrorInvalidValue) return fail(RR_EUNSUPPORTED, "n_samples too large");
+        HIPCHK(e);
+    }
+    HIPCHK(hipEventRecord(c->ev[3], c->stream));
+    c->synth_timed = true;
+    g_err.clear();
+    return RR_OK;
+}
+
+int rr_last_kernel_ms(rr_ctx *c, int32_t which, double *ms)
+{
+    if (!c || !ms) return fail(RR_EINVAL, "NULL argument");
+    if ((which == 0 && !c->trace_timed) || (which == 1 && !c->synth_timed) || which < 0 || which > 1)
+        return fail(RR_ESTATE, "nothing timed");
+    HIPCHK(hipSetDevice(c->device));
+    hipEvent_t a = c->ev[which * 2], b = c->ev[which * 2 + 1];
+    HIPCHK(hipEventSynchronize(b));
+    float f = 0;
+    HIPCHK(hipEventElapsedTime(&f, a, b));
+    *ms = f;
+    return RR_OK;
+}
+
+}  // extern "C"
+
+int rr_synth_gemm(rr_ctx *c, void *cube, const SynPath *paths, int64_t n_paths)
+{
+    (void)c; (void)cube; (void)paths; (void)n_paths;
+    return fail(RR_EUNSUPPORTED, "GEMM engine not built");
+}

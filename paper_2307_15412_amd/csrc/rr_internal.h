@@ -1,0 +1,123 @@
+// Internal declarations shared by the host code and the kernel launchers of
+// libradray.  Not part of the public ABI (see include/radray.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/radray.h"
+
+#define RR_TRACE_BLOCK 128
+#define RR_STACK 32          // BVH depth bound (the builder guarantees depth <= 31)
+#define RR_LEAF_MAX 8        // triangles per leaf (3-bit count in the child reference)
+
+// ---------------------------------------------------------------------------
+// device-side structure-of-arrays path list (planes of `cap` elements)
+// ---------------------------------------------------------------------------
+struct PathSoA {
+    int32_t *src = nullptr;
+    int32_t *K = nullptr;
+    int64_t *ray = nullptr;
+    int32_t *loc = nullptr;   // index of the path among its ray's paths (temp list only)
+    int32_t *tri = nullptr;   // [RR_KMAX][cap]
+    int32_t *vid = nullptr;   // [RR_KMAX][cap]
+    double *p = nullptr;      // [RR_KMAX*3][cap]
+    double *L = nullptr;
+    double *amp = nullptr;
+    int64_t cap = 0;
+};
+
+// ---------------------------------------------------------------------------
+// BVH on the device.  Node (64 B): child boxes and child references
+//   n[0] = (lo0.x, lo0.y, lo0.z, hi0.x)   n[1] = (hi0.y, hi0.z, lo1.x, lo1.y)
+//   n[2] = (lo1.z, hi1.x, hi1.y, hi1.z)   n[3] = (ref0, ref1, 0, 0) as int bits
+// Reference r >= 0: internal node r.  r < 0: leaf, x = ~r, first triangle
+// x >> 3 of the leaf-ordered triangle array, count (x & 7) + 1.
+// Leaf triangle (48 B): (v0.xyz, v1.x) (v1.yz, v2.xy) (v2.z, id, obj, 0)
+// with id/obj stored as int bits.
+// ---------------------------------------------------------------------------
+struct HostBvh {
+    std::vector<float> nodes;    // 16 floats per node
+    std::vector<float> tris;     // 12 floats per triangle
+    int depth = 0;
+};
+
+int rr_build_bvh(const float *verts, int64_t nv, const int32_t *tris, const int32_t *tri_obj,
+                 int64_t nt, HostBvh &out, std::string &err);
+
+// ---------------------------------------------------------------------------
+// trace kernel arguments (by value)
+// ---------------------------------------------------------------------------
+struct TraceArgs {
+    const float4 *nodes;
+    const float4 *ltris;
+    int has_bvh;
+    const float *obj_alpha;
+    const double *tx;         // [ntx][3]
+    const double *pt_pos;     // [npts][3]
+    const double *pt_ap;      // [npts]
+    double oT[3], oR[3];
+    double r2;
+    int shared;
+    int nobj, npts;
+    int64_t n_src, n_per_src, n_virt_per_src;
+    double at, bt, slo, shi, omega;
+    int bmax;
+    uint64_t seed;
+    int sampler;
+    const double *cdf;
+    int n_az, n_el;
+    // outputs
+    int32_t *hits;            // [n_src*n_per_src][bmax+1] or null
+    uint8_t *counts;          // [n_src*n_virt_per_src]
+    PathSoA tmp;
+    unsigned long long *counter;
+    int *err_flag;
+};
+
+// ---------------------------------------------------------------------------
+// synthesis path record (AoS, prepared from the path list)
+// ---------------------------------------------------------------------------
+struct SynPath {
+    double P[RR_KMAX][3];     // hit points at t = 0
+    double V[RR_KMAX][3];     // their velocities
+    double amp;
+    int32_t K;
+    int32_t src;
+};
+
+struct SynthArgs {
+    const SynPath *paths;
+    const int64_t *ranges;    // [n_groups + 1] path range of each group
+    int64_t n_paths;
+    const double *tx, *rx;    // device [n][3]
+    int ntx, nrx;
+    double oT[3], oR[3];
+    int shared;
+    int model;
+    double f0, bw, t_rep, inv_c;
+    int M, K;
+    float2 *cube;
+};
+
+// launchers (defined in the .hip files)
+hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s);
+hipError_t launch_points(const TraceArgs &a, hipStream_t s);
+hipError_t launch_scan_u8(const uint8_t *counts, int64_t n, uint32_t *offsets, uint32_t *bsums,
+                          int64_t nb_cap, unsigned long long *total, hipStream_t s);
+int64_t scan_u8_blocks(int64_t n);
+hipError_t launch_scatter(const PathSoA &tmp, const unsigned long long *counter, int64_t tmp_cap,
+                          const uint32_t *offsets, const PathSoA &dst, int64_t keep,
+                          hipStream_t s);
+
+hipError_t launch_syn_prep(const PathSoA &paths, int64_t n, const double *obj_vel, int nobj,
+                           const double *pt_vel, int npts, SynPath *out, hipStream_t s);
+hipError_t launch_ranges(const int32_t *src, int64_t n, int n_groups, int64_t *ranges,
+                         hipStream_t s);
+hipError_t launch_synth_direct(const SynthArgs &a, int n_groups, int rows_per_group,
+                               hipStream_t s);
+hipError_t launch_synth_sampled(const SynthArgs &a, const int64_t *idx, int64_t n_idx,
+                                hipStream_t s);

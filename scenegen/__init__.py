@@ -402,7 +402,7 @@ def workload_street(seed: int = 0, n_rays: int = 10_000_000) -> Workload:
                     TraceParams(n_rays=n_rays, max_bounces=3, seed=seed))
 
 
-LARGE_MIMO_RAYS = 60_000_000
+LARGE_MIMO_RAYS = 4_000_000
 LARGE_MIMO_PATHS = 100_000
 
 

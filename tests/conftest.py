@@ -18,3 +18,12 @@ def orc():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """A library context on cuda:0 (GPU tests only)."""
+    import paper_2307_15412_amd as pkg
+    ctx = pkg.Context(0)
+    yield ctx
+    ctx.close()
