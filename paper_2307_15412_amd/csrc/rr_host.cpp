@@ -144,6 +144,7 @@ struct rr_ctx {
 
     // synthesis scratch
     DevBuf syn, ranges;
+    DevBuf gT, gR, gA, gB;     // GEMM operands
 };
 
 extern "C" {
@@ -191,7 +192,8 @@ void rr_destroy(rr_ctx *c)
     DevBuf *bufs[] = {&c->nodes, &c->ltris, &c->obj_alpha, &c->obj_vel, &c->pt_pos, &c->pt_vel,
                       &c->pt_ap, &c->tx, &c->rx, &c->counts, &c->offsets, &c->bsums,
                       &c->counter, &c->total, &c->err_flag, &c->hits, &c->cdf, &c->syn,
-                      &c->ranges, &c->tmp.buf, &c->paths.buf};
+                      &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
+                      &c->gB};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -523,8 +525,30 @@ int rr_set_paths(rr_ctx *c, const rr_paths *s, int64_t n)
     return RR_OK;
 }
 
-// forward declaration (k_gemm.hip)
-int rr_synth_gemm(rr_ctx *c, void *cube, const SynPath *paths, int64_t n_paths);
+// separable model on the matrix cores: operand preparation, then the GEMM
+// (the context's events bracket the GEMM kernel alone)
+static int rr_synth_gemm(rr_ctx *c, const SynthArgs &A)
+{
+    const int C = c->ntx * c->nrx;
+    const int Cpad = (C + gemm_row_pad() - 1) / gemm_row_pad() * gemm_row_pad();
+    const int64_t n = A.n_paths;
+    const int ks = gemm_k_step();
+    const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
+    if (Ppad > (int64_t)1 << 30) return fail(RR_EUNSUPPORTED, "too many paths for the GEMM engine");
+    int rc;
+    if ((rc = c->gT.ensure((size_t)c->ntx * Ppad * 8))) return rc;
+    if ((rc = c->gR.ensure((size_t)c->nrx * Ppad * 8))) return rc;
+    if ((rc = c->gA.ensure((size_t)Cpad * Ppad * 8))) return rc;
+    if ((rc = c->gB.ensure((size_t)A.M * Ppad * 16))) return rc;
+    HIPCHK(launch_gemm_prep_tr(A, (int)Ppad, c->gT.as<float2>(), c->gR.as<float2>(), c->stream));
+    HIPCHK(launch_gemm_prep_a(c->gT.as<const float2>(), c->gR.as<const float2>(), c->nrx, C, Cpad,
+                              (int)Ppad, c->gA.as<uint4>(), c->stream));
+    HIPCHK(launch_gemm_prep_b(A, (int)Ppad, c->gB.as<uint4>(), c->stream));
+    HIPCHK(hipEventRecord(c->ev[2], c->stream));
+    HIPCHK(launch_gemm_main(c->gA.as<const uint4>(), c->gB.as<const uint4>(), Cpad, (int)Ppad, C,
+                            A.M, A.K, A.cube, c->stream));
+    return RR_OK;
+}
 
 int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t cube_elems,
                   const int64_t *idx, int64_t n_idx)
@@ -533,13 +557,19 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
     if (!c->has_array || !c->has_chirp) return fail(RR_ESTATE, "array and chirp must be set");
     if (c->n_paths < 0) return fail(RR_ESTATE, "no paths (trace or rr_set_paths first)");
     if (model != RR_EXACT && model != RR_SEPARABLE) return fail(RR_EINVAL, "unknown model");
-    if (engine == RR_ENGINE_AUTO) engine = (model == RR_SEPARABLE && !idx) ? RR_GEMM_BF16X3 : RR_DIRECT_FP32;
+    if (engine == RR_ENGINE_AUTO)
+        engine = (model == RR_SEPARABLE && !idx && c->chirp.n_samples % gemm_col_tile() == 0)
+                     ? RR_GEMM_BF16X3
+                     : RR_DIRECT_FP32;
     if (engine != RR_DIRECT_FP32 && engine != RR_GEMM_BF16X3)
         return fail(RR_EINVAL, "unknown engine");
     if (engine == RR_GEMM_BF16X3 && model != RR_SEPARABLE)
         return fail(RR_EUNSUPPORTED, "the GEMM engine needs the separable model");
     if (engine == RR_GEMM_BF16X3 && idx)
         return fail(RR_EUNSUPPORTED, "sampled entries use the direct engine");
+    if (engine == RR_GEMM_BF16X3 && c->chirp.n_samples % gemm_col_tile() != 0)
+        return fail(RR_EUNSUPPORTED, "the GEMM engine needs n_samples divisible by %d",
+                    gemm_col_tile());
     const int64_t C = (int64_t)c->ntx * c->nrx, M = c->chirp.n_chirps, K = c->chirp.n_samples;
     const int64_t total = C * M * K;
     if (idx) {
@@ -598,13 +628,14 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
     A.M = (int)M;
     A.K = (int)K;
     A.cube = static_cast<float2 *>(cube);
-    HIPCHK(hipEventRecord(c->ev[2], c->stream));
-    if (idx) {
-        HIPCHK(launch_synth_sampled(A, idx, n_idx, c->stream));
-    } else if (engine == RR_GEMM_BF16X3) {
-        rc = rr_synth_gemm(c, cube, sp, n);
+    if (engine == RR_GEMM_BF16X3) {
+        rc = rr_synth_gemm(c, A);
         if (rc) return rc;
+    } else if (idx) {
+        HIPCHK(hipEventRecord(c->ev[2], c->stream));
+        HIPCHK(launch_synth_sampled(A, idx, n_idx, c->stream));
     } else {
+        HIPCHK(hipEventRecord(c->ev[2], c->stream));
         int rows = (int)(shared ? C * M : (int64_t)c->nrx * M);
         hipError_t e = launch_synth_direct(A, n_groups, rows, c->stream);
         if (e == hipErrorInvalidValue) return fail(RR_EUNSUPPORTED, "n_samples too large");
@@ -631,9 +662,3 @@ int rr_last_kernel_ms(rr_ctx *c, int32_t which, double *ms)
 }
 
 }  // extern "C"
-
-int rr_synth_gemm(rr_ctx *c, void *cube, const SynPath *paths, int64_t n_paths)
-{
-    (void)c; (void)cube; (void)paths; (void)n_paths;
-    return fail(RR_EUNSUPPORTED, "GEMM engine not built");
-}

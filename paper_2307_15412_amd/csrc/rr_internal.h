@@ -121,3 +121,14 @@ hipError_t launch_synth_direct(const SynthArgs &a, int n_groups, int rows_per_gr
                                hipStream_t s);
 hipError_t launch_synth_sampled(const SynthArgs &a, const int64_t *idx, int64_t n_idx,
                                 hipStream_t s);
+
+// split-bf16 complex GEMM engine (k_gemm.hip)
+int gemm_row_pad();
+int gemm_col_tile();
+int gemm_k_step();
+hipError_t launch_gemm_prep_tr(const SynthArgs &a, int Ppad, float2 *T, float2 *R, hipStream_t s);
+hipError_t launch_gemm_prep_a(const float2 *T, const float2 *R, int nrx, int C, int Cpad, int Ppad,
+                              uint4 *Af, hipStream_t s);
+hipError_t launch_gemm_prep_b(const SynthArgs &a, int Ppad, uint4 *Bp, hipStream_t s);
+hipError_t launch_gemm_main(const uint4 *Af, const uint4 *Bp, int Cpad, int Ppad, int C, int M,
+                            int K, float2 *cube, hipStream_t s);

@@ -1,0 +1,122 @@
+"""Split-bf16 complex-GEMM synthesis (separable model) against the FP64
+oracle: relative error <= 1e-3 on the full cube or on seeded sampled
+entries; edge cases of the tiling (channel counts below one tile, path
+counts not divisible by the 16-path step, empty path list)."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from helpers import oracle_to_soa, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_GEMM = 1e-3
+
+
+def _upload(gpu, op):
+    soa = oracle_to_soa(op)
+    gpu.set_paths({k: torch.from_numpy(np.ascontiguousarray(v)) for k, v in soa.items()})
+
+
+def test_tiny_full_cube(gpu, orc):
+    """4 channels (one padded row tile), K = 128, paths from the oracle."""
+    w = sg.workload_tiny()
+    w.chirp = sg.Chirp(n_samples=128, n_chirps=16)
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    gpu.setup(w)
+    _upload(gpu, op)
+    got = gpu.synthesize(model=1, engine=2).cpu().numpy()
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=1)
+    assert rel_err(got, ref) < TOL_GEMM
+    # the GPU's own traced paths give the same cube
+    gpu.trace_workload(w)
+    got2 = gpu.synthesize(model=1, engine=2).cpu().numpy()
+    assert rel_err(got2, ref) < TOL_GEMM
+
+
+def test_single_channel_equals_exact(gpu, orc):
+    """1 Tx x 1 Rx: the separable model is the exact one (Eq. 4 itself)."""
+    w = sg.workload_tiny()
+    w.array = sg.Array(w.array.tx[:1], w.array.rx[:1], 0.25, sg.MODE_PER_TX)
+    w.chirp = sg.Chirp(n_samples=256, n_chirps=8)
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    gpu.setup(w)
+    _upload(gpu, op)
+    got = gpu.synthesize(model=1, engine=2).cpu().numpy()
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=0)
+    assert rel_err(got, ref) < TOL_GEMM
+
+
+@pytest.mark.parametrize("n_keep", [1, 17, 1000])
+def test_ragged_path_counts(gpu, orc, n_keep):
+    w = sg.workload_tiny()
+    w.chirp = sg.Chirp(n_samples=128, n_chirps=4)
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    op = op[:n_keep]
+    gpu.setup(w)
+    _upload(gpu, op)
+    got = gpu.synthesize(model=1, engine=2).cpu().numpy()
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=1)
+    assert rel_err(got, ref) < TOL_GEMM
+
+
+def test_empty_and_unsupported(gpu, orc):
+    import paper_2307_15412_amd as rr
+    w = sg.workload_tiny()
+    w.chirp = sg.Chirp(n_samples=128, n_chirps=2)
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    gpu.setup(w)
+    _upload(gpu, op[:0])
+    cube = gpu.synthesize(model=1, engine=2)
+    assert torch.count_nonzero(cube).item() == 0
+    gpu.set_chirp(77e9, 1e9, 50e-6, 50e-6, 64, 2)
+    _upload(gpu, op)
+    with pytest.raises(rr.RadrayError) as e:
+        gpu.synthesize(model=1, engine=2)
+    assert e.value.code == rr.binding.RR_EUNSUPPORTED
+    with pytest.raises(rr.RadrayError):
+        gpu.synthesize(model=0, engine=2)
+    # auto picks the direct engine where the GEMM cannot run
+    auto = gpu.synthesize(model=1, engine=0).cpu().numpy()
+    ch = sg.Chirp(n_samples=64, n_chirps=2)
+    assert rel_err(auto, orc.synth(op, w.scene, w.array, ch, model=1)) < 1e-4
+
+
+def test_street_per_tx_sampled(gpu, orc):
+    """12 Tx x 16 Rx per-element launch (paths feed only their own Tx rows)."""
+    w = sg.workload_street(0, n_rays=120_000)
+    _, op = orc.trace(w.scene, w.array, w.trace, want_hits=False)
+    gpu.setup(w)
+    _upload(gpu, op)
+    cube = gpu.synthesize(model=1, engine=2).cpu().numpy().reshape(-1)
+    idx = np.random.default_rng(5).choice(cube.size, 4096, replace=False)
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=1, idx=idx)
+    assert rel_err(cube[idx], ref) < TOL_GEMM
+
+
+def test_large_mimo_full_size_sampled(gpu, orc):
+    """The benchmarked configuration: street, 48 Tx x 64 Rx shared launch,
+    4e6 rays, first 1e5 paths, 3072 x 256 x 512 cube from the GPU's own
+    trace; 1024 seeded entries against the oracle evaluated from the oracle's
+    own paths for the same rays (the first 1e5 in ray order)."""
+    w = sg.workload_large_mimo(0)
+    gpu.setup(w)
+    n = gpu.trace_workload(w, record_hits=False)
+    assert n == w.path_cap
+    cube = gpu.synthesize(model=1, engine=2)
+    idx = np.random.default_rng(9).choice(cube.numel(), 1024, replace=False)
+    got = cube.reshape(-1)[torch.from_numpy(idx).to(cube.device)].cpu().numpy()
+    del cube
+    # the oracle traces rays in order, in chunks, until it holds path_cap paths
+    chunks, have, start, step = [], 0, 0, 500_000
+    while have < w.path_cap and start < w.trace.n_rays:
+        vids = np.arange(start, min(start + step, w.trace.n_rays))
+        _, part = orc.trace(w.scene, w.array, w.trace, vids=vids, want_hits=False)
+        chunks.append(part)
+        have += len(part)
+        start += step
+    op = np.concatenate(chunks)[: w.path_cap]
+    assert len(op) == w.path_cap
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=1, idx=idx)
+    assert rel_err(got, ref) < TOL_GEMM
