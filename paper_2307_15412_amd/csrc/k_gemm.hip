@@ -30,6 +30,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #define GM_TN 128          // output columns (chirp, sample) per workgroup
 #define GM_KS 16           // paths per MFMA step
 #define GM_THREADS 512     // 8 wavefronts: 4 (rows) x 2 (columns), 64 x 64 each
+#define BFRAG_U4 72        // one B fragment in LDS: 64 lanes + 8 padding (uint4 units)
 
 __device__ __forceinline__ double dist3(const double *a, const double *b)
 {
@@ -137,7 +138,7 @@ __global__ void k_prep_a(const float2 *T, const float2 *R, int nrx, int C, int R
 }
 
 // Per (chirp m, path p): beta = frac(f0 D / c), gamma = frac(B D / (K c)) as
-// 32-bit fixed point, and exp(-j 2 pi 32 gamma) for the column rotation.
+// 32-bit fixed point, and exp(-j 2 pi 64 gamma) for the column rotation.
 __global__ void k_prep_b(SynthArgs A, int Ppad, uint4 *Bp)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -165,7 +166,7 @@ __global__ void k_prep_b(SynthArgs A, int Ppad, uint4 *Bp)
         const double two32 = 4294967296.0;
         out.x = (unsigned)(unsigned long long)llrint(beta * two32);
         out.y = (unsigned)(unsigned long long)llrint(gamma * two32);
-        float2 z = phasor64(32.0 * gamma);
+        float2 z = phasor64(64.0 * gamma);
         out.z = __float_as_uint(z.x);
         out.w = __float_as_uint(z.y);
     }
@@ -185,54 +186,104 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
                                                         int KB, int Ppad, int C, int M, int K,
                                                         int n_col_tiles, float2 *__restrict__ cube)
 {
-    // B tile, two buffers x 4 planes x 4 column blocks x 64 lanes x 8 bf16
-    __shared__ uint4 Bs[2][4][4][64];
+    // A tile: two buffers x 8 row blocks x 4 planes x 64 lanes (uint4 = 8 bf16).
+    // B tile: two buffers x 4 planes x 4 column blocks, each fragment 64 lanes
+    // x 16 B with 128 B of padding after lane 31, so that the generator's
+    // 32-bit writes of both lane halves land in distinct banks.
+    __shared__ uint4 As[2][GM_TM / 32][4][64];
+    __shared__ uint4 Bs[2 * 4 * 4 * BFRAG_U4];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
-    // consecutive workgroups share a column tile (its B generation differs,
-    // its A rows differ); the column tile changes slowest
-    const int ct = blockIdx.x / (RB / (GM_TM / 32));
-    const int rt = blockIdx.x - ct * (RB / (GM_TM / 32));
+    // XCD-aware order: workgroup b runs on XCD b % 8; each XCD walks its own
+    // contiguous run of (row tile, column tile) pairs, row tile slowest, so
+    // the workgroups resident on one XCD share A through that XCD's L2.
+    const int rtiles = RB / (GM_TM / 32);
+    const int64_t total = (int64_t)rtiles * n_col_tiles;
+    int64_t q = blockIdx.x;
+    if (total % 8 == 0) q = (int64_t)(blockIdx.x % 8) * (total / 8) + blockIdx.x / 8;
+    const int rt = (int)(q / n_col_tiles);
+    const int ct = (int)(q - (int64_t)rt * n_col_tiles);
     const int64_t N = (int64_t)M * K;
     const int rb0 = rt * (GM_TM / 32) + wr * 2;
 
-    // B generator: path row pl, base column nb; columns nb + 32 q, q = 0..3
-    const int pl = tid >> 5;
-    const int nb = tid & 31;
+    // B generator: path pair (2 pp, 2 pp + 1), columns nb and nb + 64 of the tile
+    const int pp = tid & 7;
+    const int nb = tid >> 3;
     const int64_t col0 = (int64_t)ct * GM_TN;
     const int m = (int)(col0 / K);
     const unsigned kbase = (unsigned)(col0 - (int64_t)m * K) + (unsigned)nb;
-    const int flane = (pl >> 3) * 32 + nb;
-    const int fslot = pl & 7;
-    unsigned short *bsh = reinterpret_cast<unsigned short *>(&Bs[0][0][0][0]);
+    const int p0 = 2 * pp;
+    const int flane = (p0 >> 3) * 32 + (nb & 31);
+    // 32-bit word index of (fragment 0, this lane, slots p0 & 7 and +1)
+    const int wofs = (flane * 16 + (flane >= 32 ? 128 : 0) + (p0 & 7) * 2) / 4;
+    unsigned *bsw = reinterpret_cast<unsigned *>(Bs);
+    const uint4 *bprow = Bp + (int64_t)m * Ppad + p0;
 
-    auto gen = [&](int kb, int buf) {
-        const uint4 prm = Bp[(int64_t)m * Ppad + (int64_t)kb * GM_KS + pl];
-        const unsigned ph = prm.x + kbase * prm.y;
-        const float u = (float)(int)ph * 2.3283064365386963e-10f;   // 2^-32, turns in [-1/2, 1/2)
-        float zr = __builtin_amdgcn_cosf(u);
-        float zi = -__builtin_amdgcn_sinf(u);
-        const float rr = __uint_as_float(prm.z), ri = __uint_as_float(prm.w);
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            if (q > 0) {
-                float nr = zr * rr - zi * ri;
-                float ni = zr * ri + zi * rr;
-                zr = nr;
-                zi = ni;
-            }
-            unsigned short rh = bf16_bits(zr), ih = bf16_bits(zi);
-            unsigned short rl = bf16_bits(zr - bf16_float(rh));
-            unsigned short il = bf16_bits(zi - bf16_float(ih));
-            const int base = (((buf * 4 + 0) * 4 + q) * 64 + flane) * 8 + fslot;
-            const int pstride = 4 * 64 * 8;
-            bsh[base] = rh;
-            bsh[base + pstride] = rl;
-            bsh[base + 2 * pstride] = ih;
-            bsh[base + 3 * pstride] = il;
+    auto gen = [&](uint4 pa, uint4 pb, int buf) {
+        // start phasors of both paths at column nb, then rotate by 64 columns
+        float ar, ai, br, bi;
+        {
+            const float u = (float)(int)(pa.x + kbase * pa.y) * 2.3283064365386963e-10f;
+            ar = __builtin_amdgcn_cosf(u);
+            ai = -__builtin_amdgcn_sinf(u);
         }
+        {
+            const float u = (float)(int)(pb.x + kbase * pb.y) * 2.3283064365386963e-10f;
+            br = __builtin_amdgcn_cosf(u);
+            bi = -__builtin_amdgcn_sinf(u);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            if (h == 1) {
+                const float rar = __uint_as_float(pa.z), rai = __uint_as_float(pa.w);
+                const float rbr = __uint_as_float(pb.z), rbi = __uint_as_float(pb.w);
+                float t0 = ar * rar - ai * rai, t1 = ar * rai + ai * rar;
+                ar = t0; ai = t1;
+                t0 = br * rbr - bi * rbi; t1 = br * rbi + bi * rbr;
+                br = t0; bi = t1;
+            }
+            const unsigned rh = bf16_bits(ar) | ((unsigned)bf16_bits(br) << 16);
+            const unsigned ih = bf16_bits(ai) | ((unsigned)bf16_bits(bi) << 16);
+            const unsigned rl = bf16_bits(ar - bf16_float((unsigned short)rh)) |
+                                ((unsigned)bf16_bits(br - bf16_float((unsigned short)(rh >> 16))) << 16);
+            const unsigned il = bf16_bits(ai - bf16_float((unsigned short)ih)) |
+                                ((unsigned)bf16_bits(bi - bf16_float((unsigned short)(ih >> 16))) << 16);
+            const int cb = (nb >> 5) + 2 * h;
+            // word offset of (buf, plane, column block cb)
+            const int f = ((buf * 4 + 0) * 4 + cb) * (BFRAG_U4 * 4);
+            const int ps = 4 * BFRAG_U4 * 4;
+            bsw[f + wofs] = rh;
+            bsw[f + ps + wofs] = rl;
+            bsw[f + 2 * ps + wofs] = ih;
+            bsw[f + 3 * ps + wofs] = il;
+        }
+    };
+    // A staging: the tile of one step is 8 row blocks x 4 planes x 64 lanes;
+    // thread tid moves entries tid + 512 r, r = 0..3 (1 KiB contiguous runs)
+    const uint4 *abase = Af + (int64_t)rt * (GM_TM / 32) * KB * 256;
+    // (staged values travel by value in a struct so that they stay in VGPRs)
+    struct Stage {
+        uint4 r0, r1, r2, r3;
+    };
+    const int rbl0 = tid >> 8, rest0 = tid & 255;
+    auto stage_load = [&](int kb) -> Stage {
+        Stage v;
+        const uint4 *src = abase + (int64_t)kb * 256 + rest0;
+        const int64_t rstride = (int64_t)KB * 256;
+        v.r0 = src[(int64_t)(rbl0 + 0) * rstride];
+        v.r1 = src[(int64_t)(rbl0 + 2) * rstride];
+        v.r2 = src[(int64_t)(rbl0 + 4) * rstride];
+        v.r3 = src[(int64_t)(rbl0 + 6) * rstride];
+        return v;
+    };
+    auto stage_store = [&](const Stage v, int buf) {
+        uint4 *dst = &As[buf][0][0][0] + tid;
+        dst[0] = v.r0;
+        dst[GM_THREADS] = v.r1;
+        dst[2 * GM_THREADS] = v.r2;
+        dst[3 * GM_THREADS] = v.r3;
     };
 
     f32x16 sr[2][2], si[2][2];
@@ -243,42 +294,82 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
 #pragma unroll
             for (int e = 0; e < 16; e++) { sr[i][j][e] = 0.0f; si[i][j][e] = 0.0f; }
 
-    gen(0, 0);
-    __syncthreads();
-    for (int kb = 0; kb < KB; kb++) {
-        const int buf = kb & 1;
-        uint4 a[2][4];
+    struct Frags {
+        uint4 a[2][4], b[2][4];
+    };
+    auto load_frags = [&](int buf) -> Frags {
+        Frags f;
 #pragma unroll
         for (int i = 0; i < 2; i++)
 #pragma unroll
-            for (int q = 0; q < 4; q++)
-                a[i][q] = Af[(((int64_t)(rb0 + i) * KB + kb) * 4 + q) * 64 + lane];
-        if (kb + 1 < KB) gen(kb + 1, buf ^ 1);
-        uint4 b[2][4];
+            for (int q = 0; q < 4; q++) f.a[i][q] = As[buf][wr * 2 + i][q][lane];
+        const int lofs = lane + (lane >= 32 ? 8 : 0);
 #pragma unroll
         for (int j = 0; j < 2; j++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) b[j][q] = Bs[buf][q][wc * 2 + j][lane];
+            for (int q = 0; q < 4; q++)
+                f.b[j][q] = Bs[((buf * 4 + q) * 4 + wc * 2 + j) * BFRAG_U4 + lofs];
+        return f;
+    };
+    auto mma = [&](const Frags &f) {
 #pragma unroll
         for (int i = 0; i < 2; i++) {
-            const uint4 nih = neg_bf(a[i][2]), nil = neg_bf(a[i][3]);
+            const uint4 nih = neg_bf(f.a[i][2]), nil = neg_bf(f.a[i][3]);
 #pragma unroll
             for (int j = 0; j < 2; j++) {
                 // re += Ar Br - Ai Bi ; im += Ar Bi + Ai Br  (hi*hi + hi*lo + lo*hi)
-                sr[i][j] = MFMA(a[i][0], b[j][0], sr[i][j]);
-                sr[i][j] = MFMA(a[i][0], b[j][1], sr[i][j]);
-                sr[i][j] = MFMA(a[i][1], b[j][0], sr[i][j]);
-                sr[i][j] = MFMA(nih, b[j][2], sr[i][j]);
-                sr[i][j] = MFMA(nih, b[j][3], sr[i][j]);
-                sr[i][j] = MFMA(nil, b[j][2], sr[i][j]);
-                si[i][j] = MFMA(a[i][0], b[j][2], si[i][j]);
-                si[i][j] = MFMA(a[i][0], b[j][3], si[i][j]);
-                si[i][j] = MFMA(a[i][1], b[j][2], si[i][j]);
-                si[i][j] = MFMA(a[i][2], b[j][0], si[i][j]);
-                si[i][j] = MFMA(a[i][2], b[j][1], si[i][j]);
-                si[i][j] = MFMA(a[i][3], b[j][0], si[i][j]);
+                sr[i][j] = MFMA(f.a[i][0], f.b[j][0], sr[i][j]);
+                si[i][j] = MFMA(f.a[i][0], f.b[j][2], si[i][j]);
+                sr[i][j] = MFMA(f.a[i][0], f.b[j][1], sr[i][j]);
+                si[i][j] = MFMA(f.a[i][0], f.b[j][3], si[i][j]);
+                sr[i][j] = MFMA(f.a[i][1], f.b[j][0], sr[i][j]);
+                si[i][j] = MFMA(f.a[i][1], f.b[j][2], si[i][j]);
+                sr[i][j] = MFMA(nih, f.b[j][2], sr[i][j]);
+                si[i][j] = MFMA(f.a[i][2], f.b[j][0], si[i][j]);
+                sr[i][j] = MFMA(nih, f.b[j][3], sr[i][j]);
+                si[i][j] = MFMA(f.a[i][2], f.b[j][1], si[i][j]);
+                sr[i][j] = MFMA(nil, f.b[j][2], sr[i][j]);
+                si[i][j] = MFMA(f.a[i][3], f.b[j][0], si[i][j]);
             }
         }
+    };
+
+    // Pipeline: the global loads of step kb + 2 are issued during step kb and
+    // only written to LDS at the start of step kb + 1, a full step later, so
+    // their latency hides behind one step of matrix-core work.  Indices are
+    // clamped instead of branched; the surplus work at the end fills the LDS
+    // buffer that is no longer read.
+    const int last = KB - 1;
+    Stage v = stage_load(0);
+    stage_store(v, 0);
+    gen(bprow[0], bprow[1], 0);
+    v = stage_load(min(1, last));
+    uint4 pna = bprow[(int64_t)min(1, last) * GM_KS];
+    uint4 pnb = bprow[(int64_t)min(1, last) * GM_KS + 1];
+    __syncthreads();
+    for (int kb = 0; kb < KB; kb++) {
+        const int buf = kb & 1;
+        stage_store(v, buf ^ 1);
+        const int nx = min(kb + 2, last);
+        const uint4 pca = pna, pcb = pnb;
+        v = stage_load(nx);
+        pna = bprow[(int64_t)nx * GM_KS];
+        pnb = bprow[(int64_t)nx * GM_KS + 1];
+        // keep the prefetch loads above the matrix-core work
+        __builtin_amdgcn_sched_barrier(0);
+        const Frags f = load_frags(buf);
+        gen(pca, pcb, buf ^ 1);
+        mma(f);
+        // interleave the generation of the next B tile (VALU, LDS writes)
+        // with this step's MFMAs so that the matrix cores stay busy
+        __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);   // fragment reads
+#pragma unroll
+        for (int g = 0; g < 8; g++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // 6 VALU
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // 1 LDS write
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 40, 0);
         __syncthreads();
     }
     // D layout: register e of lane l is row 8*(e/4) + 4*(l/32) + e%4, column l%32
