@@ -60,6 +60,27 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": src.numel() * 4, "repeats": 5}))
 
 
+def profiled_traffic(kernel_src: str, summary: str):
+    """HBM bytes per launch recorded in a committed rocprofv3 summary, if that
+    summary was taken on the current source of the kernel (else None)."""
+    import hashlib
+    try:
+        src = open(os.path.join(ROOT, kernel_src), "rb").read()
+        txt = open(os.path.join(ROOT, summary)).read()
+    except OSError:
+        return None
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    vals = {}
+    for line in txt.splitlines():
+        line = line.strip()
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -128,19 +149,22 @@ def main():
         kern_flops = path_samples * FLOPS_PER_PATH_SAMPLE
         ach = kern_flops / (sy * 1e-3) / 1e12
         if engine == rr.GEMM_BF16X3:
-            roof = {"bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s"}
+            roof = {"bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "traffic": profiled_traffic("paper_2307_15412_amd/csrc/k_gemm.hip",
+                                                "profiles/k_gemm_large_mimo.md")}
         else:
-            roof = {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
+            roof = {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "traffic": None}
         roof["kernel"] = "synth_" + eng_name
+        roof["flops_per_launch"] = kern_flops
     else:
         # tracer bytes per segment are counted by the profile; report the rate only
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "kernel": "trace"}
+                "kernel": "trace", "traffic": None}
     if roof["achieved"] is not None:
         roof["frac"] = roof["achieved"] / roof["peak"]
     else:
         roof["frac"] = None
-    roof["traffic"] = None
 
     rel = None
     cpu = None
