@@ -196,6 +196,61 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
 int rr_synthesize(rr_ctx *ctx, int32_t model, int32_t engine, void *cube_dev, int64_t cube_elems,
                   const int64_t *sample_idx_dev, int64_t n_sample);
 
+/* ------------------------------------------------------------------------
+ * Learned ray proposal (an importance-sampling density for the launch of
+ * Sec. III-A).  Directions are binned on a grid of RR_PROP_NAZ azimuth x
+ * RR_PROP_NEL sin(elevation) bins of equal solid angle over the field of
+ * view (bin b = ie * RR_PROP_NAZ + ia).  A ray drawn from bin b gets the
+ * weight 1 / (n_bins q_b), so the cube stays an unbiased estimate.
+ * ------------------------------------------------------------------------ */
+#define RR_PROP_NAZ 128
+#define RR_PROP_NEL 64
+#define RR_MLP_PARAMS 9601   /* 18 -> 64 -> 64 -> 64 -> 1, ReLU */
+
+/* Set the sampling table explicitly: cdf double [n_az * n_el + 1] (host),
+ * non-decreasing, cdf[0] = 0, last = 1.  Errors: RR_EINVAL. */
+int rr_proposal_set_cdf(rr_ctx *ctx, const double *cdf, int32_t n_az, int32_t n_el);
+
+/* Copy the current sampling table to host memory (cap entries available). */
+int rr_proposal_get_cdf(rr_ctx *ctx, double *cdf, int64_t cap);
+
+/* Scene code of the current scene: 16 azimuth sectors x 8 probe rays at
+ * elevation 0 from the Tx phase centre over [az_min, az_max]; code16_dev[k]
+ * = mean over the sector's rays of exp(-t / 10 m) for hits on objects other
+ * than object 0 (the ground), 0 otherwise.  code16_dev: float [16] (device). */
+int rr_proposal_probe(rr_ctx *ctx, double az_min, double az_max, float *code16_dev);
+
+/* Training target from the last trace, which must have used the uniform
+ * sampler with record_hits = 1: hist_dev float [RR_PROP_NAZ * RR_PROP_NEL]
+ * (device, overwritten), per bin the sum over its rays of the number of
+ * received paths + 0.1 if the first segment hit an object other than 0. */
+int rr_proposal_histogram(rr_ctx *ctx, float *hist_dev);
+
+/* Network parameters (FP32 master copy on the device; the kernels round
+ * weights and activations to FP16 and accumulate in FP32).  Layout: W1[64][18],
+ * b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[1][64], b4[1].
+ * rr_mlp_init: He-uniform weights from `seed`, zero biases, Adam state reset. */
+int rr_mlp_init(rr_ctx *ctx, uint64_t seed);
+int rr_mlp_set_params(rr_ctx *ctx, const float *params, int64_t n);   /* host, resets Adam */
+int rr_mlp_get_params(rr_ctx *ctx, float *params, int64_t n);         /* host */
+
+/* Logits for every bin of n_scenes scenes: codes_dev float [n_scenes][16],
+ * logits_dev float [n_scenes][RR_PROP_NAZ * RR_PROP_NEL] (device). */
+int rr_mlp_forward(rr_ctx *ctx, const float *codes_dev, int32_t n_scenes, float *logits_dev);
+
+/* One training step on n_scenes scenes: loss = mean over scenes of
+ * -sum_b H_b log softmax(z)_b / sum_b H_b; backward pass and an Adam update
+ * with learning rate lr (lr = 0: gradient only).  loss_out (host, may be
+ * NULL) synchronises; grad_dev (may be NULL) receives the gradient, float
+ * [RR_MLP_PARAMS]. */
+int rr_mlp_train_step(rr_ctx *ctx, const float *codes_dev, const float *hist_dev, int32_t n_scenes,
+                      float lr, float *loss_out, float *grad_dev);
+
+/* Build the sampling table of one scene from the network: q = (1 - beta)
+ * softmax(z) + beta / n_bins, CDF in FP64.  code16_dev: that scene's code
+ * (device).  Afterwards rr_trace with sampler RR_PROPOSAL draws from it. */
+int rr_proposal_build(rr_ctx *ctx, const float *code16_dev, float beta);
+
 /* Kernel timing of the last rr_trace / rr_synthesize call, in milliseconds,
  * measured with HIP events on the context stream (synchronises).
  * which: 0 = trace (all trace kernels), 1 = synthesis main kernel. */

@@ -265,3 +265,48 @@ def to_soa(p, kmax: int = 4) -> dict:
                 vid=np.ascontiguousarray(p["vid"][:, :kmax].T.astype(np.int32)),
                 p=np.ascontiguousarray(p["p"][:, :kmax, :].reshape(n, 3 * kmax).T),
                 L=p["L"].astype(np.float64), amp=p["amp"].astype(np.float64))
+
+
+def probe_code(scene, array, tp, use_bvh=None) -> np.ndarray:
+    """16-value scene code of the learned proposal (see orc_probe)."""
+    if use_bvh is None:
+        use_bvh = scene.n_tris > 1000
+    keep = _Keep()
+    L = lib()
+    L.orc_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    out = np.zeros(16)
+    rc = L.orc_probe(C.addressof(_scene(scene, keep)), C.addressof(_array(array, keep)),
+                     C.addressof(_trace(tp, keep)), int(use_bvh), out.ctypes.data)
+    L.orc_release()
+    if rc != 0:
+        raise RuntimeError(f"orc_probe failed: {rc}")
+    return out
+
+
+def uniform_bins(scene, array, tp, n_az=128, n_el=64) -> np.ndarray:
+    L = lib()
+    L.orc_uniform_bins.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                   C.c_void_p]
+    per, ns = n_per_src(scene, array, tp), n_src(array)
+    bins = np.zeros(per * ns, dtype=np.int32)
+    L.orc_uniform_bins(int(tp.seed) & (2**64 - 1), per, ns, n_az, n_el, bins.ctypes.data)
+    return bins
+
+
+def histogram(scene, array, tp, hits, paths, n_az=128, n_el=64) -> np.ndarray:
+    """Training target of the proposal from a uniform trace: per direction bin,
+    the sum over its rays of (returned power P_i = sum of w^2 over the ray's
+    paths) + 0.1 * (first segment hit an object other than 0)."""
+    per, ns = n_per_src(scene, array, tp), n_src(array)
+    vps = per + scene.n_pts
+    bins = uniform_bins(scene, array, tp, n_az, n_el)
+    H = np.zeros(n_az * n_el)
+    traced = paths[paths["tri"][:, 0] >= 0]
+    v = traced["ray"]
+    g = (v // vps) * per + (v % vps)
+    w = traced["amp"] * per
+    np.add.at(H, bins[g], w * w)
+    first = hits[:, 0]
+    hit = (first >= 0) & (scene.tri_obj[np.maximum(first, 0)] != 0)
+    np.add.at(H, bins, 0.1 * hit)
+    return H

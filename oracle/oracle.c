@@ -710,3 +710,50 @@ int orc_synth(const orc_path *paths, int64_t np, const orc_scene *sc, const orc_
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* learned-proposal inputs                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Scene code: 16 azimuth sectors x 8 probe rays at elevation 0 from the Tx
+ * phase centre, sector s ray i at azimuth fraction (8 s + i + 1/2) / 128 of
+ * the field of view.  code[s] = mean over its rays of exp(-t / 10 m) when the
+ * closest hit belongs to an object other than object 0 (the ground), else 0. */
+int orc_probe(const orc_scene *sc, const orc_array *ar, const orc_trace_params *tp, int use_bvh,
+              double code[16])
+{
+    trace_setup s;
+    setup(sc, ar, tp, &s);
+    if (use_bvh && g_bvh_scene != sc && bvh_build(sc) != 0) return -2;
+    g_use_bvh = use_bvh;
+    for (int k = 0; k < 16; k++) {
+        double acc = 0.0;
+        for (int i = 0; i < 8; i++) {
+            double fa = ((double)(8 * k + i) + 0.5) / 128.0;
+            double turn = s.at + fa * (s.bt - s.at);
+            double sa, ca;
+            orc_sincos_turn(turn, &sa, &ca);
+            double th;
+            int64_t h = closest(sc, s.oT, mk(ca, sa, 0.0), -1, &th);
+            if (h >= 0 && sc->tri_obj[h] != 0) acc += exp(-th / 10.0);
+        }
+        code[k] = acc / 8.0;
+    }
+    return 0;
+}
+
+/* Bin (ie * n_az + ia) of the uniform launch of every traced ray, in hit-list
+ * order (source-major): ia = floor(u0 n_az), ie = floor(u1 n_el). */
+void orc_uniform_bins(uint64_t seed, int64_t n_per_src, int64_t n_src, int32_t n_az, int32_t n_el,
+                      int32_t *bins)
+{
+    for (int64_t t = 0; t < n_src; t++)
+        for (int64_t i = 0; i < n_per_src; i++) {
+            double u[4];
+            draw(seed, (uint64_t)i, (uint64_t)t, 0, u);
+            int32_t ia = (int32_t)(u[0] * n_az), ie = (int32_t)(u[1] * n_el);
+            if (ia >= n_az) ia = n_az - 1;
+            if (ie >= n_el) ie = n_el - 1;
+            bins[t * n_per_src + i] = ie * n_az + ia;
+        }
+}

@@ -263,3 +263,99 @@ class Context:
                     record_hits=record_hits, path_cap=getattr(workload, "path_cap", None) or 0)
         args.update(kw)
         return self.trace(**args)
+
+
+# --------------------------------------------------------------------------
+# learned proposal
+# --------------------------------------------------------------------------
+PROP_NAZ, PROP_NEL, MLP_PARAMS = 128, 64, 9601
+_PROP_DECLARED = False
+
+
+def _declare_proposal(L):
+    global _PROP_DECLARED
+    if _PROP_DECLARED:
+        return
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.rr_proposal_set_cdf.argtypes = [vp, vp, i32, i32]
+    L.rr_proposal_get_cdf.argtypes = [vp, vp, i64]
+    L.rr_proposal_probe.argtypes = [vp, C.c_double, C.c_double, vp]
+    L.rr_proposal_histogram.argtypes = [vp, vp]
+    L.rr_mlp_init.argtypes = [vp, C.c_uint64]
+    L.rr_mlp_set_params.argtypes = [vp, vp, i64]
+    L.rr_mlp_get_params.argtypes = [vp, vp, i64]
+    L.rr_mlp_forward.argtypes = [vp, vp, i32, vp]
+    L.rr_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp]
+    L.rr_proposal_build.argtypes = [vp, vp, C.c_float]
+    _PROP_DECLARED = True
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class _ProposalMixin:
+    def _pl(self):
+        _declare_proposal(self.lib)
+        return self.lib
+
+    def proposal_set_cdf(self, cdf, n_az=PROP_NAZ, n_el=PROP_NEL):
+        c = np.ascontiguousarray(cdf, dtype=np.float64)
+        self._check(self._pl().rr_proposal_set_cdf(self.h, c.ctypes.data, int(n_az), int(n_el)))
+
+    def proposal_get_cdf(self):
+        out = np.zeros(PROP_NAZ * PROP_NEL + 1)
+        self._check(self._pl().rr_proposal_get_cdf(self.h, out.ctypes.data, out.size))
+        return out
+
+    def proposal_probe(self, az_min=-math.pi / 2, az_max=math.pi / 2):
+        out = self.torch.empty(16, dtype=self.torch.float32, device=self.device)
+        self._check(self._pl().rr_proposal_probe(self.h, az_min, az_max, _ptr(out)))
+        return out
+
+    def proposal_histogram(self):
+        out = self.torch.empty(PROP_NAZ * PROP_NEL, dtype=self.torch.float32, device=self.device)
+        self._check(self._pl().rr_proposal_histogram(self.h, _ptr(out)))
+        return out
+
+    def mlp_init(self, seed=0):
+        self._check(self._pl().rr_mlp_init(self.h, int(seed) & (2**64 - 1)))
+
+    def mlp_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self._pl().rr_mlp_set_params(self.h, p.ctypes.data, p.size))
+
+    def mlp_get_params(self):
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._check(self._pl().rr_mlp_get_params(self.h, p.ctypes.data, p.size))
+        return p
+
+    def mlp_forward(self, codes):
+        codes = codes.to(self.device, self.torch.float32).contiguous().reshape(-1, 16)
+        out = self.torch.empty((codes.shape[0], PROP_NAZ * PROP_NEL), dtype=self.torch.float32,
+                               device=self.device)
+        self._check(self._pl().rr_mlp_forward(self.h, _ptr(codes), codes.shape[0], _ptr(out)))
+        return out
+
+    def mlp_train_step(self, codes, hists, lr, want_grad=False):
+        codes = codes.to(self.device, self.torch.float32).contiguous().reshape(-1, 16)
+        hists = hists.to(self.device, self.torch.float32).contiguous().reshape(-1, PROP_NAZ * PROP_NEL)
+        grad = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.device) if want_grad else None
+        loss = C.c_float()
+        self._check(self._pl().rr_mlp_train_step(self.h, _ptr(codes), _ptr(hists), codes.shape[0],
+                                                 float(lr), C.byref(loss),
+                                                 _ptr(grad) if grad is not None else None))
+        return (loss.value, grad) if want_grad else loss.value
+
+    def proposal_build(self, code, beta=0.1):
+        code = code.to(self.device, self.torch.float32).contiguous().reshape(16)
+        self._check(self._pl().rr_proposal_build(self.h, _ptr(code), float(beta)))
+        self._keep_code = code
+
+
+for _name, _fn in list(vars(_ProposalMixin).items()):
+    if callable(_fn) and not _name.startswith("__"):
+        setattr(Context, _name, _fn)
+EXPORTED += ["rr_proposal_set_cdf", "rr_proposal_get_cdf", "rr_proposal_probe",
+             "rr_proposal_histogram", "rr_mlp_init", "rr_mlp_set_params", "rr_mlp_get_params",
+             "rr_mlp_forward", "rr_mlp_train_step", "rr_proposal_build"]

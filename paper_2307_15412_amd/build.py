@@ -29,6 +29,7 @@ SOURCES = {
     "k_trace.hip": ["-ffp-contract=off"],
     "k_synth.hip": [],
     "k_gemm.hip": [],
+    "k_mlp.hip": [],
 }
 
 

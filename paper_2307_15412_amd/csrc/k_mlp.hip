@@ -1,0 +1,381 @@
+// k_mlp.hip -- the learned ray proposal: scene probe, training histogram,
+// a 4-layer MLP (18 -> 64 -> 64 -> 64 -> 1, ReLU) with forward, backward and
+// Adam kernels, and the sampling table (softmax mixed with the uniform density,
+// then its CDF) that the tracer's importance sampler reads.
+//
+// Weights and activations are stored in FP16; every product is formed and
+// accumulated in FP32 (an FP16 x FP16 product is exact in FP32).  The network
+// is small (9 601 parameters, ~1.6e6 rows per epoch of 200 scenes) so each lane
+// evaluates one row with the weights broadcast from LDS.
+#include <hip/hip_fp16.h>
+
+#include "rr_internal.h"
+
+namespace {
+
+#define NAZ 128
+#define NEL 64
+#define NBINS (NAZ * NEL)
+#define NIN 18
+#define NH 64
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + NH * NIN)
+#define OFF_W2 (OFF_B1 + NH)
+#define OFF_B2 (OFF_W2 + NH * NH)
+#define OFF_W3 (OFF_B2 + NH)
+#define OFF_B3 (OFF_W3 + NH * NH)
+#define OFF_W4 (OFF_B3 + NH)
+#define OFF_B4 (OFF_W4 + NH)
+#define NPARAMS (OFF_B4 + 1)
+
+static_assert(NPARAMS == RR_MLP_PARAMS, "parameter count");
+
+__device__ __forceinline__ float h16(float x) { return __half2float(__float2half(x)); }
+
+// load the parameters into LDS rounded to FP16
+__device__ __forceinline__ void load_params(const float *P, float *W)
+{
+    for (int i = threadIdx.x; i < NPARAMS; i += blockDim.x) W[i] = h16(P[i]);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void row_input(const float *codes, int64_t r, float x[NIN])
+{
+    const int64_t s = r / NBINS;
+    const int b = (int)(r - s * NBINS);
+    const int ia = b % NAZ, ie = b / NAZ;
+    x[0] = h16(2.0f * ((float)ia + 0.5f) / (float)NAZ - 1.0f);
+    x[1] = h16(2.0f * ((float)ie + 0.5f) / (float)NEL - 1.0f);
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[2 + k] = h16(codes[s * 16 + k]);
+}
+
+// forward: logits z[r]; activations h1..h3 kept in FP16 for the backward pass
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float *P, const float *codes, int64_t n,
+                                                 __half *acts, float *z)
+{
+    __shared__ float W[NPARAMS];
+    load_params(P, W);
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    float x[NIN];
+    row_input(codes, r, x);
+    float h[NH], g[NH];
+#pragma unroll
+    for (int j = 0; j < NH; j++) {
+        float a = W[OFF_B1 + j];
+#pragma unroll
+        for (int i = 0; i < NIN; i++) a = fmaf(W[OFF_W1 + j * NIN + i], x[i], a);
+        h[j] = h16(fmaxf(a, 0.0f));
+    }
+    if (acts) {
+#pragma unroll
+        for (int j = 0; j < NH; j++) acts[(0 * n + r) * NH + j] = __float2half(h[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NH; j++) {
+        float a = W[OFF_B2 + j];
+#pragma unroll
+        for (int i = 0; i < NH; i++) a = fmaf(W[OFF_W2 + j * NH + i], h[i], a);
+        g[j] = h16(fmaxf(a, 0.0f));
+    }
+    if (acts) {
+#pragma unroll
+        for (int j = 0; j < NH; j++) acts[(1 * n + r) * NH + j] = __float2half(g[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NH; j++) {
+        float a = W[OFF_B3 + j];
+#pragma unroll
+        for (int i = 0; i < NH; i++) a = fmaf(W[OFF_W3 + j * NH + i], g[i], a);
+        h[j] = h16(fmaxf(a, 0.0f));
+    }
+    if (acts) {
+#pragma unroll
+        for (int j = 0; j < NH; j++) acts[(2 * n + r) * NH + j] = __float2half(h[j]);
+    }
+    float a = W[OFF_B4];
+#pragma unroll
+    for (int i = 0; i < NH; i++) a = fmaf(W[OFF_W4 + i], h[i], a);
+    z[r] = a;
+}
+
+// per scene: softmax of the logits; loss -sum H log q / sum H and its
+// gradient dz = (q - H / sum H) / n_scenes (zero for a scene with no target)
+__global__ __launch_bounds__(1024) void k_softmax_grad(const float *z, const float *H, int n_scenes,
+                                                       float *dz, float *loss)
+{
+    __shared__ float red[1024];
+    const int s = blockIdx.x;
+    const float *zs = z + (int64_t)s * NBINS;
+    const float *hs = H + (int64_t)s * NBINS;
+    float mx = -3.0e38f, hsum = 0.0f;
+    for (int b = threadIdx.x; b < NBINS; b += 1024) {
+        mx = fmaxf(mx, zs[b]);
+        hsum += hs[b];
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    mx = red[0];
+    __syncthreads();
+    float es = 0.0f;
+    for (int b = threadIdx.x; b < NBINS; b += 1024) es += __expf(zs[b] - mx);
+    red[threadIdx.x] = es;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const float lse = logf(red[0]);
+    __syncthreads();
+    red[threadIdx.x] = hsum;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const float Hs = red[0];
+    __syncthreads();
+    float l = 0.0f;
+    for (int b = threadIdx.x; b < NBINS; b += 1024) {
+        const float logq = zs[b] - mx - lse;
+        float d = 0.0f;
+        if (Hs > 0.0f) {
+            l -= hs[b] * logq;
+            d = (__expf(logq) - hs[b] / Hs) / (float)n_scenes;
+        }
+        dz[(int64_t)s * NBINS + b] = d;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[s] = Hs > 0.0f ? red[0] / Hs / (float)n_scenes : 0.0f;
+}
+
+// backward through the layers for each row: d3, d2, d1 (pre-activation grads)
+__global__ __launch_bounds__(256) void k_mlp_bwd(const float *P, const float *dz, int64_t n,
+                                                 const __half *acts, float *d1, float *d2, float *d3)
+{
+    __shared__ float W[NPARAMS];
+    load_params(P, W);
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const float g = dz[r];
+    float a[NH], b[NH];
+    const __half *h3 = acts + (2 * n + r) * NH;
+    const __half *h2 = acts + (1 * n + r) * NH;
+    const __half *h1 = acts + (0 * n + r) * NH;
+#pragma unroll
+    for (int j = 0; j < NH; j++) {
+        a[j] = __half2float(h3[j]) > 0.0f ? g * W[OFF_W4 + j] : 0.0f;
+        d3[r * NH + j] = a[j];
+    }
+#pragma unroll
+    for (int i = 0; i < NH; i++) {
+        float s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NH; j++) s = fmaf(W[OFF_W3 + j * NH + i], a[j], s);
+        b[i] = __half2float(h2[i]) > 0.0f ? s : 0.0f;
+        d2[r * NH + i] = b[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NH; i++) {
+        float s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NH; j++) s = fmaf(W[OFF_W2 + j * NH + i], b[j], s);
+        d1[r * NH + i] = __half2float(h1[i]) > 0.0f ? s : 0.0f;
+    }
+}
+
+// weight gradients as outer-product reductions over rows:
+//   G[a][c] += sum_r D[r][a] V[r][c],  Gb[a] += sum_r D[r][a]
+// V is either the FP16 activation (mode 0, width 64) or the layer-1 input
+// (mode 1, width 18, rebuilt from the bin and the scene code).
+// 256 threads: thread t owns output row a = t / 4, 16 columns from (t % 4) * 16.
+#define WG_ROWS 64
+__global__ __launch_bounds__(256) void k_wgrad(const float *D, int da, const __half *V,
+                                               const float *codes, int vc, int64_t n,
+                                               int64_t rows_per_block, float *G, float *Gb)
+{
+    __shared__ float sD[WG_ROWS][NH + 1];
+    __shared__ float sV[WG_ROWS][NH + 1];
+    const int t = threadIdx.x;
+    const int a = t >> 2;
+    const int c0 = (t & 3) * 16;
+    float acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) acc[k] = 0.0f;
+    float accb = 0.0f;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(n, r0 + rows_per_block);
+    for (int64_t base = r0; base < r1; base += WG_ROWS) {
+        const int cnt = (int)min((int64_t)WG_ROWS, r1 - base);
+        __syncthreads();
+        for (int e = t; e < WG_ROWS * NH; e += 256) {
+            const int rr = e / NH, cc = e % NH;
+            float dv = 0.0f, vv = 0.0f;
+            if (rr < cnt) {
+                const int64_t row = base + rr;
+                if (cc < da) dv = D[row * da + cc];
+                if (V) {
+                    if (cc < vc) vv = __half2float(V[row * vc + cc]);
+                } else if (cc < vc) {
+                    float x[NIN];
+                    row_input(codes, row, x);
+                    vv = x[cc];
+                }
+            }
+            sD[rr][cc] = dv;
+            sV[rr][cc] = vv;
+        }
+        __syncthreads();
+        if (a < da) {
+            for (int rr = 0; rr < cnt; rr++) {
+                const float d = sD[rr][a];
+                accb += d;
+#pragma unroll
+                for (int k = 0; k < 16; k++) acc[k] = fmaf(d, sV[rr][c0 + k], acc[k]);
+            }
+        }
+    }
+    if (a < da) {
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            if (c0 + k < vc) atomicAdd(&G[a * vc + c0 + k], acc[k]);
+        if ((t & 3) == 0) atomicAdd(&Gb[a], accb);
+    }
+}
+
+// Adam (Kingma & Ba): FP32 master parameters and moments
+__global__ void k_adam(float *P, const float *G, float *m, float *v, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = G[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// sampling table for one scene: q_mix = (1 - beta) softmax(z) + beta / NBINS,
+// cdf[0] = 0, cdf[b + 1] = cdf[b] + q_mix[b] (FP64, block scan), normalised
+__global__ __launch_bounds__(1024) void k_build_cdf(const float *z, float beta, double *cdf)
+{
+    __shared__ double red[1024];
+    __shared__ float fred[1024];
+    const int t = threadIdx.x;
+    float mx = -3.0e38f;
+    for (int b = t; b < NBINS; b += 1024) mx = fmaxf(mx, z[b]);
+    fred[t] = mx;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (t < o) fred[t] = fmaxf(fred[t], fred[t + o]);
+        __syncthreads();
+    }
+    mx = fred[0];
+    __syncthreads();
+    // each thread owns 8 consecutive bins
+    double e[8];
+    double s = 0.0;
+    for (int k = 0; k < 8; k++) {
+        e[k] = exp((double)z[t * 8 + k] - (double)mx);
+        s += e[k];
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    const double tot = red[0];
+    __syncthreads();
+    double loc = 0.0;
+    double q[8];
+    for (int k = 0; k < 8; k++) {
+        q[k] = (1.0 - (double)beta) * e[k] / tot + (double)beta / (double)NBINS;
+        loc += q[k];
+    }
+    // inclusive scan of per-thread sums (Hillis-Steele)
+    red[t] = loc;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        double y = t >= o ? red[t - o] : 0.0;
+        __syncthreads();
+        red[t] += y;
+        __syncthreads();
+    }
+    const double total = red[1023];
+    double run = red[t] - loc;
+    for (int k = 0; k < 8; k++) {
+        run += q[k];
+        cdf[t * 8 + k + 1] = run / total;
+    }
+    if (t == 0) cdf[0] = 0.0;
+    __syncthreads();
+    if (t == 1023) cdf[NBINS] = 1.0;
+}
+
+}  // namespace
+
+hipError_t launch_mlp_forward(const float *P, const float *codes, int64_t n, __half *acts, float *z,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, codes, n,
+                       acts, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_softmax_grad(const float *z, const float *H, int n_scenes, float *dz, float *loss,
+                               hipStream_t s)
+{
+    if (n_scenes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_softmax_grad, dim3(n_scenes), dim3(1024), 0, s, z, H, n_scenes, dz, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const float *P, const float *dz, int64_t n, const __half *acts,
+                               float *d1, float *d2, float *d3, const float *codes, float *grad,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, dz, n, acts,
+                       d1, d2, d3);
+    const int64_t rpb = 4096;
+    const unsigned nb = (unsigned)((n + rpb - 1) / rpb);
+    // layer 4: dz (width 1) x h3; layer 3: d3 x h2; layer 2: d2 x h1; layer 1: d1 x input
+    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, dz, 1, acts + 2 * n * NH, codes, NH, n, rpb,
+                       grad + OFF_W4, grad + OFF_B4);
+    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d3, NH, acts + 1 * n * NH, codes, NH, n, rpb,
+                       grad + OFF_W3, grad + OFF_B3);
+    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d2, NH, acts + 0 * n * NH, codes, NH, n, rpb,
+                       grad + OFF_W2, grad + OFF_B2);
+    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d1, NH, (const __half *)nullptr, codes, NIN,
+                       n, rpb, grad + OFF_W1, grad + OFF_B1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *P, const float *G, float *m, float *v, float lr, int step, hipStream_t s)
+{
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, s, P, G, m, v, NPARAMS, lr,
+                       b1, b2, 1e-8f, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_cdf(const float *z, float beta, double *cdf, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_build_cdf, dim3(1), dim3(1024), 0, s, z, beta, cdf);
+    return hipGetLastError();
+}

@@ -399,6 +399,60 @@ __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_points(TraceArgs A)
     A.counts[v] = vis ? 1 : 0;
 }
 
+// Scene code of the learned proposal: 16 azimuth sectors x 8 probe rays at
+// elevation 0 from the Tx phase centre (sector k ray i at azimuth fraction
+// (8 k + i + 1/2) / 128 of the field of view); code[k] = mean over the
+// sector's rays of exp(-t / 10 m) for hits on objects other than object 0.
+__global__ __launch_bounds__(RR_TRACE_BLOCK) void k_probe(TraceArgs A, float *code)
+{
+    __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
+    __shared__ double vals[128];
+    int *stk = lds_stack + threadIdx.x;
+    const int t = threadIdx.x;
+    const int k = t >> 3, i = t & 7;
+    const double fa = ((double)(8 * k + i) + 0.5) / 128.0;
+    const double turn = A.at + fa * (A.bt - A.at);
+    double sa, ca;
+    sincos_turn(turn, sa, ca);
+    double th;
+    int lidx;
+    const int h = closest_hit(A, mk3(A.oT[0], A.oT[1], A.oT[2]), mk3(ca, sa, 0.0), -1, th, lidx, stk);
+    double val = 0.0;
+    if (h >= 0) {
+        const int obj = __float_as_int(A.ltris[3 * (int64_t)lidx + 2].z);
+        if (obj != 0) val = exp(-th / 10.0);
+    }
+    vals[t] = val;
+    __syncthreads();
+    if (i == 0) {
+        double acc = 0.0;
+        for (int j = 0; j < 8; j++) acc += vals[8 * k + j];
+        code[k] = (float)(acc / 8.0);
+    }
+}
+
+// Training target of the proposal from a uniform trace: per direction bin the
+// sum over its rays of (returned power = number of received paths, since
+// w = 1) + 0.1 x (first segment hit an object other than object 0).
+__global__ void k_hist(TraceArgs A, int64_t n_traced, const int32_t *hits, const int32_t *tri_obj,
+                       int n_az, int n_el, float *H)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_traced) return;
+    const int64_t t = g / A.n_per_src;
+    const int64_t i = g - t * A.n_per_src;
+    const int64_t v = t * A.n_virt_per_src + i;
+    uint64_t r[4];
+    philox((uint64_t)i, (uint64_t)t, 0, A.seed, r);
+    int ia = (int)(u01(r[0]) * n_az), ie = (int)(u01(r[1]) * n_el);
+    ia = min(ia, n_az - 1);
+    ie = min(ie, n_el - 1);
+    const int h0 = hits[g * (A.bmax + 1)];
+    const float hit = (h0 >= 0 && tri_obj[h0] != 0) ? 0.1f : 0.0f;
+    const float val = (float)A.counts[v] + hit;
+    if (val != 0.0f) atomicAdd(&H[ie * n_az + ia], val);
+}
+
 // ---------------------------------------------------------------------------
 // exclusive scan of uint8 counts -> uint32 offsets (three passes)
 // ---------------------------------------------------------------------------
@@ -520,6 +574,21 @@ hipError_t launch_points(const TraceArgs &a, hipStream_t s)
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
     hipLaunchKernelGGL(k_points, dim3((unsigned)blocks), dim3(RR_TRACE_BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(const TraceArgs &a, float *code, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_probe, dim3(1), dim3(RR_TRACE_BLOCK), 0, s, a, code);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist(const TraceArgs &a, int64_t n_traced, const int32_t *hits,
+                       const int32_t *tri_obj, int n_az, int n_el, float *H, hipStream_t s)
+{
+    if (n_traced <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)((n_traced + 255) / 256)), dim3(256), 0, s, a,
+                       n_traced, hits, tri_obj, n_az, n_el, H);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // rr_host.cpp -- the C ABI of libradray: context, validation, device buffers
 // and the launch sequence of the trace and synthesis kernels.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -145,6 +146,15 @@ struct rr_ctx {
     // synthesis scratch
     DevBuf syn, ranges;
     DevBuf gT, gR, gA, gB;     // GEMM operands
+
+    // learned proposal
+    DevBuf tri_obj;            // object of each triangle, by original id
+    TraceArgs last{};          // arguments of the last trace (histogram)
+    int64_t last_traced = 0;
+    int last_sampler = -1;
+    DevBuf mlp_p, mlp_m, mlp_v, mlp_g, mlp_acts, mlp_z, mlp_dz, mlp_d, mlp_loss;
+    bool mlp_ready = false;
+    int mlp_step = 0;
 };
 
 extern "C" {
@@ -193,7 +203,8 @@ void rr_destroy(rr_ctx *c)
                       &c->pt_ap, &c->tx, &c->rx, &c->counts, &c->offsets, &c->bsums,
                       &c->counter, &c->total, &c->err_flag, &c->hits, &c->cdf, &c->syn,
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
-                      &c->gB};
+                      &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
+                      &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -244,6 +255,9 @@ int rr_scene_upload(rr_ctx *c, const float *verts, int64_t n_verts, const int32_
     if ((rc = c->pt_pos.ensure((size_t)n_pts * 24 + 8))) return rc;
     if ((rc = c->pt_vel.ensure((size_t)n_pts * 24 + 8))) return rc;
     if ((rc = c->pt_ap.ensure((size_t)n_pts * 8 + 8))) return rc;
+    if ((rc = c->tri_obj.ensure((size_t)n_tris * 4 + 8))) return rc;
+    if (n_tris > 0)
+        HIPCHK(hipMemcpy(c->tri_obj.p, tri_obj, (size_t)n_tris * 4, hipMemcpyHostToDevice));
     if (!bvh.nodes.empty())
         HIPCHK(hipMemcpy(c->nodes.p, bvh.nodes.data(), bvh.nodes.size() * 4, hipMemcpyHostToDevice));
     if (!bvh.tris.empty())
@@ -425,6 +439,9 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
         if (errf) return fail(RR_EHIP, "traversal stack overflow (BVH depth %d)", c->bvh_depth);
         c->n_paths = keep;
         c->trace_timed = true;
+        c->last = A;
+        c->last_traced = n_traced;
+        c->last_sampler = tp->record_hits ? tp->sampler : -1;
         if (n_paths_out) *n_paths_out = keep;
         g_err.clear();
         return RR_OK;
@@ -658,6 +675,223 @@ int rr_last_kernel_ms(rr_ctx *c, int32_t which, double *ms)
     float f = 0;
     HIPCHK(hipEventElapsedTime(&f, a, b));
     *ms = f;
+    return RR_OK;
+}
+
+// --------------------------------------------------------------------------
+// learned proposal
+// --------------------------------------------------------------------------
+
+int rr_proposal_set_cdf(rr_ctx *c, const double *cdf, int32_t n_az, int32_t n_el)
+{
+    if (!c || !cdf) return fail(RR_EINVAL, "NULL argument");
+    if (n_az < 1 || n_el < 1 || (int64_t)n_az * n_el > (1 << 24)) return fail(RR_EINVAL, "bad grid");
+    const int64_t nb = (int64_t)n_az * n_el;
+    if (cdf[0] != 0.0 || cdf[nb] != 1.0) return fail(RR_EINVAL, "cdf must run from 0 to 1");
+    for (int64_t b = 0; b < nb; b++)
+        if (!(cdf[b + 1] >= cdf[b])) return fail(RR_EINVAL, "cdf must be non-decreasing");
+    HIPCHK(hipSetDevice(c->device));
+    int rc = c->cdf.ensure((size_t)(nb + 1) * 8);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(c->cdf.p, cdf, (size_t)(nb + 1) * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->n_az = n_az;
+    c->n_el = n_el;
+    return RR_OK;
+}
+
+int rr_proposal_get_cdf(rr_ctx *c, double *cdf, int64_t cap)
+{
+    if (!c || !cdf) return fail(RR_EINVAL, "NULL argument");
+    if (c->n_az <= 0) return fail(RR_ESTATE, "no proposal table");
+    const int64_t n = (int64_t)c->n_az * c->n_el + 1;
+    if (cap < n) return fail(RR_EOVERFLOW, "need %lld entries", (long long)n);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemcpyAsync(cdf, c->cdf.p, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return RR_OK;
+}
+
+int rr_proposal_probe(rr_ctx *c, double az_min, double az_max, float *code16)
+{
+    if (!c || !code16) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_scene || !c->has_array) return fail(RR_ESTATE, "scene and array must be set");
+    if (!(az_max > az_min) || !std::isfinite(az_min) || !std::isfinite(az_max))
+        return fail(RR_EINVAL, "invalid azimuth range");
+    HIPCHK(hipSetDevice(c->device));
+    TraceArgs A{};
+    A.nodes = c->nodes.as<const float4>();
+    A.ltris = c->ltris.as<const float4>();
+    A.has_bvh = c->n_tris > 0;
+    for (int a = 0; a < 3; a++) {
+        A.oT[a] = c->oT[a];
+        A.oR[a] = c->oR[a];
+    }
+    const double INV_2PI = 0.15915494309189535;
+    A.at = az_min * INV_2PI;
+    A.bt = az_max * INV_2PI;
+    A.err_flag = c->err_flag.as<int>();
+    HIPCHK(launch_probe(A, code16, c->stream));
+    return RR_OK;
+}
+
+int rr_proposal_histogram(rr_ctx *c, float *hist)
+{
+    if (!c || !hist) return fail(RR_EINVAL, "NULL argument");
+    if (c->n_paths < 0 || c->last_sampler != RR_UNIFORM || !c->hits_recorded)
+        return fail(RR_ESTATE, "needs a uniform trace with record_hits");
+    HIPCHK(hipSetDevice(c->device));
+    const int nb = RR_PROP_NAZ * RR_PROP_NEL;
+    HIPCHK(hipMemsetAsync(hist, 0, (size_t)nb * 4, c->stream));
+    HIPCHK(launch_hist(c->last, c->last_traced, c->hits.as<const int32_t>(),
+                       c->tri_obj.as<const int32_t>(), RR_PROP_NAZ, RR_PROP_NEL, hist, c->stream));
+    return RR_OK;
+}
+
+static int mlp_alloc(rr_ctx *c)
+{
+    int rc;
+    if ((rc = c->mlp_p.ensure(RR_MLP_PARAMS * 4))) return rc;
+    if ((rc = c->mlp_m.ensure(RR_MLP_PARAMS * 4))) return rc;
+    if ((rc = c->mlp_v.ensure(RR_MLP_PARAMS * 4))) return rc;
+    if ((rc = c->mlp_g.ensure(RR_MLP_PARAMS * 4))) return rc;
+    return RR_OK;
+}
+
+static int mlp_reset_adam(rr_ctx *c)
+{
+    HIPCHK(hipMemsetAsync(c->mlp_m.p, 0, RR_MLP_PARAMS * 4, c->stream));
+    HIPCHK(hipMemsetAsync(c->mlp_v.p, 0, RR_MLP_PARAMS * 4, c->stream));
+    c->mlp_step = 0;
+    return RR_OK;
+}
+
+int rr_mlp_set_params(rr_ctx *c, const float *params, int64_t n)
+{
+    if (!c || !params) return fail(RR_EINVAL, "NULL argument");
+    if (n != RR_MLP_PARAMS) return fail(RR_EINVAL, "expected %d parameters", RR_MLP_PARAMS);
+    for (int64_t i = 0; i < n; i++)
+        if (!std::isfinite(params[i])) return fail(RR_EINVAL, "non-finite parameter");
+    HIPCHK(hipSetDevice(c->device));
+    int rc = mlp_alloc(c);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(c->mlp_p.p, params, RR_MLP_PARAMS * 4, hipMemcpyHostToDevice, c->stream));
+    if ((rc = mlp_reset_adam(c))) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->mlp_ready = true;
+    return RR_OK;
+}
+
+int rr_mlp_get_params(rr_ctx *c, float *params, int64_t n)
+{
+    if (!c || !params) return fail(RR_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
+    if (n < RR_MLP_PARAMS) return fail(RR_EOVERFLOW, "need %d entries", RR_MLP_PARAMS);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemcpyAsync(params, c->mlp_p.p, RR_MLP_PARAMS * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return RR_OK;
+}
+
+int rr_mlp_init(rr_ctx *c, uint64_t seed)
+{
+    if (!c) return fail(RR_EINVAL, "NULL argument");
+    // He-uniform: U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)) from a 64-bit LCG
+    // (Knuth's MMIX constants), top 53 bits as the uniform
+    std::vector<float> p(RR_MLP_PARAMS, 0.0f);
+    uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+    auto uni = [&]() {
+        x = x * 6364136223846793005ull + 1442695040888963407ull;
+        return (double)(x >> 11) * 0x1.0p-53;
+    };
+    const int fan[4] = {18, 64, 64, 64}, rows[4] = {64, 64, 64, 1};
+    int off = 0;
+    for (int l = 0; l < 4; l++) {
+        const double lim = std::sqrt(6.0 / fan[l]);
+        for (int i = 0; i < rows[l] * fan[l]; i++) p[off + i] = (float)((2.0 * uni() - 1.0) * lim);
+        off += rows[l] * fan[l] + rows[l];
+    }
+    return rr_mlp_set_params(c, p.data(), RR_MLP_PARAMS);
+}
+
+static int mlp_buffers(rr_ctx *c, int64_t rows, int n_scenes)
+{
+    int rc;
+    if ((rc = c->mlp_acts.ensure((size_t)rows * 3 * 64 * 2))) return rc;
+    if ((rc = c->mlp_z.ensure((size_t)rows * 4))) return rc;
+    if ((rc = c->mlp_dz.ensure((size_t)rows * 4))) return rc;
+    if ((rc = c->mlp_d.ensure((size_t)rows * 3 * 64 * 4))) return rc;
+    if ((rc = c->mlp_loss.ensure((size_t)n_scenes * 4 + 4))) return rc;
+    return RR_OK;
+}
+
+int rr_mlp_forward(rr_ctx *c, const float *codes, int32_t n_scenes, float *logits)
+{
+    if (!c || !codes || !logits) return fail(RR_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
+    if (n_scenes < 1) return fail(RR_EINVAL, "n_scenes must be positive");
+    HIPCHK(hipSetDevice(c->device));
+    const int64_t rows = (int64_t)n_scenes * RR_PROP_NAZ * RR_PROP_NEL;
+    HIPCHK(launch_mlp_forward(c->mlp_p.as<const float>(), codes, rows, nullptr, logits, c->stream));
+    return RR_OK;
+}
+
+int rr_mlp_train_step(rr_ctx *c, const float *codes, const float *hist, int32_t n_scenes, float lr,
+                      float *loss_out, float *grad_out)
+{
+    if (!c || !codes || !hist) return fail(RR_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
+    if (n_scenes < 1) return fail(RR_EINVAL, "n_scenes must be positive");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(RR_EINVAL, "invalid learning rate");
+    HIPCHK(hipSetDevice(c->device));
+    const int64_t rows = (int64_t)n_scenes * RR_PROP_NAZ * RR_PROP_NEL;
+    int rc = mlp_buffers(c, rows, n_scenes);
+    if (rc) return rc;
+    __half *acts = c->mlp_acts.as<__half>();
+    float *d = c->mlp_d.as<float>();
+    HIPCHK(launch_mlp_forward(c->mlp_p.as<const float>(), codes, rows, acts, c->mlp_z.as<float>(),
+                              c->stream));
+    HIPCHK(launch_softmax_grad(c->mlp_z.as<const float>(), hist, n_scenes, c->mlp_dz.as<float>(),
+                               c->mlp_loss.as<float>(), c->stream));
+    HIPCHK(hipMemsetAsync(c->mlp_g.p, 0, RR_MLP_PARAMS * 4, c->stream));
+    HIPCHK(launch_mlp_backward(c->mlp_p.as<const float>(), c->mlp_dz.as<const float>(), rows, acts,
+                               d, d + rows * 64, d + 2 * rows * 64, codes, c->mlp_g.as<float>(),
+                               c->stream));
+    if (grad_out)
+        HIPCHK(hipMemcpyAsync(grad_out, c->mlp_g.p, RR_MLP_PARAMS * 4, hipMemcpyDeviceToDevice,
+                              c->stream));
+    if (lr > 0.0f) {
+        c->mlp_step++;
+        HIPCHK(launch_adam(c->mlp_p.as<float>(), c->mlp_g.as<const float>(), c->mlp_m.as<float>(),
+                           c->mlp_v.as<float>(), lr, c->mlp_step, c->stream));
+    }
+    if (loss_out) {
+        std::vector<float> l(n_scenes);
+        HIPCHK(hipMemcpyAsync(l.data(), c->mlp_loss.p, (size_t)n_scenes * 4, hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        double s = 0.0;
+        for (float v : l) s += v;
+        *loss_out = (float)s;
+    }
+    return RR_OK;
+}
+
+int rr_proposal_build(rr_ctx *c, const float *code16, float beta)
+{
+    if (!c || !code16) return fail(RR_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
+    if (!(beta >= 0.0f && beta <= 1.0f)) return fail(RR_EINVAL, "beta must be in [0, 1]");
+    HIPCHK(hipSetDevice(c->device));
+    const int nb = RR_PROP_NAZ * RR_PROP_NEL;
+    int rc;
+    if ((rc = c->mlp_z.ensure((size_t)nb * 4))) return rc;
+    if ((rc = c->cdf.ensure((size_t)(nb + 1) * 8))) return rc;
+    HIPCHK(launch_mlp_forward(c->mlp_p.as<const float>(), code16, nb, nullptr, c->mlp_z.as<float>(),
+                              c->stream));
+    HIPCHK(launch_build_cdf(c->mlp_z.as<const float>(), beta, c->cdf.as<double>(), c->stream));
+    c->n_az = RR_PROP_NAZ;
+    c->n_el = RR_PROP_NEL;
     return RR_OK;
 }
 

@@ -132,3 +132,18 @@ hipError_t launch_gemm_prep_a(const float2 *T, const float2 *R, int nrx, int C, 
 hipError_t launch_gemm_prep_b(const SynthArgs &a, int Ppad, uint4 *Bp, hipStream_t s);
 hipError_t launch_gemm_main(const uint4 *Af, const uint4 *Bp, int Cpad, int Ppad, int C, int M,
                             int K, float2 *cube, hipStream_t s);
+
+// learned proposal (k_trace.hip: probe and histogram; k_mlp.hip: network)
+hipError_t launch_probe(const TraceArgs &a, float *code, hipStream_t s);
+hipError_t launch_hist(const TraceArgs &a, int64_t n_traced, const int32_t *hits,
+                       const int32_t *tri_obj, int n_az, int n_el, float *H, hipStream_t s);
+#include <hip/hip_fp16.h>
+hipError_t launch_mlp_forward(const float *P, const float *codes, int64_t n, __half *acts, float *z,
+                              hipStream_t s);
+hipError_t launch_softmax_grad(const float *z, const float *H, int n_scenes, float *dz, float *loss,
+                               hipStream_t s);
+hipError_t launch_mlp_backward(const float *P, const float *dz, int64_t n, const __half *acts,
+                               float *d1, float *d2, float *d3, const float *codes, float *grad,
+                               hipStream_t s);
+hipError_t launch_adam(float *P, const float *G, float *m, float *v, float lr, int step, hipStream_t s);
+hipError_t launch_build_cdf(const float *z, float beta, double *cdf, hipStream_t s);

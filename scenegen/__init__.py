@@ -441,8 +441,12 @@ def workload_batch(n_scenes: int = 64, seed0: int = 2000, rays: int = 1_000_000,
     return out
 
 
-def workload_box_family(seed: int, n_rays: int) -> Workload:
+def workload_box_family(seed: int, n_rays: int, points: bool = True) -> Workload:
     """One scene of the learned-proposal family with the tiny scene's array
-    and chirp, 2 bounces."""
-    return Workload(f"box{seed}", scene_box_family(seed), array_c1(), Chirp(n_samples=64, n_chirps=16),
+    and chirp, 2 bounces (points=False drops the point reflectors, leaving
+    only the traced part of the cube)."""
+    sc = scene_box_family(seed)
+    if not points:
+        sc = Scene(sc.verts, sc.tris, sc.tri_obj, sc.obj_alpha, sc.obj_vel).checked()
+    return Workload(f"box{seed}", sc, array_c1(), Chirp(n_samples=64, n_chirps=16),
                     TraceParams(n_rays=n_rays, max_bounces=2, seed=seed))

@@ -1,0 +1,144 @@
+"""Learned ray proposal on the GPU against the oracle: importance-sampled
+launch (bitwise hit lists and paths for a given table), probe code, training
+histogram, network forward, gradient and Adam step, sampling table; and the
+gain of the trained network over uniform launch at equal ray budget."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from helpers import assert_paths_equal, gpu_soa_np, oracle_to_soa, traced_rows
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _texture_cdf(seed):
+    na, ne = 128, 64
+    rng = np.random.default_rng(seed)
+    ia = np.arange(na)[None, :]
+    ie = np.arange(ne)[:, None]
+    q = np.exp(-((ia - 63.5) ** 2 + (ie - 31.5) ** 2) / 60.0) + 0.05 * rng.random((ne, na)) + 1e-3
+    q = (q / q.sum()).reshape(-1)
+    cdf = np.concatenate([[0.0], np.cumsum(q)])
+    cdf /= cdf[-1]
+    cdf[-1] = 1.0
+    return cdf
+
+
+@pytest.mark.parametrize("scene", ["plate", "tiny"])
+def test_importance_sampled_trace_bit_exact(gpu, orc, scene):
+    import paper_2307_15412_amd as rr
+    if scene == "plate":
+        w = sg.Workload("plate", sg.plate(5.0, 1.0), sg.Array(np.array([[0, 0, 0.5]]),
+                        np.array([[0, 0, 0.5]]), 0.25, sg.MODE_PER_TX), sg.Chirp(),
+                        sg.TraceParams(n_rays=100_000, max_bounces=2, seed=4))
+    else:
+        w = sg.workload_tiny(3)
+        w.trace.n_rays = 50_000
+    cdf = _texture_cdf(1)
+    gpu.setup(w)
+    gpu.proposal_set_cdf(cdf)
+    n = gpu.trace_workload(w, record_hits=True, sampler=rr.PROPOSAL)
+    hits = gpu.hits().cpu().numpy()
+    oh, op = orc.trace(w.scene, w.array, w.trace, cdf=cdf, n_az=128, n_el=64)
+    rows = traced_rows(orc, w.scene, w.array, w.trace)
+    assert (hits == oh[rows]).all()
+    assert n == len(op)
+    assert_paths_equal(gpu_soa_np(gpu), oracle_to_soa(op))
+
+
+def test_probe_code(gpu, orc):
+    for seed in (1, 2, 3, 11, 12):
+        w = sg.workload_box_family(seed, 1000)
+        gpu.setup(w)
+        code = gpu.proposal_probe().cpu().numpy()
+        ref = orc.probe_code(w.scene, w.array, w.trace)
+        assert np.abs(code - ref).max() < 1e-6, (seed, code, ref)
+    assert ref.max() >= 0.0
+
+
+def test_histogram(gpu, orc):
+    for seed in (1, 5):
+        w = sg.workload_box_family(seed, 50_000)
+        gpu.setup(w)
+        gpu.trace_workload(w, record_hits=True)
+        H = gpu.proposal_histogram().cpu().numpy().astype(np.float64)
+        hits, paths = orc.trace(w.scene, w.array, w.trace)
+        rows = traced_rows(orc, w.scene, w.array, w.trace)
+        ref = orc.histogram(w.scene, w.array, w.trace, hits[rows], paths)
+        assert ref.sum() > 0
+        assert np.abs(H - ref).max() <= 1e-5 * max(1.0, ref.max())
+
+
+def _inputs(seed, S=3):
+    rng = np.random.default_rng(seed)
+    codes = (rng.random((S, 16)) * (rng.random((S, 16)) < 0.4)).astype(np.float32)
+    hist = (rng.random((S, 8192)) * (rng.random((S, 8192)) < 0.03)).astype(np.float32)
+    return codes, hist
+
+
+def _f16(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float64)
+
+
+def test_forward_and_gradient(gpu):
+    gpu.mlp_init(3)
+    p = gpu.mlp_get_params()
+    codes, hist = _inputs(7)
+    tc = torch.from_numpy(codes).cuda()
+    th = torch.from_numpy(hist).cuda()
+    z = gpu.mlp_forward(tc).cpu().numpy().reshape(-1)
+    zr, _ = mlp.forward(_f16(p), mlp.features(_f16(codes)))
+    assert np.linalg.norm(z - zr) / np.linalg.norm(zr) < 5e-3
+    loss, g = gpu.mlp_train_step(tc, th, 0.0, want_grad=True)
+    lr_, gr = mlp.loss_and_grad(_f16(p), _f16(codes), hist.astype(np.float64))
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss - lr_) < 2e-3 * abs(lr_)
+    assert np.linalg.norm(g - gr) / np.linalg.norm(gr) < 2e-2
+    assert g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)) > 0.999
+    # lr = 0 leaves the parameters unchanged
+    assert np.array_equal(gpu.mlp_get_params(), p)
+
+
+def test_adam_step(gpu):
+    gpu.mlp_init(5)
+    p0 = gpu.mlp_get_params()
+    codes, hist = _inputs(8)
+    lr = 1e-3
+    gpu.mlp_train_step(torch.from_numpy(codes).cuda(), torch.from_numpy(hist).cuda(), lr)
+    p1 = gpu.mlp_get_params().astype(np.float64)
+    _, gr = mlp.loss_and_grad(_f16(p0), _f16(codes), hist.astype(np.float64))
+    ref, _, _ = mlp.adam_step(p0.astype(np.float64), gr, np.zeros_like(gr), np.zeros_like(gr), 1, lr)
+    # the first Adam step moves each parameter by ~lr sign(g); parameters with
+    # a tiny gradient may differ in sign between FP16 and FP64 evaluation
+    close = np.abs(p1 - ref) <= 2e-6
+    assert close.mean() > 0.97
+    assert np.abs(p1 - ref).max() <= 2.1 * lr
+
+
+def test_sampling_table(gpu):
+    gpu.mlp_init(9)
+    p = gpu.mlp_get_params()
+    code = np.random.default_rng(1).random(16).astype(np.float32) * 0.3
+    gpu.proposal_build(torch.from_numpy(code).cuda(), 0.1)
+    cdf = gpu.proposal_get_cdf()
+    zr, _ = mlp.forward(_f16(p), mlp.features(_f16(code[None, :])))
+    ref = mlp.cdf_of(mlp.mixture(zr, 0.1))
+    assert cdf[0] == 0.0 and cdf[-1] == 1.0 and np.all(np.diff(cdf) >= 0)
+    assert np.abs(cdf - ref).max() < 2e-4
+
+
+def test_learned_proposal_gain(gpu):
+    """Train on uniform traces of 60 scenes of the box family, then on 10
+    held-out scenes draw 1.25e4 rays from the learned density: the traced
+    part of the cube is closer to a 1e6-ray uniform reference than the cube
+    from 1.25e4 uniform rays."""
+    from paper_2307_15412_amd import proposal
+    res = proposal.experiment(gpu, train_seeds=range(1, 61), eval_seeds=range(1001, 1011),
+                              train_rays=50_000, budget=12_500, ref_rays=1_000_000, steps=200,
+                              batch=16, lr=2e-3)
+    print({k: v for k, v in res.items() if k != "per_scene"})
+    assert res["loss_last"] < res["loss_first"]
+    assert res["err_learned_mean"] < 0.8 * res["err_uniform_mean"]
+    assert res["wins"] >= 7
