@@ -251,6 +251,49 @@ int rr_mlp_train_step(rr_ctx *ctx, const float *codes_dev, const float *hist_dev
  * (device).  Afterwards rr_trace with sampler RR_PROPOSAL draws from it. */
 int rr_proposal_build(rr_ctx *ctx, const float *code16_dev, float beta);
 
+/* ------------------------------------------------------------------------
+ * Batched launch: many scenes of uneven size (triangles, rays, channels,
+ * chirps, samples) traced and synthesised (exact model, direct FP32 engine)
+ * by one persistent trace kernel and one persistent synthesis kernel that
+ * pull (scene, chunk) and (scene, tile) items from device counters.  The
+ * whole stage sequence is captured once as a hipGraph and replayed; the
+ * per-scene synthesis tile (samples per lane) comes from rr_batch_tune.
+ * ------------------------------------------------------------------------ */
+typedef struct rr_batch rr_batch;
+
+/* A batch of n_scenes slots bound to ctx's device and stream. */
+int rr_batch_create(rr_ctx *ctx, int32_t n_scenes, rr_batch **out);
+void rr_batch_destroy(rr_batch *batch);
+
+/* Fill slot `slot` with a scene (same arrays as rr_scene_upload), an array
+ * (as rr_set_array), a chirp and trace parameters (uniform sampler only;
+ * record_hits and path_cap are ignored).  Invalidates the captured graph. */
+int rr_batch_set_scene(rr_batch *batch, int32_t slot, const float *verts, int64_t n_verts,
+                       const int32_t *tris, const int32_t *tri_obj, int64_t n_tris,
+                       const float *obj_alpha, const double *obj_vel, int32_t n_obj,
+                       const double *pt_pos, const double *pt_vel, const double *pt_aperture,
+                       int32_t n_pts, const double *tx, int32_t n_tx, const double *rx, int32_t n_rx,
+                       double rx_radius, int32_t tx_mode, const rr_chirp *chirp,
+                       const rr_trace_params *params);
+
+/* Run the batch: cubes[s] is scene s's complex64 [n_ch][n_chirps][n_samples]
+ * device buffer.  The first launch (or the first after a change) captures the
+ * pipeline as a hipGraph; later launches replay it (new cube pointers only
+ * update a device table).  The call waits for completion and checks the path
+ * pool, growing it and re-running if it overflowed.  n_paths_out (host
+ * int64 [n_scenes], may be NULL) receives each scene's path count. */
+int rr_batch_launch(rr_batch *batch, void *const *cubes, int64_t *n_paths_out);
+
+/* Autotune the synthesis tile: for every distinct sample count, time each
+ * candidate samples-per-lane value on the batch and keep the fastest.  Runs
+ * the batch into `cubes`.  rr_batch_get_tiles reports the choice per scene. */
+int rr_batch_tune(rr_batch *batch, void *const *cubes);
+int rr_batch_get_tiles(rr_batch *batch, int32_t *samples_per_lane_out);
+
+/* Timing (ms, HIP events around the graph launch) of the last launch, the
+ * synthesis stage of the last autotuner run, and the last total path count. */
+int rr_batch_stats(rr_batch *batch, double *ms_total, double *ms_synth, int64_t *total_paths);
+
 /* Kernel timing of the last rr_trace / rr_synthesize call, in milliseconds,
  * measured with HIP events on the context stream (synchronises).
  * which: 0 = trace (all trace kernels), 1 = synthesis main kernel. */

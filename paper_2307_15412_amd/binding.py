@@ -359,3 +359,99 @@ for _name, _fn in list(vars(_ProposalMixin).items()):
 EXPORTED += ["rr_proposal_set_cdf", "rr_proposal_get_cdf", "rr_proposal_probe",
              "rr_proposal_histogram", "rr_mlp_init", "rr_mlp_set_params", "rr_mlp_get_params",
              "rr_mlp_forward", "rr_mlp_train_step", "rr_proposal_build"]
+
+
+# --------------------------------------------------------------------------
+# batched launch
+# --------------------------------------------------------------------------
+def _declare_batch(L):
+    if getattr(L, "_batch_declared", False):
+        return
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.rr_batch_create.argtypes = [vp, i32, C.POINTER(vp)]
+    L.rr_batch_destroy.argtypes = [vp]
+    L.rr_batch_destroy.restype = None
+    L.rr_batch_set_scene.argtypes = [vp, i32, vp, i64, vp, vp, i64, vp, vp, i32, vp, vp, vp, i32,
+                                     vp, i32, vp, i32, f64, i32, C.POINTER(Chirp),
+                                     C.POINTER(TraceParams)]
+    L.rr_batch_launch.argtypes = [vp, vp, vp]
+    L.rr_batch_tune.argtypes = [vp, vp]
+    L.rr_batch_get_tiles.argtypes = [vp, vp]
+    L.rr_batch_stats.argtypes = [vp, C.POINTER(f64), C.POINTER(f64), C.POINTER(i64)]
+    L._batch_declared = True
+
+
+class Batch:
+    """A batch of scenes traced and synthesised by one captured launch."""
+
+    def __init__(self, ctx: "Context", n_scenes: int):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        _declare_batch(self.lib)
+        h = C.c_void_p()
+        ctx._check(self.lib.rr_batch_create(ctx.h, int(n_scenes), C.byref(h)))
+        self.h = h
+        self.n = int(n_scenes)
+        self.shapes = [None] * self.n
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_workload(self, slot, w):
+        sc, a, ch, tp = w.scene, w.array, w.chirp, w.trace
+        keep = []
+
+        def P(x, dt):
+            x = np.ascontiguousarray(x, dtype=dt)
+            keep.append(x)
+            return x.ctypes.data if x.size else None
+
+        chirp = Chirp(ch.f0, ch.bandwidth, ch.t_chirp, ch.t_rep, ch.n_samples, ch.n_chirps)
+        t = TraceParams(int(tp.n_rays), int(tp.max_bounces), int(tp.seed) & (2**64 - 1), tp.az_min,
+                        tp.az_max, tp.el_min, tp.el_max, UNIFORM, 0, 0)
+        self.ctx._check(self.lib.rr_batch_set_scene(
+            self.h, int(slot), P(sc.verts, np.float32), sc.verts.shape[0], P(sc.tris, np.int32),
+            P(sc.tri_obj, np.int32), sc.tris.shape[0], P(sc.obj_alpha, np.float32),
+            P(sc.obj_vel, np.float64), sc.obj_alpha.shape[0], P(sc.pt_pos, np.float64),
+            P(sc.pt_vel, np.float64), P(sc.pt_aperture, np.float64), sc.pt_pos.shape[0],
+            P(a.tx, np.float64), a.tx.shape[0], P(a.rx, np.float64), a.rx.shape[0],
+            float(a.rx_radius), int(a.mode), C.byref(chirp), C.byref(t)))
+        self.shapes[slot] = (a.tx.shape[0] * a.rx.shape[0], ch.n_chirps, ch.n_samples)
+
+    def alloc_cubes(self):
+        torch = self.ctx.torch
+        return [torch.empty(s, dtype=torch.complex64, device=self.ctx.device) for s in self.shapes]
+
+    def _ptrs(self, cubes):
+        arr = (C.c_void_p * self.n)(*[c.data_ptr() for c in cubes])
+        self._keep = arr
+        return arr
+
+    def launch(self, cubes, want_counts=True):
+        counts = np.zeros(self.n, dtype=np.int64) if want_counts else None
+        self.ctx._check(self.lib.rr_batch_launch(self.h, self._ptrs(cubes),
+                                                 counts.ctypes.data if want_counts else None))
+        return counts
+
+    def tune(self, cubes):
+        self.ctx._check(self.lib.rr_batch_tune(self.h, self._ptrs(cubes)))
+        tiles = np.zeros(self.n, dtype=np.int32)
+        self.ctx._check(self.lib.rr_batch_get_tiles(self.h, tiles.ctypes.data))
+        return tiles
+
+    def stats(self):
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        self.ctx._check(self.lib.rr_batch_stats(self.h, C.byref(a), C.byref(b), C.byref(n)))
+        return dict(ms_total=a.value, ms_synth_tuned=b.value, paths=n.value)
+
+
+EXPORTED += ["rr_batch_create", "rr_batch_destroy", "rr_batch_set_scene", "rr_batch_launch",
+             "rr_batch_tune", "rr_batch_get_tiles", "rr_batch_stats"]

@@ -10,6 +10,8 @@
 // in FP32 registers.  Paths are staged through LDS in chunks and read as
 // broadcasts.  A second kernel evaluates individual cube entries fully in
 // FP64 for checks at sizes where the whole cube is not needed.
+#include <algorithm>
+
 #include "rr_internal.h"
 
 namespace {
@@ -70,15 +72,14 @@ __device__ __forceinline__ void path_lengths(const SynthArgs &A, const SynPath &
 
 __device__ __forceinline__ double frac(double x) { return x - floor(x); }
 
+// One workgroup tile: rows rb * RPB .. of group g (a Tx in the per-element
+// mode, everything in the shared mode), every sample of those rows.
 template <int KR>
-__global__ __launch_bounds__(SYN_T) void k_synth_direct(SynthArgs A, int rows_per_group, int RC,
-                                                        int blocks_per_group)
+__device__ void synth_block(const SynthArgs &A, int g, int rb, int rows_per_group, int RC,
+                            SynPath *sp)
 {
-    __shared__ SynPath sp[SYN_CHUNK];
     const int TPR = A.K / KR;
     const int RPB = SYN_T / TPR;
-    const int g = blockIdx.x / blocks_per_group;
-    const int rb = blockIdx.x - g * blocks_per_group;
     const int row = rb * RPB + threadIdx.x / TPR;
     const int k0 = (threadIdx.x % TPR) * KR;
     const bool valid = row < rows_per_group && (int)(threadIdx.x / TPR) < RPB;
@@ -135,6 +136,53 @@ __global__ __launch_bounds__(SYN_T) void k_synth_direct(SynthArgs A, int rows_pe
     float2 *out = A.cube + ((int64_t)c * A.M + m) * A.K + k0;
 #pragma unroll
     for (int k = 0; k < KR; k++) out[k] = make_float2(are[k], aim[k]);
+}
+
+template <int KR>
+__global__ __launch_bounds__(SYN_T) void k_synth_direct(SynthArgs A, int rows_per_group, int RC,
+                                                        int blocks_per_group)
+{
+    __shared__ SynPath sp[SYN_CHUNK];
+    const int g = blockIdx.x / blocks_per_group;
+    synth_block<KR>(A, g, blockIdx.x - g * blocks_per_group, rows_per_group, RC, sp);
+}
+
+// Batched, persistent: workgroups pull (scene, tile) items from a device
+// counter; each scene carries its own tile shape (samples per lane KR, chosen
+// by the autotuner) and its path range comes from the batched scan.
+__global__ __launch_bounds__(SYN_T) void k_batch_synth(const SynthArgs *scenes,
+                                                       const BatchSynthInfo *info,
+                                                       const int64_t *item_start, int S,
+                                                       unsigned long long *work)
+{
+    __shared__ SynPath sp[SYN_CHUNK];
+    __shared__ long long s_item;
+    const int64_t n_items = item_start[S];
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (long long)atomicAdd(work, 1ull);
+        __syncthreads();
+        const int64_t it = s_item;
+        if (it >= n_items) break;
+        int lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (item_start[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const SynthArgs &A = scenes[lo];
+        const BatchSynthInfo &I = info[lo];
+        const int local = (int)(it - item_start[lo]);
+        const int g = local / I.bpg;
+        const int rb = local - g * I.bpg;
+        switch (I.kr) {
+        case 32: synth_block<32>(A, g, rb, I.rows_per_group, I.rc, sp); break;
+        case 16: synth_block<16>(A, g, rb, I.rows_per_group, I.rc, sp); break;
+        case 8: synth_block<8>(A, g, rb, I.rows_per_group, I.rc, sp); break;
+        case 4: synth_block<4>(A, g, rb, I.rows_per_group, I.rc, sp); break;
+        case 2: synth_block<2>(A, g, rb, I.rows_per_group, I.rc, sp); break;
+        default: synth_block<1>(A, g, rb, I.rows_per_group, I.rc, sp); break;
+        }
+    }
 }
 
 // one block per requested entry; FP64 phase, FP64 sin/cos, FP64 accumulation
@@ -219,7 +267,109 @@ __global__ void k_ranges(const int32_t *src, int64_t n, int n_groups, int64_t *r
     ranges[g] = lo;
 }
 
+// synthesis records of the batched path pool: the scene of a path follows
+// from its virtual ray id
+__global__ void k_batch_prep(PathSoA P, const unsigned long long *total, int64_t cap,
+                             const int64_t *vr_start, int S, const BatchVel *vel, SynPath *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = min((int64_t)*total, cap);
+    if (i >= n) return;
+    const int64_t v = P.ray[i];
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (vr_start[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    const BatchVel &bv = vel[lo];
+    SynPath s;
+    const int64_t c = P.cap;
+#pragma unroll
+    for (int q = 0; q < RR_KMAX; q++) {
+        const int vid = P.vid[q * c + i];
+        const double *vv = nullptr;
+        if (vid >= 0 && vid < bv.nobj) vv = bv.obj_vel + 3 * vid;
+        else if (vid >= bv.nobj && vid < bv.nobj + bv.npts) vv = bv.pt_vel + 3 * (vid - bv.nobj);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            s.P[q][a] = P.p[(3 * q + a) * c + i];
+            s.V[q][a] = vv ? vv[a] : 0.0;
+        }
+    }
+    s.amp = P.amp[i];
+    s.K = P.K[i];
+    s.src = P.src[i];
+    out[i] = s;
+}
+
+// per-scene path ranges from the batched exclusive scan: paths of virtual
+// rays [vr0 + t n_vps, ...) start at offsets[vr0 + t n_vps]
+__global__ void k_batch_ranges(const uint32_t *offsets, int64_t V, const unsigned long long *total,
+                               int64_t cap, const BatchRangeInfo *ri, int S, int64_t *ranges)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const BatchRangeInfo &R = ri[s];
+    const int64_t tot = min((int64_t)*total, cap);
+    auto off = [&](int64_t v) -> int64_t {
+        const int64_t o = v < V ? (int64_t)offsets[v] : tot;
+        return min(o, tot);
+    };
+    if (R.shared) {
+        ranges[R.base] = off(R.vr0);
+        ranges[R.base + 1] = off(R.vr0 + R.n_vps);
+    } else {
+        for (int g = 0; g <= R.n_groups; g++) ranges[R.base + g] = off(R.vr0 + (int64_t)g * R.n_vps);
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_batch_synth(const SynthArgs *scenes, const BatchSynthInfo *info,
+                              const int64_t *item_start, int S, int64_t n_items,
+                              unsigned long long *work, hipStream_t s)
+{
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t grid = std::min<int64_t>(n_items, (int64_t)cus * 8);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_synth, dim3((unsigned)grid), dim3(SYN_T), 0, s, scenes, info,
+                       item_start, S, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prep(const PathSoA &paths, const unsigned long long *total, int64_t cap,
+                             const int64_t *vr_start, int S, const BatchVel *vel, SynPath *out,
+                             hipStream_t s)
+{
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, paths,
+                       total, cap, vr_start, S, vel, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ranges(const uint32_t *offsets, int64_t V, const unsigned long long *total,
+                               int64_t cap, const BatchRangeInfo *ri, int S, int64_t *ranges,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_ranges, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, s, offsets, V,
+                       total, cap, ri, S, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_syn_prep(const PathSoA &paths, int64_t n, const double *obj_vel, int nobj,
                            const double *pt_vel, int npts, SynPath *out, hipStream_t s)

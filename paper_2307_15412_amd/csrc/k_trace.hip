@@ -13,6 +13,8 @@
 // Received paths are appended with one atomic per wavefront and later put in
 // (virtual ray, bounce) order by a scan over per-ray counts and a scatter,
 // so the result does not depend on atomic ordering.
+#include <algorithm>
+
 #include "rr_internal.h"
 
 #pragma clang fp contract(off)
@@ -264,15 +266,12 @@ __device__ __forceinline__ void append(const TraceArgs &A, bool rec, int32_t src
     T.amp[slot] = amp;
 }
 
-__global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace(TraceArgs A, int64_t n_traced)
+// one launched ray g (source-major) through all of its bounces
+__device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
 {
-    __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
-    int *stk = lds_stack + threadIdx.x;
-    int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
-    if (g >= n_traced) return;
     int64_t t = g / A.n_per_src;
     int64_t i = g - t * A.n_per_src;
-    int64_t v = t * A.n_virt_per_src + i;
+    int64_t v = A.vbase + t * A.n_virt_per_src + i;
     d3 src = A.shared ? mk3(A.oT[0], A.oT[1], A.oT[2])
                       : mk3(A.tx[3 * t], A.tx[3 * t + 1], A.tx[3 * t + 2]);
     uint64_t r[4];
@@ -364,14 +363,10 @@ __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace(TraceArgs A, int64_t n
 
 // Point reflectors: one single-bounce path per (source, point) when both the
 // source-to-point and point-to-receiver legs are unobstructed.
-__global__ __launch_bounds__(RR_TRACE_BLOCK) void k_points(TraceArgs A)
+__device__ void trace_point(const TraceArgs &A, int64_t g, int *stk)
 {
-    __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
-    int *stk = lds_stack + threadIdx.x;
-    int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
-    if (g >= A.n_src * (int64_t)A.npts) return;
     int64_t t = g / A.npts, q = g - t * A.npts;
-    int64_t v = t * A.n_virt_per_src + A.n_per_src + q;
+    int64_t v = A.vbase + t * A.n_virt_per_src + A.n_per_src + q;
     d3 src = A.shared ? mk3(A.oT[0], A.oT[1], A.oT[2])
                       : mk3(A.tx[3 * t], A.tx[3 * t + 1], A.tx[3 * t + 2]);
     d3 Q = mk3(A.pt_pos[3 * q], A.pt_pos[3 * q + 1], A.pt_pos[3 * q + 2]);
@@ -397,6 +392,57 @@ __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_points(TraceArgs A)
     R.vid[0] = A.nobj + (int)q;
     append(A, vis, A.shared ? -1 : (int32_t)t, 1, v, 0, R, la, A.pt_ap[q] / (la * la * A.omega));
     A.counts[v] = vis ? 1 : 0;
+}
+
+__global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace(TraceArgs A, int64_t n_traced)
+{
+    __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
+    const int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
+    if (g < n_traced) trace_ray(A, g, lds_stack + threadIdx.x);
+}
+
+__global__ __launch_bounds__(RR_TRACE_BLOCK) void k_points(TraceArgs A)
+{
+    __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
+    const int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
+    if (g < A.n_src * (int64_t)A.npts) trace_point(A, g, lds_stack + threadIdx.x);
+}
+
+// Batched, persistent: the launched rays and the point reflectors of every
+// scene are cut into chunks of one workgroup; workgroups pull chunk indices
+// from a device counter until the queue is empty.  chunk_start[s] is the
+// first chunk of scene s (S + 1 entries); scene s's rays come before its
+// point reflectors.
+__global__ __launch_bounds__(RR_TRACE_BLOCK) void k_batch_trace(const TraceArgs *scenes,
+                                                                const int64_t *chunk_start, int S,
+                                                                unsigned long long *work)
+{
+    __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
+    __shared__ long long s_chunk;
+    const int64_t n_chunks = chunk_start[S];
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_chunk = (long long)atomicAdd(work, 1ull);
+        __syncthreads();
+        const int64_t ch = s_chunk;
+        if (ch >= n_chunks) break;
+        int lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (chunk_start[mid] <= ch) lo = mid; else hi = mid - 1;
+        }
+        const TraceArgs &A = scenes[lo];
+        const int64_t c = ch - chunk_start[lo];
+        const int64_t n_traced = A.n_src * A.n_per_src;
+        const int64_t ray_chunks = (n_traced + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
+        if (c < ray_chunks) {
+            const int64_t g = c * RR_TRACE_BLOCK + threadIdx.x;
+            if (g < n_traced) trace_ray(A, g, lds_stack + threadIdx.x);
+        } else {
+            const int64_t g = (c - ray_chunks) * RR_TRACE_BLOCK + threadIdx.x;
+            if (g < A.n_src * (int64_t)A.npts) trace_point(A, g, lds_stack + threadIdx.x);
+        }
+    }
 }
 
 // Scene code of the learned proposal: 16 azimuth sectors x 8 probe rays at
@@ -574,6 +620,19 @@ hipError_t launch_points(const TraceArgs &a, hipStream_t s)
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
     hipLaunchKernelGGL(k_points, dim3((unsigned)blocks), dim3(RR_TRACE_BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_trace(const TraceArgs *scenes, const int64_t *chunk_start, int S,
+                              int64_t n_chunks, unsigned long long *work, hipStream_t s)
+{
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t grid = std::min<int64_t>(n_chunks, (int64_t)cus * 16);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_trace, dim3((unsigned)grid), dim3(RR_TRACE_BLOCK), 0, s, scenes,
+                       chunk_start, S, work);
     return hipGetLastError();
 }
 

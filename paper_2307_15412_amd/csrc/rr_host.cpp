@@ -3,6 +3,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -892,6 +893,503 @@ int rr_proposal_build(rr_ctx *c, const float *code16, float beta)
     HIPCHK(launch_build_cdf(c->mlp_z.as<const float>(), beta, c->cdf.as<double>(), c->stream));
     c->n_az = RR_PROP_NAZ;
     c->n_el = RR_PROP_NEL;
+    return RR_OK;
+}
+
+// --------------------------------------------------------------------------
+// batched launch
+// --------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+struct BatchScene {
+    bool set = false;
+    int64_t n_tris = 0;
+    int nobj = 0, npts = 0, ntx = 0, nrx = 0, mode = 0;
+    double rx_radius = 0.25, oT[3] = {0, 0, 0}, oR[3] = {0, 0, 0};
+    DevBuf nodes, ltris, obj_alpha, obj_vel, pt_pos, pt_vel, pt_ap, tx, rx;
+    rr_chirp chirp{};
+    rr_trace_params tp{};
+    int64_t n_src = 0, n_per_src = 0, n_vps = 0, V = 0;
+    int kr = 0;
+    void release()
+    {
+        DevBuf *b[] = {&nodes, &ltris, &obj_alpha, &obj_vel, &pt_pos, &pt_vel, &pt_ap, &tx, &rx};
+        for (DevBuf *x : b) x->release();
+    }
+};
+
+int largest_kr(int K, int limit)
+{
+    int kr = limit;
+    while (kr > 1 && (K % kr != 0 || K / kr > 256)) kr >>= 1;
+    return (K / kr > 256) ? 0 : kr;
+}
+
+}  // namespace
+
+struct rr_batch {
+    rr_ctx *c = nullptr;
+    int S = 0;
+    std::vector<BatchScene> sc;
+    hipStream_t st = nullptr;
+    hipEvent_t ev[6] = {};
+    DevBuf d_targs, d_sargs, d_info, d_chunk, d_items, d_vr, d_vel, d_rinfo, d_ranges;
+    DevBuf counts, offsets, bsums, total, counter, work;
+    PathStore tmp, fin;
+    DevBuf syn;
+    int64_t cap = 0, V_total = 0, n_chunks = 0, n_items = 0, n_ranges = 0, nb = 0;
+    std::vector<int64_t> range_base;
+    std::vector<void *> cubes;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool dirty = true;
+    float ms_trace = 0, ms_synth = 0, ms_total = 0;   // stages: last eager run; total: last launch
+    int64_t last_total = 0;
+};
+
+namespace {
+
+void batch_drop_graph(rr_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->dirty = true;
+}
+
+// per-scene tables and global buffers for the current scene set and cubes
+int batch_prepare(rr_batch *b)
+{
+    const int S = b->S;
+    std::vector<TraceArgs> ta(S);
+    std::vector<SynthArgs> sa(S);
+    std::vector<BatchSynthInfo> info(S);
+    std::vector<BatchVel> vel(S);
+    std::vector<BatchRangeInfo> ri(S);
+    std::vector<int64_t> chunk(S + 1, 0), items(S + 1, 0), vr(S + 1, 0);
+    b->range_base.assign(S + 1, 0);
+    int64_t V = 0, est = 0;
+    for (int s = 0; s < S; s++) {
+        BatchScene &x = b->sc[s];
+        if (!x.set) return fail(RR_ESTATE, "batch slot %d is empty", s);
+        const int shared = x.mode == RR_TX_SHARED;
+        x.n_src = shared ? 1 : x.ntx;
+        x.n_per_src = shared ? x.tp.n_rays : x.tp.n_rays / x.ntx;
+        x.n_vps = x.n_per_src + x.npts;
+        x.V = x.n_src * x.n_vps;
+        vr[s] = V;
+        V += x.V;
+        est += x.n_src * x.n_per_src / 16 + x.n_src * x.npts;
+        const int64_t rchunks = (x.n_src * x.n_per_src + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
+        const int64_t pchunks = (x.n_src * x.npts + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
+        chunk[s + 1] = chunk[s] + rchunks + pchunks;
+        const int K = x.chirp.n_samples, M = x.chirp.n_chirps;
+        if (x.kr <= 0) x.kr = largest_kr(K, 32);
+        if (x.kr <= 0) return fail(RR_EUNSUPPORTED, "scene %d: n_samples too large", s);
+        const int n_groups = shared ? 1 : x.ntx;
+        const int RC = shared ? x.ntx * x.nrx : x.nrx;
+        const int rows = RC * M;
+        const int RPB = 256 / (K / x.kr);
+        info[s].kr = x.kr;
+        info[s].rows_per_group = rows;
+        info[s].rc = RC;
+        info[s].bpg = (rows + RPB - 1) / RPB;
+        items[s + 1] = items[s] + (int64_t)info[s].bpg * n_groups;
+        b->range_base[s + 1] = b->range_base[s] + (shared ? 2 : n_groups + 1);
+    }
+    vr[S] = V;
+    if (V >= (int64_t(1) << 32)) return fail(RR_EUNSUPPORTED, "too many rays in the batch");
+    if (b->cap == 0) b->cap = std::max<int64_t>(65536, est);
+    b->V_total = V;
+    b->n_chunks = chunk[S];
+    b->n_items = items[S];
+    b->n_ranges = b->range_base[S];
+    b->nb = scan_u8_blocks(V);
+    int rc;
+    if ((rc = b->counts.ensure((size_t)V + 64))) return rc;
+    if ((rc = b->offsets.ensure((size_t)V * 4 + 64))) return rc;
+    if ((rc = b->bsums.ensure((size_t)(b->nb + 1) * 4))) return rc;
+    if ((rc = b->total.ensure(256))) return rc;
+    if ((rc = b->counter.ensure(256))) return rc;
+    if ((rc = b->work.ensure(256))) return rc;
+    if ((rc = b->tmp.alloc(b->cap))) return rc;
+    if ((rc = b->fin.alloc(b->cap))) return rc;
+    if ((rc = b->syn.ensure((size_t)b->cap * sizeof(SynPath)))) return rc;
+    if ((rc = b->d_targs.ensure(sizeof(TraceArgs) * S))) return rc;
+    if ((rc = b->d_sargs.ensure(sizeof(SynthArgs) * S))) return rc;
+    if ((rc = b->d_info.ensure(sizeof(BatchSynthInfo) * S))) return rc;
+    if ((rc = b->d_vel.ensure(sizeof(BatchVel) * S))) return rc;
+    if ((rc = b->d_rinfo.ensure(sizeof(BatchRangeInfo) * S))) return rc;
+    if ((rc = b->d_chunk.ensure(8 * (S + 1)))) return rc;
+    if ((rc = b->d_items.ensure(8 * (S + 1)))) return rc;
+    if ((rc = b->d_vr.ensure(8 * (S + 1)))) return rc;
+    if ((rc = b->d_ranges.ensure(8 * (b->n_ranges + 1)))) return rc;
+    const double INV_2PI = 0.15915494309189535;
+    for (int s = 0; s < S; s++) {
+        BatchScene &x = b->sc[s];
+        TraceArgs &A = ta[s];
+        A = TraceArgs{};
+        A.nodes = x.nodes.as<const float4>();
+        A.ltris = x.ltris.as<const float4>();
+        A.has_bvh = x.n_tris > 0;
+        A.obj_alpha = x.obj_alpha.as<const float>();
+        A.tx = x.tx.as<const double>();
+        A.pt_pos = x.pt_pos.as<const double>();
+        A.pt_ap = x.pt_ap.as<const double>();
+        for (int a = 0; a < 3; a++) {
+            A.oT[a] = x.oT[a];
+            A.oR[a] = x.oR[a];
+        }
+        A.r2 = x.rx_radius * x.rx_radius;
+        A.shared = x.mode == RR_TX_SHARED;
+        A.nobj = x.nobj;
+        A.npts = x.npts;
+        A.n_src = x.n_src;
+        A.n_per_src = x.n_per_src;
+        A.n_virt_per_src = x.n_vps;
+        A.at = x.tp.az_min * INV_2PI;
+        A.bt = x.tp.az_max * INV_2PI;
+        A.slo = std::sin(x.tp.el_min);
+        A.shi = std::sin(x.tp.el_max);
+        A.omega = (x.tp.az_max - x.tp.az_min) * (A.shi - A.slo);
+        A.bmax = x.tp.max_bounces;
+        A.seed = x.tp.seed;
+        A.sampler = RR_UNIFORM;
+        A.vbase = vr[s];
+        A.hits = nullptr;
+        A.counts = b->counts.as<uint8_t>();
+        A.tmp = b->tmp.soa;
+        A.counter = b->counter.as<unsigned long long>();
+        A.err_flag = b->c->err_flag.as<int>();
+        SynthArgs &Y = sa[s];
+        Y = SynthArgs{};
+        Y.paths = b->syn.as<const SynPath>();
+        Y.ranges = b->d_ranges.as<const int64_t>() + b->range_base[s];
+        Y.n_paths = 0;
+        Y.tx = x.tx.as<const double>();
+        Y.rx = x.rx.as<const double>();
+        Y.ntx = x.ntx;
+        Y.nrx = x.nrx;
+        for (int a = 0; a < 3; a++) {
+            Y.oT[a] = x.oT[a];
+            Y.oR[a] = x.oR[a];
+        }
+        Y.shared = x.mode == RR_TX_SHARED;
+        Y.model = RR_EXACT;
+        Y.f0 = x.chirp.f0;
+        Y.bw = x.chirp.bandwidth;
+        Y.t_rep = x.chirp.t_rep;
+        Y.inv_c = 1.0 / 299792458.0;
+        Y.M = x.chirp.n_chirps;
+        Y.K = x.chirp.n_samples;
+        Y.cube = static_cast<float2 *>(s < (int)b->cubes.size() ? b->cubes[s] : nullptr);
+        vel[s].obj_vel = x.obj_vel.as<const double>();
+        vel[s].pt_vel = x.pt_vel.as<const double>();
+        vel[s].nobj = x.nobj;
+        vel[s].npts = x.npts;
+        ri[s].vr0 = vr[s];
+        ri[s].n_vps = x.n_vps;
+        ri[s].base = b->range_base[s];
+        ri[s].n_groups = (int)x.n_src;
+        ri[s].shared = x.mode == RR_TX_SHARED;
+    }
+    hipStream_t st = b->st;
+    HIPCHK(hipMemcpyAsync(b->d_targs.p, ta.data(), sizeof(TraceArgs) * S, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->d_sargs.p, sa.data(), sizeof(SynthArgs) * S, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->d_info.p, info.data(), sizeof(BatchSynthInfo) * S, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->d_vel.p, vel.data(), sizeof(BatchVel) * S, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->d_rinfo.p, ri.data(), sizeof(BatchRangeInfo) * S, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->d_chunk.p, chunk.data(), 8 * (S + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->d_items.p, items.data(), 8 * (S + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->d_vr.p, vr.data(), 8 * (S + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return RR_OK;
+}
+
+// the trace stage: zero the queue and path counters (kernel fills, no
+// memset nodes), persistent trace, scan, scatter, synthesis records, ranges
+int batch_enqueue_trace(rr_batch *b, bool timed)
+{
+    hipStream_t st = b->st;
+    unsigned long long *work = b->work.as<unsigned long long>();
+    HIPCHK(launch_fill_u64(work, 2, 0ull, st));
+    HIPCHK(launch_fill_u64(b->counter.as<unsigned long long>(), 1, 0ull, st));
+    if (timed) HIPCHK(hipEventRecord(b->ev[0], st));
+    HIPCHK(launch_batch_trace(b->d_targs.as<const TraceArgs>(), b->d_chunk.as<const int64_t>(), b->S,
+                              b->n_chunks, work, st));
+    HIPCHK(launch_scan_u8(b->counts.as<const uint8_t>(), b->V_total, b->offsets.as<uint32_t>(),
+                          b->bsums.as<uint32_t>(), b->nb + 1, b->total.as<unsigned long long>(), st));
+    HIPCHK(launch_scatter(b->tmp.soa, b->counter.as<const unsigned long long>(), b->cap,
+                          b->offsets.as<const uint32_t>(), b->fin.soa, b->cap, st));
+    HIPCHK(launch_batch_prep(b->fin.soa, b->total.as<const unsigned long long>(), b->cap,
+                             b->d_vr.as<const int64_t>(), b->S, b->d_vel.as<const BatchVel>(),
+                             b->syn.as<SynPath>(), st));
+    HIPCHK(launch_batch_ranges(b->offsets.as<const uint32_t>(), b->V_total,
+                               b->total.as<const unsigned long long>(), b->cap,
+                               b->d_rinfo.as<const BatchRangeInfo>(), b->S, b->d_ranges.as<int64_t>(),
+                               st));
+    if (timed) HIPCHK(hipEventRecord(b->ev[1], st));
+    return RR_OK;
+}
+
+int batch_enqueue_synth(rr_batch *b, bool timed)
+{
+    hipStream_t st = b->st;
+    unsigned long long *work = b->work.as<unsigned long long>();
+    HIPCHK(launch_fill_u64(work + 1, 1, 0ull, st));
+    if (timed) HIPCHK(hipEventRecord(b->ev[2], st));
+    HIPCHK(launch_batch_synth(b->d_sargs.as<const SynthArgs>(), b->d_info.as<const BatchSynthInfo>(),
+                              b->d_items.as<const int64_t>(), b->S, b->n_items, work + 1, st));
+    if (timed) HIPCHK(hipEventRecord(b->ev[3], st));
+    return RR_OK;
+}
+
+int batch_check(rr_batch *b, bool *overflow)
+{
+    unsigned long long cnt = 0, tot = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, b->counter.p, 8, hipMemcpyDeviceToHost, b->st));
+    HIPCHK(hipMemcpyAsync(&tot, b->total.p, 8, hipMemcpyDeviceToHost, b->st));
+    HIPCHK(hipStreamSynchronize(b->st));
+    *overflow = (int64_t)cnt > b->cap;
+    if (*overflow) b->cap = (int64_t)cnt + (int64_t)cnt / 4 + 4096;
+    b->last_total = (int64_t)tot;
+    return RR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rr_batch_create(rr_ctx *c, int32_t n_scenes, rr_batch **out)
+{
+    if (!c || !out) return fail(RR_EINVAL, "NULL argument");
+    if (n_scenes < 1) return fail(RR_EINVAL, "n_scenes must be positive");
+    HIPCHK(hipSetDevice(c->device));
+    rr_batch *b = new rr_batch();
+    b->c = c;
+    b->S = n_scenes;
+    b->sc.resize(n_scenes);
+    if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return fail(RR_EHIP, "hipStreamCreate failed");
+    }
+    for (auto &e : b->ev) HIPCHK(hipEventCreate(&e));
+    *out = b;
+    return RR_OK;
+}
+
+void rr_batch_destroy(rr_batch *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->c->device);
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    batch_drop_graph(b);
+    for (auto &x : b->sc) x.release();
+    DevBuf *bufs[] = {&b->d_targs, &b->d_sargs, &b->d_info, &b->d_chunk, &b->d_items, &b->d_vr,
+                      &b->d_vel, &b->d_rinfo, &b->d_ranges, &b->counts, &b->offsets, &b->bsums,
+                      &b->total, &b->counter, &b->work, &b->syn, &b->tmp.buf, &b->fin.buf};
+    for (DevBuf *x : bufs) x->release();
+    for (auto &e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->st) (void)hipStreamDestroy(b->st);
+    delete b;
+}
+
+int rr_batch_set_scene(rr_batch *b, int32_t slot, const float *verts, int64_t n_verts,
+                       const int32_t *tris, const int32_t *tri_obj, int64_t n_tris,
+                       const float *obj_alpha, const double *obj_vel, int32_t n_obj,
+                       const double *pt_pos, const double *pt_vel, const double *pt_aperture,
+                       int32_t n_pts, const double *tx, int32_t n_tx, const double *rx, int32_t n_rx,
+                       double rx_radius, int32_t tx_mode, const rr_chirp *chirp,
+                       const rr_trace_params *tp)
+{
+    if (!b || !chirp || !tp) return fail(RR_EINVAL, "NULL argument");
+    if (slot < 0 || slot >= b->S) return fail(RR_EINVAL, "slot out of range");
+    // validate through the single-scene entry points on a scratch check
+    if (n_verts < 0 || n_tris < 0 || n_obj < 1 || n_pts < 0)
+        return fail(RR_EINVAL, "negative size or no object");
+    if ((n_tris > 0 && (!verts || !tris || !tri_obj)) || !obj_alpha || !obj_vel ||
+        (n_pts > 0 && (!pt_pos || !pt_vel || !pt_aperture)) || !tx || !rx || n_tx < 1 || n_rx < 1)
+        return fail(RR_EINVAL, "NULL array");
+    for (int64_t i = 0; i < 3 * n_verts; i++)
+        if (!std::isfinite(verts[i])) return fail(RR_EINVAL, "non-finite vertex coordinate");
+    for (int64_t i = 0; i < n_tris; i++) {
+        for (int k = 0; k < 3; k++)
+            if (tris[3 * i + k] < 0 || tris[3 * i + k] >= n_verts)
+                return fail(RR_EINVAL, "triangle vertex index out of range");
+        if (tri_obj[i] < 0 || tri_obj[i] >= n_obj) return fail(RR_EINVAL, "triangle object out of range");
+    }
+    for (int i = 0; i < n_obj; i++)
+        if (!(obj_alpha[i] >= 0.0f && obj_alpha[i] <= 1.0f)) return fail(RR_EINVAL, "alpha outside [0, 1]");
+    if (!finite3(obj_vel, n_obj) || (n_pts > 0 && (!finite3(pt_pos, n_pts) || !finite3(pt_vel, n_pts))) ||
+        !finite3(tx, n_tx) || !finite3(rx, n_rx))
+        return fail(RR_EINVAL, "non-finite input");
+    if (!(rx_radius > 0.0) || (tx_mode != RR_TX_PER_ELEMENT && tx_mode != RR_TX_SHARED))
+        return fail(RR_EINVAL, "invalid array");
+    if (!(chirp->f0 > 0.0) || !(chirp->bandwidth >= 0.0) || !(chirp->t_chirp > 0.0) ||
+        !(chirp->t_rep >= 0.0) || chirp->n_samples < 1 || chirp->n_chirps < 1)
+        return fail(RR_EINVAL, "degenerate chirp");
+    if (tp->max_bounces < 1 || tp->max_bounces > RR_KMAX || tp->n_rays < 0 ||
+        !(tp->az_max > tp->az_min) || !(tp->el_max > tp->el_min) || tp->sampler != RR_UNIFORM)
+        return fail(RR_EINVAL, "invalid trace parameters (batched traces use the uniform sampler)");
+    if (largest_kr(chirp->n_samples, 32) <= 0) return fail(RR_EUNSUPPORTED, "n_samples too large");
+    HIPCHK(hipSetDevice(b->c->device));
+    HIPCHK(hipStreamSynchronize(b->st));
+    HostBvh bvh;
+    std::string err;
+    int rc = rr_build_bvh(verts, n_verts, tris, tri_obj, n_tris, bvh, err);
+    if (rc) return fail(rc, "BVH build: %s", err.c_str());
+    BatchScene &x = b->sc[slot];
+    if ((rc = x.nodes.ensure(bvh.nodes.size() * 4 + 64))) return rc;
+    if ((rc = x.ltris.ensure(bvh.tris.size() * 4 + 64))) return rc;
+    if ((rc = x.obj_alpha.ensure((size_t)n_obj * 4))) return rc;
+    if ((rc = x.obj_vel.ensure((size_t)n_obj * 24))) return rc;
+    if ((rc = x.pt_pos.ensure((size_t)n_pts * 24 + 8))) return rc;
+    if ((rc = x.pt_vel.ensure((size_t)n_pts * 24 + 8))) return rc;
+    if ((rc = x.pt_ap.ensure((size_t)n_pts * 8 + 8))) return rc;
+    if ((rc = x.tx.ensure((size_t)n_tx * 24))) return rc;
+    if ((rc = x.rx.ensure((size_t)n_rx * 24))) return rc;
+    if (!bvh.nodes.empty()) HIPCHK(hipMemcpy(x.nodes.p, bvh.nodes.data(), bvh.nodes.size() * 4, hipMemcpyHostToDevice));
+    if (!bvh.tris.empty()) HIPCHK(hipMemcpy(x.ltris.p, bvh.tris.data(), bvh.tris.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(x.obj_alpha.p, obj_alpha, (size_t)n_obj * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(x.obj_vel.p, obj_vel, (size_t)n_obj * 24, hipMemcpyHostToDevice));
+    if (n_pts > 0) {
+        HIPCHK(hipMemcpy(x.pt_pos.p, pt_pos, (size_t)n_pts * 24, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(x.pt_vel.p, pt_vel, (size_t)n_pts * 24, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(x.pt_ap.p, pt_aperture, (size_t)n_pts * 8, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(x.tx.p, tx, (size_t)n_tx * 24, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(x.rx.p, rx, (size_t)n_rx * 24, hipMemcpyHostToDevice));
+    for (int a = 0; a < 3; a++) {
+        double st = 0.0, sr = 0.0;
+        for (int i = 0; i < n_tx; i++) st += tx[3 * i + a];
+        for (int i = 0; i < n_rx; i++) sr += rx[3 * i + a];
+        x.oT[a] = st / (double)n_tx;
+        x.oR[a] = sr / (double)n_rx;
+    }
+    x.n_tris = n_tris;
+    x.nobj = n_obj;
+    x.npts = n_pts;
+    x.ntx = n_tx;
+    x.nrx = n_rx;
+    x.mode = tx_mode;
+    x.rx_radius = rx_radius;
+    x.chirp = *chirp;
+    x.tp = *tp;
+    x.kr = 0;
+    x.set = true;
+    batch_drop_graph(b);
+    return RR_OK;
+}
+
+int rr_batch_launch(rr_batch *b, void *const *cubes, int64_t *n_paths_out)
+{
+    if (!b || !cubes) return fail(RR_EINVAL, "NULL argument");
+    for (int s = 0; s < b->S; s++)
+        if (!cubes[s]) return fail(RR_EINVAL, "cube %d is NULL", s);
+    rr_ctx *c = b->c;
+    HIPCHK(hipSetDevice(c->device));
+    bool new_cubes = b->cubes.size() != (size_t)b->S ||
+                     !std::equal(b->cubes.begin(), b->cubes.end(), cubes);
+    b->cubes.assign(cubes, cubes + b->S);
+    for (int attempt = 0; attempt < 3; attempt++) {
+        if (b->dirty || new_cubes) {
+            int rc = batch_prepare(b);
+            if (rc) return rc;
+            new_cubes = false;
+        }
+        if (b->dirty) {
+            // capture the whole pipeline once; later launches replay it
+            batch_drop_graph(b);
+            HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+            int rc = batch_enqueue_trace(b, false);
+            if (!rc) rc = batch_enqueue_synth(b, false);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->st, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            HIPCHK(e);
+            b->graph = g;
+            HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->dirty = false;
+        }
+        HIPCHK(hipEventRecord(b->ev[4], c->stream));
+        HIPCHK(hipStreamWaitEvent(b->st, b->ev[4], 0));
+        HIPCHK(hipEventRecord(b->ev[0], b->st));
+        HIPCHK(hipGraphLaunch(b->exec, b->st));
+        HIPCHK(hipEventRecord(b->ev[5], b->st));
+        HIPCHK(hipStreamWaitEvent(c->stream, b->ev[5], 0));
+        bool overflow = false;
+        int rc = batch_check(b, &overflow);
+        if (rc) return rc;
+        if (!overflow) break;
+        b->dirty = true;
+        if (attempt == 2) return fail(RR_EOVERFLOW, "batched path pool overflow persisted");
+    }
+    HIPCHK(hipEventElapsedTime(&b->ms_total, b->ev[0], b->ev[5]));
+    if (n_paths_out) {
+        std::vector<int64_t> r(b->n_ranges + 1);
+        HIPCHK(hipMemcpy(r.data(), b->d_ranges.p, 8 * b->n_ranges, hipMemcpyDeviceToHost));
+        for (int s = 0; s < b->S; s++) {
+            const int64_t lo = r[b->range_base[s]], hi = r[b->range_base[s + 1] - 1];
+            n_paths_out[s] = hi - lo;
+        }
+    }
+    return RR_OK;
+}
+
+int rr_batch_tune(rr_batch *b, void *const *cubes)
+{
+    if (!b || !cubes) return fail(RR_EINVAL, "NULL argument");
+    int rc = rr_batch_launch(b, cubes, nullptr);   // paths for the synthesis candidates
+    if (rc) return rc;
+    std::vector<int> Ks;
+    for (auto &x : b->sc)
+        if (std::find(Ks.begin(), Ks.end(), x.chirp.n_samples) == Ks.end()) Ks.push_back(x.chirp.n_samples);
+    for (int K : Ks) {
+        float best_ms = 3.0e38f;
+        int best = 0;
+        for (int cand : {32, 16, 8, 4}) {
+            if (K % cand != 0 || K / cand > 256) continue;
+            for (auto &x : b->sc)
+                if (x.chirp.n_samples == K) x.kr = cand;
+            if ((rc = batch_prepare(b))) return rc;
+            // the candidate runs eagerly on the paths of the last launch
+            if ((rc = batch_enqueue_synth(b, true))) return rc;
+            HIPCHK(hipStreamSynchronize(b->st));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, b->ev[2], b->ev[3]));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+        }
+        for (auto &x : b->sc)
+            if (x.chirp.n_samples == K) x.kr = best;
+    }
+    batch_drop_graph(b);
+    return RR_OK;
+}
+
+int rr_batch_get_tiles(rr_batch *b, int32_t *kr_out)
+{
+    if (!b || !kr_out) return fail(RR_EINVAL, "NULL argument");
+    for (int s = 0; s < b->S; s++) kr_out[s] = b->sc[s].kr;
+    return RR_OK;
+}
+
+int rr_batch_stats(rr_batch *b, double *ms_total, double *ms_synth, int64_t *total_paths)
+{
+    if (!b) return fail(RR_EINVAL, "NULL argument");
+    if (ms_total) *ms_total = b->ms_total;
+    if (ms_synth) *ms_synth = b->ms_synth;
+    if (total_paths) *total_paths = b->last_total;
     return RR_OK;
 }
 

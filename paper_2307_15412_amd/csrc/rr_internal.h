@@ -70,9 +70,10 @@ struct TraceArgs {
     int sampler;
     const double *cdf;
     int n_az, n_el;
+    int64_t vbase;            // first virtual ray of this scene in the (batched) ray space
     // outputs
     int32_t *hits;            // [n_src*n_per_src][bmax+1] or null
-    uint8_t *counts;          // [n_src*n_virt_per_src]
+    uint8_t *counts;          // indexed by vbase + virtual ray
     PathSoA tmp;
     unsigned long long *counter;
     int *err_flag;
@@ -101,6 +102,26 @@ struct SynthArgs {
     double f0, bw, t_rep, inv_c;
     int M, K;
     float2 *cube;
+};
+
+// batched launch: per-scene tables read by the persistent kernels
+struct BatchSynthInfo {
+    int kr;                   // samples per lane (tile shape)
+    int rows_per_group;
+    int rc;                   // channels per group
+    int bpg;                  // workgroups per group
+};
+struct BatchVel {
+    const double *obj_vel;
+    const double *pt_vel;
+    int nobj, npts;
+};
+struct BatchRangeInfo {
+    int64_t vr0;              // first virtual ray of the scene
+    int64_t n_vps;            // virtual rays per source
+    int64_t base;             // first entry of the scene in the ranges table
+    int n_groups;
+    int shared;
 };
 
 // launchers (defined in the .hip files)
@@ -147,3 +168,15 @@ hipError_t launch_mlp_backward(const float *P, const float *dz, int64_t n, const
                                hipStream_t s);
 hipError_t launch_adam(float *P, const float *G, float *m, float *v, float lr, int step, hipStream_t s);
 hipError_t launch_build_cdf(const float *z, float beta, double *cdf, hipStream_t s);
+hipError_t launch_batch_trace(const TraceArgs *scenes, const int64_t *chunk_start, int S,
+                              int64_t n_chunks, unsigned long long *work, hipStream_t s);
+hipError_t launch_batch_synth(const SynthArgs *scenes, const BatchSynthInfo *info,
+                              const int64_t *item_start, int S, int64_t n_items,
+                              unsigned long long *work, hipStream_t s);
+hipError_t launch_batch_prep(const PathSoA &paths, const unsigned long long *total, int64_t cap,
+                             const int64_t *vr_start, int S, const BatchVel *vel, SynPath *out,
+                             hipStream_t s);
+hipError_t launch_batch_ranges(const uint32_t *offsets, int64_t V, const unsigned long long *total,
+                               int64_t cap, const BatchRangeInfo *ri, int S, int64_t *ranges,
+                               hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
