@@ -44,7 +44,86 @@ def parse():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle rel-err check")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (hardware-counter calibration)")
+    ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--workload", choices=["large_mimo", "batch", "proposal"], default="large_mimo",
+                    help="large_mimo (default): the benchmarked step; batch: 64 uneven scenes in "
+                         "one captured launch; proposal: learned-proposal training and gain")
     return ap.parse_args()
+
+
+def run_batch(args):
+    """64 procedural scenes (1e4-1e6 triangles, 4-3072 channels, 128-512
+    samples, 64-256 chirps, 1e6 rays each, 3 bounces) traced and synthesised
+    (exact model, FP32 cubes) by one captured launch after autotuning."""
+    import torch
+    import scenegen as sg
+    import paper_2307_15412_amd as rr
+    log = lambda m: print(f"[batch] {m}", file=sys.stderr, flush=True)
+    t0 = time.time()
+    ws = sg.workload_batch(n_scenes=args.batch_scenes, seed0=2000, rays=1_000_000)
+    gen_s = time.time() - t0
+    log(f"generated {len(ws)} scenes in {gen_s:.1f} s")
+    ctx = rr.Context(0)
+    B = rr.Batch(ctx, len(ws))
+    t0 = time.time()
+    for i, w in enumerate(ws):
+        B.set_workload(i, w)
+        if i % 8 == 7:
+            log(f"uploaded {i + 1} scenes")
+    upload_s = time.time() - t0
+    cubes = B.alloc_cubes()
+    t0 = time.time()
+    tiles = B.tune(cubes)
+    log(f"autotune {time.time() - t0:.1f} s, tiles {sorted(set(tiles.tolist()))}")
+    for _ in range(args.warmup):
+        B.launch(cubes, want_counts=False)
+        log("warmup launch done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts = B.launch(cubes)
+        log("timed launch done")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ps = sum(float(n) * np.prod(s) for n, s in zip(counts, B.shapes))
+    rays = sum(w.trace.n_rays for w in ws)
+    print(json.dumps({
+        "metric": "batched Gpath-samples/s (64 uneven scenes, one captured launch)",
+        "value": ps / dt / 1e9, "unit": "Gpath-samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "dtype": "f64-phase/f32", "data": "synthetic (procedural streets, seeded)",
+        "config": {"workload": f"batch: {len(ws)} streets, 1e4-1e6 tris, 4-3072 ch, 128-512 samples, "
+                               "64-256 chirps, 1e6 rays each, <=3 bounces, exact model"},
+        "scenes": len(ws), "rays": rays, "paths": int(np.sum(counts)),
+        "cube_gb": sum(np.prod(s) for s in B.shapes) * 8 / 1e9,
+        "mrays_per_s_incl_synth": rays / dt / 1e6, "tiles": tiles.tolist(),
+        "scene_gen_s": gen_s, "bvh_upload_s": upload_s, "graph_ms": B.stats()["ms_total"]}))
+
+
+def run_proposal(args):
+    """Learned proposal: train on 200 scenes x 5e4 uniform rays, evaluate 50
+    held-out scenes at 1.25e4 rays (1/8 of the 1e5 uniform budget) against a
+    1e5-ray uniform cube and a 1e6-ray uniform reference."""
+    import paper_2307_15412_amd as rr
+    from paper_2307_15412_amd import proposal
+    ctx = rr.Context(0)
+    out = {}
+    log = lambda m: print(f"[proposal] {m}", file=sys.stderr, flush=True)
+    for ref_rays in (100_000, 1_000_000):
+        res = proposal.experiment(ctx, train_seeds=range(1, 201), eval_seeds=range(1001, 1051),
+                                  train_rays=50_000, budget=12_500, ref_rays=ref_rays, steps=600,
+                                  batch=16, lr=2e-3, log=log)
+        log(f"reference {ref_rays}: done")
+        out[f"ref_{ref_rays}"] = {k: v for k, v in res.items() if k != "per_scene"}
+    r = out["ref_1000000"]
+    ratio = r["err_learned_mean"] / r["err_uniform_mean"]
+    print(json.dumps({
+        "metric": "learned-proposal cube error / uniform cube error at 1.25e4 rays (lower is better)",
+        "value": ratio, "unit": "ratio", "higher_is_better": False, "n_gpus": 1,
+        "equal_error_ray_saving": 1.0 / (ratio * ratio),
+        "config": {"workload": "box family: 200 training scenes x 5e4 rays, 50 held-out scenes, "
+                               "1.25e4 rays vs 1e5 / 1e6-ray uniform references, beta 0.1"},
+        "results": out}))
 
 
 def copy_calibration():
@@ -100,6 +179,12 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        run_batch(args)
+        return
+    if args.workload == "proposal":
+        run_proposal(args)
+        return
     import torch
     import scenegen as sg
     import paper_2307_15412_amd as rr
@@ -122,12 +207,9 @@ def main():
         return n
 
     if engine == rr.ENGINE_AUTO:
-        try:
-            step()
-        except rr.RadrayError as e:
-            if e.code != rr.binding.RR_EUNSUPPORTED:
-                raise
-            engine = rr.DIRECT_FP32
+        # the library's own choice for the separable model: the GEMM engine
+        # whenever the sample count tiles by 128
+        engine = rr.GEMM_BF16X3 if K % 128 == 0 else rr.DIRECT_FP32
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

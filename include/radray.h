@@ -284,9 +284,12 @@ int rr_batch_set_scene(rr_batch *batch, int32_t slot, const float *verts, int64_
  * int64 [n_scenes], may be NULL) receives each scene's path count. */
 int rr_batch_launch(rr_batch *batch, void *const *cubes, int64_t *n_paths_out);
 
-/* Autotune the synthesis tile: for every distinct sample count, time each
- * candidate samples-per-lane value on the batch and keep the fastest.  Runs
- * the batch into `cubes`.  rr_batch_get_tiles reports the choice per scene. */
+/* Autotune the synthesis tile: run the batch once into `cubes` for its paths,
+ * then for every distinct sample count time each candidate samples-per-lane
+ * value on the scenes with that count, over at most the first 2048 paths of
+ * each path group (synthesis time is linear in the path count), and keep the
+ * fastest.  Afterwards the cubes hold partial sums: run rr_batch_launch to
+ * fill them.  rr_batch_get_tiles reports the choice per scene. */
 int rr_batch_tune(rr_batch *batch, void *const *cubes);
 int rr_batch_get_tiles(rr_batch *batch, int32_t *samples_per_lane_out);
 

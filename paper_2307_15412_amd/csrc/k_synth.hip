@@ -95,7 +95,8 @@ __device__ void synth_block(const SynthArgs &A, int g, int rb, int rows_per_grou
     float are[KR], aim[KR];
 #pragma unroll
     for (int k = 0; k < KR; k++) { are[k] = 0.0f; aim[k] = 0.0f; }
-    const int64_t p0 = A.ranges[g], p1 = A.ranges[g + 1];
+    const int64_t p0 = A.ranges[g];
+    const int64_t p1 = A.p_limit > 0 ? min(A.ranges[g + 1], p0 + A.p_limit) : A.ranges[g + 1];
     for (int64_t base = p0; base < p1; base += SYN_CHUNK) {
         const int cnt = (int)min((int64_t)SYN_CHUNK, p1 - base);
         __syncthreads();

@@ -961,8 +961,10 @@ void batch_drop_graph(rr_batch *b)
     b->dirty = true;
 }
 
-// per-scene tables and global buffers for the current scene set and cubes
-int batch_prepare(rr_batch *b)
+// per-scene tables and global buffers for the current scene set and cubes;
+// only_K > 0 gives synthesis work to the scenes with that sample count alone
+// and p_limit > 0 caps the paths of each group (both for tile timing)
+int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0)
 {
     const int S = b->S;
     std::vector<TraceArgs> ta(S);
@@ -998,7 +1000,8 @@ int batch_prepare(rr_batch *b)
         info[s].rows_per_group = rows;
         info[s].rc = RC;
         info[s].bpg = (rows + RPB - 1) / RPB;
-        items[s + 1] = items[s] + (int64_t)info[s].bpg * n_groups;
+        const bool synth = only_K <= 0 || K == only_K;
+        items[s + 1] = items[s] + (synth ? (int64_t)info[s].bpg * n_groups : 0);
         b->range_base[s + 1] = b->range_base[s] + (shared ? 2 : n_groups + 1);
     }
     vr[S] = V;
@@ -1087,6 +1090,7 @@ int batch_prepare(rr_batch *b)
         Y.M = x.chirp.n_chirps;
         Y.K = x.chirp.n_samples;
         Y.cube = static_cast<float2 *>(s < (int)b->cubes.size() ? b->cubes[s] : nullptr);
+        Y.p_limit = p_limit;
         vel[s].obj_vel = x.obj_vel.as<const double>();
         vel[s].pt_vel = x.pt_vel.as<const double>();
         vel[s].nobj = x.nobj;
@@ -1344,6 +1348,9 @@ int rr_batch_launch(rr_batch *b, void *const *cubes, int64_t *n_paths_out)
     return RR_OK;
 }
 
+// paths per group timed for each tile candidate
+static const int64_t TUNE_PATHS = 2048;
+
 int rr_batch_tune(rr_batch *b, void *const *cubes)
 {
     if (!b || !cubes) return fail(RR_EINVAL, "NULL argument");
@@ -1359,8 +1366,10 @@ int rr_batch_tune(rr_batch *b, void *const *cubes)
             if (K % cand != 0 || K / cand > 256) continue;
             for (auto &x : b->sc)
                 if (x.chirp.n_samples == K) x.kr = cand;
-            if ((rc = batch_prepare(b))) return rc;
-            // the candidate runs eagerly on the paths of the last launch
+            // the candidate runs eagerly on a bounded prefix of the paths of
+            // the last launch (time is linear in the path count), for the
+            // scenes with this sample count only
+            if ((rc = batch_prepare(b, K, TUNE_PATHS))) return rc;
             if ((rc = batch_enqueue_synth(b, true))) return rc;
             HIPCHK(hipStreamSynchronize(b->st));
             float ms = 0.0f;

@@ -102,6 +102,7 @@ struct SynthArgs {
     double f0, bw, t_rep, inv_c;
     int M, K;
     float2 *cube;
+    int64_t p_limit;          // > 0: at most this many paths of each group (tile timing only)
 };
 
 // batched launch: per-scene tables read by the persistent kernels

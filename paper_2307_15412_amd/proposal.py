@@ -84,10 +84,14 @@ def experiment(ctx, train_seeds, eval_seeds, train_rays=50_000, budget=12_500, r
     tw = [sg.workload_box_family(s, train_rays, points=False) for s in train_seeds]
     codes, hists = collect(ctx, tw)
     t1 = time.time()
+    if log:
+        log(f"collected {len(tw)} training scenes in {t1 - t0:.1f} s")
     losses = train(ctx, codes, hists, steps=steps, batch=batch, lr=lr, log=log)
     t2 = time.time()
     ew = [sg.workload_box_family(s, budget, points=False) for s in eval_seeds]
     res = evaluate(ctx, ew, budget, ref_rays, beta)
+    if log:
+        log(f"evaluated {len(res)} held-out scenes in {time.time() - t2:.1f} s")
     eu = np.array([r["err_uniform"] for r in res])
     el = np.array([r["err_learned"] for r in res])
     return dict(collect_s=t1 - t0, train_s=t2 - t1, loss_first=losses[0], loss_last=losses[-1],
