@@ -192,7 +192,8 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
  *          when non-NULL only these entries are computed, into
  *          cube_dev[0..n_sample) (direct engine, FP64-reduced phase).
  * Errors: RR_ESTATE (no paths/array/chirp), RR_EINVAL, RR_EUNSUPPORTED
- * (GEMM engine with the exact model). */
+ * (GEMM engine with the exact model, with sample_idx_dev, or with n_samples
+ * not a multiple of 64; RR_ENGINE_AUTO then picks the direct engine). */
 int rr_synthesize(rr_ctx *ctx, int32_t model, int32_t engine, void *cube_dev, int64_t cube_elems,
                   const int64_t *sample_idx_dev, int64_t n_sample);
 

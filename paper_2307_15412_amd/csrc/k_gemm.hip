@@ -17,8 +17,8 @@
 // B (paths x samples, up to 1.3e10 entries) is never stored: each workgroup
 // generates its 16 x 128 tile per step into LDS from two 32-bit fixed-point
 // phases per (path, chirp) -- start phase beta and per-sample step gamma,
-// exact modulo 2^32 in integer arithmetic -- one hardware sin/cos per lane
-// and complex rotations by a precomputed exp(-j 2 pi 32 gamma).
+// exact modulo 2^32 in integer arithmetic -- one hardware sin/cos per path
+// and lane and complex rotations by a precomputed exp(-j 2 pi 32 gamma).
 #include "rr_internal.h"
 
 namespace {
@@ -26,11 +26,21 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-#define GM_TM 256          // output rows (channels) per workgroup
-#define GM_TN 128          // output columns (chirp, sample) per workgroup
+#ifndef GM_TM
+#define GM_TM 512          // output rows (channels) per workgroup
+#endif
+#ifndef GM_TN
+#define GM_TN 64           // output columns (chirp, sample) per workgroup
+#endif
 #define GM_KS 16           // paths per MFMA step
-#define GM_THREADS 512     // 8 wavefronts: 4 (rows) x 2 (columns), 64 x 64 each
+#define GM_THREADS 256     // 4 wavefronts, one per SIMD, 128 x 64 each
+#define GM_WR 4            // 32-row blocks per wavefront
+#define GM_WC 2            // 32-column blocks per wavefront
+#define GM_NCB (GM_TN / 32)             // column blocks per tile
+#define GM_WAVES_C (GM_NCB / GM_WC)     // wavefronts across the columns
+static_assert((GM_TM / 32 / GM_WR) * GM_WAVES_C == GM_THREADS / 64, "wavefront grid");
 #define BFRAG_U4 72        // one B fragment in LDS: 64 lanes + 8 padding (uint4 units)
+
 
 __device__ __forceinline__ double dist3(const double *a, const double *b)
 {
@@ -138,7 +148,7 @@ __global__ void k_prep_a(const float2 *T, const float2 *R, int nrx, int C, int R
 }
 
 // Per (chirp m, path p): beta = frac(f0 D / c), gamma = frac(B D / (K c)) as
-// 32-bit fixed point, and exp(-j 2 pi 64 gamma) for the column rotation.
+// 32-bit fixed point, and exp(-j 2 pi 32 gamma) for the column rotation.
 __global__ void k_prep_b(SynthArgs A, int Ppad, uint4 *Bp)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,36 +176,63 @@ __global__ void k_prep_b(SynthArgs A, int Ppad, uint4 *Bp)
         const double two32 = 4294967296.0;
         out.x = (unsigned)(unsigned long long)llrint(beta * two32);
         out.y = (unsigned)(unsigned long long)llrint(gamma * two32);
-        float2 z = phasor64(64.0 * gamma);
+        float2 z = phasor64(32.0 * gamma);
         out.z = __float_as_uint(z.x);
         out.w = __float_as_uint(z.y);
     }
     Bp[i] = out;
 }
 
-__device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
-__device__ __forceinline__ uint4 neg_bf(uint4 v)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// (x, y) -> packed bf16 (x low, y high), round to nearest even
+__device__ __forceinline__ unsigned pack_bf16(float x, float y)
 {
-    return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
+    f32x2 v = {x, y};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
 }
+// hi = bf16(x, y); lo = bf16(x - hi.x, y - hi.y): x = hi + lo to ~16 bits
+__device__ __forceinline__ void split_bf16(float x, float y, unsigned &hi, unsigned &lo)
+{
+    hi = pack_bf16(x, y);
+    lo = pack_bf16(x - __uint_as_float(hi << 16), y - __uint_as_float(hi & 0xffff0000u));
+}
+
+__device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a), as_bf(b), c, 0, 0, 0)
 
+// One workgroup computes a 512 x 64 output tile with four wavefronts, one
+// per SIMD, stacked along the rows and each owning 128 x 64 (4 x 2 blocks of
+// 32 x 32, accumulators in the AGPR half of the register file).  Per 16-path
+// step a wavefront issues 96 MFMAs.  The tall tile shares each generated B
+// value among 512 rows and gives every A fragment to exactly one wavefront.
+//
+// A fragments go from global memory (L2) straight into registers: each is
+// one contiguous 1 KiB, and the fragments of row block i for step kb + 2 are
+// requested as soon as the MFMAs of row i of step kb have been issued, two
+// steps before they are needed (two register sets alternate).  Only B passes through LDS (two buffers):
+//   first half of step kb: MFMAs of rows 0-1, interleaved with the
+//     generation of B(kb + 1);
+//   barrier (B(kb + 1) complete);
+//   second half: MFMAs of rows 2-3 while the B fragments of step kb + 1 are
+//     read into registers.
 __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict__ Af,
                                                         const uint4 *__restrict__ Bp, int RB,
                                                         int KB, int Ppad, int C, int M, int K,
                                                         int n_col_tiles, float2 *__restrict__ cube)
 {
-    // A tile: two buffers x 8 row blocks x 4 planes x 64 lanes (uint4 = 8 bf16).
-    // B tile: two buffers x 4 planes x 4 column blocks, each fragment 64 lanes
-    // x 16 B with 128 B of padding after lane 31, so that the generator's
-    // 32-bit writes of both lane halves land in distinct banks.
-    __shared__ uint4 As[2][GM_TM / 32][4][64];
-    __shared__ uint4 Bs[2 * 4 * 4 * BFRAG_U4];
+    // B: two buffers x 4 planes (re_hi, re_lo, im_hi, im_lo) x column blocks,
+    // each fragment 64 lanes x 16 B with 128 B of padding after lane 31, so
+    // that the generator's 32-bit writes of both lane halves land in distinct
+    // banks.
+    __shared__ uint4 Bs[2][4 * GM_NCB * BFRAG_U4];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int w = tid >> 6;
-    const int wr = w >> 1, wc = w & 1;
+    // wavefront index, uniform by construction (kept in scalar registers)
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = w / GM_WAVES_C, wc = w % GM_WAVES_C;
     // XCD-aware order: workgroup b runs on XCD b % 8; each XCD walks its own
     // contiguous run of (row tile, column tile) pairs, row tile slowest, so
     // the workgroups resident on one XCD share A through that XCD's L2.
@@ -206,23 +243,22 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
     const int rt = (int)(q / n_col_tiles);
     const int ct = (int)(q - (int64_t)rt * n_col_tiles);
     const int64_t N = (int64_t)M * K;
-    const int rb0 = rt * (GM_TM / 32) + wr * 2;
+    const int rb0 = rt * (GM_TM / 32) + wr * GM_WR;
 
-    // B generator: path pair (2 pp, 2 pp + 1), columns nb and nb + 64 of the tile
+    // B generator: path pair (2 pp, 2 pp + 1), columns nb + 32 h, h < GM_NCB
     const int pp = tid & 7;
     const int nb = tid >> 3;
     const int64_t col0 = (int64_t)ct * GM_TN;
     const int m = (int)(col0 / K);
     const unsigned kbase = (unsigned)(col0 - (int64_t)m * K) + (unsigned)nb;
     const int p0 = 2 * pp;
-    const int flane = (p0 >> 3) * 32 + (nb & 31);
+    const int flane = (p0 >> 3) * 32 + nb;
     // 32-bit word index of (fragment 0, this lane, slots p0 & 7 and +1)
     const int wofs = (flane * 16 + (flane >= 32 ? 128 : 0) + (p0 & 7) * 2) / 4;
-    unsigned *bsw = reinterpret_cast<unsigned *>(Bs);
     const uint4 *bprow = Bp + (int64_t)m * Ppad + p0;
 
-    auto gen = [&](uint4 pa, uint4 pb, int buf) {
-        // start phasors of both paths at column nb, then rotate by 64 columns
+    auto gen = [&](uint4 pa, uint4 pb, uint4 *Bs) {
+        unsigned *bsw = reinterpret_cast<unsigned *>(Bs);
         float ar, ai, br, bi;
         {
             const float u = (float)(int)(pa.x + kbase * pa.y) * 2.3283064365386963e-10f;
@@ -234,153 +270,162 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
             br = __builtin_amdgcn_cosf(u);
             bi = -__builtin_amdgcn_sinf(u);
         }
+        const float rar = __uint_as_float(pa.z), rai = __uint_as_float(pa.w);
+        const float rbr = __uint_as_float(pb.z), rbi = __uint_as_float(pb.w);
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-            if (h == 1) {
-                const float rar = __uint_as_float(pa.z), rai = __uint_as_float(pa.w);
-                const float rbr = __uint_as_float(pb.z), rbi = __uint_as_float(pb.w);
+        for (int h = 0; h < GM_NCB; h++) {
+            if (h > 0) {
+                // advance both phasors by 32 columns
                 float t0 = ar * rar - ai * rai, t1 = ar * rai + ai * rar;
                 ar = t0; ai = t1;
                 t0 = br * rbr - bi * rbi; t1 = br * rbi + bi * rbr;
                 br = t0; bi = t1;
             }
-            const unsigned rh = bf16_bits(ar) | ((unsigned)bf16_bits(br) << 16);
-            const unsigned ih = bf16_bits(ai) | ((unsigned)bf16_bits(bi) << 16);
-            const unsigned rl = bf16_bits(ar - bf16_float((unsigned short)rh)) |
-                                ((unsigned)bf16_bits(br - bf16_float((unsigned short)(rh >> 16))) << 16);
-            const unsigned il = bf16_bits(ai - bf16_float((unsigned short)ih)) |
-                                ((unsigned)bf16_bits(bi - bf16_float((unsigned short)(ih >> 16))) << 16);
-            const int cb = (nb >> 5) + 2 * h;
-            // word offset of (buf, plane, column block cb)
-            const int f = ((buf * 4 + 0) * 4 + cb) * (BFRAG_U4 * 4);
-            const int ps = 4 * BFRAG_U4 * 4;
+            unsigned rh, rl, ih, il;
+            split_bf16(ar, br, rh, rl);
+            split_bf16(ai, bi, ih, il);
+            // word offset of (plane 0, column block h)
+            const int f = h * (BFRAG_U4 * 4);
+            const int ps = GM_NCB * BFRAG_U4 * 4;
             bsw[f + wofs] = rh;
             bsw[f + ps + wofs] = rl;
             bsw[f + 2 * ps + wofs] = ih;
             bsw[f + 3 * ps + wofs] = il;
         }
     };
-    // A staging: the tile of one step is 8 row blocks x 4 planes x 64 lanes;
-    // thread tid moves entries tid + 512 r, r = 0..3 (1 KiB contiguous runs)
-    const uint4 *abase = Af + (int64_t)rt * (GM_TM / 32) * KB * 256;
-    // (staged values travel by value in a struct so that they stay in VGPRs)
-    struct Stage {
-        uint4 r0, r1, r2, r3;
-    };
-    const int rbl0 = tid >> 8, rest0 = tid & 255;
-    auto stage_load = [&](int kb) -> Stage {
-        Stage v;
-        const uint4 *src = abase + (int64_t)kb * 256 + rest0;
-        const int64_t rstride = (int64_t)KB * 256;
-        v.r0 = src[(int64_t)(rbl0 + 0) * rstride];
-        v.r1 = src[(int64_t)(rbl0 + 2) * rstride];
-        v.r2 = src[(int64_t)(rbl0 + 4) * rstride];
-        v.r3 = src[(int64_t)(rbl0 + 6) * rstride];
-        return v;
-    };
-    auto stage_store = [&](const Stage v, int buf) {
-        uint4 *dst = &As[buf][0][0][0] + tid;
-        dst[0] = v.r0;
-        dst[GM_THREADS] = v.r1;
-        dst[2 * GM_THREADS] = v.r2;
-        dst[3 * GM_THREADS] = v.r3;
-    };
+    // A fragments of this wavefront's row blocks: fragment (rb, kb, plane)
+    // is the 1 KiB at Af + ((rb KB + kb) 4 + plane) 64
+    const uint4 *arow = Af + (int64_t)rb0 * KB * 256 + lane;
 
-    f32x16 sr[2][2], si[2][2];
+    f32x16 sr[GM_WR][GM_WC], si[GM_WR][GM_WC];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < GM_WR; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < GM_WC; j++)
 #pragma unroll
             for (int e = 0; e < 16; e++) { sr[i][j][e] = 0.0f; si[i][j][e] = 0.0f; }
 
-    struct Frags {
-        uint4 a[2][4], b[2][4];
+    struct ARow {
+        uint4 q[4];
     };
-    auto load_frags = [&](int buf) -> Frags {
-        Frags f;
-#pragma unroll
-        for (int i = 0; i < 2; i++)
-#pragma unroll
-            for (int q = 0; q < 4; q++) f.a[i][q] = As[buf][wr * 2 + i][q][lane];
-        const int lofs = lane + (lane >= 32 ? 8 : 0);
-#pragma unroll
-        for (int j = 0; j < 2; j++)
-#pragma unroll
-            for (int q = 0; q < 4; q++)
-                f.b[j][q] = Bs[((buf * 4 + q) * 4 + wc * 2 + j) * BFRAG_U4 + lofs];
-        return f;
+    // B fragments of two column blocks: planes (re_hi, re_lo, im_hi, im_lo)
+    // in q, the negated imaginary planes for the real part of the product in n
+    struct BCols {
+        uint4 q[GM_WC][4];
+        uint4 n[GM_WC][2];
     };
-    auto mma = [&](const Frags &f) {
+    auto load_a = [&](int kb, int i) -> ARow {
+        ARow a;
+        const uint4 *src = arow + ((int64_t)i * KB + kb) * 256;
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-            const uint4 nih = neg_bf(f.a[i][2]), nil = neg_bf(f.a[i][3]);
+        for (int p = 0; p < 4; p++) a.q[p] = src[p * 64];
+        return a;
+    };
+    const int lofs = lane + (lane >= 32 ? 8 : 0);
+    auto load_b = [&](const uint4 *Bs) -> BCols {
+        BCols b;
 #pragma unroll
-            for (int j = 0; j < 2; j++) {
-                // re += Ar Br - Ai Bi ; im += Ar Bi + Ai Br  (hi*hi + hi*lo + lo*hi)
-                sr[i][j] = MFMA(f.a[i][0], f.b[j][0], sr[i][j]);
-                si[i][j] = MFMA(f.a[i][0], f.b[j][2], si[i][j]);
-                sr[i][j] = MFMA(f.a[i][0], f.b[j][1], sr[i][j]);
-                si[i][j] = MFMA(f.a[i][0], f.b[j][3], si[i][j]);
-                sr[i][j] = MFMA(f.a[i][1], f.b[j][0], sr[i][j]);
-                si[i][j] = MFMA(f.a[i][1], f.b[j][2], si[i][j]);
-                sr[i][j] = MFMA(nih, f.b[j][2], sr[i][j]);
-                si[i][j] = MFMA(f.a[i][2], f.b[j][0], si[i][j]);
-                sr[i][j] = MFMA(nih, f.b[j][3], sr[i][j]);
-                si[i][j] = MFMA(f.a[i][2], f.b[j][1], si[i][j]);
-                sr[i][j] = MFMA(nil, f.b[j][2], sr[i][j]);
-                si[i][j] = MFMA(f.a[i][3], f.b[j][0], si[i][j]);
+        for (int j = 0; j < GM_WC; j++)
+#pragma unroll
+            for (int p = 0; p < 4; p++) b.q[j][p] = Bs[(p * GM_NCB + wc * GM_WC + j) * BFRAG_U4 + lofs];
+        return b;
+    };
+    // sign flip of the imaginary planes (bf16 negation is exact); applied
+    // well after the LDS reads, so that it never waits for them
+    auto negate = [&](BCols &b) {
+#pragma unroll
+        for (int j = 0; j < GM_WC; j++)
+#pragma unroll
+            for (int p = 0; p < 2; p++) {
+                const uint4 v = b.q[j][2 + p];
+                b.n[j][p] = make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u,
+                                       v.w ^ 0x80008000u);
             }
+    };
+    // re += Ar Br + Ai (-Bi) ; im += Ar Bi + Ai Br  (hi*hi + hi*lo + lo*hi)
+    auto mma_row = [&](const ARow a, const BCols &b, int i) {
+#pragma unroll
+        for (int j = 0; j < GM_WC; j++) {
+            sr[i][j] = MFMA(a.q[0], b.q[j][0], sr[i][j]);
+            si[i][j] = MFMA(a.q[0], b.q[j][2], si[i][j]);
+            sr[i][j] = MFMA(a.q[0], b.q[j][1], sr[i][j]);
+            si[i][j] = MFMA(a.q[0], b.q[j][3], si[i][j]);
+            sr[i][j] = MFMA(a.q[1], b.q[j][0], sr[i][j]);
+            si[i][j] = MFMA(a.q[1], b.q[j][2], si[i][j]);
+            sr[i][j] = MFMA(a.q[2], b.n[j][0], sr[i][j]);
+            si[i][j] = MFMA(a.q[2], b.q[j][0], si[i][j]);
+            sr[i][j] = MFMA(a.q[2], b.n[j][1], sr[i][j]);
+            si[i][j] = MFMA(a.q[2], b.q[j][1], si[i][j]);
+            sr[i][j] = MFMA(a.q[3], b.n[j][0], sr[i][j]);
+            si[i][j] = MFMA(a.q[3], b.q[j][0], si[i][j]);
         }
     };
 
-    // Pipeline: the global loads of step kb + 2 are issued during step kb and
-    // only written to LDS at the start of step kb + 1, a full step later, so
-    // their latency hides behind one step of matrix-core work.  Indices are
-    // clamped instead of branched; the surplus work at the end fills the LDS
-    // buffer that is no longer read.
+    // prologue: B(0) in LDS, the B parameters of step 1 and the A fragments
+    // of steps 0 and 1 in registers
     const int last = KB - 1;
-    Stage v = stage_load(0);
-    stage_store(v, 0);
-    gen(bprow[0], bprow[1], 0);
-    v = stage_load(min(1, last));
+    gen(bprow[0], bprow[1], Bs[0]);
     uint4 pna = bprow[(int64_t)min(1, last) * GM_KS];
     uint4 pnb = bprow[(int64_t)min(1, last) * GM_KS + 1];
+    ARow x0 = load_a(0, 0), x1 = load_a(0, 1), x2 = load_a(0, 2), x3 = load_a(0, 3);
+    ARow y0 = load_a(min(1, last), 0), y1 = load_a(min(1, last), 1);
+    ARow y2 = load_a(min(1, last), 2), y3 = load_a(min(1, last), 3);
     __syncthreads();
-    for (int kb = 0; kb < KB; kb++) {
-        const int buf = kb & 1;
-        stage_store(v, buf ^ 1);
+    BCols b0 = load_b(Bs[0]), b1;
+    negate(b0);
+
+    // One step kb on A fragments r0..r3 (of step kb, loaded two steps
+    // earlier) and B fragments bc; refills r0..r3 with step kb + 2 and
+    // returns the B fragments of step kb + 1.
+    auto step = [&](int kb, ARow &r0, ARow &r1, ARow &r2, ARow &r3, const BCols &bc) -> BCols {
         const int nx = min(kb + 2, last);
+        uint4 *Bn = Bs[(kb + 1) & 1];
         const uint4 pca = pna, pcb = pnb;
-        v = stage_load(nx);
-        pna = bprow[(int64_t)nx * GM_KS];
-        pnb = bprow[(int64_t)nx * GM_KS + 1];
-        // keep the prefetch loads above the matrix-core work
-        __builtin_amdgcn_sched_barrier(0);
-        const Frags f = load_frags(buf);
-        gen(pca, pcb, buf ^ 1);
-        mma(f);
-        // interleave the generation of the next B tile (VALU, LDS writes)
-        // with this step's MFMAs so that the matrix cores stay busy
-        __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);   // fragment reads
+        // rows 0-1 with the generation of B(kb + 1) interleaved
+        gen(pca, pcb, Bn);
+        mma_row(r0, bc, 0);
+#ifndef GM_FREE_SCHED
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
 #pragma unroll
-        for (int g = 0; g < 8; g++) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
+        for (int g = 0; g < 4 * GM_NCB; g++) {
             __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // 6 VALU
             __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // 1 LDS write
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, 40, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 23 - 4 * GM_NCB, 0);
+#endif
+        __builtin_amdgcn_sched_barrier(0);
+        r0 = load_a(nx, 0);
+        pna = bprow[(int64_t)nx * GM_KS];
+        pnb = bprow[(int64_t)nx * GM_KS + 1];
+        mma_row(r1, bc, 1);
+        __builtin_amdgcn_sched_barrier(0);
+        r1 = load_a(nx, 1);
         __syncthreads();
+        BCols bn = load_b(Bn);
+        mma_row(r2, bc, 2);
+        __builtin_amdgcn_sched_barrier(0);
+        r2 = load_a(nx, 2);
+        negate(bn);
+        mma_row(r3, bc, 3);
+        __builtin_amdgcn_sched_barrier(0);
+        r3 = load_a(nx, 3);
+        return bn;
+    };
+    // KB is even: the two register sets alternate
+    for (int kb = 0; kb < KB; kb += 2) {
+        b1 = step(kb, x0, x1, x2, x3, b0);
+        b0 = step(kb + 1, y0, y1, y2, y3, b1);
     }
     // D layout: register e of lane l is row 8*(e/4) + 4*(l/32) + e%4, column l%32
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < GM_WR; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < GM_WC; j++)
 #pragma unroll
             for (int e = 0; e < 16; e++) {
                 const int row = (rb0 + i) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                const int64_t col = col0 + (wc * 2 + j) * 32 + (lane & 31);
+                const int64_t col = col0 + (wc * GM_WC + j) * 32 + (lane & 31);
                 if (row < C) cube[(int64_t)row * N + col] = make_float2(sr[i][j][e], si[i][j][e]);
             }
 }
@@ -389,7 +434,8 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
 
 int gemm_row_pad() { return GM_TM; }
 int gemm_col_tile() { return GM_TN; }
-int gemm_k_step() { return GM_KS; }
+// paths are padded to two steps (the A register sets alternate)
+int gemm_k_step() { return 2 * GM_KS; }
 
 hipError_t launch_gemm_prep_tr(const SynthArgs &a, int Ppad, float2 *T, float2 *R, hipStream_t s)
 {

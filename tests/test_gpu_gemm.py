@@ -70,7 +70,7 @@ def test_empty_and_unsupported(gpu, orc):
     _upload(gpu, op[:0])
     cube = gpu.synthesize(model=1, engine=2)
     assert torch.count_nonzero(cube).item() == 0
-    gpu.set_chirp(77e9, 1e9, 50e-6, 50e-6, 64, 2)
+    gpu.set_chirp(77e9, 1e9, 50e-6, 50e-6, 96, 2)
     _upload(gpu, op)
     with pytest.raises(rr.RadrayError) as e:
         gpu.synthesize(model=1, engine=2)
@@ -79,7 +79,7 @@ def test_empty_and_unsupported(gpu, orc):
         gpu.synthesize(model=0, engine=2)
     # auto picks the direct engine where the GEMM cannot run
     auto = gpu.synthesize(model=1, engine=0).cpu().numpy()
-    ch = sg.Chirp(n_samples=64, n_chirps=2)
+    ch = sg.Chirp(n_samples=96, n_chirps=2)
     assert rel_err(auto, orc.synth(op, w.scene, w.array, ch, model=1)) < 1e-4
 
 
