@@ -103,7 +103,10 @@ def run_batch(args):
 def run_proposal(args):
     """Learned proposal: train on 200 scenes x 5e4 uniform rays, evaluate 50
     held-out scenes at 1.25e4 rays (1/8 of the 1e5 uniform budget) against a
-    1e5-ray uniform cube and a 1e6-ray uniform reference."""
+    1e5-ray uniform cube and a 1e6-ray uniform reference; then, on 20 held-out
+    scenes seen by the 3072-channel array (512 samples x 256 chirps), the wall
+    time of learned launch + GEMM synthesis against uniform launch + direct
+    summation at equal mean cube error."""
     import paper_2307_15412_amd as rr
     from paper_2307_15412_amd import proposal
     ctx = rr.Context(0)
@@ -115,6 +118,11 @@ def run_proposal(args):
                                   batch=16, lr=2e-3, log=log)
         log(f"reference {ref_rays}: done")
         out[f"ref_{ref_rays}"] = {k: v for k, v in res.items() if k != "per_scene"}
+    # equal cube error on the 3072-channel array: learned launch + GEMM
+    # synthesis against uniform launch + direct summation
+    eq = proposal.equal_error(ctx, eval_seeds=range(1001, 1021), log=log)
+    log(f"equal error: uniform needs {eq['uniform_rays_at_equal_error']:.0f} rays, "
+        f"speed-up {eq['speedup_at_equal_error']:.1f}x")
     r = out["ref_1000000"]
     ratio = r["err_learned_mean"] / r["err_uniform_mean"]
     print(json.dumps({
@@ -123,7 +131,8 @@ def run_proposal(args):
         "equal_error_ray_saving": 1.0 / (ratio * ratio),
         "config": {"workload": "box family: 200 training scenes x 5e4 rays, 50 held-out scenes, "
                                "1.25e4 rays vs 1e5 / 1e6-ray uniform references, beta 0.1"},
-        "results": out}))
+        "results": out,
+        "equal_error": {k: v for k, v in eq.items() if k != "per_scene"}}))
 
 
 def copy_calibration():

@@ -230,12 +230,14 @@ class Context:
             if out is None:
                 out = torch.empty((self.n_ch, self.M, self.K), dtype=torch.complex64,
                                   device=self.device)
+            check_out(out, self.device, torch.complex64, self.n_ch * self.M * self.K, "cube")
             self._check(self.lib.rr_synthesize(self.h, int(model), int(engine),
                                                C.c_void_p(out.data_ptr()), out.numel(), None, 0))
             return out
         idx = torch.as_tensor(sample_idx, dtype=torch.int64).to(self.device).contiguous()
         if out is None:
             out = torch.empty(idx.numel(), dtype=torch.complex64, device=self.device)
+        check_out(out, self.device, torch.complex64, idx.numel(), "sampled entries")
         self._check(self.lib.rr_synthesize(self.h, int(model), int(engine),
                                            C.c_void_p(out.data_ptr()), out.numel(),
                                            C.c_void_p(idx.data_ptr()), idx.numel()))
@@ -292,6 +294,16 @@ def _declare_proposal(L):
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def check_out(t, device, dtype, numel, what="output"):
+    """An output tensor handed to the library must be a contiguous tensor of
+    `dtype` on the context's device with at least `numel` elements: the
+    library receives only its address."""
+    if (not hasattr(t, "data_ptr") or t.device != device or t.dtype != dtype
+            or not t.is_contiguous() or t.numel() < numel):
+        raise ValueError(f"{what} must be a contiguous {dtype} tensor on {device} with at least "
+                         f"{numel} elements")
 
 
 class _ProposalMixin:
@@ -431,6 +443,13 @@ class Batch:
         return [torch.empty(s, dtype=torch.complex64, device=self.ctx.device) for s in self.shapes]
 
     def _ptrs(self, cubes):
+        if len(cubes) != self.n:
+            raise ValueError(f"{self.n} cubes expected")
+        torch = self.ctx.torch
+        for s, (c, shape) in enumerate(zip(cubes, self.shapes)):
+            if shape is None:
+                raise ValueError(f"batch slot {s} has no scene")
+            check_out(c, self.ctx.device, torch.complex64, int(np.prod(shape)), f"cube {s}")
         arr = (C.c_void_p * self.n)(*[c.data_ptr() for c in cubes])
         self._keep = arr
         return arr

@@ -77,6 +77,92 @@ def evaluate(ctx, workloads, budget, ref_rays, beta=0.1):
     return out
 
 
+def _rel(ctx, a, b, nb):
+    return float((a - b).abs().pow(2).sum().sqrt()) / max(nb, 1e-30)
+
+
+def _loglog(xs, ys, y):
+    """x where the piecewise log-log line through (xs, ys) reaches y (ys
+    decreasing); extrapolated from the end segments."""
+    lx, ly, t = np.log(xs), np.log(ys), math.log(y)
+    i = int(np.clip(np.searchsorted(-ly, -t) - 1, 0, len(xs) - 2))
+    f = (t - ly[i]) / (ly[i + 1] - ly[i])
+    return float(math.exp(lx[i] + f * (lx[i + 1] - lx[i])))
+
+
+def equal_error(ctx, eval_seeds, budget=12_500, uniform_budgets=(12_500, 25_000, 50_000, 100_000,
+                                                                   200_000),
+                ref_rays=1_000_000, beta=0.1, log=None):
+    """Wall time at equal cube error on the large-MIMO array (3072 channels,
+    512 samples x 256 chirps) over box-family scenes, with the network as
+    trained in `ctx`.
+
+    Learned pipeline: probe code, sampling table, `budget` rays from the
+    learned density, GEMM synthesis.  Plain pipeline: uniform rays and direct
+    summation, at each of `uniform_budgets`.  Both against a `ref_rays`
+    uniform reference (GEMM); all cubes in the separable model.  The uniform
+    budget of equal mean error is interpolated in log-log, and so is the
+    plain pipeline's time there."""
+    torch = ctx.torch
+    import scenegen as sg
+    per = []
+    ref = work = None
+    for s in eval_seeds:
+        w = sg.workload_box_mimo(s, budget)
+        ctx.setup(w)
+        tp = w.trace
+        C, M, K = w.array.n_ch, w.chirp.n_chirps, w.chirp.n_samples
+        if ref is None:
+            ref = torch.empty((C, M, K), dtype=torch.complex64, device=ctx.device)
+            work = torch.empty_like(ref)
+        kw = dict(max_bounces=tp.max_bounces, az_min=tp.az_min, az_max=tp.az_max,
+                  el_min=tp.el_min, el_max=tp.el_max, record_hits=False)
+        ctx.trace(ref_rays, seed=tp.seed + 7919, sampler=B.UNIFORM, **kw)
+        ctx.synthesize(model=B.SEPARABLE, engine=B.GEMM_BF16X3, out=ref)
+        nref = float(ref.abs().pow(2).sum().sqrt())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code = ctx.proposal_probe(tp.az_min, tp.az_max)
+        ctx.proposal_build(code, beta)
+        n_l = ctx.trace(budget, seed=tp.seed, sampler=B.PROPOSAL, **kw)
+        ctx.synthesize(model=B.SEPARABLE, engine=B.GEMM_BF16X3, out=work)
+        torch.cuda.synchronize()
+        t_l = time.perf_counter() - t0
+        row = dict(seed=s, err_learned=_rel(ctx, work, ref, nref), s_learned=t_l, paths_learned=n_l)
+        for n in uniform_budgets:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n_u = ctx.trace(n, seed=tp.seed, sampler=B.UNIFORM, **kw)
+            ctx.synthesize(model=B.SEPARABLE, engine=B.DIRECT_FP32, out=work)
+            torch.cuda.synchronize()
+            row[f"s_uniform_{n}"] = time.perf_counter() - t0
+            row[f"err_uniform_{n}"] = _rel(ctx, work, ref, nref)
+            row[f"paths_uniform_{n}"] = n_u
+        per.append(row)
+        if log:
+            log(f"equal-error scene {s}: learned err {row['err_learned']:.3f} in "
+                f"{row['s_learned'] * 1e3:.1f} ms")
+    el = float(np.mean([r["err_learned"] for r in per]))
+    tl = float(np.mean([r["s_learned"] for r in per[1:] or per]))
+    eu = np.array([np.mean([r[f"err_uniform_{n}"] for r in per]) for n in uniform_budgets])
+    tu = np.array([np.mean([r[f"s_uniform_{n}"] for r in per[1:] or per]) for n in uniform_budgets])
+    xs = np.array(uniform_budgets, dtype=np.float64)
+    n_eq = _loglog(xs, eu, el)
+    t_eq = _loglog_time(xs, tu, n_eq)
+    return dict(budget=budget, err_learned_mean=el, s_learned_mean=tl,
+                uniform_budgets=list(uniform_budgets), err_uniform_mean=eu.tolist(),
+                s_uniform_mean=tu.tolist(), uniform_rays_at_equal_error=n_eq,
+                s_uniform_at_equal_error=t_eq, speedup_at_equal_error=t_eq / tl, per_scene=per)
+
+
+def _loglog_time(xs, ts, x):
+    """Time at x on the piecewise log-log line through (xs, ts) (increasing)."""
+    lx, lt, t = np.log(xs), np.log(ts), math.log(x)
+    i = int(np.clip(np.searchsorted(lx, t) - 1, 0, len(xs) - 2))
+    f = (t - lx[i]) / (lx[i + 1] - lx[i])
+    return float(math.exp(lt[i] + f * (lt[i + 1] - lt[i])))
+
+
 def experiment(ctx, train_seeds, eval_seeds, train_rays=50_000, budget=12_500, ref_rays=100_000,
                steps=300, batch=16, lr=1e-3, beta=0.1, log=None):
     import scenegen as sg

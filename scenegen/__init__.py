@@ -441,6 +441,22 @@ def workload_batch(n_scenes: int = 64, seed0: int = 2000, rays: int = 1_000_000,
     return out
 
 
+def workload_box_mimo(seed: int, n_rays: int) -> Workload:
+    """A box-family scene (no point reflectors) seen by the large-MIMO array
+    (48 Tx x 64 Rx from the 64 x 64 grid, shared launch) moved so that its Tx
+    and Rx phase centres sit where the tiny array's Tx and Rx centre are;
+    512 samples x 256 chirps, 2 bounces."""
+    c1 = array_c1()
+    big = array_sparse_grid(48, 64, seed + 17)
+    tx = big.tx - big.tx.mean(axis=0) + c1.tx.mean(axis=0)
+    rx = big.rx - big.rx.mean(axis=0) + c1.rx.mean(axis=0)
+    sc = scene_box_family(seed)
+    sc = Scene(sc.verts, sc.tris, sc.tri_obj, sc.obj_alpha, sc.obj_vel).checked()
+    return Workload(f"boxmimo{seed}", sc, Array(tx, rx, c1.rx_radius, MODE_SHARED).checked(),
+                    Chirp(n_samples=512, n_chirps=256),
+                    TraceParams(n_rays=n_rays, max_bounces=2, seed=seed))
+
+
 def workload_box_family(seed: int, n_rays: int, points: bool = True) -> Workload:
     """One scene of the learned-proposal family with the tiny scene's array
     and chirp, 2 bounces (points=False drops the point reflectors, leaving

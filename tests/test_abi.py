@@ -59,3 +59,22 @@ def test_invalid_args_rejected_without_device():
     assert lib.rr_trace(None, None, None) == pkg.binding.RR_EINVAL
     assert lib.rr_synthesize(None, 0, 0, None, 0, None, 0) == pkg.binding.RR_EINVAL
     assert b"NULL" in lib.rr_last_error() or b"null" in lib.rr_last_error().lower()
+
+
+def test_output_tensors_checked_before_the_library_sees_them():
+    """Output tensors reach the library as bare addresses: a host tensor, a
+    wrong dtype, a strided view or a short buffer is refused in the binding."""
+    import torch
+    from paper_2307_15412_amd.binding import check_out
+    dev = torch.device("cuda", 0)
+    host = torch.zeros(16, dtype=torch.complex64)
+    with pytest.raises(ValueError):
+        check_out(host, dev, torch.complex64, 16)
+    with pytest.raises(ValueError):
+        check_out(host, torch.device("cpu"), torch.complex64, 17)
+    with pytest.raises(ValueError):
+        check_out(host, torch.device("cpu"), torch.float32, 16)
+    with pytest.raises(ValueError):
+        check_out(torch.zeros((4, 8), dtype=torch.complex64)[:, ::2], torch.device("cpu"),
+                  torch.complex64, 16)
+    check_out(host, torch.device("cpu"), torch.complex64, 16)

@@ -1,7 +1,8 @@
 """Split-bf16 complex-GEMM synthesis (separable model) against the FP64
 oracle: relative error <= 1e-3 on the full cube or on seeded sampled
-entries; edge cases of the tiling (channel counts below one tile, path
-counts not divisible by the 16-path step, empty path list)."""
+entries; edge cases of the tiling (channel counts below one 512-row tile or
+just above it, one or three 64-column tiles per chirp, odd chirp counts, path
+counts not divisible by the 32-path padding, empty path list)."""
 import numpy as np
 import pytest
 import torch
@@ -57,6 +58,25 @@ def test_ragged_path_counts(gpu, orc, n_keep):
     gpu.setup(w)
     _upload(gpu, op)
     got = gpu.synthesize(model=1, engine=2).cpu().numpy()
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=1)
+    assert rel_err(got, ref) < TOL_GEMM
+
+
+@pytest.mark.parametrize("n_tx,n_rx,K,M,n_keep", [(3, 7, 64, 3, 33), (8, 65, 192, 2, 47),
+                                                  (1, 1, 64, 1, 1)])
+def test_tile_edges(gpu, orc, n_tx, n_rx, K, M, n_keep):
+    """Full cubes at channel, column and path counts around the tile sizes;
+    the paths of a shared launch feed every channel."""
+    w = sg.workload_tiny()
+    w.array = sg.array_sparse_grid(n_tx, n_rx, 5, mode=sg.MODE_SHARED)
+    w.chirp = sg.Chirp(n_samples=K, n_chirps=M)
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    assert len(op) >= n_keep
+    op = op[:n_keep]
+    gpu.setup(w)
+    _upload(gpu, op)
+    got = gpu.synthesize(model=1, engine=2).cpu().numpy()
+    assert got.shape == (n_tx * n_rx, M, K)
     ref = orc.synth(op, w.scene, w.array, w.chirp, model=1)
     assert rel_err(got, ref) < TOL_GEMM
 
