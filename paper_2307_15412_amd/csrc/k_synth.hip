@@ -3,13 +3,16 @@
 // by the chirp's instantaneous frequency f_k = f0 + B k / K).
 //
 // Each lane owns one (channel, chirp) row and a run of KR consecutive fast-time
-// samples.  For every path it forms the per-channel path length in FP64,
-// reduces the carrier phase modulo one cycle in FP64 (the phase at 77 GHz is
-// ~1e4 cycles, beyond FP32), converts the start phasor of its run to FP32 and
-// walks the run by complex rotation (the phase is linear in k), accumulating
-// in FP32 registers.  Paths are staged through LDS in chunks and read as
-// broadcasts.  A second kernel evaluates individual cube entries fully in
-// FP64 for checks at sizes where the whole cube is not needed.
+// samples.  Paths are staged through LDS in chunks.  For every (path, row) of
+// the chunk the workgroup forms the path length once, in FP64, and reduces
+// the carrier phase f0 d / c and the per-sample step B d / (K c) modulo one
+// cycle in FP64 (the phase at 77 GHz is ~1e4 cycles, beyond FP32), keeping
+// both as 32-bit fixed-point turns in an LDS table.  A lane then forms the
+// start phase of its run exactly in integer arithmetic (beta + k0 gamma modulo
+// 2^32), takes the hardware sin/cos of it and of the step (input in turns),
+// and walks the run by complex rotation, accumulating in FP32 registers.  A
+// second kernel evaluates individual cube entries fully in FP64 for checks at
+// sizes where the whole cube is not needed.
 #include <algorithm>
 
 #include "rr_internal.h"
@@ -18,6 +21,7 @@ namespace {
 
 #define SYN_T 256
 #define SYN_CHUNK 32
+#define SYN_TAB 4096      // (path, row) phase entries per chunk: 32 KiB of LDS
 
 __device__ __forceinline__ double dist3(double ax, double ay, double az, double bx, double by,
                                         double bz)
@@ -72,24 +76,30 @@ __device__ __forceinline__ void path_lengths(const SynthArgs &A, const SynPath &
 
 __device__ __forceinline__ double frac(double x) { return x - floor(x); }
 
+// x modulo one cycle as 32-bit fixed-point turns
+__device__ __forceinline__ unsigned turns_u32(double x)
+{
+    return (unsigned)(unsigned long long)llrint(frac(x) * 4294967296.0);
+}
+
+// fixed-point turns -> FP32 turns in [-1/2, 1/2)
+__device__ __forceinline__ float turns_f32(unsigned u)
+{
+    return (float)(int)u * 2.3283064365386963e-10f;
+}
+
 // One workgroup tile: rows rb * RPB .. of group g (a Tx in the per-element
 // mode, everything in the shared mode), every sample of those rows.
 template <int KR>
 __device__ void synth_block(const SynthArgs &A, int g, int rb, int rows_per_group, int RC,
-                            SynPath *sp)
+                            SynPath *sp, uint2 *tab)
 {
     const int TPR = A.K / KR;
     const int RPB = SYN_T / TPR;
-    const int row = rb * RPB + threadIdx.x / TPR;
+    const int lrow = threadIdx.x / TPR;
+    const int row = rb * RPB + lrow;
     const int k0 = (threadIdx.x % TPR) * KR;
-    const bool valid = row < rows_per_group && (int)(threadIdx.x / TPR) < RPB;
-    const int m = valid ? row / RC : 0;
-    const int cc = valid ? row - m * RC : 0;
-    const int c = A.shared ? cc : g * A.nrx + cc;
-    const int t = c / A.nrx, r = c - (c / A.nrx) * A.nrx;
-    double tx[3] = {A.tx[3 * t], A.tx[3 * t + 1], A.tx[3 * t + 2]};
-    double rx[3] = {A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]};
-    const double tau = (double)m * A.t_rep;
+    const bool valid = lrow < RPB && row < rows_per_group;
     const double f0c = A.f0 * A.inv_c;
     const double bkc = A.bw / (double)A.K * A.inv_c;
     float are[KR], aim[KR];
@@ -97,8 +107,9 @@ __device__ void synth_block(const SynthArgs &A, int g, int rb, int rows_per_grou
     for (int k = 0; k < KR; k++) { are[k] = 0.0f; aim[k] = 0.0f; }
     const int64_t p0 = A.ranges[g];
     const int64_t p1 = A.p_limit > 0 ? min(A.ranges[g + 1], p0 + A.p_limit) : A.ranges[g + 1];
-    for (int64_t base = p0; base < p1; base += SYN_CHUNK) {
-        const int cnt = (int)min((int64_t)SYN_CHUNK, p1 - base);
+    const int chunk = min(SYN_CHUNK, SYN_TAB / RPB);
+    for (int64_t base = p0; base < p1; base += chunk) {
+        const int cnt = (int)min((int64_t)chunk, p1 - base);
         __syncthreads();
         {
             const float4 *srcv = reinterpret_cast<const float4 *>(A.paths + base);
@@ -107,21 +118,33 @@ __device__ void synth_block(const SynthArgs &A, int g, int rb, int rows_per_grou
             for (int i = threadIdx.x; i < nv; i += SYN_T) dstv[i] = srcv[i];
         }
         __syncthreads();
+        // phase table, entry q * RPB + l: (beta, gamma) of path q in row l
+        for (int e = threadIdx.x; e < cnt * RPB; e += SYN_T) {
+            const int q = e / RPB, l = e - q * RPB;
+            const int rw = rb * RPB + l;
+            uint2 v = make_uint2(0u, 0u);
+            if (rw < rows_per_group) {
+                const int m = rw / RC, cc = rw - (rw / RC) * RC;
+                const int c = A.shared ? cc : g * A.nrx + cc;
+                const int t = c / A.nrx, r = c - (c / A.nrx) * A.nrx;
+                const double tx[3] = {A.tx[3 * t], A.tx[3 * t + 1], A.tx[3 * t + 2]};
+                const double rx[3] = {A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]};
+                double db, ds;
+                path_lengths(A, sp[q], (double)m * A.t_rep, tx, rx, db, ds);
+                v = make_uint2(turns_u32(db * f0c), turns_u32(ds * bkc));
+            }
+            tab[e] = v;
+        }
+        __syncthreads();
         if (!valid) continue;
         for (int q = 0; q < cnt; q++) {
-            double db, ds;
-            path_lengths(A, sp[q], tau, tx, rx, db, ds);
-            double bf = frac(db * f0c), sf = frac(ds * bkc);
-            double st = frac(bf + (double)k0 * sf);
-            if (st >= 0.5) st -= 1.0;
-            if (sf >= 0.5) sf -= 1.0;
-            float s0, c0, s1, c1;
-            sincospif(2.0f * (float)st, &s0, &c0);
-            sincospif(2.0f * (float)sf, &s1, &c1);
+            const uint2 ph = tab[q * RPB + lrow];
             const float a = (float)sp[q].amp;
-            // exp(-j 2 pi phi) = cos - j sin
-            float pr = a * c0, pi = -a * s0;
-            const float rr = c1, ri = -s1;
+            // exp(-j 2 pi phi) = cos - j sin, phi in turns
+            const float u0 = turns_f32(ph.x + (unsigned)k0 * ph.y);
+            const float u1 = turns_f32(ph.y);
+            float pr = a * __builtin_amdgcn_cosf(u0), pi = -a * __builtin_amdgcn_sinf(u0);
+            const float rr = __builtin_amdgcn_cosf(u1), ri = -__builtin_amdgcn_sinf(u1);
 #pragma unroll
             for (int k = 0; k < KR; k++) {
                 are[k] += pr;
@@ -134,6 +157,8 @@ __device__ void synth_block(const SynthArgs &A, int g, int rb, int rows_per_grou
         }
     }
     if (!valid) return;
+    const int m = row / RC, cc = row - (row / RC) * RC;
+    const int c = A.shared ? cc : g * A.nrx + cc;
     float2 *out = A.cube + ((int64_t)c * A.M + m) * A.K + k0;
 #pragma unroll
     for (int k = 0; k < KR; k++) out[k] = make_float2(are[k], aim[k]);
@@ -144,8 +169,9 @@ __global__ __launch_bounds__(SYN_T) void k_synth_direct(SynthArgs A, int rows_pe
                                                         int blocks_per_group)
 {
     __shared__ SynPath sp[SYN_CHUNK];
+    __shared__ uint2 tab[SYN_TAB];
     const int g = blockIdx.x / blocks_per_group;
-    synth_block<KR>(A, g, blockIdx.x - g * blocks_per_group, rows_per_group, RC, sp);
+    synth_block<KR>(A, g, blockIdx.x - g * blocks_per_group, rows_per_group, RC, sp, tab);
 }
 
 // Batched, persistent: workgroups pull (scene, tile) items from a device
@@ -157,6 +183,7 @@ __global__ __launch_bounds__(SYN_T) void k_batch_synth(const SynthArgs *scenes,
                                                        unsigned long long *work)
 {
     __shared__ SynPath sp[SYN_CHUNK];
+    __shared__ uint2 tab[SYN_TAB];
     __shared__ long long s_item;
     const int64_t n_items = item_start[S];
     while (true) {
@@ -176,12 +203,12 @@ __global__ __launch_bounds__(SYN_T) void k_batch_synth(const SynthArgs *scenes,
         const int g = local / I.bpg;
         const int rb = local - g * I.bpg;
         switch (I.kr) {
-        case 32: synth_block<32>(A, g, rb, I.rows_per_group, I.rc, sp); break;
-        case 16: synth_block<16>(A, g, rb, I.rows_per_group, I.rc, sp); break;
-        case 8: synth_block<8>(A, g, rb, I.rows_per_group, I.rc, sp); break;
-        case 4: synth_block<4>(A, g, rb, I.rows_per_group, I.rc, sp); break;
-        case 2: synth_block<2>(A, g, rb, I.rows_per_group, I.rc, sp); break;
-        default: synth_block<1>(A, g, rb, I.rows_per_group, I.rc, sp); break;
+        case 32: synth_block<32>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
+        case 16: synth_block<16>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
+        case 8: synth_block<8>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
+        case 4: synth_block<4>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
+        case 2: synth_block<2>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
+        default: synth_block<1>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
         }
     }
 }
