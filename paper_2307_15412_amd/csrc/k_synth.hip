@@ -190,20 +190,28 @@ __global__ __launch_bounds__(SYN_T) void k_batch_synth(const SynthArgs *scenes,
         __syncthreads();
         if (threadIdx.x == 0) s_item = (long long)atomicAdd(work, 1ull);
         __syncthreads();
-        const int64_t it = s_item;
+        // the item is the same in every lane: keep it, the scene search and
+        // the scene's arguments in scalar registers
+        const long long iv = s_item;
+        const int64_t it = (int64_t)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                                          (int)(iv >> 32)) << 32) |
+                                     (unsigned)__builtin_amdgcn_readfirstlane((int)iv));
         if (it >= n_items) break;
         int lo = 0, hi = S - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
             if (item_start[mid] <= it) lo = mid; else hi = mid - 1;
         }
-        const SynthArgs &A = scenes[lo];
-        const BatchSynthInfo &I = info[lo];
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const SynthArgs A = scenes[lo];
+        const BatchSynthInfo I = info[lo];
         const int local = (int)(it - item_start[lo]);
         const int g = local / I.bpg;
         const int rb = local - g * I.bpg;
         switch (I.kr) {
+#if RR_BATCH_MAX_KR >= 32
         case 32: synth_block<32>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
+#endif
         case 16: synth_block<16>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
         case 8: synth_block<8>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;
         case 4: synth_block<4>(A, g, rb, I.rows_per_group, I.rc, sp, tab); break;

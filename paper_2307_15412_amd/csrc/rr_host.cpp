@@ -990,7 +990,7 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0)
         const int64_t pchunks = (x.n_src * x.npts + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
         chunk[s + 1] = chunk[s] + rchunks + pchunks;
         const int K = x.chirp.n_samples, M = x.chirp.n_chirps;
-        if (x.kr <= 0) x.kr = largest_kr(K, 32);
+        if (x.kr <= 0) x.kr = largest_kr(K, RR_BATCH_MAX_KR);
         if (x.kr <= 0) return fail(RR_EUNSUPPORTED, "scene %d: n_samples too large", s);
         const int n_groups = shared ? 1 : x.ntx;
         const int RC = shared ? x.ntx * x.nrx : x.nrx;
@@ -1363,7 +1363,7 @@ int rr_batch_tune(rr_batch *b, void *const *cubes)
         float best_ms = 3.0e38f;
         int best = 0;
         for (int cand : {32, 16, 8, 4}) {
-            if (K % cand != 0 || K / cand > 256) continue;
+            if (cand > RR_BATCH_MAX_KR || K % cand != 0 || K / cand > 256) continue;
             for (auto &x : b->sc)
                 if (x.chirp.n_samples == K) x.kr = cand;
             // the candidate runs eagerly on a bounded prefix of the paths of

@@ -105,6 +105,12 @@ struct SynthArgs {
     int64_t p_limit;          // > 0: at most this many paths of each group (tile timing only)
 };
 
+// largest samples-per-lane tile of the batched synthesis kernel (its
+// register use, hence its occupancy, follows the largest tile it contains)
+#ifndef RR_BATCH_MAX_KR
+#define RR_BATCH_MAX_KR 32
+#endif
+
 // batched launch: per-scene tables read by the persistent kernels
 struct BatchSynthInfo {
     int kr;                   // samples per lane (tile shape)
