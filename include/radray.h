@@ -184,16 +184,17 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
  *          uses f0 and chirp 0 (a per-channel factor times a per-(chirp,
  *          sample) factor), which allows the complex-GEMM engine.
  *   engine RR_DIRECT_FP32 (either model), RR_GEMM_BF16X3 (separable only:
- *          split-bf16 hi+lo complex GEMM on MFMA, FP32 accumulation), or
- *          RR_ENGINE_AUTO (GEMM for the separable model, direct otherwise).
+ *          split-bf16 hi+lo complex GEMM on MFMA, FP32 accumulation; each
+ *          chirp's samples are computed in whole tiles of 64), or
+ *          RR_ENGINE_AUTO (GEMM for the separable model when the 64-sample
+ *          tiling pads a chirp by at most a quarter, direct otherwise).
  *   cube_dev complex64 [n_ch][n_chirps][n_samples], cube_elems = its complex
  *          element count; the cube is overwritten.
  *   sample_idx_dev int64 [n_sample] flat entry indices (c*M*K + m*K + k):
  *          when non-NULL only these entries are computed, into
  *          cube_dev[0..n_sample) (direct engine, FP64-reduced phase).
  * Errors: RR_ESTATE (no paths/array/chirp), RR_EINVAL, RR_EUNSUPPORTED
- * (GEMM engine with the exact model, with sample_idx_dev, or with n_samples
- * not a multiple of 64; RR_ENGINE_AUTO then picks the direct engine). */
+ * (GEMM engine with the exact model or with sample_idx_dev). */
 int rr_synthesize(rr_ctx *ctx, int32_t model, int32_t engine, void *cube_dev, int64_t cube_elems,
                   const int64_t *sample_idx_dev, int64_t n_sample);
 

@@ -242,15 +242,17 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
     if (total % 8 == 0) q = (int64_t)(blockIdx.x % 8) * (total / 8) + blockIdx.x / 8;
     const int rt = (int)(q / n_col_tiles);
     const int ct = (int)(q - (int64_t)rt * n_col_tiles);
-    const int64_t N = (int64_t)M * K;
     const int rb0 = rt * (GM_TM / 32) + wr * GM_WR;
 
     // B generator: path pair (2 pp, 2 pp + 1), columns nb + 32 h, h < GM_NCB
     const int pp = tid & 7;
     const int nb = tid >> 3;
-    const int64_t col0 = (int64_t)ct * GM_TN;
-    const int m = (int)(col0 / K);
-    const unsigned kbase = (unsigned)(col0 - (int64_t)m * K) + (unsigned)nb;
+    // column tile ct: chirp m, samples k0 .. k0 + GM_TN - 1 (each chirp's
+    // samples are padded to whole tiles; samples k >= K are not stored)
+    const int tpc = (K + GM_TN - 1) / GM_TN;
+    const int m = ct / tpc;
+    const int k0 = (ct - m * tpc) * GM_TN;
+    const unsigned kbase = (unsigned)k0 + (unsigned)nb;
     const int p0 = 2 * pp;
     const int flane = (p0 >> 3) * 32 + nb;
     // 32-bit word index of (fragment 0, this lane, slots p0 & 7 and +1)
@@ -425,8 +427,9 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
 #pragma unroll
             for (int e = 0; e < 16; e++) {
                 const int row = (rb0 + i) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                const int64_t col = col0 + (wc * GM_WC + j) * 32 + (lane & 31);
-                if (row < C) cube[(int64_t)row * N + col] = make_float2(sr[i][j][e], si[i][j][e]);
+                const int k = k0 + (wc * GM_WC + j) * 32 + (lane & 31);
+                if (row < C && k < K)
+                    cube[((int64_t)row * M + m) * K + k] = make_float2(sr[i][j][e], si[i][j][e]);
             }
 }
 
@@ -468,9 +471,9 @@ hipError_t launch_gemm_main(const uint4 *Af, const uint4 *Bp, int Cpad, int Ppad
                             int K, float2 *cube, hipStream_t s)
 {
     const int RB = Cpad / 32, KB = Ppad / GM_KS;
-    const int64_t N = (int64_t)M * K;
-    const int64_t n_col_tiles = N / GM_TN;
+    const int64_t n_col_tiles = (int64_t)M * ((K + GM_TN - 1) / GM_TN);
     const int64_t blocks = (int64_t)(Cpad / GM_TM) * n_col_tiles;
+    if (n_col_tiles > INT32_MAX || blocks > UINT32_MAX) return hipErrorInvalidValue;
     if (blocks <= 0 || KB <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gemm, dim3((unsigned)blocks), dim3(GM_THREADS), 0, s, Af, Bp, RB, KB, Ppad,
                        C, M, K, (int)n_col_tiles, cube);

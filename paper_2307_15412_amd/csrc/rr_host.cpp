@@ -575,19 +575,20 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
     if (!c->has_array || !c->has_chirp) return fail(RR_ESTATE, "array and chirp must be set");
     if (c->n_paths < 0) return fail(RR_ESTATE, "no paths (trace or rr_set_paths first)");
     if (model != RR_EXACT && model != RR_SEPARABLE) return fail(RR_EINVAL, "unknown model");
-    if (engine == RR_ENGINE_AUTO)
-        engine = (model == RR_SEPARABLE && !idx && c->chirp.n_samples % gemm_col_tile() == 0)
-                     ? RR_GEMM_BF16X3
-                     : RR_DIRECT_FP32;
+    if (engine == RR_ENGINE_AUTO) {
+        // the GEMM engine pads each chirp's samples to whole column tiles:
+        // take it for the separable model when that pads by at most a quarter
+        const int64_t K = c->chirp.n_samples, T = gemm_col_tile();
+        const int64_t Kp = (K + T - 1) / T * T;
+        engine = (model == RR_SEPARABLE && !idx && 4 * Kp <= 5 * K) ? RR_GEMM_BF16X3
+                                                                     : RR_DIRECT_FP32;
+    }
     if (engine != RR_DIRECT_FP32 && engine != RR_GEMM_BF16X3)
         return fail(RR_EINVAL, "unknown engine");
     if (engine == RR_GEMM_BF16X3 && model != RR_SEPARABLE)
         return fail(RR_EUNSUPPORTED, "the GEMM engine needs the separable model");
     if (engine == RR_GEMM_BF16X3 && idx)
         return fail(RR_EUNSUPPORTED, "sampled entries use the direct engine");
-    if (engine == RR_GEMM_BF16X3 && c->chirp.n_samples % gemm_col_tile() != 0)
-        return fail(RR_EUNSUPPORTED, "the GEMM engine needs n_samples divisible by %d",
-                    gemm_col_tile());
     const int64_t C = (int64_t)c->ntx * c->nrx, M = c->chirp.n_chirps, K = c->chirp.n_samples;
     const int64_t total = C * M * K;
     if (idx) {

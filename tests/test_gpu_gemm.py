@@ -1,8 +1,9 @@
 """Split-bf16 complex-GEMM synthesis (separable model) against the FP64
 oracle: relative error <= 1e-3 on the full cube or on seeded sampled
 entries; edge cases of the tiling (channel counts below one 512-row tile or
-just above it, one or three 64-column tiles per chirp, odd chirp counts, path
-counts not divisible by the 32-path padding, empty path list)."""
+just above it, one or three 64-column tiles per chirp, sample counts that end
+inside a column tile, odd chirp counts, path counts not divisible by the
+32-path padding, empty path list)."""
 import numpy as np
 import pytest
 import torch
@@ -63,7 +64,8 @@ def test_ragged_path_counts(gpu, orc, n_keep):
 
 
 @pytest.mark.parametrize("n_tx,n_rx,K,M,n_keep", [(3, 7, 64, 3, 33), (8, 65, 192, 2, 47),
-                                                  (1, 1, 64, 1, 1)])
+                                                  (1, 1, 64, 1, 1), (3, 7, 96, 3, 33),
+                                                  (8, 65, 200, 2, 47), (2, 3, 5, 2, 9)])
 def test_tile_edges(gpu, orc, n_tx, n_rx, K, M, n_keep):
     """Full cubes at channel, column and path counts around the tile sizes;
     the paths of a shared launch feed every channel."""
@@ -93,14 +95,17 @@ def test_empty_and_unsupported(gpu, orc):
     gpu.set_chirp(77e9, 1e9, 50e-6, 50e-6, 96, 2)
     _upload(gpu, op)
     with pytest.raises(rr.RadrayError) as e:
-        gpu.synthesize(model=1, engine=2)
-    assert e.value.code == rr.binding.RR_EUNSUPPORTED
-    with pytest.raises(rr.RadrayError):
         gpu.synthesize(model=0, engine=2)
-    # auto picks the direct engine where the GEMM cannot run
-    auto = gpu.synthesize(model=1, engine=0).cpu().numpy()
+    assert e.value.code == rr.binding.RR_EUNSUPPORTED
+    with pytest.raises(rr.RadrayError) as e:
+        gpu.synthesize(model=1, engine=2, sample_idx=np.arange(4))
+    assert e.value.code == rr.binding.RR_EUNSUPPORTED
+    # 96 samples pad to 128: auto picks the direct engine, the GEMM still runs
     ch = sg.Chirp(n_samples=96, n_chirps=2)
-    assert rel_err(auto, orc.synth(op, w.scene, w.array, ch, model=1)) < 1e-4
+    ref = orc.synth(op, w.scene, w.array, ch, model=1)
+    auto = gpu.synthesize(model=1, engine=0).cpu().numpy()
+    assert rel_err(auto, ref) < 1e-4
+    assert rel_err(gpu.synthesize(model=1, engine=2).cpu().numpy(), ref) < TOL_GEMM
 
 
 def test_street_per_tx_sampled(gpu, orc):
