@@ -81,6 +81,9 @@ def lib():
         L.orc_trace.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                 C.POINTER(C.c_int64)]
+        L.orc_trace_rays.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_uint64,
+                                     C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
         L.orc_synth.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_int, C.c_void_p, C.c_int64, C.c_void_p]
         L.orc_release.argtypes = []
@@ -226,6 +229,40 @@ def trace(scene, array, tp, vids=None, use_bvh=None, cdf=None, n_az=0, n_el=0,
                              _p(v), n, _p(hits), paths.ctypes.data, cap, C.byref(npaths))
         if rc != 0:
             raise RuntimeError(f"orc_trace failed: {rc}")
+        if npaths.value <= cap:
+            break
+        cap = npaths.value
+    lib().orc_release()
+    return hits, paths[: npaths.value].copy()
+
+
+def trace_rays(scene, array, orig, dirs, amp, src, max_bounces, seed, use_bvh=None,
+               want_hits=True):
+    """Trace caller-supplied rays: orig, dirs float64 [n][3] (directions are
+    normalised), amp float64 [n], src int32 [n] (-1 for a shared launch, else
+    ascending Tx indices).  Returns (hits, paths) as trace() does, with
+    ray = the index of the ray."""
+    if use_bvh is None:
+        use_bvh = scene.n_tris > 1000
+    keep = _Keep()
+    sc = _scene(scene, keep)
+    ar = _array(array, keep)
+    o = keep.add(orig, np.float64).reshape(-1, 3)
+    d = keep.add(dirs, np.float64).reshape(-1, 3)
+    a = keep.add(amp, np.float64).reshape(-1)
+    s = keep.add(src, np.int32).reshape(-1)
+    n = o.shape[0]
+    assert d.shape[0] == n and a.shape[0] == n and s.shape[0] == n
+    hits = np.full((n, max_bounces + 1), -1, dtype=np.int32) if want_hits else None
+    cap = max(1024, n // 8)
+    while True:
+        paths = np.zeros(cap, dtype=PATH_DTYPE)
+        npaths = C.c_int64()
+        rc = lib().orc_trace_rays(C.addressof(sc), C.addressof(ar), int(use_bvh), n, _p(o), _p(d),
+                                  _p(a), _p(s), int(max_bounces), int(seed) & (2**64 - 1),
+                                  _p(hits), paths.ctypes.data, cap, C.byref(npaths))
+        if rc != 0:
+            raise ValueError(f"orc_trace_rays rejected its input ({rc})")
         if npaths.value <= cap:
             break
         cap = npaths.value

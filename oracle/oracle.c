@@ -536,6 +536,52 @@ static int emit(orc_path *paths, int64_t cap, int64_t *np, const orc_path *p)
     return 0;
 }
 
+/* The bounces of one ray leaving o along the unit vector dir (Sec. III-A):
+ * closest hit, reception of every segment that follows a hit (reading R15:
+ * its closest approach to the Rx phase centre oR lies ahead, before the next
+ * hit, inside the sphere of radius sqrt(r2)), and at each hit the new
+ * direction of Eqs. 1-3 with the random numbers of counter (i, t, j + 1).
+ * pa carries src, ray and amp; its hit points are filled in here. */
+static void trace_from(const orc_scene *sc, vec3 oR, uint64_t seed, int32_t B, double r2, vec3 o,
+                       vec3 dir, int64_t i, int64_t t, orc_path *pa, int32_t *hrow,
+                       orc_path *paths, int64_t cap, int64_t *np)
+{
+    double L = 0.0;
+    int64_t prev = -1;
+    for (int32_t j = 0; j <= B; j++) {
+        double th;
+        int64_t h = closest(sc, o, dir, prev, &th);
+        if (hrow) hrow[j] = (int32_t)h;
+        if (j >= 1) {
+            vec3 w2 = vsub(oR, o);
+            double ts = vdot(w2, dir);
+            if (ts > 0.0 && ts < th) {
+                double cx = (o.x + ts * dir.x) - oR.x;
+                double cy = (o.y + ts * dir.y) - oR.y;
+                double cz = (o.z + ts * dir.z) - oR.z;
+                if (cx * cx + cy * cy + cz * cz <= r2) {
+                    pa->K = j;
+                    pa->L = L;
+                    emit(paths, cap, np, pa);
+                }
+            }
+        }
+        if (h < 0 || j == B) break;
+        vec3 p = mk(o.x + th * dir.x, o.y + th * dir.y, o.z + th * dir.z);
+        L += th;
+        pa->tri[j] = (int32_t)h;
+        pa->vid[j] = sc->tri_obj[h];
+        pa->p[j][0] = p.x; pa->p[j][1] = p.y; pa->p[j][2] = p.z;
+        vec3 n = orc_face_normal(sc, h, dir);
+        double u[4];
+        draw(seed, (uint64_t)i, (uint64_t)t, (uint64_t)(j + 1), u);
+        double alpha = (double)sc->obj_alpha[sc->tri_obj[h]];
+        dir = bounce_dir(dir, n, alpha, u[0], u[1]);
+        o = p;
+        prev = h;
+    }
+}
+
 /* Trace the listed virtual rays (all of them when vids == NULL).
  * Virtual ray v of source t = v / (n_per_src + npts): index i = v mod that;
  * i < n_per_src is a launched ray, otherwise point reflector i - n_per_src.
@@ -594,43 +640,57 @@ int orc_trace(const orc_scene *sc, const orc_array *ar, const orc_trace_params *
         double w;
         vec3 dir = launch(tp, &s, i, t, &w);
         pa.amp = w / (double)s.n_per_src;
-        vec3 o = src;
-        double L = 0.0;
-        int64_t prev = -1;
-        for (int32_t j = 0; j <= B; j++) {
-            double th;
-            int64_t h = closest(sc, o, dir, prev, &th);
-            if (hrow) hrow[j] = (int32_t)h;
-            if (j >= 1) {
-                /* reception: closest approach of this segment to the Rx phase
-                 * centre lies ahead, before the next hit, inside the sphere */
-                vec3 w2 = vsub(s.oR, o);
-                double ts = vdot(w2, dir);
-                if (ts > 0.0 && ts < th) {
-                    double cx = (o.x + ts * dir.x) - s.oR.x;
-                    double cy = (o.y + ts * dir.y) - s.oR.y;
-                    double cz = (o.z + ts * dir.z) - s.oR.z;
-                    if (cx * cx + cy * cy + cz * cz <= r2) {
-                        pa.K = j;
-                        pa.L = L;
-                        emit(paths, cap, &np, &pa);
-                    }
-                }
-            }
-            if (h < 0 || j == B) break;
-            vec3 p = mk(o.x + th * dir.x, o.y + th * dir.y, o.z + th * dir.z);
-            L += th;
-            pa.tri[j] = (int32_t)h;
-            pa.vid[j] = sc->tri_obj[h];
-            pa.p[j][0] = p.x; pa.p[j][1] = p.y; pa.p[j][2] = p.z;
-            vec3 n = orc_face_normal(sc, h, dir);
-            double u[4];
-            draw(tp->seed, (uint64_t)i, (uint64_t)t, (uint64_t)(j + 1), u);
-            double alpha = (double)sc->obj_alpha[sc->tri_obj[h]];
-            dir = bounce_dir(dir, n, alpha, u[0], u[1]);
-            o = p;
-            prev = h;
-        }
+        trace_from(sc, s.oR, tp->seed, B, r2, src, dir, i, t, &pa, hrow, paths, cap, &np);
+    }
+    *n_paths = np;
+    return 0;
+}
+
+/* Trace n caller-supplied rays (Sec. III-A launches rays from each
+ * transmitter; here the caller picks them): ray i starts at orig[i] along
+ * dir[i] (normalised here), every path it produces has amplitude amp[i] and
+ * source src[i] (-1 for a shared launch, else a Tx index in [0, ntx),
+ * ascending over i).  The bounce at hit j uses the random numbers of counter
+ * (i - i0, max(src[i], 0), j + 1), i0 the first ray of the same source: so
+ * the launch's own rays reproduce orc_trace exactly.  No point reflectors.  Paths are emitted in
+ * (ray, bounce) order with ray = i; hits as in orc_trace.  Returns -1 for an
+ * invalid source list or a non-finite or zero vector. */
+int orc_trace_rays(const orc_scene *sc, const orc_array *ar, int use_bvh, int64_t n,
+                   const double *orig, const double *dir, const double *amp, const int32_t *src,
+                   int32_t max_bounces, uint64_t seed, int32_t *hits, orc_path *paths, int64_t cap,
+                   int64_t *n_paths)
+{
+    if (max_bounces < 1 || max_bounces > ORC_KMAX || n < 0) return -1;
+    if (ar->ntx < 1 || ar->nrx < 1) return -1;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t t = src[i];
+        if (ar->shared ? t != -1 : (t < 0 || t >= ar->ntx || (i > 0 && t < src[i - 1]))) return -1;
+        for (int a = 0; a < 3; a++)
+            if (!isfinite(orig[3 * i + a]) || !isfinite(dir[3 * i + a])) return -1;
+        if (!isfinite(amp[i])) return -1;
+        if (dir[3 * i] == 0.0 && dir[3 * i + 1] == 0.0 && dir[3 * i + 2] == 0.0) return -1;
+    }
+    if (use_bvh && g_bvh_scene != sc && bvh_build(sc) != 0) return -2;
+    g_use_bvh = use_bvh;
+    vec3 oR = centroid(ar->rx, ar->nrx);
+    double r2 = ar->rx_radius * ar->rx_radius;
+    int32_t B = max_bounces;
+    int64_t np = 0;
+    int64_t i0 = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (i > 0 && src[i] != src[i - 1]) i0 = i;
+        int32_t *hrow = hits ? hits + i * (B + 1) : NULL;
+        if (hrow) for (int j = 0; j <= B; j++) hrow[j] = -1;
+        orc_path pa;
+        memset(&pa, 0, sizeof(pa));
+        pa.src = src[i];
+        pa.ray = i;
+        pa.amp = amp[i];
+        for (int j = 0; j < ORC_KMAX; j++) { pa.tri[j] = -1; pa.vid[j] = -1; }
+        vec3 d = vload3d(dir + 3 * i);
+        d = vdiv(d, vlen(d));
+        trace_from(sc, oR, seed, B, r2, vload3d(orig + 3 * i), d, i - i0, src[i] > 0 ? src[i] : 0,
+                   &pa, hrow, paths, cap, &np);
     }
     *n_paths = np;
     return 0;
