@@ -135,6 +135,29 @@ typedef struct {
  * RR_EINVAL, RR_ENOMEM, RR_EHIP. */
 int rr_trace(rr_ctx *ctx, const rr_trace_params *params, int64_t *n_paths_out);
 
+/* Trace caller-supplied rays instead of the launch (Sec. III-A sends rays
+ * out from each transmitter; here the caller chooses them, e.g. for another
+ * launch density or rays cast at given triangles).
+ *   orig_dev, dir_dev double [n][3]: origin and direction of ray i (the
+ *                     direction is normalised here; it must be non-zero)
+ *   amp_dev  double [n]: amplitude of every path ray i produces (the launch
+ *                     uses w / N_t)
+ *   src_dev  int32 [n]: -1 for every ray with a RR_TX_SHARED array; with
+ *                     RR_TX_PER_ELEMENT the Tx index in [0, n_tx), ascending
+ *                     over i (each path feeds its Tx's channels)
+ * Bounces, reception and path bookkeeping are those of rr_trace, with the
+ * random numbers of the bounce at hit j drawn from counter (i - i0, src, j + 1)
+ * (i0: the first ray of the same source, src: 0 for -1), so that the launch's
+ * own rays reproduce rr_trace exactly.  Point reflectors are not traced.
+ * Paths are ordered by (ray, bounce) with ray = i; with record_hits the hit
+ * list has n rows (rr_get_hits).  Synchronises; n_paths_out may be NULL.
+ * Errors: RR_ESTATE (no scene or array), RR_EINVAL (bad bounce count, NULL
+ * arrays, a source out of range or not ascending, a non-finite value or a
+ * zero direction, found by a device check before tracing), RR_ENOMEM. */
+int rr_trace_rays(rr_ctx *ctx, const double *orig_dev, const double *dir_dev,
+                  const double *amp_dev, const int32_t *src_dev, int64_t n,
+                  int32_t max_bounces, uint64_t seed, int32_t record_hits, int64_t *n_paths_out);
+
 /* Number of paths held by the context (synchronises).  RR_EOVERFLOW (with
  * the needed count in *n_out) if the last asynchronous trace overflowed. */
 int rr_get_path_count(rr_ctx *ctx, int64_t *n_out);

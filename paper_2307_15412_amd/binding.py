@@ -26,8 +26,8 @@ KMAX = 4
 
 EXPORTED = [
     "rr_create", "rr_destroy", "rr_last_error", "rr_version", "rr_scene_upload", "rr_set_array",
-    "rr_set_chirp", "rr_trace", "rr_get_path_count", "rr_get_hits", "rr_get_paths",
-    "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms",
+    "rr_set_chirp", "rr_trace", "rr_trace_rays", "rr_get_path_count", "rr_get_hits",
+    "rr_get_paths", "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms",
 ]
 
 
@@ -76,6 +76,8 @@ def load_library(path: str = LIB_PATH):
     L.rr_set_array.argtypes = [vp, vp, i32, vp, i32, f64, i32]
     L.rr_set_chirp.argtypes = [vp, C.POINTER(Chirp)]
     L.rr_trace.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
+    L.rr_trace_rays.argtypes = [vp, vp, vp, vp, vp, i64, C.c_int32, C.c_uint64, C.c_int32,
+                                C.POINTER(i64)]
     L.rr_get_path_count.argtypes = [vp, C.POINTER(i64)]
     L.rr_get_hits.argtypes = [vp, vp, i64]
     L.rr_get_paths.argtypes = [vp, C.POINTER(Paths), C.POINTER(i64)]
@@ -170,6 +172,29 @@ class Context:
         n_src = 1 if self.mode == TX_SHARED else self.n_tx
         per = int(n_rays) if self.mode == TX_SHARED else int(n_rays) // self.n_tx
         self.n_traced = n_src * per
+        self.max_bounces = int(max_bounces)
+        self.record_hits = bool(record_hits)
+        return self.n_paths
+
+    def trace_rays(self, orig, dirs, amp, src, max_bounces=2, seed=0, record_hits=True) -> int:
+        """Trace caller-supplied rays: orig, dirs [n][3] and amp [n] as float64,
+        src [n] int32 (host or device tensors or arrays)."""
+        torch = self.torch
+        dev = lambda x, dt: torch.as_tensor(x).to(device=self.device, dtype=dt).contiguous()
+        o = dev(orig, torch.float64).reshape(-1, 3)
+        d = dev(dirs, torch.float64).reshape(-1, 3)
+        a = dev(amp, torch.float64).reshape(-1)
+        s = dev(src, torch.int32).reshape(-1)
+        n = o.shape[0]
+        if d.shape[0] != n or a.shape[0] != n or s.shape[0] != n:
+            raise ValueError("orig, dirs, amp and src must have the same number of rays")
+        cnt = C.c_int64()
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if n else None
+        self._check(self.lib.rr_trace_rays(self.h, ptr(o), ptr(d), ptr(a), ptr(s), n,
+                                           int(max_bounces), int(seed) & (2**64 - 1),
+                                           int(bool(record_hits)), C.byref(cnt)))
+        self.n_paths = cnt.value
+        self.n_traced = n
         self.max_bounces = int(max_bounces)
         self.record_hits = bool(record_hits)
         return self.n_paths

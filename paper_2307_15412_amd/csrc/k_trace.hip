@@ -267,6 +267,9 @@ __device__ __forceinline__ void append(const TraceArgs &A, bool rec, int32_t src
 }
 
 // one launched ray g (source-major) through all of its bounces
+__device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, int64_t i, int64_t t, int64_t v,
+                           double amp, int32_t srcid, int32_t *hrow, int *stk);
+
 __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
 {
     int64_t t = g / A.n_per_src;
@@ -298,7 +301,34 @@ __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
     const double amp = w / (double)A.n_per_src;
     const int32_t srcid = A.shared ? -1 : (int32_t)t;
     int32_t *hrow = A.hits ? A.hits + g * (A.bmax + 1) : nullptr;
+    trace_from(A, src, dir, i, t, v, amp, srcid, hrow, stk);
+}
 
+// Caller-supplied ray g: origin, direction (normalised here), amplitude and
+// source from U; its bounce random numbers use the ray's index within its
+// source's run of rays, so that the launch's own rays reproduce k_trace.
+__device__ void trace_user(const TraceArgs &A, const UserRays &U, int64_t g, int *stk)
+{
+    const int32_t srcid = U.src[g];
+    int64_t lo = 0, hi = g;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (U.src[mid] < srcid) lo = mid + 1; else hi = mid;
+    }
+    d3 o = mk3(U.orig[3 * g], U.orig[3 * g + 1], U.orig[3 * g + 2]);
+    d3 d = mk3(U.dir[3 * g], U.dir[3 * g + 1], U.dir[3 * g + 2]);
+    d = div3(d, sqrt(dot3(d, d)));
+    int32_t *hrow = A.hits ? A.hits + g * (A.bmax + 1) : nullptr;
+    trace_from(A, o, d, g - lo, srcid > 0 ? srcid : 0, A.vbase + g, U.amp[g], srcid, hrow, stk);
+}
+
+// The bounces of one ray from o along the unit vector dir: closest hit,
+// reception of every segment that follows a hit, the direction of Eqs. 1-3
+// at each hit with the random numbers of counter (i, t, j + 1); paths carry
+// source srcid, virtual ray v and amplitude amp.
+__device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, int64_t i, int64_t t, int64_t v,
+                           double amp, int32_t srcid, int32_t *hrow, int *stk)
+{
     Rec R;
 #pragma unroll
     for (int q = 0; q < RR_KMAX; q++) {
@@ -399,6 +429,30 @@ __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace(TraceArgs A, int64_t n
     __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
     const int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
     if (g < n_traced) trace_ray(A, g, lds_stack + threadIdx.x);
+}
+
+__global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace_user(TraceArgs A, UserRays U)
+{
+    __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
+    const int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
+    if (g < U.n) trace_user(A, U, g, lds_stack + threadIdx.x);
+}
+
+// flag = 1 if a source is out of range (-1 only, for a shared launch) or
+// below its predecessor, or a vector is non-finite or zero
+__global__ void k_check_user(UserRays U, int shared, int ntx, int *flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= U.n) return;
+    const int32_t t = U.src[i];
+    bool bad = shared ? t != -1 : (t < 0 || t >= ntx || (i > 0 && t < U.src[i - 1]));
+    double ss = 0.0;
+    for (int a = 0; a < 3; a++) {
+        bad = bad || !isfinite(U.orig[3 * i + a]) || !isfinite(U.dir[3 * i + a]);
+        ss += fabs(U.dir[3 * i + a]);
+    }
+    bad = bad || !isfinite(U.amp[i]) || ss == 0.0;
+    if (bad) *flag = 1;
 }
 
 __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_points(TraceArgs A)
@@ -611,6 +665,22 @@ hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s)
     if (n_traced <= 0) return hipSuccess;
     int64_t blocks = (n_traced + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
     hipLaunchKernelGGL(k_trace, dim3((unsigned)blocks), dim3(RR_TRACE_BLOCK), 0, s, a, n_traced);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_user(const TraceArgs &a, const UserRays &u, hipStream_t s)
+{
+    if (u.n <= 0) return hipSuccess;
+    int64_t blocks = (u.n + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
+    hipLaunchKernelGGL(k_trace_user, dim3((unsigned)blocks), dim3(RR_TRACE_BLOCK), 0, s, a, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_user(const UserRays &u, int shared, int ntx, int *flag, hipStream_t s)
+{
+    if (u.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_user, dim3((unsigned)((u.n + 255) / 256)), dim3(256), 0, s, u,
+                       shared, ntx, flag);
     return hipGetLastError();
 }
 

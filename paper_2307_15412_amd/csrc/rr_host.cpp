@@ -158,6 +158,54 @@ struct rr_ctx {
     int mlp_step = 0;
 };
 
+namespace {
+
+// The trace stage of rr_trace / rr_trace_rays: tracing kernels, scan of the
+// per-ray counts, scatter into (ray, bounce) order; grows the temporary
+// buffer and re-runs once if it overflowed.
+template <class Kernels>
+int run_trace(rr_ctx *c, TraceArgs &A, int64_t V, int64_t nb, int64_t path_cap, Kernels kernels,
+              int64_t *n_paths_out)
+{
+    int rc;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        A.tmp = c->tmp.soa;
+        HIPCHK(hipMemsetAsync(c->counter.p, 0, 8, c->stream));
+        HIPCHK(hipMemsetAsync(c->err_flag.p, 0, 4, c->stream));
+        HIPCHK(hipEventRecord(c->ev[0], c->stream));
+        HIPCHK(kernels(A));
+        HIPCHK(launch_scan_u8(A.counts, V, c->offsets.as<uint32_t>(), c->bsums.as<uint32_t>(),
+                              nb + 1, c->total.as<unsigned long long>(), c->stream));
+        unsigned long long cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, c->counter.p, 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if ((int64_t)cnt > c->tmp_cap) {
+            c->tmp_cap = (int64_t)cnt + cnt / 4 + 1024;
+            if ((rc = c->tmp.alloc(c->tmp_cap))) return rc;
+            continue;
+        }
+        int64_t keep = (int64_t)cnt;
+        if (path_cap > 0 && keep > path_cap) keep = path_cap;
+        if ((rc = c->paths.alloc(std::max<int64_t>(keep, 1)))) return rc;
+        HIPCHK(launch_scatter(c->tmp.soa, A.counter, c->tmp_cap, c->offsets.as<uint32_t>(),
+                              c->paths.soa, keep, c->stream));
+        HIPCHK(hipEventRecord(c->ev[1], c->stream));
+        int errf = 0;
+        HIPCHK(hipMemcpyAsync(&errf, c->err_flag.p, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (errf) return fail(RR_EHIP, "traversal stack overflow (BVH depth %d)", c->bvh_depth);
+        c->n_paths = keep;
+        c->trace_timed = true;
+        c->last = A;
+        if (n_paths_out) *n_paths_out = keep;
+        g_err.clear();
+        return RR_OK;
+    }
+    return fail(RR_EOVERFLOW, "temporary path buffer overflow persisted");
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *rr_last_error(void) { return g_err.c_str(); }
@@ -411,44 +459,93 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
     A.counter = c->counter.as<unsigned long long>();
     A.err_flag = c->err_flag.as<int>();
 
-    for (int attempt = 0; attempt < 2; attempt++) {
-        A.tmp = c->tmp.soa;
-        HIPCHK(hipMemsetAsync(c->counter.p, 0, 8, c->stream));
-        HIPCHK(hipMemsetAsync(c->err_flag.p, 0, 4, c->stream));
-        HIPCHK(hipEventRecord(c->ev[0], c->stream));
-        HIPCHK(launch_trace(A, n_traced, c->stream));
-        HIPCHK(launch_points(A, c->stream));
-        HIPCHK(launch_scan_u8(A.counts, V, c->offsets.as<uint32_t>(), c->bsums.as<uint32_t>(),
-                              nb + 1, c->total.as<unsigned long long>(), c->stream));
-        unsigned long long cnt = 0;
-        HIPCHK(hipMemcpyAsync(&cnt, c->counter.p, 8, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if ((int64_t)cnt > c->tmp_cap) {
-            c->tmp_cap = (int64_t)cnt + cnt / 4 + 1024;
-            if ((rc = c->tmp.alloc(c->tmp_cap))) return rc;
-            continue;
-        }
-        int64_t keep = (int64_t)cnt;
-        if (tp->path_cap > 0 && keep > tp->path_cap) keep = tp->path_cap;
-        if ((rc = c->paths.alloc(std::max<int64_t>(keep, 1)))) return rc;
-        HIPCHK(launch_scatter(c->tmp.soa, A.counter, c->tmp_cap, c->offsets.as<uint32_t>(),
-                              c->paths.soa, keep, c->stream));
-        HIPCHK(hipEventRecord(c->ev[1], c->stream));
-        int errf = 0;
-        HIPCHK(hipMemcpyAsync(&errf, c->err_flag.p, 4, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (errf) return fail(RR_EHIP, "traversal stack overflow (BVH depth %d)", c->bvh_depth);
-        c->n_paths = keep;
-        c->trace_timed = true;
-        c->last = A;
-        c->last_traced = n_traced;
-        c->last_sampler = tp->record_hits ? tp->sampler : -1;
-        if (n_paths_out) *n_paths_out = keep;
-        g_err.clear();
-        return RR_OK;
-    }
-    return fail(RR_EOVERFLOW, "temporary path buffer overflow persisted");
+    auto kernels = [&](const TraceArgs &a) -> hipError_t {
+        hipError_t e = launch_trace(a, n_traced, c->stream);
+        return e == hipSuccess ? launch_points(a, c->stream) : e;
+    };
+    int rc2 = run_trace(c, A, V, nb, tp->path_cap, kernels, n_paths_out);
+    if (rc2) return rc2;
+    c->last_traced = n_traced;
+    c->last_sampler = tp->record_hits ? tp->sampler : -1;
+    return RR_OK;
 }
+
+// Caller-supplied rays: validated on the device, then traced like the launch.
+int rr_trace_rays(rr_ctx *c, const double *orig, const double *dir, const double *amp,
+                  const int32_t *src, int64_t n, int32_t max_bounces, uint64_t seed,
+                  int32_t record_hits, int64_t *n_paths_out)
+{
+    if (!c) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_scene || !c->has_array) return fail(RR_ESTATE, "scene and array must be set");
+    if (max_bounces < 1 || max_bounces > RR_KMAX)
+        return fail(RR_EINVAL, "max_bounces must be in [1, %d]", RR_KMAX);
+    if (n < 0) return fail(RR_EINVAL, "negative ray count");
+    if (n > 0 && (!orig || !dir || !amp || !src)) return fail(RR_EINVAL, "NULL ray array");
+    if (n >= (int64_t(1) << 32)) return fail(RR_EUNSUPPORTED, "too many rays");
+    HIPCHK(hipSetDevice(c->device));
+    const int shared = c->mode == RR_TX_SHARED;
+    UserRays U{orig, dir, amp, src, n};
+    int rc;
+    if (n > 0) {
+        int bad = 0;
+        HIPCHK(hipMemsetAsync(c->err_flag.p, 0, 4, c->stream));
+        HIPCHK(launch_check_user(U, shared, c->ntx, c->err_flag.as<int>(), c->stream));
+        HIPCHK(hipMemcpyAsync(&bad, c->err_flag.p, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (bad)
+            return fail(RR_EINVAL, shared ? "rays: sources must be -1 (shared launch), vectors finite, directions non-zero"
+                                          : "rays: sources must ascend within [0, n_tx), vectors finite, directions non-zero");
+    }
+    const int64_t V = n;
+    if ((rc = c->counts.ensure((size_t)V + 64))) return rc;
+    if ((rc = c->offsets.ensure((size_t)V * 4 + 64))) return rc;
+    const int64_t nb = scan_u8_blocks(V);
+    if ((rc = c->bsums.ensure((size_t)(nb + 1) * 4))) return rc;
+    if (record_hits) {
+        if ((rc = c->hits.ensure((size_t)n * (max_bounces + 1) * 4 + 64))) return rc;
+        c->hits_elems = n * (max_bounces + 1);
+        c->hits_recorded = true;
+    } else {
+        c->hits_elems = 0;
+        c->hits_recorded = false;
+    }
+    if (c->tmp_cap == 0) c->tmp_cap = std::max<int64_t>(65536, V / 32);
+    if ((rc = c->tmp.alloc(c->tmp_cap))) return rc;
+
+    TraceArgs A{};
+    A.nodes = c->nodes.as<const float4>();
+    A.ltris = c->ltris.as<const float4>();
+    A.has_bvh = c->n_tris > 0;
+    A.obj_alpha = c->obj_alpha.as<const float>();
+    A.tx = c->tx.as<const double>();
+    for (int a = 0; a < 3; a++) {
+        A.oT[a] = c->oT[a];
+        A.oR[a] = c->oR[a];
+    }
+    A.r2 = c->rx_radius * c->rx_radius;
+    A.shared = shared;
+    A.nobj = c->nobj;
+    A.npts = 0;
+    A.n_src = 1;
+    A.n_per_src = n;
+    A.n_virt_per_src = n;
+    A.bmax = max_bounces;
+    A.seed = seed;
+    A.sampler = RR_UNIFORM;
+    A.hits = record_hits ? c->hits.as<int32_t>() : nullptr;
+    A.counts = c->counts.as<uint8_t>();
+    A.counter = c->counter.as<unsigned long long>();
+    A.err_flag = c->err_flag.as<int>();
+    auto kernels = [&](const TraceArgs &a) -> hipError_t {
+        return launch_trace_user(a, U, c->stream);
+    };
+    if ((rc = run_trace(c, A, V, nb, 0, kernels, n_paths_out))) return rc;
+    c->last_traced = n;
+    c->last_sampler = -1;
+    return RR_OK;
+}
+
+
 
 int rr_get_path_count(rr_ctx *c, int64_t *n_out)
 {

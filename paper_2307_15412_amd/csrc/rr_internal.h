@@ -79,6 +79,15 @@ struct TraceArgs {
     int *err_flag;
 };
 
+// caller-supplied rays (device arrays)
+struct UserRays {
+    const double *orig;       // [n][3]
+    const double *dir;        // [n][3]
+    const double *amp;        // [n]
+    const int32_t *src;       // [n]
+    int64_t n;
+};
+
 // ---------------------------------------------------------------------------
 // synthesis path record (AoS, prepared from the path list)
 // ---------------------------------------------------------------------------
@@ -134,6 +143,8 @@ struct BatchRangeInfo {
 // launchers (defined in the .hip files)
 hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s);
 hipError_t launch_points(const TraceArgs &a, hipStream_t s);
+hipError_t launch_trace_user(const TraceArgs &a, const UserRays &u, hipStream_t s);
+hipError_t launch_check_user(const UserRays &u, int shared, int ntx, int *flag, hipStream_t s);
 hipError_t launch_scan_u8(const uint8_t *counts, int64_t n, uint32_t *offsets, uint32_t *bsums,
                           int64_t nb_cap, unsigned long long *total, hipStream_t s);
 int64_t scan_u8_blocks(int64_t n);
