@@ -271,6 +271,17 @@ int rr_mlp_forward(rr_ctx *ctx, const float *codes_dev, int32_t n_scenes, float 
 int rr_mlp_train_step(rr_ctx *ctx, const float *codes_dev, const float *hist_dev, int32_t n_scenes,
                       float lr, float *loss_out, float *grad_dev);
 
+/* `steps` Adam steps on minibatches of `batch` scenes (all scenes when
+ * batch >= n_scenes), each drawn without replacement by a partial
+ * Fisher-Yates shuffle driven by SplitMix64 (Steele et al. 2014) from `seed`;
+ * every step is rr_mlp_train_step on the gathered rows.  codes_dev float
+ * [n_scenes][16], hist_dev float [n_scenes][RR_PROP_NAZ * RR_PROP_NEL]
+ * (device).  loss_out (host float [steps], may be NULL): each step's loss
+ * summed over its scenes.  Synchronises only when loss_out is given.
+ * Errors: RR_ESTATE (network not initialised), RR_EINVAL. */
+int rr_proposal_train(rr_ctx *ctx, const float *codes_dev, const float *hist_dev, int32_t n_scenes,
+                      int32_t steps, int32_t batch, float lr, uint64_t seed, float *loss_out);
+
 /* Build the sampling table of one scene from the network: q = (1 - beta)
  * softmax(z) + beta / n_bins, CDF in FP64.  code16_dev: that scene's code
  * (device).  Afterwards rr_trace with sampler RR_PROPOSAL draws from it. */

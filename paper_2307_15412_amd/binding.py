@@ -313,6 +313,7 @@ def _declare_proposal(L):
     L.rr_mlp_get_params.argtypes = [vp, vp, i64]
     L.rr_mlp_forward.argtypes = [vp, vp, i32, vp]
     L.rr_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp]
+    L.rr_proposal_train.argtypes = [vp, vp, vp, i32, i32, i32, C.c_float, C.c_uint64, vp]
     L.rr_proposal_build.argtypes = [vp, vp, C.c_float]
     _PROP_DECLARED = True
 
@@ -384,6 +385,19 @@ class _ProposalMixin:
                                                  _ptr(grad) if grad is not None else None))
         return (loss.value, grad) if want_grad else loss.value
 
+    def proposal_train(self, codes, hists, steps, batch=16, lr=1e-3, seed=0):
+        """`steps` Adam steps on minibatches drawn in the library; returns the
+        per-step losses (numpy float32 [steps])."""
+        codes = codes.to(self.device, self.torch.float32).contiguous().reshape(-1, 16)
+        hists = hists.to(self.device, self.torch.float32).contiguous().reshape(-1, PROP_NAZ * PROP_NEL)
+        if codes.shape[0] != hists.shape[0]:
+            raise ValueError("codes and histograms must have the same number of scenes")
+        loss = np.zeros(max(int(steps), 1), dtype=np.float32)
+        self._check(self._pl().rr_proposal_train(self.h, _ptr(codes), _ptr(hists), codes.shape[0],
+                                                  int(steps), int(batch), float(lr),
+                                                  int(seed) & (2**64 - 1), loss.ctypes.data))
+        return loss[: int(steps)]
+
     def proposal_build(self, code, beta=0.1):
         code = code.to(self.device, self.torch.float32).contiguous().reshape(16)
         self._check(self._pl().rr_proposal_build(self.h, _ptr(code), float(beta)))
@@ -395,7 +409,7 @@ for _name, _fn in list(vars(_ProposalMixin).items()):
         setattr(Context, _name, _fn)
 EXPORTED += ["rr_proposal_set_cdf", "rr_proposal_get_cdf", "rr_proposal_probe",
              "rr_proposal_histogram", "rr_mlp_init", "rr_mlp_set_params", "rr_mlp_get_params",
-             "rr_mlp_forward", "rr_mlp_train_step", "rr_proposal_build"]
+             "rr_mlp_forward", "rr_mlp_train_step", "rr_proposal_train", "rr_proposal_build"]
 
 
 # --------------------------------------------------------------------------

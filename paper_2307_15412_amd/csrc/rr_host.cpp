@@ -154,6 +154,7 @@ struct rr_ctx {
     int64_t last_traced = 0;
     int last_sampler = -1;
     DevBuf mlp_p, mlp_m, mlp_v, mlp_g, mlp_acts, mlp_z, mlp_dz, mlp_d, mlp_loss;
+    DevBuf tr_codes, tr_hist, tr_loss;   // minibatch staging of rr_proposal_train
     bool mlp_ready = false;
     int mlp_step = 0;
 };
@@ -253,7 +254,8 @@ void rr_destroy(rr_ctx *c)
                       &c->counter, &c->total, &c->err_flag, &c->hits, &c->cdf, &c->syn,
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
-                      &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss};
+                      &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
+                      &c->tr_codes, &c->tr_hist, &c->tr_loss};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -935,14 +937,11 @@ int rr_mlp_forward(rr_ctx *c, const float *codes, int32_t n_scenes, float *logit
     return RR_OK;
 }
 
-int rr_mlp_train_step(rr_ctx *c, const float *codes, const float *hist, int32_t n_scenes, float lr,
-                      float *loss_out, float *grad_out)
+// one Adam step (lr > 0) on n_scenes rows of codes / hist (device); the
+// per-scene losses stay in mlp_loss
+static int mlp_step(rr_ctx *c, const float *codes, const float *hist, int32_t n_scenes, float lr,
+                    float *grad_out)
 {
-    if (!c || !codes || !hist) return fail(RR_EINVAL, "NULL argument");
-    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
-    if (n_scenes < 1) return fail(RR_EINVAL, "n_scenes must be positive");
-    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(RR_EINVAL, "invalid learning rate");
-    HIPCHK(hipSetDevice(c->device));
     const int64_t rows = (int64_t)n_scenes * RR_PROP_NAZ * RR_PROP_NEL;
     int rc = mlp_buffers(c, rows, n_scenes);
     if (rc) return rc;
@@ -964,6 +963,19 @@ int rr_mlp_train_step(rr_ctx *c, const float *codes, const float *hist, int32_t 
         HIPCHK(launch_adam(c->mlp_p.as<float>(), c->mlp_g.as<const float>(), c->mlp_m.as<float>(),
                            c->mlp_v.as<float>(), lr, c->mlp_step, c->stream));
     }
+    return RR_OK;
+}
+
+int rr_mlp_train_step(rr_ctx *c, const float *codes, const float *hist, int32_t n_scenes, float lr,
+                      float *loss_out, float *grad_out)
+{
+    if (!c || !codes || !hist) return fail(RR_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
+    if (n_scenes < 1) return fail(RR_EINVAL, "n_scenes must be positive");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(RR_EINVAL, "invalid learning rate");
+    HIPCHK(hipSetDevice(c->device));
+    int rc = mlp_step(c, codes, hist, n_scenes, lr, grad_out);
+    if (rc) return rc;
     if (loss_out) {
         std::vector<float> l(n_scenes);
         HIPCHK(hipMemcpyAsync(l.data(), c->mlp_loss.p, (size_t)n_scenes * 4, hipMemcpyDeviceToHost,
@@ -972,6 +984,73 @@ int rr_mlp_train_step(rr_ctx *c, const float *codes, const float *hist, int32_t 
         double s = 0.0;
         for (float v : l) s += v;
         *loss_out = (float)s;
+    }
+    return RR_OK;
+}
+
+// SplitMix64 (Steele, Lea and Flood 2014)
+static uint64_t splitmix64(uint64_t &x)
+{
+    uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+int rr_proposal_train(rr_ctx *c, const float *codes, const float *hist, int32_t n_scenes,
+                      int32_t steps, int32_t batch, float lr, uint64_t seed, float *loss_out)
+{
+    if (!c || !codes || !hist) return fail(RR_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
+    if (n_scenes < 1 || steps < 0 || batch < 1)
+        return fail(RR_EINVAL, "n_scenes and batch must be positive, steps non-negative");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(RR_EINVAL, "invalid learning rate");
+    HIPCHK(hipSetDevice(c->device));
+    const int B = std::min(batch, n_scenes);
+    const int64_t nb = RR_PROP_NAZ * RR_PROP_NEL;
+    int rc;
+    if ((rc = mlp_buffers(c, (int64_t)B * nb, B))) return rc;
+    const bool gather = B < n_scenes;
+    if (gather) {
+        if ((rc = c->tr_codes.ensure((size_t)B * 16 * 4))) return rc;
+        if ((rc = c->tr_hist.ensure((size_t)B * nb * 4))) return rc;
+    }
+    if (loss_out && steps > 0 && (rc = c->tr_loss.ensure((size_t)steps * B * 4))) return rc;
+    std::vector<int32_t> perm(n_scenes);
+    for (int32_t i = 0; i < n_scenes; i++) perm[i] = i;
+    uint64_t st = seed;
+    for (int32_t s = 0; s < steps; s++) {
+        const float *cb = codes, *hb = hist;
+        if (gather) {
+            // B distinct scenes: the first B entries of a partial Fisher-Yates shuffle
+            for (int k = 0; k < B; k++) {
+                const int j = k + (int)(splitmix64(st) % (uint64_t)(n_scenes - k));
+                std::swap(perm[k], perm[j]);
+                HIPCHK(hipMemcpyAsync(c->tr_codes.as<float>() + (int64_t)k * 16,
+                                      codes + (int64_t)perm[k] * 16, 16 * 4,
+                                      hipMemcpyDeviceToDevice, c->stream));
+                HIPCHK(hipMemcpyAsync(c->tr_hist.as<float>() + (int64_t)k * nb,
+                                      hist + (int64_t)perm[k] * nb, (size_t)nb * 4,
+                                      hipMemcpyDeviceToDevice, c->stream));
+            }
+            cb = c->tr_codes.as<const float>();
+            hb = c->tr_hist.as<const float>();
+        }
+        if ((rc = mlp_step(c, cb, hb, B, lr, nullptr))) return rc;
+        if (loss_out)
+            HIPCHK(hipMemcpyAsync(c->tr_loss.as<float>() + (int64_t)s * B, c->mlp_loss.p,
+                                  (size_t)B * 4, hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (loss_out && steps > 0) {
+        std::vector<float> l((size_t)steps * B);
+        HIPCHK(hipMemcpyAsync(l.data(), c->tr_loss.p, l.size() * 4, hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int32_t s = 0; s < steps; s++) {
+            double sum = 0.0;
+            for (int k = 0; k < B; k++) sum += l[(size_t)s * B + k];
+            loss_out[s] = (float)sum;
+        }
     }
     return RR_OK;
 }

@@ -34,18 +34,12 @@ def collect(ctx, workloads):
 
 
 def train(ctx, codes, hists, steps=300, batch=16, lr=1e-3, seed=0, log=None):
-    """Adam on random minibatches of scenes; returns the loss history."""
+    """Adam on random minibatches of scenes (drawn and run in the library);
+    returns the loss history."""
     ctx.mlp_init(seed)
-    rng = np.random.default_rng(seed)
-    S = codes.shape[0]
-    losses = []
-    for it in range(steps):
-        idx = rng.choice(S, size=min(batch, S), replace=False)
-        ix = ctx.torch.as_tensor(idx, device=codes.device)
-        loss = ctx.mlp_train_step(codes[ix], hists[ix], lr)
-        losses.append(loss)
-        if log and (it % 50 == 0 or it == steps - 1):
-            log(f"step {it} loss {loss:.4f}")
+    losses = ctx.proposal_train(codes, hists, steps, batch=batch, lr=lr, seed=seed).tolist()
+    if log and losses:
+        log(f"{steps} steps: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     return losses
 
 
@@ -99,7 +93,8 @@ def equal_error(ctx, eval_seeds, budget=12_500, uniform_budgets=(12_500, 25_000,
 
     Learned pipeline: probe code, sampling table, `budget` rays from the
     learned density, GEMM synthesis.  Plain pipeline: uniform rays and direct
-    summation, at each of `uniform_budgets`.  Both against a `ref_rays`
+    summation, at each of `uniform_budgets` (and, timed alongside, the same
+    uniform rays with GEMM synthesis, which separates the proposal's share).  Both against a `ref_rays`
     uniform reference (GEMM); all cubes in the separable model.  The uniform
     budget of equal mean error is interpolated in log-log, and so is the
     plain pipeline's time there."""
@@ -138,6 +133,13 @@ def equal_error(ctx, eval_seeds, budget=12_500, uniform_budgets=(12_500, 25_000,
             row[f"s_uniform_{n}"] = time.perf_counter() - t0
             row[f"err_uniform_{n}"] = _rel(ctx, work, ref, nref)
             row[f"paths_uniform_{n}"] = n_u
+            # the same uniform paths through the GEMM engine (time only)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.trace(n, seed=tp.seed, sampler=B.UNIFORM, **kw)
+            ctx.synthesize(model=B.SEPARABLE, engine=B.GEMM_BF16X3, out=work)
+            torch.cuda.synchronize()
+            row[f"s_uniform_gemm_{n}"] = time.perf_counter() - t0
         per.append(row)
         if log:
             log(f"equal-error scene {s}: learned err {row['err_learned']:.3f} in "
@@ -146,13 +148,21 @@ def equal_error(ctx, eval_seeds, budget=12_500, uniform_budgets=(12_500, 25_000,
     tl = float(np.mean([r["s_learned"] for r in per[1:] or per]))
     eu = np.array([np.mean([r[f"err_uniform_{n}"] for r in per]) for n in uniform_budgets])
     tu = np.array([np.mean([r[f"s_uniform_{n}"] for r in per[1:] or per]) for n in uniform_budgets])
+    tg = np.array([np.mean([r[f"s_uniform_gemm_{n}"] for r in per[1:] or per])
+                   for n in uniform_budgets])
+    pl = float(np.mean([r["paths_learned"] for r in per]))
+    pu = np.array([np.mean([r[f"paths_uniform_{n}"] for r in per]) for n in uniform_budgets])
     xs = np.array(uniform_budgets, dtype=np.float64)
     n_eq = _loglog(xs, eu, el)
     t_eq = _loglog_time(xs, tu, n_eq)
-    return dict(budget=budget, err_learned_mean=el, s_learned_mean=tl,
+    tg_eq = _loglog_time(xs, tg, n_eq)
+    return dict(budget=budget, err_learned_mean=el, s_learned_mean=tl, paths_learned_mean=pl,
                 uniform_budgets=list(uniform_budgets), err_uniform_mean=eu.tolist(),
-                s_uniform_mean=tu.tolist(), uniform_rays_at_equal_error=n_eq,
-                s_uniform_at_equal_error=t_eq, speedup_at_equal_error=t_eq / tl, per_scene=per)
+                s_uniform_mean=tu.tolist(), s_uniform_gemm_mean=tg.tolist(),
+                paths_uniform_mean=pu.tolist(), uniform_rays_at_equal_error=n_eq,
+                s_uniform_at_equal_error=t_eq, speedup_at_equal_error=t_eq / tl,
+                s_uniform_gemm_at_equal_error=tg_eq,
+                speedup_vs_uniform_gemm_at_equal_error=tg_eq / tl, per_scene=per)
 
 
 def _loglog_time(xs, ts, x):

@@ -129,6 +129,44 @@ def test_sampling_table(gpu):
     assert np.abs(cdf - ref).max() < 2e-4
 
 
+def _splitmix_batches(seed, n, batch, steps):
+    """Minibatches of a partial Fisher-Yates shuffle driven by SplitMix64
+    (Steele, Lea and Flood 2014), written out from its published definition."""
+    M = (1 << 64) - 1
+    perm, x = list(range(n)), seed
+    for _ in range(steps):
+        for k in range(batch):
+            x = (x + 0x9E3779B97F4A7C15) & M
+            z = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & M
+            z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+            z ^= z >> 31
+            j = k + z % (n - k)
+            perm[k], perm[j] = perm[j], perm[k]
+        yield perm[:batch]
+
+
+@pytest.mark.parametrize("batch", [3, 8])
+def test_train_loop_equals_single_steps(gpu, batch):
+    """rr_proposal_train = its minibatches fed one by one to rr_mlp_train_step
+    (up to the order of the gradient's atomic sums; the first Adam steps move
+    parameters with a near-zero gradient by up to lr either way)."""
+    S, steps, lr = 8, 4, 1e-3
+    codes, hist = _inputs(21, S)
+    tc, th = torch.from_numpy(codes).cuda(), torch.from_numpy(hist).cuda()
+    gpu.mlp_init(2)
+    ref_loss = []
+    for idx in _splitmix_batches(99, S, min(batch, S), steps):
+        ix = torch.tensor(idx, device=tc.device)
+        ref_loss.append(gpu.mlp_train_step(tc[ix], th[ix], lr))
+    ref = gpu.mlp_get_params().astype(np.float64)
+    gpu.mlp_init(2)
+    loss = gpu.proposal_train(tc, th, steps, batch=batch, lr=lr, seed=99)
+    got = gpu.mlp_get_params().astype(np.float64)
+    assert np.allclose(loss, ref_loss, rtol=1e-4)
+    assert (np.abs(got - ref) <= 1e-6).mean() > 0.97
+    assert np.abs(got - ref).max() <= 2.1 * lr * steps
+
+
 def test_learned_proposal_gain(gpu):
     """Train on uniform traces of 60 scenes of the box family, then on 10
     held-out scenes draw 1.25e4 rays from the learned density: the traced
