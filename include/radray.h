@@ -44,7 +44,7 @@ enum {
     RR_EHIP = -3,          /* a HIP runtime call failed */
     RR_ESTATE = -4,        /* call order violated (e.g. synthesize before trace) */
     RR_EOVERFLOW = -5,     /* an output buffer is too small; needed size reported */
-    RR_EUNSUPPORTED = -6   /* valid request that this build does not support */
+    RR_EUNSUPPORTED = -6   /* valid request that this library does not support */
 };
 
 enum { RR_TX_PER_ELEMENT = 0, RR_TX_SHARED = 1 };
