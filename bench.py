@@ -245,7 +245,8 @@ def main():
                                                 "profiles/k_gemm_large_mimo.md")}
         else:
             roof = {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "traffic": None}
+                    "traffic": profiled_traffic("paper_2307_15412_amd/csrc/k_synth.hip",
+                                                "profiles/k_synth_direct_large_mimo.md")}
         roof["kernel"] = "synth_" + eng_name
         roof["flops_per_launch"] = kern_flops
     else:
@@ -261,12 +262,14 @@ def main():
     cpu = None
     if not args.no_check or not args.no_cpu_baseline:
         import oracle
+        # a bounded sample, about 10-20 s of oracle work: a quarter of the rays,
+        # and 8192 cube entries over the paths they return
         sub = sg.workload_large_mimo(0)
-        sub.trace.n_rays = 200_000
+        sub.trace.n_rays = 1_000_000
         t0 = time.perf_counter()
         _, op = oracle.trace(sub.scene, sub.array, sub.trace, want_hits=False)
         t_trace = time.perf_counter() - t0
-        idx = np.random.default_rng(11).choice(C * M * K, 2048, replace=False)
+        idx = np.random.default_rng(11).choice(C * M * K, 8192, replace=False)
         t0 = time.perf_counter()
         ref = oracle.synth(op, sub.scene, sub.array, sub.chirp, model=1, idx=idx)
         t_syn = time.perf_counter() - t0
