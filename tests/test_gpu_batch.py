@@ -22,6 +22,11 @@ def _workloads():
     ws.append(sg.Workload("street_small", sg.scene_street(1, scale=0.05, n_cars=5, n_poles=6),
                           sg.array_ula(4, 8), sg.Chirp(n_samples=96, n_chirps=32),
                           sg.TraceParams(n_rays=100_003, max_bounces=3, seed=5)))
+    # no triangles: every ray misses, only the point reflectors return
+    ws.append(sg.Workload("points", sg.point_only([[8.0, 1.0, 0.5], [15.0, -2.0, 0.6]],
+                                                  vel=[[1.0, 0.0, 0.0], [-2.0, 0.5, 0.0]]),
+                          sg.array_ula(2, 3), sg.Chirp(n_samples=64, n_chirps=8),
+                          sg.TraceParams(n_rays=1000, max_bounces=2, seed=3)))
     return ws
 
 
@@ -83,7 +88,7 @@ def test_batch_autotune(gpu):
 
 def test_batch_against_oracle(gpu, orc):
     import paper_2307_15412_amd as rr
-    ws = _workloads()[:2] + _workloads()[-1:]
+    ws = _workloads()[:2] + _workloads()[-2:]
     B = rr.Batch(gpu, len(ws))
     for i, w in enumerate(ws):
         B.set_workload(i, w)
