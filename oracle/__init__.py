@@ -86,6 +86,8 @@ def lib():
                                      C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
         L.orc_synth.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_int, C.c_void_p, C.c_int64, C.c_void_p]
+        L.orc_backproject.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p,
+                                      C.c_void_p, C.c_int64, C.c_void_p]
         L.orc_release.argtypes = []
         _lib = L
     return _lib
@@ -268,6 +270,23 @@ def trace_rays(scene, array, orig, dirs, amp, src, max_bounces, seed, use_bvh=No
         cap = npaths.value
     lib().orc_release()
     return hits, paths[: npaths.value].copy()
+
+
+def backproject(array, f0, df, cube, voxels) -> np.ndarray:
+    """Delay-and-sum image (complex128 [nv]) of a single-sweep cube
+    (complex [n_tx n_rx][nf], frequencies f0 + n df) at voxels [nv][3]."""
+    keep = _Keep()
+    ar = _array(array, keep)
+    cb = np.ascontiguousarray(np.asarray(cube).reshape(array.n_ch, -1).astype(np.complex128))
+    nf = cb.shape[1]
+    cr = keep.add(np.stack([cb.real, cb.imag], -1), np.float64)
+    vx = keep.add(voxels, np.float64).reshape(-1, 3)
+    out = np.zeros((vx.shape[0], 2))
+    rc = lib().orc_backproject(C.addressof(ar), float(f0), float(df), nf, cr.ctypes.data,
+                               _p(vx), vx.shape[0], out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_backproject failed: {rc}")
+    return out[:, 0] + 1j * out[:, 1]
 
 
 def synth(paths, scene, array, chirp, model=0, idx=None) -> np.ndarray:

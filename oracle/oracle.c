@@ -817,3 +817,43 @@ void orc_uniform_bins(uint64_t seed, int64_t n_per_src, int64_t n_src, int32_t n
             bins[t * n_per_src + i] = ie * n_az + ia;
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* imaging: delay-and-sum back-projection of a stepped-frequency cube        */
+/* ------------------------------------------------------------------------ */
+
+/* The textbook delay-and-sum image of a single-sweep cube (the paper forms
+ * its hand images by brute-force back-projection; here written from the
+ * definition): for voxel x,
+ *   image(x) = sum_{t, r} sum_n s[t n_rx + r][n] exp(+j 2 pi f_n d / c),
+ *   d = |x - tx_t| + |x - rx_r|,  f_n = f0 + n df,
+ * the matched filter of the synthesis phase exp(-j 2 pi f_n d / c).
+ * cube: [n_tx n_rx][nf][2] (re, im); vox: [nv][3]; out: [nv][2].  FP64,
+ * one sin / cos per term. */
+#define ORC_PI 3.14159265358979323846
+
+int orc_backproject(const orc_array *ar, double f0, double df, int32_t nf, const double *cube,
+                    const double *vox, int64_t nv, double *out)
+{
+    if (ar->ntx < 1 || ar->nrx < 1 || nf < 1 || nv < 0) return -1;
+    for (int64_t v = 0; v < nv; v++) {
+        vec3 x = vload3d(vox + 3 * v);
+        double re = 0.0, im = 0.0;
+        for (int32_t t = 0; t < ar->ntx; t++) {
+            double dt = vlen(vsub(x, vload3d(ar->tx + 3 * t)));
+            for (int32_t r = 0; r < ar->nrx; r++) {
+                double d = dt + vlen(vsub(x, vload3d(ar->rx + 3 * r)));
+                const double *s = cube + 2 * ((int64_t)(t * ar->nrx + r) * nf);
+                for (int32_t n = 0; n < nf; n++) {
+                    double ph = 2.0 * ORC_PI * (f0 + (double)n * df) * d / C0;
+                    double c = cos(ph), sn = sin(ph);
+                    re += s[2 * n] * c - s[2 * n + 1] * sn;
+                    im += s[2 * n] * sn + s[2 * n + 1] * c;
+                }
+            }
+        }
+        out[2 * v] = re;
+        out[2 * v + 1] = im;
+    }
+    return 0;
+}

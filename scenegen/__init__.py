@@ -107,6 +107,15 @@ class Chirp:
     n_chirps: int = 16
 
 
+def chirp_sfcw(f_start: float = 72e9, f_stop: float = 82e9, n_steps: int = 128) -> Chirp:
+    """A stepped-frequency sweep f_n = f_start + n (f_stop - f_start) / (n_steps - 1),
+    n = 0 .. n_steps - 1 (both ends included), as one chirp of n_steps samples:
+    f0 + B k / K with B = (f_stop - f_start) n_steps / (n_steps - 1)."""
+    bw = (f_stop - f_start) * n_steps / (n_steps - 1)
+    return Chirp(f0=f_start, bandwidth=bw, t_chirp=1e-3, t_rep=1e-3, n_samples=n_steps,
+                 n_chirps=1)
+
+
 @dataclass
 class TraceParams:
     n_rays: int = 100_000            # total launched rays (split over Tx in PER_TX mode)
@@ -239,6 +248,22 @@ def array_c1() -> Array:
     tx = np.array([[0.0, -2 * lam, 0.5]])
     rx = np.array([[0.0, (r - 1.5) * lam / 2, 0.5] for r in range(4)])
     return Array(tx, rx, 0.25, MODE_PER_TX).checked()
+
+
+def array_square(n_side: int = 47, pitch: float = 3e-3, mode: int = MODE_SHARED,
+                 rx_radius: float = 0.07) -> Array:
+    """Square MIMO frame in the y-z plane centred on the origin: n_side
+    elements at `pitch` on each side; Tx on the two sides y = -+L/2, Rx on the
+    two sides z = -+L/2 (L = n_side * pitch), so 2 n_side x 2 n_side channels
+    (94 x 94 for n_side = 47: a 14.1 cm aperture)."""
+    s = (np.arange(n_side) - (n_side - 1) / 2) * pitch
+    h = n_side * pitch / 2
+    z = np.zeros(n_side)
+    tx = np.concatenate([np.stack([z, np.full(n_side, -h), s], 1),
+                         np.stack([z, np.full(n_side, h), s], 1)])
+    rx = np.concatenate([np.stack([z, s, np.full(n_side, -h)], 1),
+                         np.stack([z, s, np.full(n_side, h)], 1)])
+    return Array(tx, rx, rx_radius, mode).checked()
 
 
 def array_ula(n_tx: int, n_rx: int, mode: int = MODE_PER_TX, height: float = 0.5) -> Array:
@@ -439,6 +464,46 @@ def workload_batch(n_scenes: int = 64, seed0: int = 2000, rays: int = 1_000_000,
         out.append(Workload(f"batch{i}", scene, arr, Chirp(n_samples=K, n_chirps=M),
                             TraceParams(n_rays=rays, max_bounces=3, seed=s)))
     return out
+
+
+def scene_hand_proxy(seed: int = 0, step: float = 2e-3, rng_x: float = 0.30,
+                     alpha: float = 0.3) -> Scene:
+    """A static open hand facing the array: a palm (8 cm wide, 9 cm tall,
+    1.5 cm thick) at range rng_x and five fingers (1.6-1.8 cm wide) above it,
+    lengths and spread drawn from `seed`, the thumb to the side; faces
+    subdivided at `step`.  One object, material alpha."""
+    rng = np.random.default_rng(seed)
+    mb = _MeshBuilder()
+    t = 0.015
+    mb.box((rng_x, -0.04, -0.05), (rng_x + t, 0.04, 0.04), step, 0)
+    for i in range(4):
+        y0 = -0.038 + i * 0.0195
+        w = 0.016 + 0.002 * rng.random()
+        ln = 0.06 + 0.025 * rng.random()
+        mb.box((rng_x + 0.002, y0, 0.04), (rng_x + t - 0.002, y0 + w, 0.04 + ln), step, 0)
+    ln = 0.05 + 0.015 * rng.random()
+    mb.box((rng_x + 0.002, 0.04, -0.03), (rng_x + t - 0.002, 0.04 + ln, -0.012), step, 0)
+    return mb.build([alpha], [[0.0, 0.0, 0.0]])
+
+
+def workload_hand(seed: int = 0, n_rays: int = 10_000_000) -> Workload:
+    """The paper's imaging set-up with a synthetic hand: the 94 x 94 square
+    array (shared launch from its centre, reception sphere 7 cm), a
+    72-82 GHz stepped-frequency sweep of 128 steps, rays within +-25 degrees
+    of boresight, 2 bounces."""
+    deg = math.pi / 180.0
+    return Workload("hand", scene_hand_proxy(seed), array_square(), chirp_sfcw(),
+                    TraceParams(n_rays=n_rays, max_bounces=2, seed=seed, az_min=-25 * deg,
+                                az_max=25 * deg, el_min=-25 * deg, el_max=25 * deg))
+
+
+def imaging_grid(x_lo: float = 0.26, x_hi: float = 0.34, half: float = 0.10,
+                 step: float = 1e-3):
+    """Voxel grid of the imaging volume: range x in [x_lo, x_hi], y and z in
+    [-half, half], spacing `step`; returns (origin, step, (nx, ny, nz))."""
+    nx = int(round((x_hi - x_lo) / step)) + 1
+    ny = nz = int(round(2 * half / step)) + 1
+    return (x_lo, -half, -half), step, (nx, ny, nz)
 
 
 def workload_box_mimo(seed: int, n_rays: int) -> Workload:
