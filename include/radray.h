@@ -333,9 +333,39 @@ int rr_batch_get_tiles(rr_batch *batch, int32_t *samples_per_lane_out);
  * synthesis stage of the last autotuner run, and the last total path count. */
 int rr_batch_stats(rr_batch *batch, double *ms_total, double *ms_synth, int64_t *total_paths);
 
-/* Kernel timing of the last rr_trace / rr_synthesize call, in milliseconds,
- * measured with HIP events on the context stream (synchronises).
- * which: 0 = trace (all trace kernels), 1 = synthesis main kernel. */
+/* ------------------------------------------------------------------------
+ * Imaging (the paper forms images of its simulated data by brute-force
+ * back-projection and shows their maximum projection in dB).
+ * Voxel (i, j, k) is centred at (x0 + i step, y0 + j step, z0 + k step);
+ * images are complex64 [nx][ny][nz] (x, the boresight range axis, slowest). */
+typedef struct {
+    double x0, y0, z0, step;
+    int32_t nx, ny, nz;
+} rr_volume;
+
+/* Delay-and-sum back-projection of one sweep per channel: for every voxel x,
+ *   image(x) = sum_{t, r} sum_k s[t n_rx + r][k] exp(+j 2 pi f_k d / c),
+ *   d = |x - tx_t| + |x - rx_r|, f_k = f0 + B k / K (the context's chirp; a
+ *   stepped-frequency sweep is one chirp of K steps),
+ * the matched filter of the synthesis phase.  cube_dev: complex64
+ * [n_ch][n_chirps][n_samples] as rr_synthesize writes it (chirp 0 of each
+ * channel is used); image_dev: complex64, image_elems >= nx ny nz.  Lengths
+ * and phase reduction in FP64, sums in FP32.  Errors: RR_ESTATE (array or
+ * chirp missing), RR_EINVAL (sizes, grid), RR_EUNSUPPORTED (more than 4096
+ * steps). */
+int rr_backproject(rr_ctx *ctx, const void *cube_dev, int64_t cube_elems, const rr_volume *vol,
+                   void *image_dev, int64_t image_elems);
+
+/* Maximum over x of |image| per (y, z), in dB relative to the largest of
+ * them, clamped below at floor_db (e.g. -15): out_dev float [ny][nz].
+ * Errors: RR_EINVAL. */
+int rr_max_projection(rr_ctx *ctx, const void *image_dev, const rr_volume *vol, float *out_dev,
+                      float floor_db);
+
+/* Kernel timing of the last rr_trace / rr_synthesize / rr_backproject call,
+ * in milliseconds, measured with HIP events on the context stream
+ * (synchronises).  which: 0 = trace (all trace kernels), 1 = synthesis main
+ * kernel, 2 = back-projection. */
 int rr_last_kernel_ms(rr_ctx *ctx, int32_t which, double *ms_out);
 
 #ifdef __cplusplus

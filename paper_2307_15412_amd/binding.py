@@ -27,7 +27,8 @@ KMAX = 4
 EXPORTED = [
     "rr_create", "rr_destroy", "rr_last_error", "rr_version", "rr_scene_upload", "rr_set_array",
     "rr_set_chirp", "rr_trace", "rr_trace_rays", "rr_get_path_count", "rr_get_hits",
-    "rr_get_paths", "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms",
+    "rr_get_paths", "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms", "rr_backproject",
+    "rr_max_projection",
 ]
 
 
@@ -47,6 +48,11 @@ class TraceParams(C.Structure):
                 ("az_min", C.c_double), ("az_max", C.c_double), ("el_min", C.c_double),
                 ("el_max", C.c_double), ("sampler", C.c_int32), ("record_hits", C.c_int32),
                 ("path_cap", C.c_int64)]
+
+
+class Volume(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double), ("step", C.c_double),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
 
 
 class Paths(C.Structure):
@@ -79,6 +85,8 @@ def load_library(path: str = LIB_PATH):
     L.rr_trace_rays.argtypes = [vp, vp, vp, vp, vp, i64, C.c_int32, C.c_uint64, C.c_int32,
                                 C.POINTER(i64)]
     L.rr_get_path_count.argtypes = [vp, C.POINTER(i64)]
+    L.rr_backproject.argtypes = [vp, vp, i64, C.POINTER(Volume), vp, i64]
+    L.rr_max_projection.argtypes = [vp, vp, C.POINTER(Volume), vp, C.c_float]
     L.rr_get_hits.argtypes = [vp, vp, i64]
     L.rr_get_paths.argtypes = [vp, C.POINTER(Paths), C.POINTER(i64)]
     L.rr_set_paths.argtypes = [vp, C.POINTER(Paths), i64]
@@ -267,6 +275,33 @@ class Context:
                                            C.c_void_p(out.data_ptr()), out.numel(),
                                            C.c_void_p(idx.data_ptr()), idx.numel()))
         self._keep_idx = idx
+        return out
+
+    # ------------------------------------------------------------ imaging
+    def backproject(self, cube, grid, out=None):
+        """Delay-and-sum image (complex64 [nx][ny][nz]) of `cube` (this
+        context's array and chirp) on grid = (origin (x0, y0, z0), step,
+        (nx, ny, nz)) as scenegen.imaging_grid returns it."""
+        torch = self.torch
+        (x0, y0, z0), step, (nx, ny, nz) = grid
+        vol = Volume(float(x0), float(y0), float(z0), float(step), int(nx), int(ny), int(nz))
+        check_out(cube, self.device, torch.complex64, self.n_ch * self.M * self.K, "cube")
+        if out is None:
+            out = torch.empty((nx, ny, nz), dtype=torch.complex64, device=self.device)
+        check_out(out, self.device, torch.complex64, nx * ny * nz, "image")
+        self._check(self.lib.rr_backproject(self.h, C.c_void_p(cube.data_ptr()), cube.numel(),
+                                            C.byref(vol), C.c_void_p(out.data_ptr()), out.numel()))
+        return out
+
+    def max_projection(self, image, grid, floor_db=-15.0):
+        """Maximum over range of |image| per (y, z) in dB, float32 [ny][nz]."""
+        torch = self.torch
+        (x0, y0, z0), step, (nx, ny, nz) = grid
+        vol = Volume(float(x0), float(y0), float(z0), float(step), int(nx), int(ny), int(nz))
+        check_out(image, self.device, torch.complex64, nx * ny * nz, "image")
+        out = torch.empty((ny, nz), dtype=torch.float32, device=self.device)
+        self._check(self.lib.rr_max_projection(self.h, C.c_void_p(image.data_ptr()), C.byref(vol),
+                                               C.c_void_p(out.data_ptr()), float(floor_db)))
         return out
 
     def kernel_ms(self, which: int) -> float:

@@ -30,6 +30,7 @@ SOURCES = {
     "k_synth.hip": [],
     "k_gemm.hip": [],
     "k_mlp.hip": [],
+    "k_image.hip": [],
 }
 
 

@@ -112,8 +112,8 @@ bool finite3(const double *p, int64_t n)
 struct rr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    bool trace_timed = false, synth_timed = false;
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool trace_timed = false, synth_timed = false, image_timed = false;
 
     // scene
     bool has_scene = false;
@@ -155,6 +155,7 @@ struct rr_ctx {
     int last_sampler = -1;
     DevBuf mlp_p, mlp_m, mlp_v, mlp_g, mlp_acts, mlp_z, mlp_dz, mlp_d, mlp_loss;
     DevBuf tr_codes, tr_hist, tr_loss;   // minibatch staging of rr_proposal_train
+    DevBuf bp_peak;                      // peak of the last maximum projection
     bool mlp_ready = false;
     int mlp_step = 0;
 };
@@ -255,7 +256,7 @@ void rr_destroy(rr_ctx *c)
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
-                      &c->tr_codes, &c->tr_hist, &c->tr_loss};
+                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -768,7 +769,8 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
 int rr_last_kernel_ms(rr_ctx *c, int32_t which, double *ms)
 {
     if (!c || !ms) return fail(RR_EINVAL, "NULL argument");
-    if ((which == 0 && !c->trace_timed) || (which == 1 && !c->synth_timed) || which < 0 || which > 1)
+    if (which < 0 || which > 2 || (which == 0 && !c->trace_timed) ||
+        (which == 1 && !c->synth_timed) || (which == 2 && !c->image_timed))
         return fail(RR_ESTATE, "nothing timed");
     HIPCHK(hipSetDevice(c->device));
     hipEvent_t a = c->ev[which * 2], b = c->ev[which * 2 + 1];
@@ -776,6 +778,73 @@ int rr_last_kernel_ms(rr_ctx *c, int32_t which, double *ms)
     float f = 0;
     HIPCHK(hipEventElapsedTime(&f, a, b));
     *ms = f;
+    return RR_OK;
+}
+
+// --------------------------------------------------------------------------
+// imaging
+// --------------------------------------------------------------------------
+
+static bool bad_volume(const rr_volume *v)
+{
+    return !(v->step > 0.0) || !std::isfinite(v->step) || !std::isfinite(v->x0) ||
+           !std::isfinite(v->y0) || !std::isfinite(v->z0) || v->nx < 1 || v->ny < 1 || v->nz < 1;
+}
+
+int rr_backproject(rr_ctx *c, const void *cube, int64_t cube_elems, const rr_volume *vol,
+                   void *image, int64_t image_elems)
+{
+    if (!c || !cube || !vol || !image) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_array || !c->has_chirp) return fail(RR_ESTATE, "array and chirp must be set");
+    if (bad_volume(vol)) return fail(RR_EINVAL, "invalid voxel grid");
+    const int64_t C = (int64_t)c->ntx * c->nrx, M = c->chirp.n_chirps, K = c->chirp.n_samples;
+    if (K > RR_BP_KMAX) return fail(RR_EUNSUPPORTED, "sweeps of at most %d steps", RR_BP_KMAX);
+    if (cube_elems < C * M * K) return fail(RR_EINVAL, "cube needs %lld complex elements",
+                                            (long long)(C * M * K));
+    const int64_t nv = (int64_t)vol->nx * vol->ny * vol->nz;
+    if (image_elems < nv) return fail(RR_EINVAL, "image needs %lld complex elements", (long long)nv);
+    HIPCHK(hipSetDevice(c->device));
+    BackProjArgs A{};
+    A.cube = static_cast<const float2 *>(cube);
+    A.stride = M * K;
+    A.tx = c->tx.as<const double>();
+    A.rx = c->rx.as<const double>();
+    A.ntx = c->ntx;
+    A.nrx = c->nrx;
+    A.C = (int)C;
+    A.K = (int)K;
+    A.f0 = c->chirp.f0;
+    A.df = c->chirp.bandwidth / (double)K;
+    A.inv_c = 1.0 / 299792458.0;
+    A.x0 = vol->x0;
+    A.y0 = vol->y0;
+    A.z0 = vol->z0;
+    A.step = vol->step;
+    A.nx = vol->nx;
+    A.ny = vol->ny;
+    A.nz = vol->nz;
+    A.n_vox = nv;
+    A.image = static_cast<float2 *>(image);
+    HIPCHK(hipEventRecord(c->ev[4], c->stream));
+    HIPCHK(launch_backproject(A, c->stream));
+    HIPCHK(hipEventRecord(c->ev[5], c->stream));
+    c->image_timed = true;
+    return RR_OK;
+}
+
+int rr_max_projection(rr_ctx *c, const void *image, const rr_volume *vol, float *out,
+                      float floor_db)
+{
+    if (!c || !image || !vol || !out) return fail(RR_EINVAL, "NULL argument");
+    if (bad_volume(vol)) return fail(RR_EINVAL, "invalid voxel grid");
+    if (!(floor_db <= 0.0f)) return fail(RR_EINVAL, "floor_db must be <= 0");
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    if ((rc = c->bp_peak.ensure(256))) return rc;
+    HIPCHK(hipMemsetAsync(c->bp_peak.p, 0, 4, c->stream));
+    HIPCHK(launch_max_projection(static_cast<const float2 *>(image), vol->nx,
+                                 (int64_t)vol->ny * vol->nz, out, c->bp_peak.as<float>(), floor_db,
+                                 c->stream));
     return RR_OK;
 }
 

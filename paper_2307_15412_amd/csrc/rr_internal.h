@@ -114,6 +114,20 @@ struct SynthArgs {
     int64_t p_limit;          // > 0: at most this many paths of each group (tile timing only)
 };
 
+// back-projection (imaging): one single-sweep cube onto a voxel grid
+#define RR_BP_KMAX 4096          // longest sweep: one channel fills the staging buffer
+struct BackProjArgs {
+    const float2 *cube;       // channel c's sweep at cube + c * stride
+    int64_t stride;
+    const double *tx, *rx;    // device [n][3]
+    int ntx, nrx, C, K;
+    double f0, df, inv_c;
+    double x0, y0, z0, step;  // voxel (i, j, k) at (x0 + i step, y0 + j step, z0 + k step)
+    int nx, ny, nz;
+    int64_t n_vox;
+    float2 *image;            // [nx][ny][nz]
+};
+
 // largest samples-per-lane tile of the batched synthesis kernel (its
 // register use, hence its occupancy, follows the largest tile it contains)
 #ifndef RR_BATCH_MAX_KR
@@ -144,6 +158,9 @@ struct BatchRangeInfo {
 hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s);
 hipError_t launch_points(const TraceArgs &a, hipStream_t s);
 hipError_t launch_trace_user(const TraceArgs &a, const UserRays &u, hipStream_t s);
+hipError_t launch_backproject(const BackProjArgs &a, hipStream_t s);
+hipError_t launch_max_projection(const float2 *img, int64_t nx, int64_t nyz, float *out,
+                                 float *peak, float floor_db, hipStream_t s);
 hipError_t launch_check_user(const UserRays &u, int shared, int ntx, int *flag, hipStream_t s);
 hipError_t launch_scan_u8(const uint8_t *counts, int64_t n, uint32_t *offsets, uint32_t *bsums,
                           int64_t nb_cap, unsigned long long *total, hipStream_t s);
