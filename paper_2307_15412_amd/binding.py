@@ -293,13 +293,15 @@ class Context:
                                             C.byref(vol), C.c_void_p(out.data_ptr()), out.numel()))
         return out
 
-    def max_projection(self, image, grid, floor_db=-15.0):
+    def max_projection(self, image, grid, floor_db=-15.0, out=None):
         """Maximum over range of |image| per (y, z) in dB, float32 [ny][nz]."""
         torch = self.torch
         (x0, y0, z0), step, (nx, ny, nz) = grid
         vol = Volume(float(x0), float(y0), float(z0), float(step), int(nx), int(ny), int(nz))
         check_out(image, self.device, torch.complex64, nx * ny * nz, "image")
-        out = torch.empty((ny, nz), dtype=torch.float32, device=self.device)
+        if out is None:
+            out = torch.empty((ny, nz), dtype=torch.float32, device=self.device)
+        check_out(out, self.device, torch.float32, ny * nz, "projection")
         self._check(self.lib.rr_max_projection(self.h, C.c_void_p(image.data_ptr()), C.byref(vol),
                                                C.c_void_p(out.data_ptr()), float(floor_db)))
         return out
