@@ -88,6 +88,22 @@ int rr_scene_upload(rr_ctx *ctx, const float *verts, int64_t n_verts,
                     const double *pt_pos, const double *pt_vel, const double *pt_aperture,
                     int32_t n_pts);
 
+enum { RR_ALPHA_PER_OBJECT = 0, RR_ALPHA_PER_TRIANGLE = 1 };
+
+/* Replace the material mix alpha of Eq. 3 (Sec. III-A) of the uploaded scene
+ * without rebuilding the BVH: for a sweep of alpha over one mesh (the paper
+ * varies alpha from 0 to 1 in steps of 0.1, Sec. IV) and per-face variation
+ * for data diversity (Sec. V).
+ *   alpha float [n], host, copied; each in [0, 1].
+ *   per   RR_ALPHA_PER_OBJECT: n = n_obj, every face takes its object's value;
+ *         RR_ALPHA_PER_TRIANGLE: n = n_tris, face i (upload index) takes
+ *         alpha[i], overriding its object's.
+ * Drains the context's stream, then enqueues the update on it; traces issued
+ * later see the new values, earlier traced paths are kept.
+ * Errors: RR_ESTATE without a scene; RR_EINVAL for a wrong count, an unknown
+ * mode or a value outside [0, 1] (nothing is changed then). */
+int rr_scene_set_alpha(rr_ctx *ctx, const float *alpha, int64_t n, int32_t per);
+
 /* MIMO array geometry (Section II).  tx double [n_tx][3], rx double [n_rx][3].
  * rx_radius: radius of the array-level reception sphere centred on the Rx
  * phase centre (mean of rx).  tx_mode: RR_TX_PER_ELEMENT (rays from every Tx,
@@ -311,6 +327,12 @@ int rr_batch_set_scene(rr_batch *batch, int32_t slot, const float *verts, int64_
                        int32_t n_pts, const double *tx, int32_t n_tx, const double *rx, int32_t n_rx,
                        double rx_radius, int32_t tx_mode, const rr_chirp *chirp,
                        const rr_trace_params *params);
+
+/* As rr_scene_set_alpha for the scene in slot `slot` (per-object or per-face
+ * alpha, Eq. 3); drains the batch's stream first.  The captured graph reads
+ * the updated values on its next replay (no re-capture).
+ * Errors: RR_EINVAL (slot, count, mode, range), RR_ESTATE (empty slot). */
+int rr_batch_set_alpha(rr_batch *batch, int32_t slot, const float *alpha, int64_t n, int32_t per);
 
 /* Run the batch: cubes[s] is scene s's complex64 [n_ch][n_chirps][n_samples]
  * device buffer.  The first launch (or the first after a change) captures the

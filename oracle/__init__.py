@@ -41,7 +41,8 @@ class _Scene(C.Structure):
     _fields_ = [("verts", C.c_void_p), ("nv", C.c_int64), ("tris", C.c_void_p),
                 ("tri_obj", C.c_void_p), ("nt", C.c_int64), ("obj_alpha", C.c_void_p),
                 ("obj_vel", C.c_void_p), ("nobj", C.c_int32), ("pt_pos", C.c_void_p),
-                ("pt_vel", C.c_void_p), ("pt_ap", C.c_void_p), ("npts", C.c_int32)]
+                ("pt_vel", C.c_void_p), ("pt_ap", C.c_void_p), ("npts", C.c_int32),
+                ("tri_alpha", C.c_void_p)]
 
 
 class _Array(C.Structure):
@@ -118,8 +119,10 @@ def _scene(s, keep):
     pp = keep.add(s.pt_pos, np.float64)
     pv = keep.add(s.pt_vel, np.float64)
     pa = keep.add(s.pt_aperture, np.float64)
+    ta = getattr(s, "tri_alpha", None)
+    ta = None if ta is None else keep.add(ta, np.float32)
     st = _Scene(_p(v), v.shape[0], _p(t), _p(o), t.shape[0], _p(a), _p(ov), a.shape[0],
-                _p(pp), _p(pv), _p(pa), pp.shape[0])
+                _p(pp), _p(pv), _p(pa), pp.shape[0], None if ta is None else _p(ta))
     keep.bufs.append(st)
     return st
 

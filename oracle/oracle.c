@@ -49,6 +49,7 @@ typedef struct {
     const double *pt_vel;    /* [npts][3] */
     const double *pt_ap;     /* [npts] aperture, m^2 */
     int32_t npts;
+    const float *tri_alpha;  /* [nt] per-triangle alpha, or NULL: the object's */
 } orc_scene;
 
 typedef struct {
@@ -575,7 +576,8 @@ static void trace_from(const orc_scene *sc, vec3 oR, uint64_t seed, int32_t B, d
         vec3 n = orc_face_normal(sc, h, dir);
         double u[4];
         draw(seed, (uint64_t)i, (uint64_t)t, (uint64_t)(j + 1), u);
-        double alpha = (double)sc->obj_alpha[sc->tri_obj[h]];
+        /* material mix of Eq. 3: the face's own value when faces carry one */
+        double alpha = sc->tri_alpha ? (double)sc->tri_alpha[h] : (double)sc->obj_alpha[sc->tri_obj[h]];
         dir = bounce_dir(dir, n, alpha, u[0], u[1]);
         o = p;
         prev = h;

@@ -23,12 +23,13 @@ UNIFORM, PROPOSAL = 0, 1
 EXACT, SEPARABLE = 0, 1
 ENGINE_AUTO, DIRECT_FP32, GEMM_BF16X3 = 0, 1, 2
 KMAX = 4
+ALPHA_PER_OBJECT, ALPHA_PER_TRIANGLE = 0, 1
 
 EXPORTED = [
     "rr_create", "rr_destroy", "rr_last_error", "rr_version", "rr_scene_upload", "rr_set_array",
     "rr_set_chirp", "rr_trace", "rr_trace_rays", "rr_get_path_count", "rr_get_hits",
     "rr_get_paths", "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms", "rr_backproject",
-    "rr_max_projection",
+    "rr_max_projection", "rr_scene_set_alpha",
 ]
 
 
@@ -79,6 +80,7 @@ def load_library(path: str = LIB_PATH):
     L.rr_last_error.restype = C.c_char_p
     L.rr_version.restype = C.c_char_p
     L.rr_scene_upload.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, i32, vp, vp, vp, i32]
+    L.rr_scene_set_alpha.argtypes = [vp, vp, i64, i32]
     L.rr_set_array.argtypes = [vp, vp, i32, vp, i32, f64, i32]
     L.rr_set_chirp.argtypes = [vp, C.POINTER(Chirp)]
     L.rr_trace.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
@@ -151,9 +153,18 @@ class Context:
                                              a.size, ppp, ppv, ppa, pp.size // 3))
 
     def upload(self, scene):
-        """Upload an object with verts/tris/tri_obj/obj_alpha/obj_vel/pt_* fields."""
+        """Upload an object with verts/tris/tri_obj/obj_alpha/obj_vel/pt_* fields
+        (and per-face alpha when its tri_alpha is not None)."""
         self.scene_upload(scene.verts, scene.tris, scene.tri_obj, scene.obj_alpha, scene.obj_vel,
                           scene.pt_pos, scene.pt_vel, scene.pt_aperture)
+        ta = getattr(scene, "tri_alpha", None)
+        if ta is not None:
+            self.set_alpha(ta, per=ALPHA_PER_TRIANGLE)
+
+    def set_alpha(self, alpha, per=ALPHA_PER_OBJECT):
+        """Replace the scene's material mix (Eq. 3) per object or per face."""
+        a, pa = _np(alpha, np.float32)
+        self._check(self.lib.rr_scene_set_alpha(self.h, pa, a.size, int(per)))
 
     def set_array(self, tx, rx, rx_radius=0.25, mode=TX_PER_ELEMENT):
         tx, ptx = _np(tx, np.float64)
@@ -462,6 +473,7 @@ def _declare_batch(L):
     L.rr_batch_set_scene.argtypes = [vp, i32, vp, i64, vp, vp, i64, vp, vp, i32, vp, vp, vp, i32,
                                      vp, i32, vp, i32, f64, i32, C.POINTER(Chirp),
                                      C.POINTER(TraceParams)]
+    L.rr_batch_set_alpha.argtypes = [vp, i32, vp, i64, i32]
     L.rr_batch_launch.argtypes = [vp, vp, vp]
     L.rr_batch_tune.argtypes = [vp, vp]
     L.rr_batch_get_tiles.argtypes = [vp, vp]
@@ -513,6 +525,14 @@ class Batch:
             P(a.tx, np.float64), a.tx.shape[0], P(a.rx, np.float64), a.rx.shape[0],
             float(a.rx_radius), int(a.mode), C.byref(chirp), C.byref(t)))
         self.shapes[slot] = (a.tx.shape[0] * a.rx.shape[0], ch.n_chirps, ch.n_samples)
+        ta = getattr(sc, "tri_alpha", None)
+        if ta is not None:
+            self.set_alpha(slot, ta, per=ALPHA_PER_TRIANGLE)
+
+    def set_alpha(self, slot, alpha, per=ALPHA_PER_OBJECT):
+        """Replace slot's material mix (Eq. 3) per object or per face."""
+        a, pa = _np(alpha, np.float32)
+        self.ctx._check(self.lib.rr_batch_set_alpha(self.h, int(slot), pa, a.size, int(per)))
 
     def alloc_cubes(self):
         torch = self.ctx.torch
@@ -548,5 +568,6 @@ class Batch:
         return dict(ms_total=a.value, ms_synth_tuned=b.value, paths=n.value)
 
 
-EXPORTED += ["rr_batch_create", "rr_batch_destroy", "rr_batch_set_scene", "rr_batch_launch",
+EXPORTED += ["rr_batch_create", "rr_batch_destroy", "rr_batch_set_scene", "rr_batch_set_alpha",
+             "rr_batch_launch",
              "rr_batch_tune", "rr_batch_get_tiles", "rr_batch_stats"]

@@ -382,7 +382,7 @@ __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, i
         }
         uint64_t rb[4];
         philox((uint64_t)i, (uint64_t)t, (uint64_t)(j + 1), A.seed, rb);
-        dir = bounce_dir(dir, n, (double)A.obj_alpha[obj], u01(rb[0]), u01(rb[1]));
+        dir = bounce_dir(dir, n, (double)t2.w, u01(rb[0]), u01(rb[1]));
         o = p;
         prev = h;
     }
@@ -658,7 +658,30 @@ __global__ void k_scatter(PathSoA tmp, const unsigned long long *counter, int64_
     dst.amp[d] = tmp.amp[s];
 }
 
+// Material mix of every leaf triangle (word 11 of its 12-word record): the
+// per-face value indexed by the triangle's upload index (word 9) when given,
+// else its object's (object index in word 10).  No BVH rebuild needed.
+__global__ void k_set_alpha(float *ltris, int64_t n, const float *tri_alpha, const float *obj_alpha)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float *T = ltris + 12 * k;
+    const int id = __float_as_int(T[9]), obj = __float_as_int(T[10]);
+    T[11] = tri_alpha ? tri_alpha[id] : obj_alpha[obj];
+}
+
 }  // namespace
+
+hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alpha,
+                            const float *obj_alpha, hipStream_t s)
+{
+    if (n_tris <= 0) return hipSuccess;
+    if (!tri_alpha && !obj_alpha) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((n_tris + 255) / 256);
+    hipLaunchKernelGGL(k_set_alpha, dim3(blocks), dim3(256), 0, s, reinterpret_cast<float *>(ltris),
+                       n_tris, tri_alpha, obj_alpha);
+    return hipGetLastError();
+}
 
 hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s)
 {

@@ -7,7 +7,9 @@
 // never overflow.  Child boxes are stored in the parent, rounded outward to
 // float and padded by 1 mm plus 1e-6 of the scene extent: the FP32 slab test
 // on the device can therefore only over-include, never miss a triangle that
-// the FP64 intersection test would accept.
+// the FP64 intersection test would accept.  Leaf triangles are stored in leaf
+// order as 12 words: 9 vertex coordinates, the triangle's upload index, its
+// object and its material mix alpha.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -201,7 +203,7 @@ struct Builder {
 }  // namespace
 
 int rr_build_bvh(const float *verts, int64_t nv, const int32_t *tris, const int32_t *tri_obj,
-                 int64_t nt, HostBvh &out, std::string &err)
+                 const float *obj_alpha, int64_t nt, HostBvh &out, std::string &err)
 {
     out.nodes.clear();
     out.tris.clear();
@@ -265,10 +267,10 @@ int rr_build_bvh(const float *verts, int64_t nv, const int32_t *tris, const int3
             T[3 * c + 1] = v[1];
             T[3 * c + 2] = v[2];
         }
-        int32_t id = (int32_t)i, ob = tri_obj[i], z = 0;
+        int32_t id = (int32_t)i, ob = tri_obj[i];
         std::memcpy(&T[9], &id, 4);
         std::memcpy(&T[10], &ob, 4);
-        std::memcpy(&T[11], &z, 4);
+        T[11] = obj_alpha[ob];   // the face's material mix (Eq. 3), replaceable per face
     }
     return 0;
 }

@@ -150,6 +150,7 @@ struct rr_ctx {
 
     // learned proposal
     DevBuf tri_obj;            // object of each triangle, by original id
+    DevBuf tri_alpha;          // staging of per-face alpha for rr_scene_set_alpha
     TraceArgs last{};          // arguments of the last trace (histogram)
     int64_t last_traced = 0;
     int last_sampler = -1;
@@ -256,7 +257,7 @@ void rr_destroy(rr_ctx *c)
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
-                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak};
+                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -295,7 +296,7 @@ int rr_scene_upload(rr_ctx *c, const float *verts, int64_t n_verts, const int32_
     HIPCHK(hipSetDevice(c->device));
     HostBvh bvh;
     std::string err;
-    int rc = rr_build_bvh(verts, n_verts, tris, tri_obj, n_tris, bvh, err);
+    int rc = rr_build_bvh(verts, n_verts, tris, tri_obj, obj_alpha, n_tris, bvh, err);
     if (rc) return fail(rc, "BVH build: %s", err.c_str());
     c->has_scene = false;
     c->n_paths = -1;
@@ -326,6 +327,53 @@ int rr_scene_upload(rr_ctx *c, const float *verts, int64_t n_verts, const int32_
     c->npts = n_pts;
     c->bvh_depth = bvh.depth;
     c->has_scene = true;
+    g_err.clear();
+    return RR_OK;
+}
+
+namespace {
+
+// Replace the material mix of a scene's leaf records: alpha[n] per face
+// (n = n_tris, by upload index) or per object (n = n_obj).  The stream is
+// drained first so that no earlier launch still reads the staging buffers.
+int set_alpha_common(hipStream_t st, DevBuf &ltris, DevBuf &obj_buf, DevBuf &tri_buf,
+                     int64_t n_tris, int nobj, const float *alpha, int64_t n, int32_t per)
+{
+    if (!alpha && n > 0) return fail(RR_EINVAL, "NULL alpha");
+    if (per == RR_ALPHA_PER_OBJECT) {
+        if (n != nobj) return fail(RR_EINVAL, "per-object alpha needs one value per object (%d)", nobj);
+    } else if (per == RR_ALPHA_PER_TRIANGLE) {
+        if (n != n_tris)
+            return fail(RR_EINVAL, "per-face alpha needs one value per triangle (%lld)", (long long)n_tris);
+    } else {
+        return fail(RR_EINVAL, "unknown alpha mode");
+    }
+    for (int64_t i = 0; i < n; i++)
+        if (!(alpha[i] >= 0.0f && alpha[i] <= 1.0f))
+            return fail(RR_EINVAL, "alpha %lld outside [0, 1]", (long long)i);
+    HIPCHK(hipStreamSynchronize(st));
+    int rc;
+    if (per == RR_ALPHA_PER_OBJECT) {
+        HIPCHK(hipMemcpy(obj_buf.p, alpha, (size_t)n * 4, hipMemcpyHostToDevice));
+        HIPCHK(launch_set_alpha(ltris.as<float4>(), n_tris, nullptr, obj_buf.as<const float>(), st));
+    } else if (n > 0) {
+        if ((rc = tri_buf.ensure((size_t)n * 4))) return rc;
+        HIPCHK(hipMemcpy(tri_buf.p, alpha, (size_t)n * 4, hipMemcpyHostToDevice));
+        HIPCHK(launch_set_alpha(ltris.as<float4>(), n_tris, tri_buf.as<const float>(), nullptr, st));
+    }
+    return RR_OK;
+}
+
+}  // namespace
+
+int rr_scene_set_alpha(rr_ctx *c, const float *alpha, int64_t n, int32_t per)
+{
+    if (!c) return fail(RR_EINVAL, "ctx is NULL");
+    if (!c->has_scene) return fail(RR_ESTATE, "no scene uploaded");
+    HIPCHK(hipSetDevice(c->device));
+    int rc = set_alpha_common(c->stream, c->ltris, c->obj_alpha, c->tri_alpha, c->n_tris, c->nobj,
+                              alpha, n, per);
+    if (rc) return rc;
     g_err.clear();
     return RR_OK;
 }
@@ -430,7 +478,6 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
     A.nodes = c->nodes.as<const float4>();
     A.ltris = c->ltris.as<const float4>();
     A.has_bvh = c->n_tris > 0;
-    A.obj_alpha = c->obj_alpha.as<const float>();
     A.tx = c->tx.as<const double>();
     A.pt_pos = c->pt_pos.as<const double>();
     A.pt_ap = c->pt_ap.as<const double>();
@@ -519,7 +566,6 @@ int rr_trace_rays(rr_ctx *c, const double *orig, const double *dir, const double
     A.nodes = c->nodes.as<const float4>();
     A.ltris = c->ltris.as<const float4>();
     A.has_bvh = c->n_tris > 0;
-    A.obj_alpha = c->obj_alpha.as<const float>();
     A.tx = c->tx.as<const double>();
     for (int a = 0; a < 3; a++) {
         A.oT[a] = c->oT[a];
@@ -1185,7 +1231,7 @@ struct rr_batch {
     DevBuf d_targs, d_sargs, d_info, d_chunk, d_items, d_vr, d_vel, d_rinfo, d_ranges;
     DevBuf counts, offsets, bsums, total, counter, work;
     PathStore tmp, fin;
-    DevBuf syn;
+    DevBuf syn, alpha_tmp;
     int64_t cap = 0, V_total = 0, n_chunks = 0, n_items = 0, n_ranges = 0, nb = 0;
     std::vector<int64_t> range_base;
     std::vector<void *> cubes;
@@ -1285,7 +1331,6 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0)
         A.nodes = x.nodes.as<const float4>();
         A.ltris = x.ltris.as<const float4>();
         A.has_bvh = x.n_tris > 0;
-        A.obj_alpha = x.obj_alpha.as<const float>();
         A.tx = x.tx.as<const double>();
         A.pt_pos = x.pt_pos.as<const double>();
         A.pt_ap = x.pt_ap.as<const double>();
@@ -1441,7 +1486,8 @@ void rr_batch_destroy(rr_batch *b)
     for (auto &x : b->sc) x.release();
     DevBuf *bufs[] = {&b->d_targs, &b->d_sargs, &b->d_info, &b->d_chunk, &b->d_items, &b->d_vr,
                       &b->d_vel, &b->d_rinfo, &b->d_ranges, &b->counts, &b->offsets, &b->bsums,
-                      &b->total, &b->counter, &b->work, &b->syn, &b->tmp.buf, &b->fin.buf};
+                      &b->total, &b->counter, &b->work, &b->syn, &b->alpha_tmp, &b->tmp.buf,
+                      &b->fin.buf};
     for (DevBuf *x : bufs) x->release();
     for (auto &e : b->ev)
         if (e) (void)hipEventDestroy(e);
@@ -1491,7 +1537,7 @@ int rr_batch_set_scene(rr_batch *b, int32_t slot, const float *verts, int64_t n_
     HIPCHK(hipStreamSynchronize(b->st));
     HostBvh bvh;
     std::string err;
-    int rc = rr_build_bvh(verts, n_verts, tris, tri_obj, n_tris, bvh, err);
+    int rc = rr_build_bvh(verts, n_verts, tris, tri_obj, obj_alpha, n_tris, bvh, err);
     if (rc) return fail(rc, "BVH build: %s", err.c_str());
     BatchScene &x = b->sc[slot];
     if ((rc = x.nodes.ensure(bvh.nodes.size() * 4 + 64))) return rc;
@@ -1533,6 +1579,21 @@ int rr_batch_set_scene(rr_batch *b, int32_t slot, const float *verts, int64_t n_
     x.kr = 0;
     x.set = true;
     batch_drop_graph(b);
+    return RR_OK;
+}
+
+int rr_batch_set_alpha(rr_batch *b, int32_t slot, const float *alpha, int64_t n, int32_t per)
+{
+    if (!b) return fail(RR_EINVAL, "NULL batch");
+    if (slot < 0 || slot >= b->S) return fail(RR_EINVAL, "slot out of range");
+    BatchScene &x = b->sc[slot];
+    if (!x.set) return fail(RR_ESTATE, "slot %d has no scene", slot);
+    HIPCHK(hipSetDevice(b->c->device));
+    // the captured launch reads the leaf records in place: no re-capture needed
+    int rc = set_alpha_common(b->st, x.ltris, x.obj_alpha, b->alpha_tmp, x.n_tris, x.nobj, alpha,
+                              n, per);
+    if (rc) return rc;
+    g_err.clear();
     return RR_OK;
 }
 

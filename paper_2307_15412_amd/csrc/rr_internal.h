@@ -46,7 +46,7 @@ struct HostBvh {
 };
 
 int rr_build_bvh(const float *verts, int64_t nv, const int32_t *tris, const int32_t *tri_obj,
-                 int64_t nt, HostBvh &out, std::string &err);
+                 const float *obj_alpha, int64_t nt, HostBvh &out, std::string &err);
 
 // ---------------------------------------------------------------------------
 // trace kernel arguments (by value)
@@ -55,7 +55,6 @@ struct TraceArgs {
     const float4 *nodes;
     const float4 *ltris;
     int has_bvh;
-    const float *obj_alpha;
     const double *tx;         // [ntx][3]
     const double *pt_pos;     // [npts][3]
     const double *pt_ap;      // [npts]
@@ -158,6 +157,8 @@ struct BatchRangeInfo {
 hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s);
 hipError_t launch_points(const TraceArgs &a, hipStream_t s);
 hipError_t launch_trace_user(const TraceArgs &a, const UserRays &u, hipStream_t s);
+hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alpha,
+                            const float *obj_alpha, hipStream_t s);
 hipError_t launch_backproject(const BackProjArgs &a, hipStream_t s);
 hipError_t launch_max_projection(const float2 *img, int64_t nx, int64_t nyz, float *out,
                                  float *peak, float floor_db, hipStream_t s);

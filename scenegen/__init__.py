@@ -14,7 +14,8 @@ Conventions (both sides rely on them):
     names the object of each triangle; object 0 is the ground when present.
   * obj_alpha float32 [nobj] is the material mix of the paper's Eq. 3
     (0 = specular, 1 = diffuse), obj_vel float64 [nobj][3] is a constant
-    velocity.
+    velocity; an optional tri_alpha float32 [nt] gives every face its own
+    mix instead of its object's.
   * point reflectors: pt_pos / pt_vel float64 [np][3], pt_aperture float64 [np]
     (m^2).
   * Tx / Rx positions float64 [n][3]; virtual channel c = t * n_rx + r.
@@ -44,6 +45,7 @@ class Scene:
     pt_pos: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     pt_vel: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     pt_aperture: np.ndarray = field(default_factory=lambda: np.zeros((0,)))
+    tri_alpha: np.ndarray | None = None   # float32 [nt] per-face alpha (None: the object's)
 
     @property
     def n_tris(self) -> int:
@@ -66,6 +68,9 @@ class Scene:
         self.pt_pos = np.ascontiguousarray(self.pt_pos, dtype=np.float64).reshape(-1, 3)
         self.pt_vel = np.ascontiguousarray(self.pt_vel, dtype=np.float64).reshape(-1, 3)
         self.pt_aperture = np.ascontiguousarray(self.pt_aperture, dtype=np.float64).reshape(-1)
+        if self.tri_alpha is not None:
+            self.tri_alpha = np.ascontiguousarray(self.tri_alpha, dtype=np.float32).reshape(-1)
+            assert self.tri_alpha.shape[0] == self.tris.shape[0]
         assert self.tri_obj.shape[0] == self.tris.shape[0]
         assert self.obj_vel.shape[0] == self.obj_alpha.shape[0]
         assert self.pt_vel.shape[0] == self.pt_pos.shape[0] == self.pt_aperture.shape[0]
@@ -495,6 +500,31 @@ def workload_hand(seed: int = 0, n_rays: int = 10_000_000) -> Workload:
     return Workload("hand", scene_hand_proxy(seed), array_square(), chirp_sfcw(),
                     TraceParams(n_rays=n_rays, max_bounces=2, seed=seed, az_min=-25 * deg,
                                 az_max=25 * deg, el_min=-25 * deg, el_max=25 * deg))
+
+
+def with_alpha(scene: Scene, alpha: float) -> Scene:
+    """The same scene with every object (and no face override) at one alpha."""
+    return Scene(scene.verts, scene.tris, scene.tri_obj,
+                 np.full(scene.n_obj, alpha, dtype=np.float32), scene.obj_vel, scene.pt_pos,
+                 scene.pt_vel, scene.pt_aperture).checked()
+
+
+def alpha_sweep(lo: float = 0.0, hi: float = 1.0, step: float = 0.1) -> list[float]:
+    """Alpha values lo, lo + step, ..., hi (the paper's sweep: 0 to 1 by 0.1),
+    each rounded to float32 as the scene stores it."""
+    n = int(round((hi - lo) / step)) + 1
+    return [float(np.float32(lo + i * step)) for i in range(n)]
+
+
+def vary_alpha(scene: Scene, seed: int, spread: float = 0.2) -> Scene:
+    """Per-face alpha for data diversity: each face draws its own mix
+    uniformly within +-spread of its object's, clipped to [0, 1]."""
+    rng = np.random.default_rng(seed)
+    base = scene.obj_alpha[scene.tri_obj].astype(np.float64)
+    ta = np.clip(base + rng.uniform(-spread, spread, scene.n_tris), 0.0, 1.0)
+    return Scene(scene.verts, scene.tris, scene.tri_obj, scene.obj_alpha, scene.obj_vel,
+                 scene.pt_pos, scene.pt_vel, scene.pt_aperture,
+                 ta.astype(np.float32)).checked()
 
 
 def imaging_grid(x_lo: float = 0.26, x_hi: float = 0.34, half: float = 0.10,
