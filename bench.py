@@ -45,11 +45,12 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (hardware-counter calibration)")
     ap.add_argument("--batch-scenes", type=int, default=64)
-    ap.add_argument("--workload", choices=["large_mimo", "batch", "proposal", "hand"],
+    ap.add_argument("--workload", choices=["large_mimo", "batch", "proposal", "hand", "alpha_sweep"],
                     default="large_mimo",
                     help="large_mimo (default): the benchmarked step; batch: 64 uneven scenes in "
                          "one captured launch; proposal: learned-proposal training and gain; "
-                         "hand: SFCW hand imaging (trace, synthesis, back-projection, projection)")
+                         "hand: SFCW hand imaging (trace, synthesis, back-projection, projection); "
+                         "alpha_sweep: the hand imaged at alpha = 0, 0.1, ..., 1")
     return ap.parse_args()
 
 
@@ -137,14 +138,15 @@ def run_proposal(args):
         "equal_error": {k: v for k, v in eq.items() if k != "per_scene"}}))
 
 
-def run_hand(args):
+def run_hand(args, sweep=False):
     """The paper's imaging set-up on a synthetic hand: trace 1e7 rays (+-25
     degrees, 2 bounces) from the 94 x 94 square array, synthesise the
     8836-channel x 128-step SFCW cube with the exact model, back-project it
     onto the 81 x 201 x 201 grid of 1 mm voxels and take the maximum
     projection over range in dB.  A step is that whole chain; the dominant
     kernel is the back-projection (one complex multiply-add per voxel,
-    channel and frequency step)."""
+    channel and frequency step).  With sweep, a step images the hand at every
+    alpha of the paper's sweep (0 to 1 by 0.1), set on the uploaded mesh."""
     import torch
     import scenegen as sg
     import paper_2307_15412_amd as rr
@@ -163,27 +165,48 @@ def run_hand(args):
     img = torch.empty((nx, ny, nz), dtype=torch.complex64, device="cuda:0")
     proj = torch.empty((ny, nz), dtype=torch.float32, device="cuda:0")
 
-    def step():
-        n = ctx.trace_workload(w, record_hits=False)
-        ctx.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32, out=cube)
-        ctx.backproject(cube, grid, out=img)
-        ctx.max_projection(img, grid, out=proj)
-        return n
+    alphas = sg.alpha_sweep() if sweep else [float(w.scene.obj_alpha[0])]
+    tr, sy, bp, per_alpha = [], [], [], []
+    projs = [torch.empty((ny, nz), dtype=torch.float32, device="cuda:0") for _ in alphas]
+
+    def step(record):
+        ns = []
+        for a, pr in zip(alphas, projs):
+            if sweep:
+                ctx.set_alpha([a] * w.scene.n_obj)
+            ns.append(ctx.trace_workload(w, record_hits=False))
+            ctx.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32, out=cube)
+            ctx.backproject(cube, grid, out=img)
+            ctx.max_projection(img, grid, out=pr)
+            if record:
+                tr.append(ctx.kernel_ms(0))
+                sy.append(ctx.kernel_ms(1))
+                bp.append(ctx.kernel_ms(2))
+        return ns
 
     for _ in range(args.warmup):
-        step()
+        step(False)
         log("warmup step done")
     torch.cuda.synchronize()
-    tr, sy, bp = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        P = step()
-        tr.append(ctx.kernel_ms(0))
-        sy.append(ctx.kernel_ms(1))
-        bp.append(ctx.kernel_ms(2))
+        ns = step(True)
+        log("timed step done")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     log(f"timed {args.steps} steps, {dt * 1e3:.1f} ms each")
+    P = int(round(float(np.mean(ns))))   # paths per image (mean over the sweep)
+    if sweep:
+        # how the image changes with alpha: pixels above the -15 dB floor and
+        # the correlation of each dB image with the specular (alpha = 0) one
+        ref = projs[0].reshape(-1)
+        for a, n, pr in zip(alphas, ns, projs):
+            v = pr.reshape(-1)
+            corr = torch.corrcoef(torch.stack([ref, v]))[0, 1].item()
+            per_alpha.append({"alpha": a, "paths": n,
+                              "frac_above_floor": (v > -15.0).float().mean().item(),
+                              "corr_with_alpha0": corr})
+        ctx.set_alpha(list(w.scene.obj_alpha))
     bp_ms = float(np.mean(bp))
     flops = terms * FLOPS_PER_PATH_SAMPLE
     roof = {"bound": "alu", "achieved": flops / (bp_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
@@ -238,9 +261,13 @@ def run_hand(args):
                              f"{len(vox)} back-projected voxels ({t_bp:.2f} s), each scaled "
                              f"to the full step ({P} paths, {C} x {K} cube, {n_vox} voxels); "
                              f"host {cpu_model()}, nproc {os.cpu_count()}"}
-    print(json.dumps({
-        "metric": "hand images/s (trace + SFCW synthesis + back-projection + max projection)",
-        "value": 1.0 / dt, "unit": "images/s", "n_gpus": 1, "steps": args.steps,
+    if sweep and cpu is not None:
+        cpu["sample"] += "; the sweep's images each cost the same"
+    out = {
+        "metric": ("hand images/s over the alpha sweep 0..1 by 0.1 (trace + SFCW synthesis + "
+                   "back-projection + max projection per alpha)") if sweep else
+                  "hand images/s (trace + SFCW synthesis + back-projection + max projection)",
+        "value": len(alphas) / dt, "unit": "images/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64-phase/f32",
         "data": "synthetic (procedural hand proxy, seeded)",
@@ -251,7 +278,12 @@ def run_hand(args):
         "trace_ms": float(np.mean(tr)), "synth_ms": float(np.mean(sy)), "backproject_ms": bp_ms,
         "backproject_tterms_per_s": terms / (bp_ms * 1e-3) / 1e12,
         "cube_rel_err": cube_rel, "image_rel_err": img_rel,
-        "roofline": roof, "cpu_baseline": cpu}))
+        "roofline": roof, "cpu_baseline": cpu}
+    if sweep:
+        out["config"]["workload"] = "alpha sweep: " + out["config"]["workload"] + \
+            f", alpha in {alphas[0]}..{alphas[-1]} ({len(alphas)} images per step)"
+        out["per_alpha"] = per_alpha
+    print(json.dumps(out))
 
 
 def copy_calibration():
@@ -313,8 +345,8 @@ def main():
     if args.workload == "proposal":
         run_proposal(args)
         return
-    if args.workload == "hand":
-        run_hand(args)
+    if args.workload in ("hand", "alpha_sweep"):
+        run_hand(args, sweep=args.workload == "alpha_sweep")
         return
     import torch
     import scenegen as sg
