@@ -59,7 +59,7 @@ class _Trace(C.Structure):
     _fields_ = [("n_rays", C.c_int64), ("max_bounces", C.c_int32), ("seed", C.c_uint64),
                 ("az_min", C.c_double), ("az_max", C.c_double), ("el_min", C.c_double),
                 ("el_max", C.c_double), ("cdf", C.c_void_p), ("n_az", C.c_int32),
-                ("n_el", C.c_int32)]
+                ("n_el", C.c_int32), ("tri_g", C.c_int32)]
 
 
 _lib = None
@@ -138,7 +138,7 @@ def _array(a, keep):
 def _trace(tp, keep, cdf=None, n_az=0, n_el=0):
     c = None if cdf is None else keep.add(cdf, np.float64)
     st = _Trace(int(tp.n_rays), int(tp.max_bounces), int(tp.seed) & (2**64 - 1), tp.az_min,
-                tp.az_max, tp.el_min, tp.el_max, _p(c), n_az, n_el)
+                tp.az_max, tp.el_min, tp.el_max, _p(c), n_az, n_el, tri_grid(tp))
     keep.bufs.append(st)
     return st
 
@@ -199,7 +199,21 @@ def launch_dir(scene, array, tp, i, t, cdf=None, n_az=0, n_el=0) -> np.ndarray:
 # trace and synthesis
 # ----------------------------------------------------------------------------
 
+def tri_grid(tp) -> int:
+    """g of per-triangle casting (g^2 rays per triangle and source), 0 if off."""
+    n = int(getattr(tp, "rays_per_tri", 0) or 0)
+    if n <= 0:
+        return 0
+    g = int(round(n ** 0.5))
+    if g * g != n:
+        raise ValueError("rays_per_tri must be a perfect square")
+    return g
+
+
 def n_per_src(scene, array, tp) -> int:
+    g = tri_grid(tp)
+    if g:
+        return scene.n_tris * g * g
     return int(tp.n_rays) if array.mode == 1 else int(tp.n_rays) // array.n_tx
 
 

@@ -32,6 +32,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#define ORC_PI 3.14159265358979323846
+
 /* ------------------------------------------------------------------------ */
 /* public structs (mirrored by ctypes in oracle/__init__.py)                */
 /* ------------------------------------------------------------------------ */
@@ -74,6 +76,9 @@ typedef struct {
      * cdf[nb] = 1.  cdf == NULL selects uniform sampling. */
     const double *cdf;
     int32_t n_az, n_el;
+    /* per-triangle casting when tri_g > 0: tri_g^2 rays towards every
+     * triangle from every source (n_rays is then unused) */
+    int32_t tri_g;
 } orc_trace_params;
 
 #define ORC_KMAX 8
@@ -458,6 +463,7 @@ typedef struct {
     int64_t n_virt_per_src;          /* rays + points per source */
     vec3 oT, oR;
     double at, bt, slo, shi, omega;
+    double c0, s0, c1, s1;           /* cos, sin of the azimuth bounds */
 } trace_setup;
 
 static vec3 centroid(const double *p, int32_t n)
@@ -470,7 +476,10 @@ static vec3 centroid(const double *p, int32_t n)
 static void setup(const orc_scene *sc, const orc_array *ar, const orc_trace_params *tp, trace_setup *s)
 {
     s->n_src = ar->shared ? 1 : ar->ntx;
-    s->n_per_src = ar->shared ? tp->n_rays : tp->n_rays / ar->ntx;
+    if (tp->tri_g > 0)
+        s->n_per_src = sc->nt * (int64_t)tp->tri_g * tp->tri_g;
+    else
+        s->n_per_src = ar->shared ? tp->n_rays : tp->n_rays / ar->ntx;
     s->n_virt_per_src = s->n_per_src + sc->npts;
     s->oT = centroid(ar->tx, ar->ntx);
     s->oR = centroid(ar->rx, ar->nrx);
@@ -479,6 +488,53 @@ static void setup(const orc_scene *sc, const orc_array *ar, const orc_trace_para
     s->slo = sin(tp->el_min);
     s->shi = sin(tp->el_max);
     s->omega = (tp->az_max - tp->az_min) * (s->shi - s->slo);
+    s->c0 = cos(tp->az_min);
+    s->s0 = sin(tp->az_min);
+    s->c1 = cos(tp->az_max);
+    s->s1 = sin(tp->az_max);
+}
+
+/* Per-triangle casting (Sec. III: many rays are cast towards each mesh
+ * triangle).  Ray i of a source aims at triangle f = i / g^2; its index
+ * k = i mod g^2 picks cell (k mod g, k / g) of a g x g grid over the unit
+ * square, (u1, u2) is uniform in that cell and the area-preserving map
+ * x = (1 - sqrt u1) v0 + sqrt u1 (1 - u2) v1 + sqrt u1 u2 v2 puts it on the
+ * triangle, so the rays are uniform over the triangle's area and stratified.
+ * A point uniform over area A seen from src has the solid-angle density
+ * d^2 / (A |cos theta|), so the weight p0 A |cos theta| / d^2 (p0 = 1 / solid
+ * angle of the field of view; A |cos theta| = |n_area . dir| / 2) makes the
+ * sum over triangles estimate the same mean as the uniform launch, provided
+ * every direction is counted once: a ray counts only if its first hit is the
+ * triangle it aims at, and rays outside the field of view are not traced
+ * (reading: the field of view is the same azimuth / elevation box as the
+ * uniform launch; the azimuth test below needs a span of at most pi).
+ * Returns 0 for a ray that is not traced. */
+static int launch_tri(const orc_scene *sc, const orc_trace_params *tp, const trace_setup *s,
+                      vec3 src, int64_t i, int64_t t, vec3 *dir, double *w)
+{
+    int64_t g = tp->tri_g, gg = g * g;
+    int64_t f = i / gg, k = i % gg;
+    double u[4];
+    draw(tp->seed, (uint64_t)i, (uint64_t)t, 0, u);
+    double u1 = ((double)(k % g) + u[0]) / (double)g;
+    double u2 = ((double)(k / g) + u[1]) / (double)g;
+    vec3 v0, v1, v2;
+    tri_verts(sc, f, &v0, &v1, &v2);
+    double su = sqrt(u1);
+    double b0 = 1.0 - su, b1 = su * (1.0 - u2), b2 = su * u2;
+    vec3 x = mk(b0 * v0.x + b1 * v1.x + b2 * v2.x, b0 * v0.y + b1 * v1.y + b2 * v2.y,
+                b0 * v0.z + b1 * v1.z + b2 * v2.z);
+    vec3 a = vsub(x, src);
+    double d2 = vdot(a, a);
+    if (!(d2 > 0.0)) return 0;
+    vec3 d = vdiv(a, sqrt(d2));
+    if (!(d.z >= s->slo && d.z <= s->shi)) return 0;
+    if (!(s->c0 * d.y - s->s0 * d.x >= 0.0 && s->c1 * d.y - s->s1 * d.x <= 0.0)) return 0;
+    vec3 na = vcross(vsub(v1, v0), vsub(v2, v0));
+    *w = (0.5 * fabs(vdot(na, d))) / (d2 * s->omega);
+    if (!(*w > 0.0)) return 0;
+    *dir = d;
+    return 1;
 }
 
 /* first bin b with u < cdf[b+1] */
@@ -542,9 +598,11 @@ static int emit(orc_path *paths, int64_t cap, int64_t *np, const orc_path *p)
  * its closest approach to the Rx phase centre oR lies ahead, before the next
  * hit, inside the sphere of radius sqrt(r2)), and at each hit the new
  * direction of Eqs. 1-3 with the random numbers of counter (i, t, j + 1).
- * pa carries src, ray and amp; its hit points are filled in here. */
+ * pa carries src, ray and amp; its hit points are filled in here.  target >= 0:
+ * the ray is dropped (no hits recorded, no paths) unless its first hit is that
+ * triangle. */
 static void trace_from(const orc_scene *sc, vec3 oR, uint64_t seed, int32_t B, double r2, vec3 o,
-                       vec3 dir, int64_t i, int64_t t, orc_path *pa, int32_t *hrow,
+                       vec3 dir, int64_t i, int64_t t, int64_t target, orc_path *pa, int32_t *hrow,
                        orc_path *paths, int64_t cap, int64_t *np)
 {
     double L = 0.0;
@@ -552,6 +610,8 @@ static void trace_from(const orc_scene *sc, vec3 oR, uint64_t seed, int32_t B, d
     for (int32_t j = 0; j <= B; j++) {
         double th;
         int64_t h = closest(sc, o, dir, prev, &th);
+        /* a ray cast towards a triangle counts only if that triangle is its first hit */
+        if (j == 0 && target >= 0 && h != target) return;
         if (hrow) hrow[j] = (int32_t)h;
         if (j >= 1) {
             vec3 w2 = vsub(oR, o);
@@ -597,6 +657,7 @@ int orc_trace(const orc_scene *sc, const orc_array *ar, const orc_trace_params *
 {
     if (tp->max_bounces < 1 || tp->max_bounces > ORC_KMAX) return -1;
     if (ar->ntx < 1 || ar->nrx < 1) return -1;
+    if (tp->tri_g < 0 || (tp->tri_g > 0 && !(tp->az_max - tp->az_min <= ORC_PI))) return -1;
     trace_setup s;
     setup(sc, ar, tp, &s);
     if (use_bvh && g_bvh_scene != sc && bvh_build(sc) != 0) return -2;
@@ -640,9 +701,17 @@ int orc_trace(const orc_scene *sc, const orc_array *ar, const orc_trace_params *
             continue;
         }
         double w;
-        vec3 dir = launch(tp, &s, i, t, &w);
-        pa.amp = w / (double)s.n_per_src;
-        trace_from(sc, s.oR, tp->seed, B, r2, src, dir, i, t, &pa, hrow, paths, cap, &np);
+        vec3 dir;
+        int64_t target = -1;
+        if (tp->tri_g > 0) {
+            if (!launch_tri(sc, tp, &s, src, i, t, &dir, &w)) continue;
+            pa.amp = w / (double)((int64_t)tp->tri_g * tp->tri_g);
+            target = i / ((int64_t)tp->tri_g * tp->tri_g);
+        } else {
+            dir = launch(tp, &s, i, t, &w);
+            pa.amp = w / (double)s.n_per_src;
+        }
+        trace_from(sc, s.oR, tp->seed, B, r2, src, dir, i, t, target, &pa, hrow, paths, cap, &np);
     }
     *n_paths = np;
     return 0;
@@ -692,7 +761,7 @@ int orc_trace_rays(const orc_scene *sc, const orc_array *ar, int use_bvh, int64_
         vec3 d = vload3d(dir + 3 * i);
         d = vdiv(d, vlen(d));
         trace_from(sc, oR, seed, B, r2, vload3d(orig + 3 * i), d, i - i0, src[i] > 0 ? src[i] : 0,
-                   &pa, hrow, paths, cap, &np);
+                   -1, &pa, hrow, paths, cap, &np);
     }
     *n_paths = np;
     return 0;
@@ -832,7 +901,6 @@ void orc_uniform_bins(uint64_t seed, int64_t n_per_src, int64_t n_src, int32_t n
  * the matched filter of the synthesis phase exp(-j 2 pi f_n d / c).
  * cube: [n_tx n_rx][nf][2] (re, im); vox: [nv][3]; out: [nv][2].  FP64,
  * one sin / cos per term. */
-#define ORC_PI 3.14159265358979323846
 
 int orc_backproject(const orc_array *ar, double f0, double df, int32_t nf, const double *cube,
                     const double *vox, int64_t nv, double *out)

@@ -130,6 +130,8 @@ class TraceParams:
     az_max: float = math.pi / 2
     el_min: float = -math.pi / 2
     el_max: float = math.pi / 2
+    rays_per_tri: int = 0            # > 0: cast this many rays (a perfect square) towards
+                                     # every triangle from every source instead of n_rays
 
 
 @dataclass

@@ -1,0 +1,128 @@
+"""Pins of the oracle's per-triangle ray casting (Sec. III: rays are cast
+towards every mesh triangle) against closed forms.  With a reception sphere
+that takes every specular return, the summed path amplitude of a launch is p0
+times the solid angle its counted rays cover (p0 = 1 / field-of-view solid
+angle), so:
+  * one triangle: p0 times the Van Oosterom-Strackee solid angle (pins the
+    area-uniform point map, the A |cos| / d^2 weight and its factor 1/2);
+  * a small triangle in front of a large one: p0 times the large one's solid
+    angle, and no counted ray of the large one crosses the small one's
+    silhouette (pins the first-hit rule: nothing counted twice);
+  * the specular plate of the uniform-launch pin: p0 times the solid angle of
+    the returning disc, 2 pi (1 - cos theta_max);
+plus: every counted ray's first hit is its own triangle, weights scale as
+1/g^2, rays outside the field of view are not traced, invalid grids raise."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+
+def _scene(tris_xyz, alpha=0.0):
+    v = np.asarray(tris_xyz, dtype=np.float32).reshape(-1, 3)
+    n = v.shape[0] // 3
+    return sg.Scene(v, np.arange(3 * n, dtype=np.int32).reshape(n, 3), np.zeros(n, np.int32),
+                    np.array([alpha], np.float32), np.zeros((1, 3))).checked()
+
+
+def _solid_angle(tri, o):
+    a, b, c = (np.asarray(p, np.float64) - o for p in tri)
+    la, lb, lc = (np.linalg.norm(x) for x in (a, b, c))
+    num = abs(np.dot(a, np.cross(b, c)))
+    den = la * lb * lc + np.dot(a, b) * lc + np.dot(a, c) * lb + np.dot(b, c) * la
+    return 2.0 * math.atan2(num, den)
+
+
+def _mono(r=1e3):
+    o = np.zeros((1, 3))
+    return sg.Array(o, o.copy(), r, sg.MODE_PER_TX)
+
+
+def _tp(g, b=1, seed=1, **fov):
+    return sg.TraceParams(n_rays=0, max_bounces=b, seed=seed, rays_per_tri=g * g, **fov)
+
+
+def test_single_triangle_solid_angle():
+    tri = [[5.0, -0.3, 0.2], [5.4, 0.9, -0.1], [4.8, 0.1, 1.1]]
+    sc = _scene(tri)
+    tri32 = sc.verts.astype(np.float64)
+    omega_fov = math.pi * 2.0                      # the default hemisphere
+    want = _solid_angle(tri32, np.zeros(3)) / omega_fov
+    for g in (16, 64):
+        hits, paths = oracle.trace(sc, _mono(), _tp(g))
+        assert len(paths) == g * g                 # every ray is counted and returns
+        assert (hits[:, 0] == 0).all()
+        got = paths["amp"].sum()
+        assert abs(got / want - 1) < (2e-3 if g == 16 else 2e-4), (g, got, want)
+    # g = 1: a single ray, weight p0 A |cos| / d^2
+    _, p1 = oracle.trace(sc, _mono(), _tp(1))
+    assert len(p1) == 1 and abs(p1["amp"][0] / want - 1) < 0.2
+
+
+def test_occluded_rays_not_counted_twice():
+    big = [[6.0, -1.0, -1.0], [6.0, 1.5, -0.8], [6.0, -0.2, 1.4]]
+    small = [[4.0, -0.2, -0.1], [4.0, 0.3, -0.1], [4.0, 0.0, 0.3]]   # inside big's silhouette
+    sc = _scene(small + big)
+    tri32 = sc.verts.astype(np.float64).reshape(2, 3, 3)
+    want = _solid_angle(tri32[1], np.zeros(3)) / (2 * math.pi)
+    g = 64
+    hits, paths = oracle.trace(sc, _mono(), _tp(g))
+    ray_tri = np.arange(hits.shape[0]) // (g * g)
+    counted = hits[:, 0] >= 0
+    assert (hits[counted, 0] == ray_tri[counted]).all()
+    assert counted[: g * g].all()                  # the front triangle is never occluded
+    blocked = ~counted[g * g:]
+    assert 0 < blocked.mean() < 1
+    # the big triangle's dropped share = the small one's solid angle over the big one's
+    frac = _solid_angle(tri32[0], np.zeros(3)) / _solid_angle(tri32[1], np.zeros(3))
+    w = np.zeros(hits.shape[0])
+    w[paths["ray"]] = paths["amp"]
+    assert abs(paths["amp"].sum() / want - 1) < 1e-3
+    assert abs(w[g * g:][blocked].size / (g * g) - frac) < 0.05
+
+
+def test_specular_plate_disc():
+    R, r = 5.0, 0.25
+    sc = sg.plate(R, 1.0, alpha=0.0)
+    o = np.array([[0.0, 0.0, 0.5]])
+    ar = sg.Array(o, o.copy(), r, sg.MODE_PER_TX)
+    st = r / (2 * R)
+    want = 1.0 - math.sqrt(1 - st * st)            # p0 * 2 pi (1 - cos theta_max), p0 = 1 / 2 pi
+    _, paths = oracle.trace(sc, ar, _tp(256))
+    assert abs(paths["amp"].sum() / want - 1) < 0.01
+    assert np.allclose(paths["p"][:, 0, 0], R, atol=1e-12)
+
+
+def test_weights_scale_and_field_of_view():
+    tri = [[5.0, -0.3, 0.2], [5.4, 0.9, -0.1], [4.8, 0.1, 1.1]]
+    sc = _scene(tri)
+    a = oracle.trace(sc, _mono(), _tp(8))[1]["amp"].sum()
+    b = oracle.trace(sc, _mono(), _tp(32))[1]["amp"].sum()
+    assert abs(a / b - 1) < 0.02
+    # a field of view that excludes the triangle: nothing is traced
+    hits, paths = oracle.trace(sc, _mono(), _tp(8, az_min=-1.0, az_max=-0.5))
+    assert len(paths) == 0 and (hits == -1).all()
+    # a field of view that cuts it: fewer rays, the rest at the same points
+    # with weights scaled by p0 = 1 / (d_az (sin el_max - sin el_min))
+    h2, p2 = oracle.trace(sc, _mono(), _tp(8, az_min=-0.2, az_max=0.05))
+    h1, p1 = oracle.trace(sc, _mono(), _tp(8))
+    kept = np.isin(p1["ray"], p2["ray"])
+    assert 0 < len(p2) < len(p1)
+    assert np.array_equal(p1["p"][kept], p2["p"])
+    assert np.allclose(p1["amp"][kept] * 2 * math.pi, p2["amp"] * 0.25 * 2, rtol=1e-13, atol=0)
+    # p0 follows the field of view: twice the solid angle, half the weight
+    h3, p3 = oracle.trace(sc, _mono(), _tp(8, el_min=-math.pi / 2, el_max=math.pi / 2,
+                                            az_min=-math.pi / 2, az_max=math.pi / 2))
+    assert np.array_equal(p3["amp"], p1["amp"])
+
+
+def test_invalid_grids():
+    sc = _scene([[5.0, 0, 0], [5.0, 1, 0], [5.0, 0, 1]])
+    with pytest.raises(ValueError):
+        oracle.trace(sc, _mono(), sg.TraceParams(n_rays=0, max_bounces=1, rays_per_tri=5))
+    with pytest.raises(RuntimeError):
+        oracle.trace(sc, _mono(), sg.TraceParams(n_rays=0, max_bounces=1, rays_per_tri=4,
+                                                 az_min=-2.0, az_max=2.0))
