@@ -48,7 +48,7 @@ enum {
 };
 
 enum { RR_TX_PER_ELEMENT = 0, RR_TX_SHARED = 1 };
-enum { RR_UNIFORM = 0, RR_PROPOSAL = 1 };
+enum { RR_UNIFORM = 0, RR_PROPOSAL = 1, RR_PER_TRIANGLE = 2 };
 enum { RR_EXACT = 0, RR_SEPARABLE = 1 };
 enum { RR_ENGINE_AUTO = 0, RR_DIRECT_FP32 = 1, RR_GEMM_BF16X3 = 2 };
 
@@ -122,12 +122,23 @@ typedef struct {
 int rr_set_chirp(rr_ctx *ctx, const rr_chirp *chirp);
 
 /* Trace parameters (Sec. III-A: each Tx sends out many rays).
- *   n_rays      total launched rays (split evenly over Tx in per-element mode)
+ *   n_rays      total launched rays (split evenly over Tx in per-element mode);
+ *               with RR_PER_TRIANGLE: rays cast towards each triangle from
+ *               each source, a perfect square g^2 >= 1
  *   max_bounces surface hits per ray, 1..RR_KMAX
  *   seed        Philox4x64-10 key
  *   az/el range field of view in radians; directions uniform in solid angle
  *   sampler     RR_UNIFORM, or RR_PROPOSAL (bins of the proposal table set by
- *               rr_proposal_set_cdf or rr_proposal_build, weight p0/q)
+ *               rr_proposal_set_cdf or rr_proposal_build, weight p0/q), or
+ *               RR_PER_TRIANGLE (Sec. III: rays cast towards every mesh
+ *               triangle): ray k of triangle f (virtual ray f g^2 + k of its
+ *               source) aims at a point uniform in cell (k mod g, k / g) of a
+ *               g x g grid, mapped area-preservingly onto the triangle, with
+ *               weight p0 A |cos theta| / d^2 / g^2 (p0 = 1 / field-of-view
+ *               solid angle): the same estimate as the uniform launch.  Rays
+ *               outside the field of view, and rays whose first hit is not the
+ *               aimed-at triangle, are not counted (hit row all -1).  Needs an
+ *               azimuth span of at most pi.
  *   record_hits 1: keep the per-ray hit list for rr_get_hits
  *   path_cap    keep at most this many paths (first in ray, bounce order);
  *               0 = keep all */

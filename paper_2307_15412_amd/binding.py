@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libradray.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_ESTATE, RR_EOVERFLOW, RR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 TX_PER_ELEMENT, TX_SHARED = 0, 1
-UNIFORM, PROPOSAL = 0, 1
+UNIFORM, PROPOSAL, PER_TRIANGLE = 0, 1, 2
 EXACT, SEPARABLE = 0, 1
 ENGINE_AUTO, DIRECT_FP32, GEMM_BF16X3 = 0, 1, 2
 KMAX = 4
@@ -151,6 +151,7 @@ class Context:
         pa2, ppa = _np(np.zeros((0,)) if pt_aperture is None else pt_aperture, np.float64)
         self._check(self.lib.rr_scene_upload(self.h, pv, v.size // 3, pt, po, t.size // 3, pa, pov,
                                              a.size, ppp, ppv, ppa, pp.size // 3))
+        self.n_tris = t.size // 3
 
     def upload(self, scene):
         """Upload an object with verts/tris/tri_obj/obj_alpha/obj_vel/pt_* fields
@@ -189,7 +190,10 @@ class Context:
         self._check(self.lib.rr_trace(self.h, C.byref(tp), C.byref(n)))
         self.n_paths = n.value
         n_src = 1 if self.mode == TX_SHARED else self.n_tx
-        per = int(n_rays) if self.mode == TX_SHARED else int(n_rays) // self.n_tx
+        if sampler == PER_TRIANGLE:
+            per = self.n_tris * int(n_rays)
+        else:
+            per = int(n_rays) if self.mode == TX_SHARED else int(n_rays) // self.n_tx
         self.n_traced = n_src * per
         self.max_bounces = int(max_bounces)
         self.record_hits = bool(record_hits)
@@ -336,6 +340,9 @@ class Context:
         args = dict(n_rays=tp.n_rays, max_bounces=tp.max_bounces, seed=tp.seed, az_min=tp.az_min,
                     az_max=tp.az_max, el_min=tp.el_min, el_max=tp.el_max,
                     record_hits=record_hits, path_cap=getattr(workload, "path_cap", None) or 0)
+        rpt = int(getattr(tp, "rays_per_tri", 0) or 0)
+        if rpt > 0:
+            args.update(n_rays=rpt, sampler=PER_TRIANGLE)
         args.update(kw)
         return self.trace(**args)
 

@@ -268,7 +268,48 @@ __device__ __forceinline__ void append(const TraceArgs &A, bool rec, int32_t src
 
 // one launched ray g (source-major) through all of its bounces
 __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, int64_t i, int64_t t, int64_t v,
-                           double amp, int32_t srcid, int32_t *hrow, int *stk);
+                           double amp, int32_t srcid, int32_t *hrow, int *stk, int64_t target);
+
+// Per-triangle casting: ray i of a source aims at triangle f = i / g^2, at a
+// point drawn uniformly in cell (k mod g, k / g), k = i mod g^2, of a g x g
+// grid over the unit square and carried onto the triangle by the
+// area-preserving map (1 - sqrt u1) v0 + sqrt u1 (1 - u2) v1 + sqrt u1 u2 v2.
+// Weight p0 A |cos| / d^2 (A |cos| = |area normal . dir| / 2) over g^2 rays;
+// only rays inside the field of view are traced, and they count only when the
+// aimed-at triangle is their first hit.
+__device__ void trace_tri(const TraceArgs &A, int64_t g, int64_t t, int64_t i, int64_t v, d3 src,
+                          int *stk)
+{
+    const int64_t gs = A.tri_g, gg = gs * gs;
+    const int64_t f = i / gg, k = i - f * gg;
+    int32_t *hrow = A.hits ? A.hits + g * (A.bmax + 1) : nullptr;
+    uint64_t r[4];
+    philox((uint64_t)i, (uint64_t)t, 0, A.seed, r);
+    const double u1 = ((double)(k % gs) + u01(r[0])) / (double)gs;
+    const double u2 = ((double)(k / gs) + u01(r[1])) / (double)gs;
+    const float *T = A.tri_geom + 9 * f;
+    const d3 v0 = mk3(T[0], T[1], T[2]), v1 = mk3(T[3], T[4], T[5]), v2 = mk3(T[6], T[7], T[8]);
+    const double su = sqrt(u1);
+    const double b0 = 1.0 - su, b1 = su * (1.0 - u2), b2 = su * u2;
+    const d3 x = mk3(b0 * v0.x + b1 * v1.x + b2 * v2.x, b0 * v0.y + b1 * v1.y + b2 * v2.y,
+                     b0 * v0.z + b1 * v1.z + b2 * v2.z);
+    const d3 a = sub3(x, src);
+    const double d2 = dot3(a, a);
+    bool ok = d2 > 0.0;
+    d3 d = div3(a, sqrt(d2));
+    ok = ok && d.z >= A.slo && d.z <= A.shi;
+    ok = ok && A.fov_c0 * d.y - A.fov_s0 * d.x >= 0.0 && A.fov_c1 * d.y - A.fov_s1 * d.x <= 0.0;
+    const d3 na = cross3(sub3(v1, v0), sub3(v2, v0));
+    const double w = (0.5 * fabs(dot3(na, d))) / (d2 * A.omega);
+    ok = ok && w > 0.0;
+    if (!ok) {
+        if (hrow)
+            for (int q = 0; q <= A.bmax; q++) hrow[q] = -1;
+        A.counts[v] = 0;
+        return;
+    }
+    trace_from(A, src, d, i, t, v, w / (double)gg, A.shared ? -1 : (int32_t)t, hrow, stk, f);
+}
 
 __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
 {
@@ -277,6 +318,10 @@ __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
     int64_t v = A.vbase + t * A.n_virt_per_src + i;
     d3 src = A.shared ? mk3(A.oT[0], A.oT[1], A.oT[2])
                       : mk3(A.tx[3 * t], A.tx[3 * t + 1], A.tx[3 * t + 2]);
+    if (A.sampler == RR_PER_TRIANGLE) {
+        trace_tri(A, g, t, i, v, src, stk);
+        return;
+    }
     uint64_t r[4];
     philox((uint64_t)i, (uint64_t)t, 0, A.seed, r);
     double fa, fs, w = 1.0;
@@ -301,7 +346,7 @@ __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
     const double amp = w / (double)A.n_per_src;
     const int32_t srcid = A.shared ? -1 : (int32_t)t;
     int32_t *hrow = A.hits ? A.hits + g * (A.bmax + 1) : nullptr;
-    trace_from(A, src, dir, i, t, v, amp, srcid, hrow, stk);
+    trace_from(A, src, dir, i, t, v, amp, srcid, hrow, stk, -1);
 }
 
 // Caller-supplied ray g: origin, direction (normalised here), amplitude and
@@ -319,15 +364,16 @@ __device__ void trace_user(const TraceArgs &A, const UserRays &U, int64_t g, int
     d3 d = mk3(U.dir[3 * g], U.dir[3 * g + 1], U.dir[3 * g + 2]);
     d = div3(d, sqrt(dot3(d, d)));
     int32_t *hrow = A.hits ? A.hits + g * (A.bmax + 1) : nullptr;
-    trace_from(A, o, d, g - lo, srcid > 0 ? srcid : 0, A.vbase + g, U.amp[g], srcid, hrow, stk);
+    trace_from(A, o, d, g - lo, srcid > 0 ? srcid : 0, A.vbase + g, U.amp[g], srcid, hrow, stk, -1);
 }
 
 // The bounces of one ray from o along the unit vector dir: closest hit,
 // reception of every segment that follows a hit, the direction of Eqs. 1-3
 // at each hit with the random numbers of counter (i, t, j + 1); paths carry
-// source srcid, virtual ray v and amplitude amp.
+// source srcid, virtual ray v and amplitude amp.  target >= 0: the ray is
+// dropped (hit row all -1, no paths) unless its first hit is that triangle.
 __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, int64_t i, int64_t t, int64_t v,
-                           double amp, int32_t srcid, int32_t *hrow, int *stk)
+                           double amp, int32_t srcid, int32_t *hrow, int *stk, int64_t target)
 {
     Rec R;
 #pragma unroll
@@ -345,6 +391,13 @@ __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, i
         double th;
         int lidx;
         int h = closest_hit(A, o, dir, prev, th, lidx, stk);
+        if (j == 0 && target >= 0 && h != target) {
+            // cast towards a triangle that is not its first hit: not counted
+            if (hrow)
+                for (int q = 0; q <= A.bmax; q++) hrow[q] = -1;
+            A.counts[v] = 0;
+            return;
+        }
         if (hrow) hrow[j] = h;
         bool rec = false;
         if (j >= 1) {

@@ -151,6 +151,7 @@ struct rr_ctx {
     // learned proposal
     DevBuf tri_obj;            // object of each triangle, by original id
     DevBuf tri_alpha;          // staging of per-face alpha for rr_scene_set_alpha
+    DevBuf tri_geom;           // [n_tris][9] vertices by upload index (per-triangle casting)
     TraceArgs last{};          // arguments of the last trace (histogram)
     int64_t last_traced = 0;
     int last_sampler = -1;
@@ -257,7 +258,7 @@ void rr_destroy(rr_ctx *c)
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
-                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha};
+                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->tri_geom};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -309,8 +310,16 @@ int rr_scene_upload(rr_ctx *c, const float *verts, int64_t n_verts, const int32_
     if ((rc = c->pt_vel.ensure((size_t)n_pts * 24 + 8))) return rc;
     if ((rc = c->pt_ap.ensure((size_t)n_pts * 8 + 8))) return rc;
     if ((rc = c->tri_obj.ensure((size_t)n_tris * 4 + 8))) return rc;
-    if (n_tris > 0)
+    if ((rc = c->tri_geom.ensure((size_t)n_tris * 36 + 8))) return rc;
+    if (n_tris > 0) {
         HIPCHK(hipMemcpy(c->tri_obj.p, tri_obj, (size_t)n_tris * 4, hipMemcpyHostToDevice));
+        std::vector<float> geom((size_t)n_tris * 9);
+        for (int64_t i = 0; i < n_tris; i++)
+            for (int k = 0; k < 3; k++)
+                for (int a = 0; a < 3; a++)
+                    geom[9 * i + 3 * k + a] = verts[3 * (int64_t)tris[3 * i + k] + a];
+        HIPCHK(hipMemcpy(c->tri_geom.p, geom.data(), geom.size() * 4, hipMemcpyHostToDevice));
+    }
     if (!bvh.nodes.empty())
         HIPCHK(hipMemcpy(c->nodes.p, bvh.nodes.data(), bvh.nodes.size() * 4, hipMemcpyHostToDevice));
     if (!bvh.tris.empty())
@@ -442,8 +451,16 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
     if (!(tp->az_max > tp->az_min) || !(tp->el_max > tp->el_min) || tp->el_min < -M_PI / 2 - 1e-12 ||
         tp->el_max > M_PI / 2 + 1e-12 || !std::isfinite(tp->az_min) || !std::isfinite(tp->az_max))
         return fail(RR_EINVAL, "invalid field of view");
-    if (tp->sampler != RR_UNIFORM && tp->sampler != RR_PROPOSAL)
+    if (tp->sampler != RR_UNIFORM && tp->sampler != RR_PROPOSAL && tp->sampler != RR_PER_TRIANGLE)
         return fail(RR_EINVAL, "unknown sampler");
+    int tri_g = 0;
+    if (tp->sampler == RR_PER_TRIANGLE) {
+        tri_g = (int)std::llround(std::sqrt((double)tp->n_rays));
+        if (tp->n_rays < 1 || (int64_t)tri_g * tri_g != tp->n_rays)
+            return fail(RR_EINVAL, "per-triangle casting needs n_rays = g^2 >= 1 rays per triangle");
+        if (!(tp->az_max - tp->az_min <= M_PI))
+            return fail(RR_EINVAL, "per-triangle casting needs an azimuth span of at most pi");
+    }
     if (tp->sampler == RR_PROPOSAL && c->n_az <= 0)
         return fail(RR_ESTATE, "proposal sampler without a proposal table");
     if (tp->path_cap < 0) return fail(RR_EINVAL, "negative path_cap");
@@ -451,7 +468,8 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
 
     const int shared = c->mode == RR_TX_SHARED;
     const int64_t n_src = shared ? 1 : c->ntx;
-    const int64_t n_per_src = shared ? tp->n_rays : tp->n_rays / c->ntx;
+    const int64_t n_per_src = tri_g ? c->n_tris * tp->n_rays
+                                    : shared ? tp->n_rays : tp->n_rays / c->ntx;
     const int64_t n_vps = n_per_src + c->npts;
     const int64_t V = n_src * n_vps;
     const int64_t n_traced = n_src * n_per_src;
@@ -504,6 +522,12 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
     A.cdf = c->cdf.as<const double>();
     A.n_az = c->n_az;
     A.n_el = c->n_el;
+    A.tri_geom = c->tri_geom.as<const float>();
+    A.tri_g = tri_g;
+    A.fov_c0 = std::cos(tp->az_min);
+    A.fov_s0 = std::sin(tp->az_min);
+    A.fov_c1 = std::cos(tp->az_max);
+    A.fov_s1 = std::sin(tp->az_max);
     A.hits = tp->record_hits ? c->hits.as<int32_t>() : nullptr;
     A.counts = c->counts.as<uint8_t>();
     A.counter = c->counter.as<unsigned long long>();

@@ -69,6 +69,9 @@ struct TraceArgs {
     int sampler;
     const double *cdf;
     int n_az, n_el;
+    const float *tri_geom;    // [n_tris][9] vertices by upload index (per-triangle casting)
+    int tri_g;                // g: g^2 rays per triangle and source
+    double fov_c0, fov_s0, fov_c1, fov_s1;   // cos, sin of the azimuth bounds
     int64_t vbase;            // first virtual ray of this scene in the (batched) ray space
     // outputs
     int32_t *hits;            // [n_src*n_per_src][bmax+1] or null

@@ -1,0 +1,83 @@
+"""Per-triangle ray casting on the GPU against the FP64 oracle: hit lists
+(all -1 for rays that are outside the field of view or whose first hit is not
+the aimed-at triangle) and path records bitwise, on the tiny scene (per-element
+launch, several bounce counts), the hand proxy (shared launch, +-25 degree
+field of view that cuts the mesh), an occluding pair of triangles and a reduced
+street; the cube synthesised from those paths against the oracle's; invalid
+grids rejected."""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from helpers import assert_paths_equal, gpu_soa_np, oracle_to_soa, rel_err, traced_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(gpu, orc, w):
+    gpu.setup(w)
+    n = gpu.trace_workload(w, record_hits=True)
+    hits = gpu.hits().cpu().numpy()
+    oh, op = orc.trace(w.scene, w.array, w.trace)
+    oh = oh[traced_rows(orc, w.scene, w.array, w.trace)]
+    assert hits.shape == oh.shape
+    bad = np.argwhere((hits != oh).any(axis=1))
+    assert bad.size == 0, f"{bad.size} rays differ, first {bad[:5].ravel().tolist()}"
+    assert n == len(op)
+    assert_paths_equal(gpu_soa_np(gpu), oracle_to_soa(op))
+    return n, hits, op
+
+
+def test_tiny_per_element(gpu, orc):
+    for g, b in ((16, 2), (8, 1), (1, 3)):
+        w = sg.workload_tiny(4)
+        w.trace = sg.TraceParams(n_rays=0, max_bounces=b, seed=6, rays_per_tri=g * g)
+        n, hits, _ = _compare(gpu, orc, w)
+        assert (hits[:, 0] == -1).any()
+    assert n > 0
+
+
+def test_hand_shared_cut_fov(gpu, orc):
+    deg = math.pi / 180
+    w = sg.Workload("hand", sg.scene_hand_proxy(5, step=6e-3),
+                    sg.array_square(n_side=5, pitch=3e-3, rx_radius=0.07), sg.chirp_sfcw(72e9, 82e9, 32),
+                    sg.TraceParams(n_rays=0, max_bounces=2, seed=3, az_min=-8 * deg, az_max=12 * deg,
+                                   el_min=-10 * deg, el_max=6 * deg, rays_per_tri=9))
+    n, hits, op = _compare(gpu, orc, w)
+    assert n > 20
+    counted = hits[:, 0] >= 0
+    assert 0.05 < counted.mean() < 0.95
+    # the cube of these paths (exact model, direct engine)
+    import paper_2307_15412_amd as rr
+    cube = gpu.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32).cpu().numpy()
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=0)
+    assert rel_err(cube, ref) < 1e-4
+
+
+def test_occluding_pair_and_street(gpu, orc):
+    v = np.array([[4.0, -0.2, -0.1], [4.0, 0.3, -0.1], [4.0, 0.0, 0.3],
+                  [6.0, -1.0, -1.0], [6.0, 1.5, -0.8], [6.0, -0.2, 1.4]], np.float32)
+    sc = sg.Scene(v, np.arange(6, dtype=np.int32).reshape(2, 3), np.zeros(2, np.int32),
+                  np.array([0.5], np.float32), np.zeros((1, 3))).checked()
+    o = np.zeros((1, 3))
+    w = sg.Workload("pair", sc, sg.Array(o, o.copy(), 1e3, sg.MODE_PER_TX), sg.Chirp(),
+                    sg.TraceParams(n_rays=0, max_bounces=2, seed=2, rays_per_tri=32 * 32))
+    n, hits, _ = _compare(gpu, orc, w)
+    assert (hits[: 1024, 0] == 0).all() and (hits[1024:, 0] == -1).any()
+    st = sg.Workload("street", sg.scene_street(3, scale=0.05, n_cars=5, n_poles=6),
+                     sg.array_ula(2, 4, mode=sg.MODE_PER_TX), sg.Chirp(n_samples=64, n_chirps=8),
+                     sg.TraceParams(n_rays=0, max_bounces=3, seed=8, rays_per_tri=16))
+    assert st.scene.n_tris > 1000
+    _compare(gpu, orc, st)
+
+
+def test_invalid_grids(gpu):
+    import paper_2307_15412_amd as rr
+    w = sg.workload_tiny()
+    gpu.setup(w)
+    for n, az in ((5, 1.0), (0, 1.0), (4, 1.7)):
+        with pytest.raises(rr.RadrayError) as e:
+            gpu.trace(n_rays=n, max_bounces=2, az_min=-az, az_max=az, sampler=rr.PER_TRIANGLE)
+        assert e.value.code == rr.binding.RR_EINVAL
