@@ -59,15 +59,24 @@ def evaluate(ctx, workloads, budget, ref_rays, beta=0.1):
         ctx.trace(ref_rays, seed=tp.seed + 7919, sampler=B.UNIFORM, **kw)
         ref = _cube(ctx).clone()
         nref = float(ref.abs().pow(2).sum().sqrt())
-        ctx.trace(budget, seed=tp.seed, sampler=B.UNIFORM, **kw)
+        p_u = ctx.trace(budget, seed=tp.seed, sampler=B.UNIFORM, **kw)
         t_u = ctx.kernel_ms(0)
         eu = float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30)
         code = ctx.proposal_probe(tp.az_min, tp.az_max)
         ctx.proposal_build(code, beta)
-        ctx.trace(budget, seed=tp.seed, sampler=B.PROPOSAL, **kw)
+        p_l = ctx.trace(budget, seed=tp.seed, sampler=B.PROPOSAL, **kw)
         t_l = ctx.kernel_ms(0)
         el = float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30)
-        out.append(dict(seed=tp.seed, err_uniform=eu, err_learned=el, ms_uniform=t_u, ms_learned=t_l))
+        # per-triangle casting with at most the same number of rays
+        g = int(math.isqrt(budget // max(w.scene.n_tris, 1)))
+        rec = dict(seed=tp.seed, err_uniform=eu, err_learned=el, ms_uniform=t_u, ms_learned=t_l,
+                   paths_uniform=p_u, paths_learned=p_l)
+        if g >= 1:
+            p_t = ctx.trace(g * g, seed=tp.seed, sampler=B.PER_TRIANGLE, **kw)
+            # an empty cube scores exactly 1: read it with paths_tri
+            rec.update(err_tri=float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30),
+                       ms_tri=ctx.kernel_ms(0), rays_tri=g * g * w.scene.n_tris, paths_tri=p_t)
+        out.append(rec)
     return out
 
 
@@ -190,7 +199,17 @@ def experiment(ctx, train_seeds, eval_seeds, train_rays=50_000, budget=12_500, r
         log(f"evaluated {len(res)} held-out scenes in {time.time() - t2:.1f} s")
     eu = np.array([r["err_uniform"] for r in res])
     el = np.array([r["err_learned"] for r in res])
-    return dict(collect_s=t1 - t0, train_s=t2 - t1, loss_first=losses[0], loss_last=losses[-1],
-                err_uniform_mean=float(eu.mean()), err_learned_mean=float(el.mean()),
-                err_ratio_mean=float(np.mean(el / eu)), wins=int((el < eu).sum()),
-                n_eval=len(res), per_scene=res)
+    out = dict(collect_s=t1 - t0, train_s=t2 - t1, loss_first=losses[0], loss_last=losses[-1],
+               err_uniform_mean=float(eu.mean()), err_learned_mean=float(el.mean()),
+               err_ratio_mean=float(np.mean(el / eu)), wins=int((el < eu).sum()),
+               n_eval=len(res), per_scene=res)
+    if all("err_tri" in r for r in res):
+        et = np.array([r["err_tri"] for r in res])
+        out.update(err_tri_mean=float(et.mean()), err_ratio_tri_mean=float(np.mean(et / eu)),
+                   wins_tri=int((et < eu).sum()),
+                   rays_tri_mean=float(np.mean([r["rays_tri"] for r in res])),
+                   paths_tri_mean=float(np.mean([r["paths_tri"] for r in res])),
+                   empty_tri=int(sum(r["paths_tri"] == 0 for r in res)))
+    out.update(paths_uniform_mean=float(np.mean([r["paths_uniform"] for r in res])),
+               paths_learned_mean=float(np.mean([r["paths_learned"] for r in res])))
+    return out
