@@ -88,6 +88,28 @@ int rr_scene_upload(rr_ctx *ctx, const float *verts, int64_t n_verts,
                     const double *pt_pos, const double *pt_vel, const double *pt_aperture,
                     int32_t n_pts);
 
+/* Move the uploaded scene's vertices (same count, same triangles): for
+ * animated or deforming meshes such as moving hands (Sec. V), traced frame
+ * by frame.  verts float [n_verts][3], host, copied.  Instead of a host
+ * rebuild the BVH is refit on the GPU: leaf triangles take the new
+ * positions, then every node's child boxes are recomputed bottom-up (one
+ * launch per depth) from the exact bounds of the child subtrees, padded and
+ * rounded outward like the host build, so traversal stays exact (boxes only
+ * over-include); an unchanged mesh refits to the identical tree.  The
+ * topology of the tree is kept, so large motions can make traversal slower,
+ * never wrong.  Drains the context's stream first; later traces see the new
+ * geometry, paths already traced are kept.
+ * Errors: RR_ESTATE (no scene), RR_EINVAL (count differs from the upload,
+ * NULL or non-finite vertices). */
+int rr_scene_update_vertices(rr_ctx *ctx, const float *verts, int64_t n_verts);
+
+/* Copy of the BVH node array (16 floats per node: both child boxes, lo.xyz
+ * hi.xyz each, then the two child references as int32 bits: >= 0 a node,
+ * < 0 the leaf ~(first << 3 | (count - 1)) of leaf-ordered triangles) for
+ * inspection.  dst host (NULL: only *n_floats is written); capacity in
+ * floats.  Errors: RR_ESTATE, RR_EOVERFLOW (capacity too small). */
+int rr_get_bvh_nodes(rr_ctx *ctx, float *dst, int64_t capacity, int64_t *n_floats);
+
 enum { RR_ALPHA_PER_OBJECT = 0, RR_ALPHA_PER_TRIANGLE = 1 };
 
 /* Replace the material mix alpha of Eq. 3 (Sec. III-A) of the uploaded scene

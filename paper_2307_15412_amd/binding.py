@@ -29,7 +29,7 @@ EXPORTED = [
     "rr_create", "rr_destroy", "rr_last_error", "rr_version", "rr_scene_upload", "rr_set_array",
     "rr_set_chirp", "rr_trace", "rr_trace_rays", "rr_get_path_count", "rr_get_hits",
     "rr_get_paths", "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms", "rr_backproject",
-    "rr_max_projection", "rr_scene_set_alpha",
+    "rr_max_projection", "rr_scene_set_alpha", "rr_scene_update_vertices", "rr_get_bvh_nodes",
 ]
 
 
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     L.rr_version.restype = C.c_char_p
     L.rr_scene_upload.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, i32, vp, vp, vp, i32]
     L.rr_scene_set_alpha.argtypes = [vp, vp, i64, i32]
+    L.rr_scene_update_vertices.argtypes = [vp, vp, i64]
+    L.rr_get_bvh_nodes.argtypes = [vp, vp, i64, C.POINTER(i64)]
     L.rr_set_array.argtypes = [vp, vp, i32, vp, i32, f64, i32]
     L.rr_set_chirp.argtypes = [vp, C.POINTER(Chirp)]
     L.rr_trace.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
@@ -161,6 +163,20 @@ class Context:
         ta = getattr(scene, "tri_alpha", None)
         if ta is not None:
             self.set_alpha(ta, per=ALPHA_PER_TRIANGLE)
+
+    def update_vertices(self, verts):
+        """Move the scene's vertices (same topology); the BVH is refit on the GPU."""
+        v, pv = _np(verts, np.float32)
+        self._check(self.lib.rr_scene_update_vertices(self.h, pv, v.size // 3))
+
+    def bvh_nodes(self):
+        """The BVH node array, float32 [n_nodes][16] (host copy)."""
+        n = C.c_int64()
+        self._check(self.lib.rr_get_bvh_nodes(self.h, None, 0, C.byref(n)))
+        out = np.zeros(n.value, dtype=np.float32)
+        self._check(self.lib.rr_get_bvh_nodes(self.h, out.ctypes.data if n.value else None,
+                                              n.value, C.byref(n)))
+        return out.reshape(-1, 16)
 
     def set_alpha(self, alpha, per=ALPHA_PER_OBJECT):
         """Replace the scene's material mix (Eq. 3) per object or per face."""

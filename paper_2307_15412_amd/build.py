@@ -31,6 +31,7 @@ SOURCES = {
     "k_gemm.hip": [],
     "k_mlp.hip": [],
     "k_image.hip": [],
+    "k_refit.hip": ["-ffp-contract=off"],
 }
 
 

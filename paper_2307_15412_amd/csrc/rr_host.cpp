@@ -152,6 +152,11 @@ struct rr_ctx {
     DevBuf tri_obj;            // object of each triangle, by original id
     DevBuf tri_alpha;          // staging of per-face alpha for rr_scene_set_alpha
     DevBuf tri_geom;           // [n_tris][9] vertices by upload index (per-triangle casting)
+    // refit of the BVH to moved vertices (rr_scene_update_vertices)
+    DevBuf tris_dev, verts_dev, refit_order, ubox;
+    std::vector<int64_t> refit_levels;   // starts of the levels in refit_order, deepest first
+    std::vector<int32_t> h_tris;
+    int64_t n_verts = 0, n_nodes = 0;
     TraceArgs last{};          // arguments of the last trace (histogram)
     int64_t last_traced = 0;
     int last_sampler = -1;
@@ -258,7 +263,8 @@ void rr_destroy(rr_ctx *c)
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
-                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->tri_geom};
+                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->tri_geom, &c->tris_dev, &c->verts_dev,
+                      &c->refit_order, &c->ubox};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -331,11 +337,89 @@ int rr_scene_upload(rr_ctx *c, const float *verts, int64_t n_verts, const int32_
         HIPCHK(hipMemcpy(c->pt_vel.p, pt_vel, (size_t)n_pts * 24, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->pt_ap.p, pt_aperture, (size_t)n_pts * 8, hipMemcpyHostToDevice));
     }
+    // refit support: topology on the device, internal nodes by depth (deepest first)
+    c->refit_levels.clear();
+    c->n_nodes = (int64_t)bvh.nodes.size() / 16;
+    if (n_tris > 0) {
+        std::vector<std::vector<int32_t>> lv;
+        std::vector<int32_t> cur{0};
+        while (!cur.empty()) {
+            lv.push_back(cur);
+            std::vector<int32_t> nxt;
+            for (int32_t n : cur)
+                for (int ch = 0; ch < 2; ch++) {
+                    int32_t ref;
+                    std::memcpy(&ref, &bvh.nodes[16 * (size_t)n + 12 + ch], 4);
+                    if (ref >= 0) nxt.push_back(ref);
+                }
+            cur.swap(nxt);
+        }
+        std::vector<int32_t> order;
+        for (size_t l = lv.size(); l-- > 0;) {
+            c->refit_levels.push_back((int64_t)order.size());
+            order.insert(order.end(), lv[l].begin(), lv[l].end());
+        }
+        c->refit_levels.push_back((int64_t)order.size());
+        if ((rc = c->refit_order.ensure(order.size() * 4 + 8))) return rc;
+        if ((rc = c->ubox.ensure((size_t)c->n_nodes * 24 + 8))) return rc;
+        if ((rc = c->tris_dev.ensure((size_t)n_tris * 12))) return rc;
+        if ((rc = c->verts_dev.ensure((size_t)n_verts * 12 + 8))) return rc;
+        HIPCHK(hipMemcpy(c->refit_order.p, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->tris_dev.p, tris, (size_t)n_tris * 12, hipMemcpyHostToDevice));
+        c->h_tris.assign(tris, tris + 3 * n_tris);
+    } else {
+        c->h_tris.clear();
+    }
+    c->n_verts = n_verts;
     c->n_tris = n_tris;
     c->nobj = n_obj;
     c->npts = n_pts;
     c->bvh_depth = bvh.depth;
     c->has_scene = true;
+    g_err.clear();
+    return RR_OK;
+}
+
+int rr_scene_update_vertices(rr_ctx *c, const float *verts, int64_t n_verts)
+{
+    if (!c) return fail(RR_EINVAL, "ctx is NULL");
+    if (!c->has_scene) return fail(RR_ESTATE, "no scene uploaded");
+    if (n_verts != c->n_verts)
+        return fail(RR_EINVAL, "vertex count %lld differs from the uploaded scene's %lld",
+                    (long long)n_verts, (long long)c->n_verts);
+    if (n_verts > 0 && !verts) return fail(RR_EINVAL, "NULL vertices");
+    for (int64_t i = 0; i < 3 * n_verts; i++)
+        if (!std::isfinite(verts[i])) return fail(RR_EINVAL, "non-finite vertex coordinate");
+    if (c->n_tris == 0) return RR_OK;
+    // the padding of the host build, from the vertices the triangles use
+    double maxabs = 0.0;
+    for (int64_t i = 0; i < 3 * c->n_tris; i++) {
+        const float *v = verts + 3 * (int64_t)c->h_tris[i];
+        for (int a = 0; a < 3; a++) maxabs = std::max(maxabs, (double)std::fabs(v[a]));
+    }
+    const double pad = 1e-3 + 1e-6 * maxabs;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(c->verts_dev.p, verts, (size_t)n_verts * 12, hipMemcpyHostToDevice));
+    HIPCHK(launch_refit(c->nodes.as<float4>(), c->ubox.as<float>(), c->refit_order.as<const int32_t>(),
+                        c->refit_levels.data(), (int)c->refit_levels.size() - 1, c->ltris.as<float4>(),
+                        c->tri_geom.as<float>(), c->n_tris, c->tris_dev.as<const int32_t>(),
+                        c->verts_dev.as<const float>(), pad, c->stream));
+    g_err.clear();
+    return RR_OK;
+}
+
+int rr_get_bvh_nodes(rr_ctx *c, float *dst, int64_t capacity, int64_t *n_floats)
+{
+    if (!c || !n_floats) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_scene) return fail(RR_ESTATE, "no scene uploaded");
+    *n_floats = 16 * c->n_nodes;
+    if (!dst) return RR_OK;
+    if (capacity < *n_floats) return fail(RR_EOVERFLOW, "need %lld floats", (long long)*n_floats);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (*n_floats > 0)
+        HIPCHK(hipMemcpy(dst, c->nodes.p, (size_t)*n_floats * 4, hipMemcpyDeviceToHost));
     g_err.clear();
     return RR_OK;
 }

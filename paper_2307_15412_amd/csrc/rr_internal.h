@@ -162,6 +162,10 @@ hipError_t launch_points(const TraceArgs &a, hipStream_t s);
 hipError_t launch_trace_user(const TraceArgs &a, const UserRays &u, hipStream_t s);
 hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alpha,
                             const float *obj_alpha, hipStream_t s);
+hipError_t launch_refit(float4 *nodes, float *ubox, const int32_t *order,
+                        const int64_t *level_start, int n_levels, float4 *ltris, float *tri_geom,
+                        int64_t n_tris, const int32_t *tris, const float *verts, double pad,
+                        hipStream_t s);
 hipError_t launch_backproject(const BackProjArgs &a, hipStream_t s);
 hipError_t launch_max_projection(const float2 *img, int64_t nx, int64_t nyz, float *out,
                                  float *peak, float floor_db, hipStream_t s);

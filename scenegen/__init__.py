@@ -473,24 +473,77 @@ def workload_batch(n_scenes: int = 64, seed0: int = 2000, rays: int = 1_000_000,
     return out
 
 
+def _hand_builder(seed: int, step: float, rng_x: float):
+    """Mesh builder of the hand proxy and the vertex range of each part
+    (palm, four fingers, thumb)."""
+    rng = np.random.default_rng(seed)
+    mb = _MeshBuilder()
+    t = 0.015
+    parts = []
+
+    def part(lo, hi):
+        a = mb.nv
+        mb.box(lo, hi, step, 0)
+        parts.append((a, mb.nv))
+
+    part((rng_x, -0.04, -0.05), (rng_x + t, 0.04, 0.04))
+    for i in range(4):
+        y0 = -0.038 + i * 0.0195
+        w = 0.016 + 0.002 * rng.random()
+        ln = 0.06 + 0.025 * rng.random()
+        part((rng_x + 0.002, y0, 0.04), (rng_x + t - 0.002, y0 + w, 0.04 + ln))
+    ln = 0.05 + 0.015 * rng.random()
+    part((rng_x + 0.002, 0.04, -0.03), (rng_x + t - 0.002, 0.04 + ln, -0.012))
+    return mb, parts
+
+
 def scene_hand_proxy(seed: int = 0, step: float = 2e-3, rng_x: float = 0.30,
                      alpha: float = 0.3) -> Scene:
     """A static open hand facing the array: a palm (8 cm wide, 9 cm tall,
     1.5 cm thick) at range rng_x and five fingers (1.6-1.8 cm wide) above it,
     lengths and spread drawn from `seed`, the thumb to the side; faces
     subdivided at `step`.  One object, material alpha."""
-    rng = np.random.default_rng(seed)
-    mb = _MeshBuilder()
-    t = 0.015
-    mb.box((rng_x, -0.04, -0.05), (rng_x + t, 0.04, 0.04), step, 0)
-    for i in range(4):
-        y0 = -0.038 + i * 0.0195
-        w = 0.016 + 0.002 * rng.random()
-        ln = 0.06 + 0.025 * rng.random()
-        mb.box((rng_x + 0.002, y0, 0.04), (rng_x + t - 0.002, y0 + w, 0.04 + ln), step, 0)
-    ln = 0.05 + 0.015 * rng.random()
-    mb.box((rng_x + 0.002, 0.04, -0.03), (rng_x + t - 0.002, 0.04 + ln, -0.012), step, 0)
+    mb, _ = _hand_builder(seed, step, rng_x)
     return mb.build([alpha], [[0.0, 0.0, 0.0]])
+
+
+def hand_motion(seed: int = 0, n_frames: int = 32, step: float = 2e-3, rng_x: float = 0.30,
+                alpha: float = 0.3, curl_deg: float = 70.0, drift: float = 0.01):
+    """The hand proxy moving: over n_frames (one period), finger i curls
+    towards the array about its knuckle line (the y axis through the finger's
+    base at the palm's mid-thickness) by curl_deg (1 - cos(2 pi f / n + i pi / 4)) / 2,
+    the thumb swings about its base (the z axis) by half that, and the whole
+    hand drifts by drift sin(2 pi f / n) along y.  Returns (scene at frame 0,
+    [float32 vertex arrays of frames 0..n-1]); the topology never changes."""
+    mb, parts = _hand_builder(seed, step, rng_x)
+    scene = mb.build([alpha], [[0.0, 0.0, 0.0]])
+    base = np.concatenate(mb.v).astype(np.float64)
+    cx = rng_x + 0.0075
+    frames = []
+    for f in range(n_frames):
+        v = base.copy()
+        ph = 2 * math.pi * f / n_frames
+        for i in range(4):
+            a, b = parts[1 + i]
+            th = math.radians(curl_deg) * (1 - math.cos(ph + i * math.pi / 4)) / 2
+            dx, dz = v[a:b, 0] - cx, v[a:b, 2] - 0.04
+            v[a:b, 0] = cx + dx * math.cos(th) - dz * math.sin(th)
+            v[a:b, 2] = 0.04 + dz * math.cos(th) + dx * math.sin(th)
+        a, b = parts[5]
+        th = 0.5 * math.radians(curl_deg) * (1 - math.cos(ph)) / 2
+        dx, dy = v[a:b, 0] - cx, v[a:b, 1] - 0.04
+        v[a:b, 0] = cx + dx * math.cos(th) - dy * math.sin(th)
+        v[a:b, 1] = 0.04 + dy * math.cos(th) + dx * math.sin(th)
+        v[:, 1] += drift * math.sin(ph)
+        frames.append(v.astype(np.float32))
+    return with_verts(scene, frames[0]), frames
+
+
+def with_verts(scene: Scene, verts) -> Scene:
+    """The same scene (topology, objects, materials) with new vertex positions."""
+    return Scene(np.asarray(verts, np.float32), scene.tris, scene.tri_obj, scene.obj_alpha,
+                 scene.obj_vel, scene.pt_pos, scene.pt_vel, scene.pt_aperture,
+                 scene.tri_alpha).checked()
 
 
 def workload_hand(seed: int = 0, n_rays: int = 10_000_000) -> Workload:
