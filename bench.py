@@ -144,7 +144,8 @@ def run_proposal(args):
 def run_hand(args, sweep=False):
     """The paper's imaging set-up on a synthetic hand: trace 1e7 rays (+-25
     degrees, 2 bounces) from the 94 x 94 square array, synthesise the
-    8836-channel x 128-step SFCW cube with the exact model, back-project it
+    8836-channel x 128-step SFCW cube with the exact model (one split-bf16
+    complex product per frequency on the matrix cores), back-project it
     onto the 81 x 201 x 201 grid of 1 mm voxels and take the maximum
     projection over range in dB.  A step is that whole chain; the dominant
     kernel is the back-projection (one complex multiply-add per voxel,
@@ -178,7 +179,7 @@ def run_hand(args, sweep=False):
             if sweep:
                 ctx.set_alpha([a] * w.scene.n_obj)
             ns.append(ctx.trace_workload(w, record_hits=False))
-            ctx.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32, out=cube)
+            ctx.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT, out=cube)
             ctx.backproject(cube, grid, out=img)
             ctx.max_projection(img, grid, out=pr)
             if record:
@@ -246,7 +247,7 @@ def run_hand(args, sweep=False):
         if not args.no_check:
             soa = oracle.to_soa(op)
             ctx.set_paths({kk: torch.from_numpy(np.ascontiguousarray(v)) for kk, v in soa.items()})
-            full = ctx.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32, out=cube)
+            full = ctx.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT, out=cube)
             got = full.reshape(-1)[torch.from_numpy(idx).to(full.device)].cpu().numpy()
             cube_rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
             cin = torch.from_numpy(ocube.reshape(C, 1, K).astype(np.complex64)).cuda()
@@ -278,7 +279,8 @@ def run_hand(args, sweep=False):
                                "+-25 deg, <=2 bounces, 72-82 GHz SFCW 128 steps, exact model, "
                                f"{nx} x {ny} x {nz} voxels at 1 mm",
                    "paths": P},
-        "trace_ms": float(np.mean(tr)), "synth_ms": float(np.mean(sy)), "backproject_ms": bp_ms,
+        "trace_ms": float(np.mean(tr)), "synth_ms": float(np.mean(sy)), "synth_engine": "gemm_exact",
+        "backproject_ms": bp_ms,
         "backproject_tterms_per_s": terms / (bp_ms * 1e-3) / 1e12,
         "cube_rel_err": cube_rel, "image_rel_err": img_rel,
         "roofline": roof, "cpu_baseline": cpu}
@@ -308,7 +310,7 @@ def run_tri_cast(args):
               el_max=tp.el_max, record_hits=False)
     ref_rays = 100_000_000
     ctx.trace(ref_rays, seed=tp.seed + 7919, sampler=rr.UNIFORM, **kw)
-    ref = ctx.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32)
+    ref = ctx.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT)
     nref = float(ref.abs().pow(2).sum().sqrt())
     log(f"reference: {ctx.n_paths} paths from {ref_rays} rays")
     cube = torch.empty_like(ref)
@@ -323,7 +325,7 @@ def run_tri_cast(args):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             P = ctx.trace(n, seed=tp.seed, sampler=sampler, **kw)
-            ctx.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32, out=cube)
+            ctx.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT, out=cube)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             err = float((cube - ref).abs().pow(2).sum().sqrt()) / nref
@@ -370,7 +372,7 @@ def run_hand_motion(args):
         for f in range(n_frames):
             ctx.update_vertices(frames[f])
             ns.append(ctx.trace_workload(w, record_hits=False))
-            ctx.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32, out=cubes[f])
+            ctx.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT, out=cubes[f])
         return ns
 
     for _ in range(args.warmup):

@@ -50,7 +50,7 @@ enum {
 enum { RR_TX_PER_ELEMENT = 0, RR_TX_SHARED = 1 };
 enum { RR_UNIFORM = 0, RR_PROPOSAL = 1, RR_PER_TRIANGLE = 2 };
 enum { RR_EXACT = 0, RR_SEPARABLE = 1 };
-enum { RR_ENGINE_AUTO = 0, RR_DIRECT_FP32 = 1, RR_GEMM_BF16X3 = 2 };
+enum { RR_ENGINE_AUTO = 0, RR_DIRECT_FP32 = 1, RR_GEMM_BF16X3 = 2, RR_GEMM_EXACT = 3 };
 
 #define RR_KMAX 4          /* largest supported bounce count */
 

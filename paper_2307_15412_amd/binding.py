@@ -21,7 +21,7 @@ RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_ESTATE, RR_EOVERFLOW, RR_EUNSUPPORTED =
 TX_PER_ELEMENT, TX_SHARED = 0, 1
 UNIFORM, PROPOSAL, PER_TRIANGLE = 0, 1, 2
 EXACT, SEPARABLE = 0, 1
-ENGINE_AUTO, DIRECT_FP32, GEMM_BF16X3 = 0, 1, 2
+ENGINE_AUTO, DIRECT_FP32, GEMM_BF16X3, GEMM_EXACT = 0, 1, 2, 3
 KMAX = 4
 ALPHA_PER_OBJECT, ALPHA_PER_TRIANGLE = 0, 1
 

@@ -32,6 +32,7 @@ SOURCES = {
     "k_mlp.hip": [],
     "k_image.hip": [],
     "k_refit.hip": ["-ffp-contract=off"],
+    "k_freq.hip": [],
 }
 
 

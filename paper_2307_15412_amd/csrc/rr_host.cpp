@@ -154,6 +154,7 @@ struct rr_ctx {
     DevBuf tri_geom;           // [n_tris][9] vertices by upload index (per-triangle casting)
     // refit of the BVH to moved vertices (rr_scene_update_vertices)
     DevBuf tris_dev, verts_dev, refit_order, ubox;
+    DevBuf fq_pm, fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact-model GEMM engine
     std::vector<int64_t> refit_levels;   // starts of the levels in refit_order, deepest first
     std::vector<int32_t> h_tris;
     int64_t n_verts = 0, n_nodes = 0;
@@ -264,7 +265,8 @@ void rr_destroy(rr_ctx *c)
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
                       &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->tri_geom, &c->tris_dev, &c->verts_dev,
-                      &c->refit_order, &c->ubox};
+                      &c->refit_order, &c->ubox,
+                      &c->fq_pm, &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -822,6 +824,49 @@ static int rr_synth_gemm(rr_ctx *c, const SynthArgs &A)
     return RR_OK;
 }
 
+// Exact model as one complex product per (chirp, sample): leg tables per
+// (chirp, element, path), then the split-bf16 MFMA kernel over path splits.
+static const int64_t FREQ_TABLE_MAX = (int64_t)4 << 30;   // AUTO's table budget (bytes)
+
+static int64_t freq_table_bytes(const rr_ctx *c, int64_t n)
+{
+    const int64_t ks = freq_k_step();
+    const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
+    return (int64_t)c->chirp.n_chirps * (c->ntx + c->nrx) * Ppad * 8;
+}
+
+static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
+{
+    const int64_t n = A.n_paths;
+    const int64_t ks = freq_k_step();
+    const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
+    const int T = c->ntx, R = c->nrx, M = A.M, K = A.K;
+    const int64_t tiles = (int64_t)M * K * ((T + 95) / 96) * ((R + 95) / 96);
+    // enough workgroups to fill the chip, at least 16 steps of paths each
+    int64_t n_split = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
+    n_split = std::min<int64_t>(n_split, std::max<int64_t>(1, Ppad / (16 * ks)));
+    int64_t split_len = (Ppad + n_split - 1) / n_split;
+    split_len = (split_len + ks - 1) / ks * ks;
+    n_split = (Ppad + split_len - 1) / split_len;
+    int rc;
+    if ((rc = c->fq_pm.ensure((size_t)M * Ppad * 64))) return rc;
+    if ((rc = c->fq_xt.ensure((size_t)M * T * Ppad * 8))) return rc;
+    if ((rc = c->fq_yt.ensure((size_t)M * R * Ppad * 8))) return rc;
+    if ((rc = c->fq_amp.ensure((size_t)Ppad * 4))) return rc;
+    if ((rc = c->fq_src.ensure((size_t)Ppad * 4))) return rc;
+    if (n_split > 1 && (rc = c->fq_part.ensure((size_t)n_split * M * K * T * R * 8))) return rc;
+    HIPCHK(hipEventRecord(c->ev[2], c->stream));
+    HIPCHK(launch_freq_prep(A.paths, n, Ppad, M, A.t_rep, A.tx, T, A.rx, R, A.f0 * A.inv_c,
+                            A.bw / (double)K * A.inv_c, c->fq_pm.as<double>(), c->fq_xt.as<uint2>(),
+                            c->fq_yt.as<uint2>(), c->fq_amp.as<float>(), c->fq_src.as<int32_t>(),
+                            c->stream));
+    HIPCHK(launch_freq_gemm(c->fq_xt.as<const uint2>(), c->fq_yt.as<const uint2>(),
+                            c->fq_amp.as<const float>(), c->fq_src.as<const int32_t>(), T, R, M, K,
+                            Ppad, (int)n_split, split_len, c->fq_part.as<float2>(), A.cube,
+                            c->stream));
+    return RR_OK;
+}
+
 int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t cube_elems,
                   const int64_t *idx, int64_t n_idx)
 {
@@ -832,13 +877,24 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
     if (engine == RR_ENGINE_AUTO) {
         // the GEMM engine pads each chirp's samples to whole column tiles:
         // take it for the separable model when that pads by at most a quarter
-        const int64_t K = c->chirp.n_samples, T = gemm_col_tile();
-        const int64_t Kp = (K + T - 1) / T * T;
+        const int64_t K = c->chirp.n_samples, CT = gemm_col_tile();
+        const int64_t Kp = (K + CT - 1) / CT * CT;
         engine = (model == RR_SEPARABLE && !idx && 4 * Kp <= 5 * K) ? RR_GEMM_BF16X3
                                                                      : RR_DIRECT_FP32;
+        // the exact model as per-sample products: for a shared launch whose
+        // 96 x 96 tiles are well filled and whose leg tables fit the budget
+        if (model == RR_EXACT && !idx && c->mode == RR_TX_SHARED && c->n_paths > 0) {
+            const int64_t tp = (int64_t)((c->ntx + 95) / 96) * 96, rp = (int64_t)((c->nrx + 95) / 96) * 96;
+            if (2 * (int64_t)c->ntx * c->nrx >= tp * rp && freq_table_bytes(c, c->n_paths) <= FREQ_TABLE_MAX)
+                engine = RR_GEMM_EXACT;
+        }
     }
-    if (engine != RR_DIRECT_FP32 && engine != RR_GEMM_BF16X3)
+    if (engine != RR_DIRECT_FP32 && engine != RR_GEMM_BF16X3 && engine != RR_GEMM_EXACT)
         return fail(RR_EINVAL, "unknown engine");
+    if (engine == RR_GEMM_EXACT && model != RR_EXACT)
+        return fail(RR_EUNSUPPORTED, "the per-sample GEMM engine computes the exact model");
+    if (engine == RR_GEMM_EXACT && idx)
+        return fail(RR_EUNSUPPORTED, "sampled entries use the direct engine");
     if (engine == RR_GEMM_BF16X3 && model != RR_SEPARABLE)
         return fail(RR_EUNSUPPORTED, "the GEMM engine needs the separable model");
     if (engine == RR_GEMM_BF16X3 && idx)
@@ -903,6 +959,9 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
     A.cube = static_cast<float2 *>(cube);
     if (engine == RR_GEMM_BF16X3) {
         rc = rr_synth_gemm(c, A);
+        if (rc) return rc;
+    } else if (engine == RR_GEMM_EXACT) {
+        rc = rr_synth_freq(c, A);
         if (rc) return rc;
     } else if (idx) {
         HIPCHK(hipEventRecord(c->ev[2], c->stream));

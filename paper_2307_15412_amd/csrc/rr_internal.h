@@ -162,6 +162,14 @@ hipError_t launch_points(const TraceArgs &a, hipStream_t s);
 hipError_t launch_trace_user(const TraceArgs &a, const UserRays &u, hipStream_t s);
 hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alpha,
                             const float *obj_alpha, hipStream_t s);
+int freq_k_step();
+hipError_t launch_freq_prep(const SynPath *paths, int64_t n, int64_t Ppad, int M, double t_rep,
+                            const double *tx, int T, const double *rx, int R, double f0c, double dfc,
+                            double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
+                            hipStream_t s);
+hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
+                            int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
+                            float2 *partial, float2 *cube, hipStream_t s);
 hipError_t launch_refit(float4 *nodes, float *ubox, const int32_t *order,
                         const int64_t *level_start, int n_levels, float4 *ltris, float *tri_geom,
                         int64_t n_tris, const int32_t *tris, const float *verts, double pad,

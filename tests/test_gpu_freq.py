@@ -1,0 +1,119 @@
+"""Exact-model synthesis as one split-bf16 complex product per (chirp,
+sample) against the FP64 oracle (relative error <= 1e-3, the split-bf16
+tolerance): full cubes at Tx / Rx counts around the 32-row blocks and 96-wide
+tiles, several chirps of a moving scene, the per-element launch (paths feed
+only their own Tx), path counts around the 16-path steps and the split
+boundaries, an empty path list; the hand set-up against the direct FP32 engine
+and sampled oracle entries; invalid requests refused."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from helpers import oracle_to_soa, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+
+
+def _upload(gpu, op):
+    soa = oracle_to_soa(op)
+    gpu.set_paths({k: torch.from_numpy(np.ascontiguousarray(v)) for k, v in soa.items()})
+
+
+def _exact(gpu):
+    import paper_2307_15412_amd as rr
+    return gpu.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT).cpu().numpy()
+
+
+@pytest.mark.parametrize("n_tx,n_rx,K,M", [(3, 7, 32, 2), (33, 97, 16, 1), (96, 96, 8, 1),
+                                           (97, 5, 12, 3), (1, 1, 40, 1)])
+def test_tile_edges(gpu, orc, n_tx, n_rx, K, M):
+    w = sg.workload_tiny(1)
+    w.array = sg.array_sparse_grid(n_tx, n_rx, 3, grid=128, mode=sg.MODE_SHARED)
+    w.chirp = sg.Chirp(n_samples=K, n_chirps=M)
+    w.trace.n_rays = 20_000
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    op = op[:300]
+    gpu.setup(w)
+    _upload(gpu, op)
+    got = _exact(gpu)
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=0)
+    assert got.shape == ref.shape
+    assert rel_err(got, ref) < TOL
+
+
+def test_moving_scene_chirps_and_per_element(gpu, orc):
+    """The tiny scene's box moves at 5 m/s: every chirp has its own lengths;
+    then a per-element launch (12 Tx) whose paths feed only their own Tx."""
+    w = sg.workload_tiny(2)
+    w.array = sg.array_sparse_grid(8, 12, 5, mode=sg.MODE_SHARED)
+    w.chirp = sg.Chirp(n_samples=64, n_chirps=16)
+    w.trace.n_rays = 30_000
+    gpu.setup(w)
+    gpu.trace_workload(w, record_hits=False)
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    assert rel_err(_exact(gpu), orc.synth(op, w.scene, w.array, w.chirp, model=0)) < TOL
+    w2 = sg.workload_tiny(3)
+    w2.array = sg.array_ula(12, 8, mode=sg.MODE_PER_TX)
+    w2.chirp = sg.Chirp(n_samples=32, n_chirps=4)
+    w2.trace.n_rays = 36_000
+    gpu.setup(w2)
+    gpu.trace_workload(w2, record_hits=False)
+    _, op2 = orc.trace(w2.scene, w2.array, w2.trace)
+    assert rel_err(_exact(gpu), orc.synth(op2, w2.scene, w2.array, w2.chirp, model=0)) < TOL
+
+
+@pytest.mark.parametrize("n_keep", [1, 15, 16, 17, 4097])
+def test_ragged_paths(gpu, orc, n_keep):
+    w = sg.workload_tiny(4)
+    w.array = sg.array_sparse_grid(5, 9, 2, mode=sg.MODE_SHARED)
+    w.chirp = sg.Chirp(n_samples=16, n_chirps=1)
+    w.trace.n_rays = 200_000
+    _, op = orc.trace(w.scene, w.array, w.trace, want_hits=False)
+    assert len(op) >= n_keep
+    op = op[:n_keep]
+    gpu.setup(w)
+    _upload(gpu, op)
+    assert rel_err(_exact(gpu), orc.synth(op, w.scene, w.array, w.chirp, model=0)) < TOL
+
+
+def test_empty_and_refused(gpu, orc):
+    import paper_2307_15412_amd as rr
+    w = sg.workload_tiny()
+    w.array = sg.array_sparse_grid(4, 4, 1, mode=sg.MODE_SHARED)
+    w.chirp = sg.Chirp(n_samples=16, n_chirps=2)
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    gpu.setup(w)
+    _upload(gpu, op[:0])
+    assert torch.count_nonzero(gpu.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT)).item() == 0
+    _upload(gpu, op)
+    for kw in (dict(model=rr.SEPARABLE, engine=rr.GEMM_EXACT),
+               dict(model=rr.EXACT, engine=rr.GEMM_EXACT, sample_idx=np.arange(4))):
+        with pytest.raises(rr.RadrayError) as e:
+            gpu.synthesize(**kw)
+        assert e.value.code == rr.binding.RR_EUNSUPPORTED
+
+
+def test_hand_against_direct_and_oracle(gpu, orc):
+    """The paper's set-up: 94 x 94 array, 128 steps, 2e5 rays; the product
+    engine against the direct FP32 engine on the whole cube and against the
+    oracle on sampled entries; AUTO picks the product engine here."""
+    import paper_2307_15412_amd as rr
+    w = sg.workload_hand(0, n_rays=200_000)
+    gpu.setup(w)
+    n = gpu.trace_workload(w, record_hits=False)
+    assert n > 1000
+    prod = gpu.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT).clone()
+    direct = gpu.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32)
+    assert rel_err(prod.cpu().numpy(), direct.cpu().numpy()) < TOL
+    auto = gpu.synthesize(model=rr.EXACT, engine=rr.ENGINE_AUTO)
+    assert torch.equal(auto, prod)
+    _, op = orc.trace(w.scene, w.array, w.trace, want_hits=False)
+    idx = np.random.default_rng(2).choice(prod.numel(), 512, replace=False)
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=0, idx=idx)
+    got = prod.reshape(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert rel_err(got, ref) < TOL
