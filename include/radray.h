@@ -404,12 +404,23 @@ typedef struct {
  *   stepped-frequency sweep is one chirp of K steps),
  * the matched filter of the synthesis phase.  cube_dev: complex64
  * [n_ch][n_chirps][n_samples] as rr_synthesize writes it (chirp 0 of each
- * channel is used); image_dev: complex64, image_elems >= nx ny nz.  Lengths
- * and phase reduction in FP64, sums in FP32.  Errors: RR_ESTATE (array or
- * chirp missing), RR_EINVAL (sizes, grid), RR_EUNSUPPORTED (more than 4096
- * steps). */
+ * channel is used); image_dev: complex64, image_elems >= nx ny nz.
+ * engine:
+ *   RR_DIRECT_FP32  one lane per voxel: both legs and the phase reduction in
+ *                   FP64 per (voxel, channel), the sum over frequencies by
+ *                   Horner's rule in FP32 (at most 4096 steps);
+ *   RR_GEMM_EXACT   per frequency, the Rx sum as a split-bf16 complex product
+ *                   of the cube slice (Tx x Rx) with the Rx phasors of 128
+ *                   voxels on the matrix cores, then the Tx sum on the vector
+ *                   units; legs formed in FP64 and kept in FP32 (phases below
+ *                   256 turns: volumes within ~0.9 m of the array at 80 GHz);
+ *                   at most 96 Tx and 96 Rx;
+ *   RR_ENGINE_AUTO  RR_GEMM_EXACT when it applies, else RR_DIRECT_FP32.
+ * Both agree with the FP64 sum to ~1e-5 of the image's peak.  Errors:
+ * RR_ESTATE (array or chirp missing), RR_EINVAL (sizes, grid, engine),
+ * RR_EUNSUPPORTED (an engine's limits exceeded). */
 int rr_backproject(rr_ctx *ctx, const void *cube_dev, int64_t cube_elems, const rr_volume *vol,
-                   void *image_dev, int64_t image_elems);
+                   void *image_dev, int64_t image_elems, int32_t engine);
 
 /* Maximum over x of |image| per (y, z), in dB relative to the largest of
  * them, clamped below at floor_db (e.g. -15): out_dev float [ny][nz].

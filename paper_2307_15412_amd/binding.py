@@ -89,7 +89,7 @@ def load_library(path: str = LIB_PATH):
     L.rr_trace_rays.argtypes = [vp, vp, vp, vp, vp, i64, C.c_int32, C.c_uint64, C.c_int32,
                                 C.POINTER(i64)]
     L.rr_get_path_count.argtypes = [vp, C.POINTER(i64)]
-    L.rr_backproject.argtypes = [vp, vp, i64, C.POINTER(Volume), vp, i64]
+    L.rr_backproject.argtypes = [vp, vp, i64, C.POINTER(Volume), vp, i64, i32]
     L.rr_max_projection.argtypes = [vp, vp, C.POINTER(Volume), vp, C.c_float]
     L.rr_get_hits.argtypes = [vp, vp, i64]
     L.rr_get_paths.argtypes = [vp, C.POINTER(Paths), C.POINTER(i64)]
@@ -309,10 +309,11 @@ class Context:
         return out
 
     # ------------------------------------------------------------ imaging
-    def backproject(self, cube, grid, out=None):
+    def backproject(self, cube, grid, out=None, engine=ENGINE_AUTO):
         """Delay-and-sum image (complex64 [nx][ny][nz]) of `cube` (this
         context's array and chirp) on grid = (origin (x0, y0, z0), step,
-        (nx, ny, nz)) as scenegen.imaging_grid returns it."""
+        (nx, ny, nz)) as scenegen.imaging_grid returns it; engine
+        DIRECT_FP32 (Horner, vector units), GEMM_EXACT (matrix cores) or AUTO."""
         torch = self.torch
         (x0, y0, z0), step, (nx, ny, nz) = grid
         vol = Volume(float(x0), float(y0), float(z0), float(step), int(nx), int(ny), int(nz))
@@ -321,7 +322,8 @@ class Context:
             out = torch.empty((nx, ny, nz), dtype=torch.complex64, device=self.device)
         check_out(out, self.device, torch.complex64, nx * ny * nz, "image")
         self._check(self.lib.rr_backproject(self.h, C.c_void_p(cube.data_ptr()), cube.numel(),
-                                            C.byref(vol), C.c_void_p(out.data_ptr()), out.numel()))
+                                            C.byref(vol), C.c_void_p(out.data_ptr()), out.numel(),
+                                            int(engine)))
         return out
 
     def max_projection(self, image, grid, floor_db=-15.0, out=None):

@@ -33,6 +33,7 @@ SOURCES = {
     "k_image.hip": [],
     "k_refit.hip": ["-ffp-contract=off"],
     "k_freq.hip": [],
+    "k_bpmfma.hip": [],
 }
 
 

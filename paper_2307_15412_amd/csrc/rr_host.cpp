@@ -155,6 +155,8 @@ struct rr_ctx {
     // refit of the BVH to moved vertices (rr_scene_update_vertices)
     DevBuf tris_dev, verts_dev, refit_order, ubox;
     DevBuf fq_pm, fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact-model GEMM engine
+    DevBuf bp_sf;              // cube slices in fragment layout (MFMA back-projection)
+    std::vector<double> h_tx, h_rx;
     std::vector<int64_t> refit_levels;   // starts of the levels in refit_order, deepest first
     std::vector<int32_t> h_tris;
     int64_t n_verts = 0, n_nodes = 0;
@@ -266,7 +268,7 @@ void rr_destroy(rr_ctx *c)
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
                       &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->tri_geom, &c->tris_dev, &c->verts_dev,
                       &c->refit_order, &c->ubox,
-                      &c->fq_pm, &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part};
+                      &c->fq_pm, &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part, &c->bp_sf};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -490,6 +492,8 @@ int rr_set_array(rr_ctx *c, const double *tx, int32_t n_tx, const double *rx, in
     if ((rc = c->rx.ensure((size_t)n_rx * 24))) return rc;
     HIPCHK(hipMemcpy(c->tx.p, tx, (size_t)n_tx * 24, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->rx.p, rx, (size_t)n_rx * 24, hipMemcpyHostToDevice));
+    c->h_tx.assign(tx, tx + 3 * n_tx);
+    c->h_rx.assign(rx, rx + 3 * n_rx);
     c->tx_h.assign(tx, tx + 3 * n_tx);
     c->rx_h.assign(rx, rx + 3 * n_rx);
     // phase centres: sums in index order divided by the count
@@ -1005,13 +1009,40 @@ static bool bad_volume(const rr_volume *v)
 }
 
 int rr_backproject(rr_ctx *c, const void *cube, int64_t cube_elems, const rr_volume *vol,
-                   void *image, int64_t image_elems)
+                   void *image, int64_t image_elems, int32_t engine)
 {
     if (!c || !cube || !vol || !image) return fail(RR_EINVAL, "NULL argument");
     if (!c->has_array || !c->has_chirp) return fail(RR_ESTATE, "array and chirp must be set");
     if (bad_volume(vol)) return fail(RR_EINVAL, "invalid voxel grid");
     const int64_t C = (int64_t)c->ntx * c->nrx, M = c->chirp.n_chirps, K = c->chirp.n_samples;
-    if (K > RR_BP_KMAX) return fail(RR_EUNSUPPORTED, "sweeps of at most %d steps", RR_BP_KMAX);
+    // the MFMA engine keeps FP32 legs: the phase f d / c must stay below the
+    // hardware sin/cos range of 256 turns at the top frequency
+    double dmax = 0.0;
+    {
+        const double cx[2] = {vol->x0, vol->x0 + (vol->nx - 1) * vol->step};
+        const double cy[2] = {vol->y0, vol->y0 + (vol->ny - 1) * vol->step};
+        const double cz[2] = {vol->z0, vol->z0 + (vol->nz - 1) * vol->step};
+        for (int e = 0; e < 2; e++) {
+            const std::vector<double> &el = e ? c->h_rx : c->h_tx;
+            double m = 0.0;
+            for (size_t q = 0; q + 2 < el.size(); q += 3)
+                for (int a = 0; a < 8; a++) {
+                    const double dx = cx[a & 1] - el[q], dy = cy[(a >> 1) & 1] - el[q + 1],
+                                 dz = cz[a >> 2] - el[q + 2];
+                    m = std::max(m, std::sqrt(dx * dx + dy * dy + dz * dz));
+                }
+            dmax = std::max(dmax, m);
+        }
+    }
+    const double fmax = c->chirp.f0 + c->chirp.bandwidth * (double)(K - 1) / (double)K;
+    const bool mfma_ok = c->ntx <= 96 && c->nrx <= 96 && dmax * fmax / 299792458.0 < 250.0;
+    if (engine == RR_ENGINE_AUTO) engine = mfma_ok ? RR_GEMM_EXACT : RR_DIRECT_FP32;
+    if (engine != RR_DIRECT_FP32 && engine != RR_GEMM_EXACT) return fail(RR_EINVAL, "unknown engine");
+    if (engine == RR_GEMM_EXACT && !mfma_ok)
+        return fail(RR_EUNSUPPORTED, "the MFMA back-projection needs <= 96 Tx and Rx and phases "
+                                     "below 250 turns");
+    if (engine == RR_DIRECT_FP32 && K > RR_BP_KMAX)
+        return fail(RR_EUNSUPPORTED, "sweeps of at most %d steps", RR_BP_KMAX);
     if (cube_elems < C * M * K) return fail(RR_EINVAL, "cube needs %lld complex elements",
                                             (long long)(C * M * K));
     const int64_t nv = (int64_t)vol->nx * vol->ny * vol->nz;
@@ -1039,7 +1070,15 @@ int rr_backproject(rr_ctx *c, const void *cube, int64_t cube_elems, const rr_vol
     A.n_vox = nv;
     A.image = static_cast<float2 *>(image);
     HIPCHK(hipEventRecord(c->ev[4], c->stream));
-    HIPCHK(launch_backproject(A, c->stream));
+    if (engine == RR_GEMM_EXACT) {
+        int rc;
+        if ((rc = c->bp_sf.ensure((size_t)bp_mfma_frag_bytes((int)K)))) return rc;
+        HIPCHK(launch_bp_mfma(A.cube, A.stride, A.tx, c->ntx, A.rx, c->nrx, (int)K, A.f0, A.df,
+                              A.inv_c, A.x0, A.y0, A.z0, A.step, A.nx, A.ny, A.nz,
+                              c->bp_sf.as<uint4>(), A.image, c->stream));
+    } else {
+        HIPCHK(launch_backproject(A, c->stream));
+    }
     HIPCHK(hipEventRecord(c->ev[5], c->stream));
     c->image_timed = true;
     return RR_OK;

@@ -162,6 +162,11 @@ hipError_t launch_points(const TraceArgs &a, hipStream_t s);
 hipError_t launch_trace_user(const TraceArgs &a, const UserRays &u, hipStream_t s);
 hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alpha,
                             const float *obj_alpha, hipStream_t s);
+hipError_t launch_bp_mfma(const float2 *cube, int64_t stride, const double *tx, int T,
+                          const double *rx, int R, int K, double f0, double df, double inv_c,
+                          double x0, double y0, double z0, double step, int nx, int ny, int nz,
+                          uint4 *Sf, float2 *image, hipStream_t s);
+int64_t bp_mfma_frag_bytes(int K);
 int freq_k_step();
 hipError_t launch_freq_prep(const SynPath *paths, int64_t n, int64_t Ppad, int M, double t_rep,
                             const double *tx, int T, const double *rx, int R, double f0c, double dfc,
