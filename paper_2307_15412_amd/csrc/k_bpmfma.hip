@@ -5,29 +5,31 @@
 // because the two legs of the delay add: the inner sum over receivers is, for
 // every frequency, the complex product of the cube slice S_n (Tx x Rx) with
 // the matrix of receive phasors of a block of voxels (Rx x voxels), the same
-// multiply-adds as the brute-force sum.  A workgroup of four wavefronts owns
-// 128 voxels (32 per wavefront); per frequency each wavefront computes
-// U = S_n B (96 x 32, three 32 x 32 blocks over six 16-receiver steps, split
-// bf16 hi + lo, 216 v_mfma_f32_32x32x16_bf16) and adds sum_t a_t U[t, voxel]
-// to its voxels on the vector units.  S_n, prepared once in the A-operand
-// fragment layout, is double-buffered in LDS and loaded by LDS DMA one
-// frequency ahead.  Leg lengths are formed in FP64 once per voxel and kept in
-// FP32 (the phase f d / c stays below 256 turns in an imaging volume of a few
-// tens of centimetres, where FP32 keeps it to ~1e-5 turn); the hardware
-// sin/cos take turns.  Needs at most 96 transmitters and 96 receivers.
+// multiply-adds as the brute-force sum.  A workgroup of eight wavefronts (two
+// per SIMD) owns 128 voxels, 16 per wavefront; per frequency each wavefront
+// computes U = S_n B (96 x 16 over 96 receivers: six 16 x 16 blocks, three
+// 32-receiver steps, split bf16 hi + lo, 216 v_mfma_f32_16x16x32_bf16) and
+// adds sum_t a_t U[t, voxel] on the vector units; the two wavefronts of a SIMD
+// overlap one's phasor work with the other's products.  S_n, prepared once in
+// the A-operand fragment layout, is double-buffered in LDS and loaded by LDS
+// DMA one frequency ahead.  Leg lengths are formed in FP64 once per voxel and
+// kept in FP32 (the phase f d / c stays below 256 turns in an imaging volume
+// of a few tens of centimetres, where FP32 keeps it to ~1e-5 turn); the
+// hardware sin/cos take turns.  Needs at most 96 transmitters and receivers.
 #include "rr_internal.h"
 
 namespace {
 
-#define BG_W 4                 // wavefronts per workgroup
-#define BG_TB 3                // 32-row Tx blocks
-#define BG_RS 6                // 16-receiver steps
+#define BG_W 8                 // wavefronts per workgroup
+#define BG_VW 16               // voxels per wavefront
+#define BG_TB 6                // 16-row Tx blocks
+#define BG_RS 3                // 32-receiver steps
 #define BG_NF (BG_TB * BG_RS * 4)   // 1 KiB fragments per frequency (4 planes)
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned pack_bf16(float x, float y)
 {
@@ -48,11 +50,12 @@ __device__ __forceinline__ uint4 neg(uint4 v)
     return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
 }
 
-#define MFMA(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a), as_bf(b), c, 0, 0, 0)
+#define MFMA(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a), as_bf(b), c, 0, 0, 0)
 
-// Cube slices in the A-operand layout: fragment (n, tb, rs, plane) lane l
-// holds S_n[32 tb + l % 32][16 rs + 8 (l / 32) + e], e = 0..7, as bf16;
-// planes: real hi, real lo, imaginary hi, imaginary lo; zero outside T x R.
+// Cube slices in the A-operand layout of the 16 x 16 x 32 product: fragment
+// (n, tb, rs, plane) lane l holds S_n[16 tb + l % 16][32 rs + 8 (l / 16) + e],
+// e = 0..7, as bf16; planes: real hi, real lo, imaginary hi, imaginary lo;
+// zero outside T x R.
 __global__ void k_bp_prep(const float2 *cube, int64_t stride, int T, int R, int K, uint4 *Sf)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,8 +66,8 @@ __global__ void k_bp_prep(const float2 *cube, int64_t stride, int T, int R, int 
     f /= BG_RS;
     const int tb = (int)(f % BG_TB);
     const int n = (int)(f / BG_TB);
-    const int t = tb * 32 + (lane & 31);
-    const int r0 = rs * 16 + (lane >> 5) * 8;
+    const int t = tb * 16 + (lane & 15);
+    const int r0 = rs * 32 + (lane >> 4) * 8;
     float re[8], im[8];
     for (int e = 0; e < 8; e++) {
         float2 v = make_float2(0.0f, 0.0f);
@@ -104,8 +107,8 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
     __shared__ uint4 Ss[2][BG_NF * 64];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int hi = lane >> 5;
-    const int64_t v = (int64_t)blockIdx.x * (BG_W * 32) + w * 32 + (lane & 31);
+    const int q4 = lane >> 4;
+    const int64_t v = (int64_t)blockIdx.x * (BG_W * BG_VW) + w * BG_VW + (lane & 15);
     const bool valid = v < A.n_vox;
     const int64_t plane = (int64_t)A.ny * A.nz;
     const int64_t vv = valid ? v : 0;
@@ -114,24 +117,24 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
     const int j = (int)(rem / A.nz), k = (int)(rem - (int64_t)j * A.nz);
     const double x = A.x0 + (double)i * A.step, y = A.y0 + (double)j * A.step,
                  z = A.z0 + (double)k * A.step;
-    // this lane's legs: Tx rows of its accumulator elements, Rx rows of its
-    // B-operand slots
-    float dt[BG_TB * 16], dr[BG_RS * 8];
+    // this lane's legs: the Tx rows of its accumulator elements (16 tb + 4 q4
+    // + e) and the Rx rows of its B-operand slots (32 rs + 8 q4 + e)
+    float dt[BG_TB * 4], dr[BG_RS * 8];
 #pragma unroll
     for (int tb = 0; tb < BG_TB; tb++)
 #pragma unroll
-        for (int e = 0; e < 16; e++) {
-            const int t = tb * 32 + 8 * (e >> 2) + 4 * hi + (e & 3);
-            dt[tb * 16 + e] = t < A.T ? (float)dist3(x, y, z, A.tx + 3 * t) : 0.0f;
+        for (int e = 0; e < 4; e++) {
+            const int t = tb * 16 + 4 * q4 + e;
+            dt[tb * 4 + e] = t < A.T ? (float)dist3(x, y, z, A.tx + 3 * t) : 0.0f;
         }
 #pragma unroll
     for (int rs = 0; rs < BG_RS; rs++)
 #pragma unroll
         for (int e = 0; e < 8; e++) {
-            const int r = rs * 16 + 8 * hi + e;
+            const int r = rs * 32 + 8 * q4 + e;
             dr[rs * 8 + e] = r < A.R ? (float)dist3(x, y, z, A.rx + 3 * r) : 0.0f;
         }
-    // LDS DMA of one frequency's 72 fragments: 18 per wavefront
+    // LDS DMA of one frequency's 72 fragments: 9 per wavefront
     auto fetch = [&](int n, int buf) {
         const uint4 *src = A.Sf + (int64_t)n * (BG_NF * 64) + lane;
 #pragma unroll
@@ -146,18 +149,11 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
     fetch(0, 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    const f32x4 zero = {};
     for (int n = 0; n < A.K; n++) {
-        const int buf = n & 1;
         const float fc = (float)((A.f0 + (double)n * A.df) * A.inv_c);
-        f32x16 ur[BG_TB], ui[BG_TB];
-#pragma unroll
-        for (int tb = 0; tb < BG_TB; tb++)
-#pragma unroll
-            for (int e = 0; e < 16; e++) {
-                ur[tb][e] = 0.0f;
-                ui[tb][e] = 0.0f;
-            }
-        const uint4 *S = Ss[buf];
+        const uint4 *S = Ss[n & 1];
+        f32x4 ur[BG_TB], ui[BG_TB];
 #pragma unroll
         for (int rs = 0; rs < BG_RS; rs++) {
             // receive phasors of 8 receivers for this lane's voxel
@@ -181,13 +177,13 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
                 const int fb = ((tb * BG_RS + rs) * 4) * 64 + lane;
                 const uint4 Srh = S[fb], Srl = S[fb + 64], Sih = S[fb + 128], Sil = S[fb + 192];
                 // U_re += Sr Br - Si Bi, U_im += Sr Bi + Si Br (hi*hi + hi*lo + lo*hi)
-                ur[tb] = MFMA(Srh, Brh, ur[tb]);
+                ur[tb] = MFMA(Srh, Brh, rs == 0 ? zero : ur[tb]);
                 ur[tb] = MFMA(Srh, Brl, ur[tb]);
                 ur[tb] = MFMA(Srl, Brh, ur[tb]);
                 ur[tb] = MFMA(Sih, nBih, ur[tb]);
                 ur[tb] = MFMA(Sih, nBil, ur[tb]);
                 ur[tb] = MFMA(Sil, nBih, ur[tb]);
-                ui[tb] = MFMA(Srh, Bih, ui[tb]);
+                ui[tb] = MFMA(Srh, Bih, rs == 0 ? zero : ui[tb]);
                 ui[tb] = MFMA(Srh, Bil, ui[tb]);
                 ui[tb] = MFMA(Srl, Bih, ui[tb]);
                 ui[tb] = MFMA(Sih, Brh, ui[tb]);
@@ -197,13 +193,14 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
         }
         // every wavefront has read this frequency's slice: the next one may
         // be requested into the other buffer
-        if (n + 1 < A.K) fetch(n + 1, buf ^ 1);
-        // transmit phasors of this lane's Tx rows times U
+        if (n + 1 < A.K) fetch(n + 1, (n + 1) & 1);
+        // transmit phasors of this lane's Tx rows times U (D layout: element e
+        // of lane l is row 4 (l / 16) + e, column l % 16 of each block)
 #pragma unroll
         for (int tb = 0; tb < BG_TB; tb++)
 #pragma unroll
-            for (int e = 0; e < 16; e++) {
-                const float ph = dt[tb * 16 + e] * fc;
+            for (int e = 0; e < 4; e++) {
+                const float ph = dt[tb * 4 + e] * fc;
                 const float ar = __builtin_amdgcn_cosf(ph), ai = __builtin_amdgcn_sinf(ph);
                 img_re = fmaf(ar, ur[tb][e], fmaf(-ai, ui[tb][e], img_re));
                 img_im = fmaf(ar, ui[tb][e], fmaf(ai, ur[tb][e], img_im));
@@ -211,10 +208,12 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
-    // lanes l and l + 32 hold the two halves of the Tx rows of one voxel
+    // the four lanes l % 16 + 16 q hold the four quarters of one voxel's Tx rows
+    img_re += __shfl_xor(img_re, 16);
+    img_im += __shfl_xor(img_im, 16);
     img_re += __shfl_xor(img_re, 32);
     img_im += __shfl_xor(img_im, 32);
-    if (valid && hi == 0) A.image[v] = make_float2(img_re, img_im);
+    if (valid && q4 == 0) A.image[v] = make_float2(img_re, img_im);
 }
 
 }  // namespace
@@ -226,7 +225,7 @@ hipError_t launch_bp_mfma(const float2 *cube, int64_t stride, const double *tx, 
 {
     const int64_t n_vox = (int64_t)nx * ny * nz;
     if (n_vox <= 0 || K <= 0) return hipSuccess;
-    if (T < 1 || R < 1 || T > BG_TB * 32 || R > BG_RS * 16) return hipErrorInvalidValue;
+    if (T < 1 || R < 1 || T > BG_TB * 16 || R > BG_RS * 32) return hipErrorInvalidValue;
     const int64_t nf = (int64_t)K * BG_TB * BG_RS * 64;
     hipLaunchKernelGGL(k_bp_prep, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, cube, stride,
                        T, R, K, Sf);
@@ -249,7 +248,7 @@ hipError_t launch_bp_mfma(const float2 *cube, int64_t stride, const double *tx, 
     A.nz = nz;
     A.n_vox = n_vox;
     A.image = image;
-    const int64_t blocks = (n_vox + BG_W * 32 - 1) / (BG_W * 32);
+    const int64_t blocks = (n_vox + BG_W * BG_VW - 1) / (BG_W * BG_VW);
     hipLaunchKernelGGL(k_bp_mfma, dim3((unsigned)blocks), dim3(BG_W * 64), 0, s, A);
     return hipGetLastError();
 }
