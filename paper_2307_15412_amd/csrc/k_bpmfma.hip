@@ -146,17 +146,14 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
         }
     };
     float img_re = 0.0f, img_im = 0.0f;
-    fetch(0, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    const f32x4 zero = {};
-    for (int n = 0; n < A.K; n++) {
-        const float fc = (float)((A.f0 + (double)n * A.df) * A.inv_c);
-        const uint4 *S = Ss[n & 1];
-        f32x4 ur[BG_TB], ui[BG_TB];
+    // the B operands of one frequency: receive phasors of this lane's voxel
+    // for its 24 receiver slots, split into six bf16 planes per step
+    struct BOps {
+        uint4 rh[BG_RS], rl[BG_RS], ih[BG_RS], il[BG_RS], nih[BG_RS], nil[BG_RS];
+    };
+    auto gen_b = [&](float fc, BOps &b) {
 #pragma unroll
         for (int rs = 0; rs < BG_RS; rs++) {
-            // receive phasors of 8 receivers for this lane's voxel
             float br[8], bi[8];
 #pragma unroll
             for (int e = 0; e < 8; e++) {
@@ -164,31 +161,52 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
                 br[e] = __builtin_amdgcn_cosf(ph);
                 bi[e] = __builtin_amdgcn_sinf(ph);
             }
-            uint4 Brh, Brl, Bih, Bil;
-            unsigned *prh = &Brh.x, *prl = &Brl.x, *pih = &Bih.x, *pil = &Bil.x;
+            unsigned *prh = &b.rh[rs].x, *prl = &b.rl[rs].x, *pih = &b.ih[rs].x, *pil = &b.il[rs].x;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 split_bf16(br[2 * q], br[2 * q + 1], prh[q], prl[q]);
                 split_bf16(bi[2 * q], bi[2 * q + 1], pih[q], pil[q]);
             }
-            const uint4 nBih = neg(Bih), nBil = neg(Bil);
+            b.nih[rs] = neg(b.ih[rs]);
+            b.nil[rs] = neg(b.il[rs]);
+        }
+    };
+    auto freq = [&](int n) { return (float)((A.f0 + (double)n * A.df) * A.inv_c); };
+    // The two wavefronts of a SIMD run skewed: the leading half (w >= 4)
+    // makes the next frequency's B operands after its Tx sum, so it starts
+    // each frequency with matrix products while the other half is still
+    // generating phasors, and the other way round at the end.
+    const bool lead = w >= BG_W / 2;
+    BOps b;
+    fetch(0, 0);
+    if (lead) gen_b(freq(0), b);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const f32x4 zero = {};
+    for (int n = 0; n < A.K; n++) {
+        const float fc = freq(n);
+        if (!lead) gen_b(fc, b);
+        const uint4 *S = Ss[n & 1];
+        f32x4 ur[BG_TB], ui[BG_TB];
+#pragma unroll
+        for (int rs = 0; rs < BG_RS; rs++) {
 #pragma unroll
             for (int tb = 0; tb < BG_TB; tb++) {
                 const int fb = ((tb * BG_RS + rs) * 4) * 64 + lane;
                 const uint4 Srh = S[fb], Srl = S[fb + 64], Sih = S[fb + 128], Sil = S[fb + 192];
                 // U_re += Sr Br - Si Bi, U_im += Sr Bi + Si Br (hi*hi + hi*lo + lo*hi)
-                ur[tb] = MFMA(Srh, Brh, rs == 0 ? zero : ur[tb]);
-                ur[tb] = MFMA(Srh, Brl, ur[tb]);
-                ur[tb] = MFMA(Srl, Brh, ur[tb]);
-                ur[tb] = MFMA(Sih, nBih, ur[tb]);
-                ur[tb] = MFMA(Sih, nBil, ur[tb]);
-                ur[tb] = MFMA(Sil, nBih, ur[tb]);
-                ui[tb] = MFMA(Srh, Bih, rs == 0 ? zero : ui[tb]);
-                ui[tb] = MFMA(Srh, Bil, ui[tb]);
-                ui[tb] = MFMA(Srl, Bih, ui[tb]);
-                ui[tb] = MFMA(Sih, Brh, ui[tb]);
-                ui[tb] = MFMA(Sih, Brl, ui[tb]);
-                ui[tb] = MFMA(Sil, Brh, ui[tb]);
+                ur[tb] = MFMA(Srh, b.rh[rs], rs == 0 ? zero : ur[tb]);
+                ur[tb] = MFMA(Srh, b.rl[rs], ur[tb]);
+                ur[tb] = MFMA(Srl, b.rh[rs], ur[tb]);
+                ur[tb] = MFMA(Sih, b.nih[rs], ur[tb]);
+                ur[tb] = MFMA(Sih, b.nil[rs], ur[tb]);
+                ur[tb] = MFMA(Sil, b.nih[rs], ur[tb]);
+                ui[tb] = MFMA(Srh, b.ih[rs], rs == 0 ? zero : ui[tb]);
+                ui[tb] = MFMA(Srh, b.il[rs], ui[tb]);
+                ui[tb] = MFMA(Srl, b.ih[rs], ui[tb]);
+                ui[tb] = MFMA(Sih, b.rh[rs], ui[tb]);
+                ui[tb] = MFMA(Sih, b.rl[rs], ui[tb]);
+                ui[tb] = MFMA(Sil, b.rh[rs], ui[tb]);
             }
         }
         // every wavefront has read this frequency's slice: the next one may
@@ -205,6 +223,7 @@ __global__ __launch_bounds__(BG_W * 64) void k_bp_mfma(BpMfmaArgs A)
                 img_re = fmaf(ar, ur[tb][e], fmaf(-ai, ui[tb][e], img_re));
                 img_im = fmaf(ar, ui[tb][e], fmaf(ai, ur[tb][e], img_im));
             }
+        if (lead && n + 1 < A.K) gen_b(freq(n + 1), b);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
