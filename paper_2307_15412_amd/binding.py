@@ -532,6 +532,8 @@ class Batch:
 
     def set_workload(self, slot, w):
         sc, a, ch, tp = w.scene, w.array, w.chirp, w.trace
+        if int(getattr(tp, "rays_per_tri", 0) or 0) > 0:
+            raise ValueError("batched launches use the uniform sampler (no per-triangle casting)")
         keep = []
 
         def P(x, dt):

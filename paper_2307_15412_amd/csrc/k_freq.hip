@@ -258,15 +258,18 @@ __global__ __launch_bounds__(FQ_W * 64) void k_freq_gemm(FreqArgs A)
             sr[j][e] = 0.0f;
             si[j][e] = 0.0f;
         }
+    // table words two steps ahead of their use (the leg tables stream from
+    // beyond L2; one step of products does not cover that latency)
     Step cur = load(pbeg);
+    Step nx1 = load(pbeg + FQ_KS < pend ? pbeg + FQ_KS : pbeg);
     Frag x = leg_frag(cur.x, ku, cur.a);
     put_y(cur.y, 0);
     __syncthreads();
     int buf = 0;
     for (int64_t p0 = pbeg; p0 < pend; p0 += FQ_KS) {
         const bool more = p0 + FQ_KS < pend;
-        // next step's table words are requested before this step's products
-        Step nxt = load(more ? p0 + FQ_KS : p0);
+        const int64_t p2 = p0 + 2 * FQ_KS < pend ? p0 + 2 * FQ_KS : p0;
+        Step nx2 = load(p2);
         uint4 y[FQ_W][4];
 #pragma unroll
         for (int j = 0; j < FQ_W; j++)
@@ -290,9 +293,10 @@ __global__ __launch_bounds__(FQ_W * 64) void k_freq_gemm(FreqArgs A)
             si[j] = MFMA(x.il, y[j][0], si[j]);
         }
         if (more) {
-            put_y(nxt.y, buf ^ 1);
-            x = leg_frag(nxt.x, ku, nxt.a);
+            put_y(nx1.y, buf ^ 1);
+            x = leg_frag(nx1.x, ku, nx1.a);
         }
+        nx1 = nx2;
         buf ^= 1;
         __syncthreads();
     }

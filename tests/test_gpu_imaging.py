@@ -148,3 +148,23 @@ def test_max_projection_db(gpu, orc):
     want = np.maximum(20 * np.log10(m / m.max()), -15.0)
     assert np.abs(proj - want).max() < 1e-3
     assert proj.max() == 0.0 and proj.min() >= -15.0
+
+
+def test_far_volume_falls_back(gpu, orc):
+    """A volume whose phases exceed the matrix engine's FP32 range (metres
+    away at 80 GHz): AUTO uses the Horner engine and matches the oracle, the
+    matrix engine is refused."""
+    import paper_2307_15412_amd as rr
+    array = sg.array_square(n_side=4, pitch=3e-3)
+    chirp = sg.chirp_sfcw(72e9, 82e9, 16)
+    scene = sg.point_only([[2.0, 0.01, 0.0]], aperture=[0.05])
+    _, op = orc.trace(scene, array, sg.TraceParams(n_rays=0, max_bounces=1))
+    cube = orc.synth(op, scene, array, chirp, model=0)
+    _setup(gpu, scene, array, chirp)
+    grid = ((1.99, -0.01, -0.01), 5e-3, (3, 5, 5))
+    with pytest.raises(rr.RadrayError) as e:
+        gpu.backproject(_upload(cube), grid, engine=rr.GEMM_EXACT)
+    assert e.value.code == rr.binding.RR_EUNSUPPORTED
+    img = gpu.backproject(_upload(cube), grid).cpu().numpy().reshape(-1)
+    ref = orc.backproject(array, chirp.f0, chirp.bandwidth / chirp.n_samples, cube, _voxels(grid))
+    assert np.abs(img - ref).max() <= TOL * np.abs(ref).max()
