@@ -78,3 +78,21 @@ def test_output_tensors_checked_before_the_library_sees_them():
         check_out(torch.zeros((4, 8), dtype=torch.complex64)[:, ::2], torch.device("cpu"),
                   torch.complex64, 16)
     check_out(host, torch.device("cpu"), torch.complex64, 16)
+
+
+def test_new_entry_points_reject_null_handles():
+    """Per-face alpha, vertex update, BVH export, imaging and batch alpha
+    refuse a NULL context before touching HIP."""
+    import ctypes as C
+    import paper_2307_15412_amd as pkg
+    lib = pkg.load_library()
+    E = pkg.binding.RR_EINVAL
+    n = C.c_int64()
+    assert lib.rr_scene_set_alpha(None, None, 0, 0) == E
+    assert lib.rr_scene_update_vertices(None, None, 0) == E
+    assert lib.rr_get_bvh_nodes(None, None, 0, C.byref(n)) == E
+    assert lib.rr_backproject(None, None, 0, None, None, 0, 0) == E
+    assert lib.rr_max_projection(None, None, None, None, C.c_float(-15.0)) == E
+    pkg.binding._declare_batch(lib)
+    assert lib.rr_batch_set_alpha(None, 0, None, 0, 0) == E
+    assert lib.rr_last_error() != b""
