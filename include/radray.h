@@ -134,6 +134,26 @@ int rr_scene_set_alpha(rr_ctx *ctx, const float *alpha, int64_t n, int32_t per);
 int rr_set_array(rr_ctx *ctx, const double *tx, int32_t n_tx, const double *rx, int32_t n_rx,
                  double rx_radius, int32_t tx_mode);
 
+/* Pieces of the RR_PER_TRIANGLE launch (Sec. III casts rays towards every
+ * triangle; a coarse mesh with a large near triangle gets its rays spread by
+ * cutting it).  Every triangle, in upload order, is cut by midpoint
+ * subdivision into four while the piece subtends more than max_solid_angle
+ * steradians from the Tx phase centre (Van Oosterom-Strackee formula, FP64)
+ * and its depth is below max_depth; the children of (a, b, c) are
+ * (a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca), depth first.
+ * max_solid_angle = 0 (the default, with max_depth 8) casts at the triangles
+ * themselves.  Takes effect at the next per-triangle trace; the pieces are
+ * rebuilt on the host after a change of these parameters, the scene, its
+ * vertices or the array.  Errors: RR_EINVAL (negative or non-finite angle,
+ * max_depth outside [0, 20]). */
+int rr_set_casting(rr_ctx *ctx, double max_solid_angle, int32_t max_depth);
+
+/* Number of pieces the next RR_PER_TRIANGLE trace casts at (builds them if
+ * needed); a per-triangle trace launches n_pieces * n_rays rays per source.
+ * Errors: RR_ESTATE (no scene or array), RR_EOVERFLOW (more than 2^26
+ * pieces), RR_EINVAL (NULL). */
+int rr_casting_pieces(rr_ctx *ctx, int64_t *n_pieces);
+
 /* FMCW chirp: start frequency f0, sweep bandwidth B over t_chirp, chirp
  * repetition t_rep, n_samples fast-time samples per chirp (sample k at
  * frequency f0 + B k / n_samples), n_chirps chirps.  Errors: RR_EINVAL. */
@@ -153,14 +173,16 @@ int rr_set_chirp(rr_ctx *ctx, const rr_chirp *chirp);
  *   sampler     RR_UNIFORM, or RR_PROPOSAL (bins of the proposal table set by
  *               rr_proposal_set_cdf or rr_proposal_build, weight p0/q), or
  *               RR_PER_TRIANGLE (Sec. III: rays cast towards every mesh
- *               triangle): ray k of triangle f (virtual ray f g^2 + k of its
- *               source) aims at a point uniform in cell (k mod g, k / g) of a
- *               g x g grid, mapped area-preservingly onto the triangle, with
- *               weight p0 A |cos theta| / d^2 / g^2 (p0 = 1 / field-of-view
- *               solid angle): the same estimate as the uniform launch.  Rays
- *               outside the field of view, and rays whose first hit is not the
- *               aimed-at triangle, are not counted (hit row all -1).  Needs an
- *               azimuth span of at most pi.
+ *               triangle): each triangle is first cut into pieces (see
+ *               rr_set_casting; by default a piece is the triangle itself);
+ *               ray k of piece f (virtual ray f g^2 + k of its source) aims at
+ *               a point uniform in cell (k mod g, k / g) of a g x g grid,
+ *               mapped area-preservingly onto the piece, with weight
+ *               p0 A |cos theta| / d^2 / g^2 (A the piece's area, p0 = 1 /
+ *               field-of-view solid angle): the same estimate as the uniform
+ *               launch.  Rays outside the field of view, and rays whose first
+ *               hit is not the piece's parent triangle, are not counted (hit
+ *               row all -1).  Needs an azimuth span of at most pi.
  *   record_hits 1: keep the per-ray hit list for rr_get_hits
  *   path_cap    keep at most this many paths (first in ray, bounce order);
  *               0 = keep all */

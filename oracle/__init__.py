@@ -59,7 +59,8 @@ class _Trace(C.Structure):
     _fields_ = [("n_rays", C.c_int64), ("max_bounces", C.c_int32), ("seed", C.c_uint64),
                 ("az_min", C.c_double), ("az_max", C.c_double), ("el_min", C.c_double),
                 ("el_max", C.c_double), ("cdf", C.c_void_p), ("n_az", C.c_int32),
-                ("n_el", C.c_int32), ("tri_g", C.c_int32)]
+                ("n_el", C.c_int32), ("tri_g", C.c_int32), ("tri_omega_max", C.c_double),
+                ("tri_depth_max", C.c_int32)]
 
 
 _lib = None
@@ -89,6 +90,9 @@ def lib():
                                 C.c_int, C.c_void_p, C.c_int64, C.c_void_p]
         L.orc_backproject.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p,
                                       C.c_void_p, C.c_int64, C.c_void_p]
+        L.orc_pieces.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p,
+                                 C.c_void_p, C.c_int64]
+        L.orc_pieces.restype = C.c_int64
         L.orc_release.argtypes = []
         _lib = L
     return _lib
@@ -138,7 +142,9 @@ def _array(a, keep):
 def _trace(tp, keep, cdf=None, n_az=0, n_el=0):
     c = None if cdf is None else keep.add(cdf, np.float64)
     st = _Trace(int(tp.n_rays), int(tp.max_bounces), int(tp.seed) & (2**64 - 1), tp.az_min,
-                tp.az_max, tp.el_min, tp.el_max, _p(c), n_az, n_el, tri_grid(tp))
+                tp.az_max, tp.el_min, tp.el_max, _p(c), n_az, n_el, tri_grid(tp),
+                float(getattr(tp, "tri_omega_max", 0.0) or 0.0),
+                int(getattr(tp, "tri_depth_max", 8)))
     keep.bufs.append(st)
     return st
 
@@ -210,10 +216,30 @@ def tri_grid(tp) -> int:
     return g
 
 
+def pieces(scene, array, omega_max=0.0, depth_max=8):
+    """The per-triangle launch's pieces: (vertices float64 [n][3][3], parent
+    triangle int64 [n])."""
+    keep = _Keep()
+    sc = _scene(scene, keep)
+    ar = _array(array, keep)
+    n = lib().orc_pieces(C.addressof(sc), C.addressof(ar), float(omega_max), int(depth_max),
+                         None, None, 0)
+    if n < 0:
+        raise RuntimeError("orc_pieces failed")
+    v = np.zeros((max(n, 1), 3, 3))
+    par = np.zeros(max(n, 1), dtype=np.int64)
+    lib().orc_pieces(C.addressof(sc), C.addressof(ar), float(omega_max), int(depth_max),
+                     v.ctypes.data, par.ctypes.data, n)
+    return v[:n], par[:n]
+
+
 def n_per_src(scene, array, tp) -> int:
     g = tri_grid(tp)
     if g:
-        return scene.n_tris * g * g
+        om = float(getattr(tp, "tri_omega_max", 0.0) or 0.0)
+        n = scene.n_tris if om <= 0.0 else len(pieces(scene, array, om,
+                                                          int(getattr(tp, "tri_depth_max", 8)))[1])
+        return n * g * g
     return int(tp.n_rays) if array.mode == 1 else int(tp.n_rays) // array.n_tx
 
 

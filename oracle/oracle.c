@@ -77,8 +77,11 @@ typedef struct {
     const double *cdf;
     int32_t n_az, n_el;
     /* per-triangle casting when tri_g > 0: tri_g^2 rays towards every
-     * triangle from every source (n_rays is then unused) */
+     * triangle from every source (n_rays is then unused); with
+     * tri_omega_max > 0 each triangle is first cut into pieces (below) */
     int32_t tri_g;
+    double tri_omega_max;    /* sr; 0: no subdivision */
+    int32_t tri_depth_max;   /* at most 4^depth pieces per triangle */
 } orc_trace_params;
 
 #define ORC_KMAX 8
@@ -458,6 +461,15 @@ void orc_bounce(const double d[3], const double n[3], double alpha, double u0, d
 
 #define INV_2PI 0.15915494309189535
 
+/* pieces of the per-triangle launch (built by build_pieces below) */
+typedef struct {
+    vec3 v[3];
+    int64_t parent;
+} orc_piece;
+
+static orc_piece *g_pieces;
+static int64_t g_n_pieces, g_cap_pieces;
+
 typedef struct {
     int64_t n_src, n_per_src;        /* rays per source */
     int64_t n_virt_per_src;          /* rays + points per source */
@@ -477,7 +489,7 @@ static void setup(const orc_scene *sc, const orc_array *ar, const orc_trace_para
 {
     s->n_src = ar->shared ? 1 : ar->ntx;
     if (tp->tri_g > 0)
-        s->n_per_src = sc->nt * (int64_t)tp->tri_g * tp->tri_g;
+        s->n_per_src = g_n_pieces * (int64_t)tp->tri_g * tp->tri_g;
     else
         s->n_per_src = ar->shared ? tp->n_rays : tp->n_rays / ar->ntx;
     s->n_virt_per_src = s->n_per_src + sc->npts;
@@ -509,17 +521,94 @@ static void setup(const orc_scene *sc, const orc_array *ar, const orc_trace_para
  * (reading: the field of view is the same azimuth / elevation box as the
  * uniform launch; the azimuth test below needs a span of at most pi).
  * Returns 0 for a ray that is not traced. */
+/* Pieces of the per-triangle launch: every triangle (in upload order), cut
+ * by midpoint subdivision into four while the piece subtends more than
+ * omega_max steradians from the Tx phase centre o (and depth < depth_max);
+ * children in the order (v0, m01, m20), (m01, v1, m12), (m20, m12, v2),
+ * (m01, m12, m20), depth first.  A piece keeps its parent triangle, the one
+ * its rays must hit first.  With omega_max = 0 the pieces are the triangles.
+ * Any subdivision leaves the estimate unbiased (every ray is weighted by its
+ * own piece's area); it only moves rays towards the triangles that fill the
+ * most solid angle, where area-uniform points on a large triangle would be
+ * sparse (the near-field ground). */
+/* solid angle of triangle (a, b, c) seen from o (Van Oosterom and Strackee 1983) */
+static double tri_solid_angle(vec3 a, vec3 b, vec3 c, vec3 o)
+{
+    vec3 x = vsub(a, o), y = vsub(b, o), z = vsub(c, o);
+    double lx = vlen(x), ly = vlen(y), lz = vlen(z);
+    double num = fabs(vdot(x, vcross(y, z)));
+    double den = lx * ly * lz + vdot(x, y) * lz + vdot(x, z) * ly + vdot(y, z) * lx;
+    return 2.0 * atan2(num, den);
+}
+
+static vec3 mid(vec3 a, vec3 b) { return mk((a.x + b.x) * 0.5, (a.y + b.y) * 0.5, (a.z + b.z) * 0.5); }
+
+static int push_piece(vec3 a, vec3 b, vec3 c, int64_t parent)
+{
+    if (g_n_pieces == g_cap_pieces) {
+        int64_t cap = g_cap_pieces ? 2 * g_cap_pieces : 1024;
+        orc_piece *p = (orc_piece *)realloc(g_pieces, (size_t)cap * sizeof(orc_piece));
+        if (!p) return -1;
+        g_pieces = p;
+        g_cap_pieces = cap;
+    }
+    orc_piece *q = &g_pieces[g_n_pieces++];
+    q->v[0] = a; q->v[1] = b; q->v[2] = c;
+    q->parent = parent;
+    return 0;
+}
+
+static int cut(vec3 a, vec3 b, vec3 c, int64_t parent, vec3 o, double omega_max, int depth,
+               int depth_max)
+{
+    if (omega_max > 0.0 && depth < depth_max && tri_solid_angle(a, b, c, o) > omega_max) {
+        vec3 ab = mid(a, b), bc = mid(b, c), ca = mid(c, a);
+        if (cut(a, ab, ca, parent, o, omega_max, depth + 1, depth_max)) return -1;
+        if (cut(ab, b, bc, parent, o, omega_max, depth + 1, depth_max)) return -1;
+        if (cut(ca, bc, c, parent, o, omega_max, depth + 1, depth_max)) return -1;
+        return cut(ab, bc, ca, parent, o, omega_max, depth + 1, depth_max);
+    }
+    return push_piece(a, b, c, parent);
+}
+
+static int build_pieces(const orc_scene *sc, vec3 o, double omega_max, int depth_max)
+{
+    g_n_pieces = 0;
+    for (int64_t f = 0; f < sc->nt; f++) {
+        vec3 v0, v1, v2;
+        tri_verts(sc, f, &v0, &v1, &v2);
+        if (cut(v0, v1, v2, f, o, omega_max, 0, depth_max)) return -1;
+    }
+    return 0;
+}
+
+/* exposed for the tests: number of pieces and the vertices / parent of each */
+int64_t orc_pieces(const orc_scene *sc, const orc_array *ar, double omega_max, int32_t depth_max,
+                   double *verts, int64_t *parent, int64_t cap)
+{
+    if (build_pieces(sc, centroid(ar->tx, ar->ntx), omega_max, depth_max)) return -1;
+    for (int64_t i = 0; i < g_n_pieces && i < cap; i++) {
+        for (int k = 0; k < 3; k++) {
+            verts[9 * i + 3 * k] = g_pieces[i].v[k].x;
+            verts[9 * i + 3 * k + 1] = g_pieces[i].v[k].y;
+            verts[9 * i + 3 * k + 2] = g_pieces[i].v[k].z;
+        }
+        parent[i] = g_pieces[i].parent;
+    }
+    return g_n_pieces;
+}
+
 static int launch_tri(const orc_scene *sc, const orc_trace_params *tp, const trace_setup *s,
                       vec3 src, int64_t i, int64_t t, vec3 *dir, double *w)
 {
+    (void)sc;
     int64_t g = tp->tri_g, gg = g * g;
     int64_t f = i / gg, k = i % gg;
     double u[4];
     draw(tp->seed, (uint64_t)i, (uint64_t)t, 0, u);
     double u1 = ((double)(k % g) + u[0]) / (double)g;
     double u2 = ((double)(k / g) + u[1]) / (double)g;
-    vec3 v0, v1, v2;
-    tri_verts(sc, f, &v0, &v1, &v2);
+    vec3 v0 = g_pieces[f].v[0], v1 = g_pieces[f].v[1], v2 = g_pieces[f].v[2];
     double su = sqrt(u1);
     double b0 = 1.0 - su, b1 = su * (1.0 - u2), b2 = su * u2;
     vec3 x = mk(b0 * v0.x + b1 * v1.x + b2 * v2.x, b0 * v0.y + b1 * v1.y + b2 * v2.y,
@@ -658,6 +747,11 @@ int orc_trace(const orc_scene *sc, const orc_array *ar, const orc_trace_params *
     if (tp->max_bounces < 1 || tp->max_bounces > ORC_KMAX) return -1;
     if (ar->ntx < 1 || ar->nrx < 1) return -1;
     if (tp->tri_g < 0 || (tp->tri_g > 0 && !(tp->az_max - tp->az_min <= ORC_PI))) return -1;
+    if (tp->tri_g > 0 && (tp->tri_omega_max < 0.0 || tp->tri_depth_max < 0 || tp->tri_depth_max > 20))
+        return -1;
+    if (tp->tri_g > 0 &&
+        build_pieces(sc, centroid(ar->tx, ar->ntx), tp->tri_omega_max, tp->tri_depth_max))
+        return -2;
     trace_setup s;
     setup(sc, ar, tp, &s);
     if (use_bvh && g_bvh_scene != sc && bvh_build(sc) != 0) return -2;
@@ -706,7 +800,7 @@ int orc_trace(const orc_scene *sc, const orc_array *ar, const orc_trace_params *
         if (tp->tri_g > 0) {
             if (!launch_tri(sc, tp, &s, src, i, t, &dir, &w)) continue;
             pa.amp = w / (double)((int64_t)tp->tri_g * tp->tri_g);
-            target = i / ((int64_t)tp->tri_g * tp->tri_g);
+            target = g_pieces[i / ((int64_t)tp->tri_g * tp->tri_g)].parent;
         } else {
             dir = launch(tp, &s, i, t, &w);
             pa.amp = w / (double)s.n_per_src;

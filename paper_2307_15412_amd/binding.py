@@ -30,6 +30,7 @@ EXPORTED = [
     "rr_set_chirp", "rr_trace", "rr_trace_rays", "rr_get_path_count", "rr_get_hits",
     "rr_get_paths", "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms", "rr_backproject",
     "rr_max_projection", "rr_scene_set_alpha", "rr_scene_update_vertices", "rr_get_bvh_nodes",
+    "rr_set_casting", "rr_casting_pieces",
 ]
 
 
@@ -84,6 +85,8 @@ def load_library(path: str = LIB_PATH):
     L.rr_scene_update_vertices.argtypes = [vp, vp, i64]
     L.rr_get_bvh_nodes.argtypes = [vp, vp, i64, C.POINTER(i64)]
     L.rr_set_array.argtypes = [vp, vp, i32, vp, i32, f64, i32]
+    L.rr_set_casting.argtypes = [vp, f64, i32]
+    L.rr_casting_pieces.argtypes = [vp, C.POINTER(i64)]
     L.rr_set_chirp.argtypes = [vp, C.POINTER(Chirp)]
     L.rr_trace.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
     L.rr_trace_rays.argtypes = [vp, vp, vp, vp, vp, i64, C.c_int32, C.c_uint64, C.c_int32,
@@ -191,6 +194,16 @@ class Context:
         self.n_tx, self.n_rx, self.mode = tx.size // 3, rx.size // 3, int(mode)
         self.n_ch = self.n_tx * self.n_rx
 
+    def set_casting(self, max_solid_angle=0.0, max_depth=8):
+        """Subdivision of the per-triangle launch's triangles into pieces."""
+        self._check(self.lib.rr_set_casting(self.h, float(max_solid_angle), int(max_depth)))
+
+    def casting_pieces(self) -> int:
+        """Number of pieces a per-triangle trace casts at."""
+        n = C.c_int64()
+        self._check(self.lib.rr_casting_pieces(self.h, C.byref(n)))
+        return n.value
+
     def set_chirp(self, f0, bandwidth, t_chirp, t_rep, n_samples, n_chirps):
         ch = Chirp(f0, bandwidth, t_chirp, t_rep, n_samples, n_chirps)
         self._check(self.lib.rr_set_chirp(self.h, C.byref(ch)))
@@ -207,7 +220,7 @@ class Context:
         self.n_paths = n.value
         n_src = 1 if self.mode == TX_SHARED else self.n_tx
         if sampler == PER_TRIANGLE:
-            per = self.n_tris * int(n_rays)
+            per = self.casting_pieces() * int(n_rays)
         else:
             per = int(n_rays) if self.mode == TX_SHARED else int(n_rays) // self.n_tx
         self.n_traced = n_src * per
@@ -361,6 +374,7 @@ class Context:
         rpt = int(getattr(tp, "rays_per_tri", 0) or 0)
         if rpt > 0:
             args.update(n_rays=rpt, sampler=PER_TRIANGLE)
+            self.set_casting(getattr(tp, "tri_omega_max", 0.0), getattr(tp, "tri_depth_max", 8))
         args.update(kw)
         return self.trace(**args)
 

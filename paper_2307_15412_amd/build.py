@@ -26,6 +26,7 @@ NO_PACKED = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = {
     "rr_host.cpp": [],
     "rr_bvh.cpp": [],
+    "rr_pieces.cpp": ["-ffp-contract=off"],
     "k_trace.hip": ["-ffp-contract=off"],
     "k_synth.hip": [],
     "k_gemm.hip": [],

@@ -15,8 +15,7 @@
 
 namespace {
 
-__global__ void k_refit_leaves(float *ltris, float *tri_geom, int64_t nt, const int32_t *tris,
-                               const float *verts)
+__global__ void k_refit_leaves(float *ltris, int64_t nt, const int32_t *tris, const float *verts)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nt) return;
@@ -24,11 +23,7 @@ __global__ void k_refit_leaves(float *ltris, float *tri_geom, int64_t nt, const 
     const int id = __float_as_int(T[9]);
     for (int c = 0; c < 3; c++) {
         const int64_t vi = tris[3 * (int64_t)id + c];
-        for (int a = 0; a < 3; a++) {
-            const float x = verts[3 * vi + a];
-            T[3 * c + a] = x;
-            tri_geom[9 * (int64_t)id + 3 * c + a] = x;
-        }
+        for (int a = 0; a < 3; a++) T[3 * c + a] = verts[3 * vi + a];
     }
 }
 
@@ -98,13 +93,12 @@ __global__ void k_refit_level(float *nodes, float *ubox, const int32_t *order, i
 }  // namespace
 
 hipError_t launch_refit(float4 *nodes, float *ubox, const int32_t *order,
-                        const int64_t *level_start, int n_levels, float4 *ltris, float *tri_geom,
-                        int64_t n_tris, const int32_t *tris, const float *verts, double pad,
-                        hipStream_t s)
+                        const int64_t *level_start, int n_levels, float4 *ltris, int64_t n_tris,
+                        const int32_t *tris, const float *verts, double pad, hipStream_t s)
 {
     if (n_tris <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_refit_leaves, dim3((unsigned)((n_tris + 255) / 256)), dim3(256), 0, s,
-                       reinterpret_cast<float *>(ltris), tri_geom, n_tris, tris, verts);
+                       reinterpret_cast<float *>(ltris), n_tris, tris, verts);
     // levels are stored deepest first: level_start[l] .. level_start[l + 1]
     for (int l = 0; l < n_levels; l++) {
         const int64_t a = level_start[l], n = level_start[l + 1] - a;

@@ -270,13 +270,14 @@ __device__ __forceinline__ void append(const TraceArgs &A, bool rec, int32_t src
 __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, int64_t i, int64_t t, int64_t v,
                            double amp, int32_t srcid, int32_t *hrow, int *stk, int64_t target);
 
-// Per-triangle casting: ray i of a source aims at triangle f = i / g^2, at a
-// point drawn uniformly in cell (k mod g, k / g), k = i mod g^2, of a g x g
-// grid over the unit square and carried onto the triangle by the
-// area-preserving map (1 - sqrt u1) v0 + sqrt u1 (1 - u2) v1 + sqrt u1 u2 v2.
-// Weight p0 A |cos| / d^2 (A |cos| = |area normal . dir| / 2) over g^2 rays;
-// only rays inside the field of view are traced, and they count only when the
-// aimed-at triangle is their first hit.
+// Per-triangle casting: ray i of a source aims at piece f = i / g^2 (a
+// triangle, or part of one cut by the host's subdivision), at a point drawn
+// uniformly in cell (k mod g, k / g), k = i mod g^2, of a g x g grid over the
+// unit square and carried onto the piece by the area-preserving map
+// (1 - sqrt u1) v0 + sqrt u1 (1 - u2) v1 + sqrt u1 u2 v2.  Weight
+// p0 A |cos| / d^2 (A |cos| = |area normal . dir| / 2) over g^2 rays; only
+// rays inside the field of view are traced, and they count only when the
+// piece's triangle is their first hit.
 __device__ void trace_tri(const TraceArgs &A, int64_t g, int64_t t, int64_t i, int64_t v, d3 src,
                           int *stk)
 {
@@ -287,7 +288,7 @@ __device__ void trace_tri(const TraceArgs &A, int64_t g, int64_t t, int64_t i, i
     philox((uint64_t)i, (uint64_t)t, 0, A.seed, r);
     const double u1 = ((double)(k % gs) + u01(r[0])) / (double)gs;
     const double u2 = ((double)(k / gs) + u01(r[1])) / (double)gs;
-    const float *T = A.tri_geom + 9 * f;
+    const double *T = A.pieces + 9 * f;
     const d3 v0 = mk3(T[0], T[1], T[2]), v1 = mk3(T[3], T[4], T[5]), v2 = mk3(T[6], T[7], T[8]);
     const double su = sqrt(u1);
     const double b0 = 1.0 - su, b1 = su * (1.0 - u2), b2 = su * u2;
@@ -308,7 +309,8 @@ __device__ void trace_tri(const TraceArgs &A, int64_t g, int64_t t, int64_t i, i
         A.counts[v] = 0;
         return;
     }
-    trace_from(A, src, d, i, t, v, w / (double)gg, A.shared ? -1 : (int32_t)t, hrow, stk, f);
+    trace_from(A, src, d, i, t, v, w / (double)gg, A.shared ? -1 : (int32_t)t, hrow, stk,
+               A.piece_parent[f]);
 }
 
 __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)

@@ -151,7 +151,13 @@ struct rr_ctx {
     // learned proposal
     DevBuf tri_obj;            // object of each triangle, by original id
     DevBuf tri_alpha;          // staging of per-face alpha for rr_scene_set_alpha
-    DevBuf tri_geom;           // [n_tris][9] vertices by upload index (per-triangle casting)
+    // per-triangle launch: pieces (triangles cut by solid angle) and their parents
+    DevBuf pieces_v, pieces_p;
+    double cast_omega = 0.0;
+    int cast_depth = 8;
+    bool pieces_valid = false;
+    int64_t n_pieces = 0;
+    std::vector<float> h_verts;
     // refit of the BVH to moved vertices (rr_scene_update_vertices)
     DevBuf tris_dev, verts_dev, refit_order, ubox;
     DevBuf fq_pm, fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact-model GEMM engine
@@ -266,7 +272,7 @@ void rr_destroy(rr_ctx *c)
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
-                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->tri_geom, &c->tris_dev, &c->verts_dev,
+                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->pieces_v, &c->pieces_p, &c->tris_dev, &c->verts_dev,
                       &c->refit_order, &c->ubox,
                       &c->fq_pm, &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part, &c->bp_sf};
     for (DevBuf *b : bufs) b->release();
@@ -320,16 +326,10 @@ int rr_scene_upload(rr_ctx *c, const float *verts, int64_t n_verts, const int32_
     if ((rc = c->pt_vel.ensure((size_t)n_pts * 24 + 8))) return rc;
     if ((rc = c->pt_ap.ensure((size_t)n_pts * 8 + 8))) return rc;
     if ((rc = c->tri_obj.ensure((size_t)n_tris * 4 + 8))) return rc;
-    if ((rc = c->tri_geom.ensure((size_t)n_tris * 36 + 8))) return rc;
-    if (n_tris > 0) {
+    if (n_tris > 0)
         HIPCHK(hipMemcpy(c->tri_obj.p, tri_obj, (size_t)n_tris * 4, hipMemcpyHostToDevice));
-        std::vector<float> geom((size_t)n_tris * 9);
-        for (int64_t i = 0; i < n_tris; i++)
-            for (int k = 0; k < 3; k++)
-                for (int a = 0; a < 3; a++)
-                    geom[9 * i + 3 * k + a] = verts[3 * (int64_t)tris[3 * i + k] + a];
-        HIPCHK(hipMemcpy(c->tri_geom.p, geom.data(), geom.size() * 4, hipMemcpyHostToDevice));
-    }
+    c->h_verts.assign(verts, verts + 3 * n_verts);
+    c->pieces_valid = false;
     if (!bvh.nodes.empty())
         HIPCHK(hipMemcpy(c->nodes.p, bvh.nodes.data(), bvh.nodes.size() * 4, hipMemcpyHostToDevice));
     if (!bvh.tris.empty())
@@ -407,8 +407,10 @@ int rr_scene_update_vertices(rr_ctx *c, const float *verts, int64_t n_verts)
     HIPCHK(hipMemcpy(c->verts_dev.p, verts, (size_t)n_verts * 12, hipMemcpyHostToDevice));
     HIPCHK(launch_refit(c->nodes.as<float4>(), c->ubox.as<float>(), c->refit_order.as<const int32_t>(),
                         c->refit_levels.data(), (int)c->refit_levels.size() - 1, c->ltris.as<float4>(),
-                        c->tri_geom.as<float>(), c->n_tris, c->tris_dev.as<const int32_t>(),
-                        c->verts_dev.as<const float>(), pad, c->stream));
+                        c->n_tris, c->tris_dev.as<const int32_t>(), c->verts_dev.as<const float>(),
+                        pad, c->stream));
+    c->h_verts.assign(verts, verts + 3 * n_verts);
+    c->pieces_valid = false;
     g_err.clear();
     return RR_OK;
 }
@@ -475,6 +477,58 @@ int rr_scene_set_alpha(rr_ctx *c, const float *alpha, int64_t n, int32_t per)
     return RR_OK;
 }
 
+namespace {
+
+// the per-triangle launch's pieces for the current scene, array and casting
+// parameters (rebuilt when any of them changed)
+int ensure_pieces(rr_ctx *c)
+{
+    if (c->pieces_valid) return RR_OK;
+    std::vector<double> pv;
+    std::vector<int32_t> par;
+    const int64_t limit = (int64_t)1 << 26;
+    int rc = rr_build_pieces(c->h_verts.data(), c->h_tris.data(), c->n_tris, c->oT, c->cast_omega,
+                             c->cast_depth, limit, pv, par);
+    if (rc) return fail(rc, "more than %lld pieces: raise the solid-angle limit", (long long)limit);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((rc = c->pieces_v.ensure(pv.size() * 8 + 8))) return rc;
+    if ((rc = c->pieces_p.ensure(par.size() * 4 + 8))) return rc;
+    if (!par.empty()) {
+        HIPCHK(hipMemcpy(c->pieces_v.p, pv.data(), pv.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->pieces_p.p, par.data(), par.size() * 4, hipMemcpyHostToDevice));
+    }
+    c->n_pieces = (int64_t)par.size();
+    c->pieces_valid = true;
+    return RR_OK;
+}
+
+}  // namespace
+
+int rr_set_casting(rr_ctx *c, double max_solid_angle, int32_t max_depth)
+{
+    if (!c) return fail(RR_EINVAL, "ctx is NULL");
+    if (!(max_solid_angle >= 0.0) || !std::isfinite(max_solid_angle) || max_depth < 0 ||
+        max_depth > 20)
+        return fail(RR_EINVAL, "need max_solid_angle >= 0 and 0 <= max_depth <= 20");
+    if (c->cast_omega != max_solid_angle || c->cast_depth != max_depth) c->pieces_valid = false;
+    c->cast_omega = max_solid_angle;
+    c->cast_depth = max_depth;
+    g_err.clear();
+    return RR_OK;
+}
+
+int rr_casting_pieces(rr_ctx *c, int64_t *n_pieces)
+{
+    if (!c || !n_pieces) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_scene || !c->has_array) return fail(RR_ESTATE, "scene and array must be set");
+    HIPCHK(hipSetDevice(c->device));
+    int rc = ensure_pieces(c);
+    if (rc) return rc;
+    *n_pieces = c->n_pieces;
+    g_err.clear();
+    return RR_OK;
+}
+
 int rr_set_array(rr_ctx *c, const double *tx, int32_t n_tx, const double *rx, int32_t n_rx,
                  double rx_radius, int32_t tx_mode)
 {
@@ -492,6 +546,7 @@ int rr_set_array(rr_ctx *c, const double *tx, int32_t n_tx, const double *rx, in
     if ((rc = c->rx.ensure((size_t)n_rx * 24))) return rc;
     HIPCHK(hipMemcpy(c->tx.p, tx, (size_t)n_tx * 24, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->rx.p, rx, (size_t)n_rx * 24, hipMemcpyHostToDevice));
+    c->pieces_valid = false;
     c->h_tx.assign(tx, tx + 3 * n_tx);
     c->h_rx.assign(rx, rx + 3 * n_rx);
     c->tx_h.assign(tx, tx + 3 * n_tx);
@@ -558,7 +613,11 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
 
     const int shared = c->mode == RR_TX_SHARED;
     const int64_t n_src = shared ? 1 : c->ntx;
-    const int64_t n_per_src = tri_g ? c->n_tris * tp->n_rays
+    if (tri_g) {
+        const int rp = ensure_pieces(c);
+        if (rp) return rp;
+    }
+    const int64_t n_per_src = tri_g ? c->n_pieces * tp->n_rays
                                     : shared ? tp->n_rays : tp->n_rays / c->ntx;
     const int64_t n_vps = n_per_src + c->npts;
     const int64_t V = n_src * n_vps;
@@ -612,7 +671,8 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
     A.cdf = c->cdf.as<const double>();
     A.n_az = c->n_az;
     A.n_el = c->n_el;
-    A.tri_geom = c->tri_geom.as<const float>();
+    A.pieces = c->pieces_v.as<const double>();
+    A.piece_parent = c->pieces_p.as<const int32_t>();
     A.tri_g = tri_g;
     A.fov_c0 = std::cos(tp->az_min);
     A.fov_s0 = std::sin(tp->az_min);

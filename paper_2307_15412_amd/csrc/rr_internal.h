@@ -45,6 +45,9 @@ struct HostBvh {
     int depth = 0;
 };
 
+int rr_build_pieces(const float *verts, const int32_t *tris, int64_t n_tris, const double *o,
+                    double omega_max, int depth_max, int64_t limit, std::vector<double> &pverts,
+                    std::vector<int32_t> &parent);
 int rr_build_bvh(const float *verts, int64_t nv, const int32_t *tris, const int32_t *tri_obj,
                  const float *obj_alpha, int64_t nt, HostBvh &out, std::string &err);
 
@@ -69,8 +72,9 @@ struct TraceArgs {
     int sampler;
     const double *cdf;
     int n_az, n_el;
-    const float *tri_geom;    // [n_tris][9] vertices by upload index (per-triangle casting)
-    int tri_g;                // g: g^2 rays per triangle and source
+    const double *pieces;     // [n_pieces][9] vertices of the per-triangle launch's pieces
+    const int32_t *piece_parent;   // [n_pieces] triangle a piece's rays must hit first
+    int tri_g;                // g: g^2 rays per piece and source
     double fov_c0, fov_s0, fov_c1, fov_s1;   // cos, sin of the azimuth bounds
     int64_t vbase;            // first virtual ray of this scene in the (batched) ray space
     // outputs
@@ -176,9 +180,8 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
                             float2 *partial, float2 *cube, hipStream_t s);
 hipError_t launch_refit(float4 *nodes, float *ubox, const int32_t *order,
-                        const int64_t *level_start, int n_levels, float4 *ltris, float *tri_geom,
-                        int64_t n_tris, const int32_t *tris, const float *verts, double pad,
-                        hipStream_t s);
+                        const int64_t *level_start, int n_levels, float4 *ltris, int64_t n_tris,
+                        const int32_t *tris, const float *verts, double pad, hipStream_t s);
 hipError_t launch_backproject(const BackProjArgs &a, hipStream_t s);
 hipError_t launch_max_projection(const float2 *img, int64_t nx, int64_t nyz, float *out,
                                  float *peak, float floor_db, hipStream_t s);

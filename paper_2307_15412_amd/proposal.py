@@ -76,6 +76,19 @@ def evaluate(ctx, workloads, budget, ref_rays, beta=0.1):
             # an empty cube scores exactly 1: read it with paths_tri
             rec.update(err_tri=float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30),
                        ms_tri=ctx.kernel_ms(0), rays_tri=g * g * w.scene.n_tris, paths_tri=p_t)
+        # the same with the triangles cut into pieces by solid angle, 4 rays
+        # per piece, the threshold raised until the pieces fit the budget
+        om_fov = (tp.az_max - tp.az_min) * (math.sin(tp.el_max) - math.sin(tp.el_min))
+        om = om_fov * 4.0 / budget
+        ctx.set_casting(om, 12)
+        while ctx.casting_pieces() * 4 > budget:
+            om *= 1.25
+            ctx.set_casting(om, 12)
+        n_pc = ctx.casting_pieces()
+        p_c = ctx.trace(4, seed=tp.seed, sampler=B.PER_TRIANGLE, **kw)
+        rec.update(err_cut=float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30),
+                   ms_cut=ctx.kernel_ms(0), rays_cut=4 * n_pc, paths_cut=p_c, omega_cut=om)
+        ctx.set_casting(0.0, 8)
         out.append(rec)
     return out
 
@@ -210,6 +223,12 @@ def experiment(ctx, train_seeds, eval_seeds, train_rays=50_000, budget=12_500, r
                    rays_tri_mean=float(np.mean([r["rays_tri"] for r in res])),
                    paths_tri_mean=float(np.mean([r["paths_tri"] for r in res])),
                    empty_tri=int(sum(r["paths_tri"] == 0 for r in res)))
+    if all("err_cut" in r for r in res):
+        ec = np.array([r["err_cut"] for r in res])
+        out.update(err_cut_mean=float(ec.mean()), err_ratio_cut_mean=float(np.mean(ec / eu)),
+                   wins_cut=int((ec < eu).sum()),
+                   rays_cut_mean=float(np.mean([r["rays_cut"] for r in res])),
+                   paths_cut_mean=float(np.mean([r["paths_cut"] for r in res])))
     out.update(paths_uniform_mean=float(np.mean([r["paths_uniform"] for r in res])),
                paths_learned_mean=float(np.mean([r["paths_learned"] for r in res])))
     return out

@@ -132,6 +132,9 @@ class TraceParams:
     el_max: float = math.pi / 2
     rays_per_tri: int = 0            # > 0: cast this many rays (a perfect square) towards
                                      # every triangle from every source instead of n_rays
+    tri_omega_max: float = 0.0       # > 0: first cut triangles into pieces of at most this
+                                     # solid angle (sr) from the Tx phase centre
+    tri_depth_max: int = 8           # at most 4^depth pieces per triangle
 
 
 @dataclass

@@ -3,8 +3,9 @@
 the aimed-at triangle) and path records bitwise, on the tiny scene (per-element
 launch, several bounce counts), the hand proxy (shared launch, +-25 degree
 field of view that cuts the mesh), an occluding pair of triangles and a reduced
-street; the cube synthesised from those paths against the oracle's; invalid
-grids rejected."""
+street, also with the triangles cut into pieces by solid angle; the cube
+synthesised from those paths against the oracle's; invalid grids and casting
+parameters rejected."""
 import math
 
 import numpy as np
@@ -73,6 +74,46 @@ def test_occluding_pair_and_street(gpu, orc):
     _compare(gpu, orc, st)
 
 
+def test_subdivided_pieces(gpu, orc):
+    """Triangles cut into pieces by solid angle: the piece count and every hit
+    and path bitwise against the oracle, on the reduced street (its ground
+    and facades fill most of the view) and on the occluding pair; changing
+    the parameters, the vertices or the array rebuilds the pieces."""
+    st = sg.Workload("street", sg.scene_street(3, scale=0.05, n_cars=5, n_poles=6),
+                     sg.array_ula(2, 4, mode=sg.MODE_PER_TX), sg.Chirp(n_samples=64, n_chirps=8),
+                     sg.TraceParams(n_rays=0, max_bounces=2, seed=8, rays_per_tri=4,
+                                    tri_omega_max=2e-3, tri_depth_max=6))
+    n_orc = len(orc.pieces(st.scene, st.array, 2e-3, 6)[1])
+    assert n_orc > st.scene.n_tris
+    _compare(gpu, orc, st)
+    assert gpu.casting_pieces() == n_orc
+    gpu.set_casting(2e-3, 2)
+    assert gpu.casting_pieces() == len(orc.pieces(st.scene, st.array, 2e-3, 2)[1])
+    gpu.set_casting(0.0, 8)
+    assert gpu.casting_pieces() == st.scene.n_tris
+    v = np.array([[4.0, -0.2, -0.1], [4.0, 0.3, -0.1], [4.0, 0.0, 0.3],
+                  [6.0, -1.0, -1.0], [6.0, 1.5, -0.8], [6.0, -0.2, 1.4]], np.float32)
+    sc = sg.Scene(v, np.arange(6, dtype=np.int32).reshape(2, 3), np.zeros(2, np.int32),
+                  np.array([0.5], np.float32), np.zeros((1, 3))).checked()
+    o = np.zeros((1, 3))
+    w = sg.Workload("pair", sc, sg.Array(o, o.copy(), 1e3, sg.MODE_PER_TX), sg.Chirp(),
+                    sg.TraceParams(n_rays=0, max_bounces=2, seed=2, rays_per_tri=16,
+                                   tri_omega_max=5e-3, tri_depth_max=5))
+    _compare(gpu, orc, w)
+    n0 = gpu.casting_pieces()
+    # moved vertices: the pieces follow
+    v2 = v - np.array([1.5, 0.0, 0.0], np.float32)
+    gpu.update_vertices(v2)
+    w2 = sg.Workload("pair2", sg.with_verts(sc, v2), w.array, w.chirp, w.trace)
+    assert gpu.casting_pieces() == len(orc.pieces(w2.scene, w2.array, 5e-3, 5)[1]) != n0
+    n = gpu.trace_workload(w2, record_hits=True)
+    oh, op = orc.trace(w2.scene, w2.array, w2.trace)
+    assert np.array_equal(gpu.hits().cpu().numpy(), oh[traced_rows(orc, w2.scene, w2.array,
+                                                                   w2.trace)])
+    assert n == len(op)
+    assert_paths_equal(gpu_soa_np(gpu), oracle_to_soa(op))
+
+
 def test_invalid_grids(gpu):
     import paper_2307_15412_amd as rr
     w = sg.workload_tiny()
@@ -80,4 +121,8 @@ def test_invalid_grids(gpu):
     for n, az in ((5, 1.0), (0, 1.0), (4, 1.7)):
         with pytest.raises(rr.RadrayError) as e:
             gpu.trace(n_rays=n, max_bounces=2, az_min=-az, az_max=az, sampler=rr.PER_TRIANGLE)
+        assert e.value.code == rr.binding.RR_EINVAL
+    for om, dm in ((-1.0, 4), (float("nan"), 4), (1e-3, 21), (1e-3, -1)):
+        with pytest.raises(rr.RadrayError) as e:
+            gpu.set_casting(om, dm)
         assert e.value.code == rr.binding.RR_EINVAL

@@ -126,3 +126,83 @@ def test_invalid_grids():
     with pytest.raises(RuntimeError):
         oracle.trace(sc, _mono(), sg.TraceParams(n_rays=0, max_bounces=1, rays_per_tri=4,
                                                  az_min=-2.0, az_max=2.0))
+
+
+# ---------------------------------------------------------------- subdivision
+def _area(t):
+    return 0.5 * np.linalg.norm(np.cross(t[1] - t[0], t[2] - t[0]))
+
+
+def test_pieces_without_subdivision_are_the_triangles():
+    sc = sg.scene_street(3, scale=0.05, n_cars=2, n_poles=2)
+    v, par = oracle.pieces(sc, _mono(), 0.0, 8)
+    assert np.array_equal(par, np.arange(sc.n_tris))
+    assert np.array_equal(v, sc.verts.astype(np.float64)[sc.tris])
+
+
+def test_one_level_midpoint_children():
+    tri = np.array([[5.0, -0.3, 0.2], [5.4, 0.9, -0.1], [4.8, 0.1, 1.1]], np.float32)
+    sc = _scene(tri)
+    v, par = oracle.pieces(sc, _mono(), 1e-9, 1)
+    a, b, c = tri.astype(np.float64)
+    ab, bc, ca = (a + b) / 2, (b + c) / 2, (c + a) / 2
+    want = np.array([[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, bc, ca]])
+    assert np.array_equal(v, want) and (par == 0).all()
+
+
+def test_pieces_tile_their_triangle():
+    """Children cover the parent exactly once: areas and solid angles add up,
+    every leaf is below the threshold unless at the depth limit, and every
+    piece lies inside its parent."""
+    sc = sg.plate(3.0, 1.0, alpha=0.0)
+    o = np.array([[0.0, 0.0, 0.5]])
+    ar = sg.Array(o, o.copy(), 0.25, sg.MODE_PER_TX)
+    for om, dm in ((2e-2, 12), (1e-3, 3)):
+        v, par = oracle.pieces(sc, ar, om, dm)
+        tris = sc.verts.astype(np.float64)[sc.tris]
+        assert len(v) > sc.n_tris and np.array_equal(np.unique(par), np.arange(sc.n_tris))
+        assert np.all(np.diff(par) >= 0)           # upload order, depth first
+        for f in range(sc.n_tris):
+            kids = v[par == f]
+            assert abs(sum(_area(k) for k in kids) / _area(tris[f]) - 1) < 1e-12
+            om_kids = [_solid_angle(k, o[0]) for k in kids]
+            assert abs(sum(om_kids) / _solid_angle(tris[f], o[0]) - 1) < 1e-10
+            depth = np.round(np.log(_area(tris[f]) / np.array([_area(k) for k in kids])) /
+                             np.log(4)).astype(int)
+            assert ((np.array(om_kids) <= om) | (depth == dm)).all()
+            # barycentric coordinates of each piece vertex in the parent
+            e1, e2 = tris[f][1] - tris[f][0], tris[f][2] - tris[f][0]
+            G = np.array([[e1 @ e1, e1 @ e2], [e1 @ e2, e2 @ e2]])
+            rhs = np.stack([(kids - tris[f][0]) @ e1, (kids - tris[f][0]) @ e2], -1)
+            uv = np.linalg.solve(G, rhs.reshape(-1, 2).T).T
+            assert (uv > -1e-12).all() and (uv.sum(1) < 1 + 1e-12).all()
+    with pytest.raises(RuntimeError):
+        oracle.trace(sc, ar, sg.TraceParams(n_rays=0, max_bounces=1, rays_per_tri=1,
+                                            tri_omega_max=1e-3, tri_depth_max=21))
+
+
+def test_subdivided_launch_keeps_the_estimate():
+    """Cutting the triangles leaves the estimate unbiased and sharpens it: the
+    single triangle's and the specular disc's closed forms hold, with fewer
+    rays per piece."""
+    tri = [[5.0, -0.3, 0.2], [5.4, 0.9, -0.1], [4.8, 0.1, 1.1]]
+    sc = _scene(tri)
+    want = _solid_angle(sc.verts.astype(np.float64), np.zeros(3)) / (2 * math.pi)
+    tp = sg.TraceParams(n_rays=0, max_bounces=1, seed=1, rays_per_tri=16, tri_omega_max=2e-3,
+                        tri_depth_max=8)
+    hits, paths = oracle.trace(sc, _mono(), tp)
+    n_p = len(oracle.pieces(sc, _mono(), 2e-3, 8)[1])
+    assert n_p == 16 and hits.shape[0] == 16 * n_p and (hits[:, 0] == 0).all()
+    assert abs(paths["amp"].sum() / want - 1) < 2e-4
+    # the disc: the near plate is cut where it fills the view
+    R, r = 5.0, 0.25
+    pl = sg.plate(R, 1.0, alpha=0.0)
+    o = np.array([[0.0, 0.0, 0.5]])
+    ar = sg.Array(o, o.copy(), r, sg.MODE_PER_TX)
+    st = r / (2 * R)
+    want = 1.0 - math.sqrt(1 - st * st)
+    tp = sg.TraceParams(n_rays=0, max_bounces=1, seed=1, rays_per_tri=64, tri_omega_max=1e-3,
+                        tri_depth_max=10)
+    _, paths = oracle.trace(pl, ar, tp)
+    assert abs(paths["amp"].sum() / want - 1) < 0.01
+    assert np.allclose(paths["p"][:, 0, 0], R, atol=1e-12)
