@@ -26,9 +26,10 @@
 
 namespace {
 
-#define FQ_W 3            // wavefronts per workgroup (32 Tx rows each)
+#define FQ_G 4            // samples per workgroup, one per wavefront
 #define FQ_TILE 96        // Tx and Rx extent of a workgroup tile
 #define FQ_KS 16          // paths per step
+#define FQ_CH 24          // 1 KiB table chunks per step (X and Y, 3 blocks, 4 pieces)
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -144,15 +145,6 @@ struct Raw {           // one lane's table words of one step: 8 (beta, gamma) pa
     uint4 w[4];
 };
 
-__device__ __forceinline__ Raw load_raw(const uint2 *row)
-{
-    const uint4 *r4 = reinterpret_cast<const uint4 *>(row);
-    Raw r;
-#pragma unroll
-    for (int q = 0; q < 4; q++) r.w[q] = r4[q];
-    return r;
-}
-
 // the 8 path slots of one fragment lane at sample k, times a (when given),
 // split into the four bf16 planes
 __device__ __forceinline__ Frag leg_frag(const Raw &raw, unsigned k, const float *a)
@@ -189,133 +181,170 @@ struct FreqArgs {
     int T, R, M, K;
     int64_t Ppad;
     int tt, rt;               // Tx and Rx tiles
+    int kg;                   // groups of FQ_G samples
     int n_split;
     int64_t split_len;        // paths per split (multiple of FQ_KS)
     float2 *out;              // cube (one split) or partial tiles [split][m][k][T][R]
     int partial;
 };
 
-__global__ __launch_bounds__(FQ_W * 64) void k_freq_gemm(FreqArgs A)
+// One workgroup: a 96 x 96 (Tx x Rx) tile of FQ_G consecutive samples of one
+// chirp over one path split; wavefront w owns sample k0 + w and the whole
+// tile (3 x 3 blocks of 32 x 32, real and imaginary accumulators: 288
+// registers, one wavefront per SIMD).  The samples of a workgroup share the
+// table words of every step: the 24 KiB of (beta, gamma) words of the 96 Tx
+// and 96 Rx rows and 16 paths, plus the paths' amplitudes and sources, are
+// loaded once per workgroup (each lane fetching six 16-byte pieces a step
+// ahead into registers) and passed through LDS (two buffers), already in the
+// fragment lane order so that every read is a contiguous 1 KiB.  Each
+// wavefront generates its own X and Y fragments for its sample.  Rows beyond
+// the array's Tx and Rx counts read row 0's words and are never stored.
+template <bool PER_EL>
+__global__ __launch_bounds__(FQ_G * 64, 1) void k_freq_gemm(FreqArgs A)
 {
-    __shared__ uint4 Ys[2][FQ_W][4][64];
+    __shared__ uint4 Ls[2][FQ_CH + 1][64];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // k fastest: the workgroups that share one split's tables run together
+    // the sample group fastest: the workgroups that share one split's tables
+    // run together
     int64_t id = blockIdx.x;
-    const int k = (int)(id % A.K);
-    id /= A.K;
+    const int kq = (int)(id % A.kg);
+    id /= A.kg;
     const int ri = (int)(id % A.rt);
     id /= A.rt;
     const int ti = (int)(id % A.tt);
     id /= A.tt;
     const int m = (int)(id % A.M);
     const int s = (int)(id / A.M);
+    const int kw = kq * FQ_G + w;
+    const bool kv = kw < A.K;
+    const unsigned ku = (unsigned)(kv ? kw : A.K - 1);
     const int64_t pbeg = (int64_t)s * A.split_len;
     const int64_t pend = min(A.Ppad, pbeg + A.split_len);
-    const int t = ti * FQ_TILE + w * 32 + (lane & 31);
-    const int ry = ri * FQ_TILE + w * 32 + (lane & 31);   // Rx row this lane generates
-    const int half = (lane >> 5) * 8;
-    const bool tv = t < A.T, rv = ry < A.R;
-    const uint2 *xrow = A.xt + ((int64_t)m * A.T + (tv ? t : 0)) * A.Ppad + half;
-    const uint2 *yrow = A.yt + ((int64_t)m * A.R + (rv ? ry : 0)) * A.Ppad + half;
-    const unsigned ku = (unsigned)k;
+    const int64_t nsteps = (pend - pbeg) / FQ_KS;
+    const int t0 = ti * FQ_TILE, r0 = ri * FQ_TILE;
+    const int half = lane >> 5;
 
-    // per step and lane: the X and Y table words of its 8 path slots and
-    // those paths' amplitudes (masked for other transmitters in the
-    // per-element launch), loaded one step ahead of their use
-    struct Step {
-        Raw x, y;
-        float a[8];
+    // loader: this wavefront fetches chunks q = w + 4 j; chunk q is table
+    // q / 12 (X, Y), block (q % 12) / 4, piece q % 4 (paths 2 (q % 4) and
+    // 2 (q % 4) + 1 of the lane's half); lane l reads row 32 block + l % 32
+    auto piece_ptr = [&](int j) -> const uint4 * {
+        const int q = w + FQ_G * j;
+        const int tab = q / 12, blk = (q % 12) >> 2, c = q & 3;
+        int row = (tab ? r0 : t0) + 32 * blk + (lane & 31);
+        if (row >= (tab ? A.R : A.T)) row = 0;    // any valid row: masked later
+        const uint2 *base = tab ? A.yt + ((int64_t)m * A.R + row) * A.Ppad
+                                : A.xt + ((int64_t)m * A.T + row) * A.Ppad;
+        return reinterpret_cast<const uint4 *>(base + 8 * half + 2 * c);
     };
-    auto load = [&](int64_t p0) -> Step {
-        Step st;
-        st.x = load_raw(xrow + p0);
-        st.y = load_raw(yrow + p0);
-        const float4 *a4 = reinterpret_cast<const float4 *>(A.amp + p0 + half);
-        const int4 *s4 = reinterpret_cast<const int4 *>(A.src + p0 + half);
-        const float4 a0 = a4[0], a1 = a4[1];
-        const int4 s0 = s4[0], s1 = s4[1];
-        const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-        const int sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    static_assert(FQ_CH / FQ_G == 6, "six pieces per lane");
+    const uint4 *lp0 = piece_ptr(0), *lp1 = piece_ptr(1), *lp2 = piece_ptr(2);
+    const uint4 *lp3 = piece_ptr(3), *lp4 = piece_ptr(4), *lp5 = piece_ptr(5);
+    // amplitudes and sources: wavefront 0, lanes 0-3 (amp) and 4-7 (src)
+    const bool aload = w == 0 && lane < 8;
+    const uint4 *ap = lane < 4 ? reinterpret_cast<const uint4 *>(A.amp) + (lane & 3)
+                               : reinterpret_cast<const uint4 *>(A.src) + (lane & 3);
+    // one step's pieces of this lane, fetched a step ahead
+    uint4 P0, P1, P2, P3, P4, P5, PA = make_uint4(0u, 0u, 0u, 0u);
+#define FQ_FETCH(p0)                                                                              \
+    do {                                                                                          \
+        const int64_t h_ = (p0) >> 1;                                                             \
+        P0 = lp0[h_]; P1 = lp1[h_]; P2 = lp2[h_]; P3 = lp3[h_]; P4 = lp4[h_]; P5 = lp5[h_];       \
+        if (aload) PA = ap[(p0) >> 2];                                                            \
+    } while (0)
+#define FQ_STASH(b)                                                                               \
+    do {                                                                                          \
+        Ls[b][w][lane] = P0; Ls[b][w + 4][lane] = P1; Ls[b][w + 8][lane] = P2;                    \
+        Ls[b][w + 12][lane] = P3; Ls[b][w + 16][lane] = P4; Ls[b][w + 20][lane] = P5;             \
+        if (aload) Ls[b][FQ_CH][lane] = PA;                                                       \
+    } while (0)
+    auto raw_of = [&](int b, int q0) -> Raw {
+        Raw r;
 #pragma unroll
-        for (int e = 0; e < 8; e++) st.a[e] = (tv && (sv[e] < 0 || sv[e] == t)) ? av[e] : 0.0f;
-        return st;
-    };
-    auto put_y = [&](const Raw &raw, int buf) {
-        Frag f = leg_frag(raw, ku, nullptr);
-        if (!rv) f.rh = f.rl = f.ih = f.il = make_uint4(0u, 0u, 0u, 0u);
-        Ys[buf][w][0][lane] = f.rh;
-        Ys[buf][w][1][lane] = f.rl;
-        Ys[buf][w][2][lane] = f.ih;
-        Ys[buf][w][3][lane] = f.il;
+        for (int c = 0; c < 4; c++) r.w[c] = Ls[b][q0 + c][lane];
+        return r;
     };
 
-    f32x16 sr[FQ_W], si[FQ_W];
+    f32x16 sr[3][3], si[3][3];
 #pragma unroll
-    for (int j = 0; j < FQ_W; j++)
+    for (int i = 0; i < 3; i++)
 #pragma unroll
-        for (int e = 0; e < 16; e++) {
-            sr[j][e] = 0.0f;
-            si[j][e] = 0.0f;
-        }
-    // table words two steps ahead of their use (the leg tables stream from
-    // beyond L2; one step of products does not cover that latency)
-    Step cur = load(pbeg);
-    Step nx1 = load(pbeg + FQ_KS < pend ? pbeg + FQ_KS : pbeg);
-    Frag x = leg_frag(cur.x, ku, cur.a);
-    put_y(cur.y, 0);
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                sr[i][j][e] = 0.0f;
+                si[i][j][e] = 0.0f;
+            }
+
+    FQ_FETCH(pbeg);
+    FQ_STASH(0);
+    FQ_FETCH(nsteps > 1 ? pbeg + FQ_KS : pbeg);
     __syncthreads();
-    int buf = 0;
-    for (int64_t p0 = pbeg; p0 < pend; p0 += FQ_KS) {
-        const bool more = p0 + FQ_KS < pend;
-        const int64_t p2 = p0 + 2 * FQ_KS < pend ? p0 + 2 * FQ_KS : p0;
-        Step nx2 = load(p2);
-        uint4 y[FQ_W][4];
+    for (int64_t st = 0; st < nsteps; st++) {
+        const int b = (int)(st & 1);
+        // Y fragments of the three Rx blocks (zero beyond the array)
+        Frag y[3];
 #pragma unroll
-        for (int j = 0; j < FQ_W; j++)
+        for (int j = 0; j < 3; j++) y[j] = leg_frag(raw_of(b, 12 + 4 * j), ku, nullptr);
+        // amplitudes of the lane's 8 paths; in a per-element launch a path
+        // feeds only its own transmitter's rows
+        const uint4 a0 = Ls[b][FQ_CH][2 * half], a1 = Ls[b][FQ_CH][2 * half + 1];
+        const uint4 s0 = Ls[b][FQ_CH][4 + 2 * half], s1 = Ls[b][FQ_CH][5 + 2 * half];
+        const unsigned av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        const unsigned sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
 #pragma unroll
-            for (int q = 0; q < 4; q++) y[j][q] = Ys[buf][j][q][lane];
-        const uint4 nih = neg(x.ih), nil = neg(x.il);
+        for (int i = 0; i < 3; i++) {
+            const int t = t0 + 32 * i + (lane & 31);
+            float a[8];
 #pragma unroll
-        for (int j = 0; j < FQ_W; j++) {
-            // re += Xr Yr - Xi Yi, im += Xr Yi + Xi Yr (each hi*hi + hi*lo + lo*hi)
-            sr[j] = MFMA(x.rh, y[j][0], sr[j]);
-            sr[j] = MFMA(x.rh, y[j][1], sr[j]);
-            sr[j] = MFMA(x.rl, y[j][0], sr[j]);
-            sr[j] = MFMA(nih, y[j][2], sr[j]);
-            sr[j] = MFMA(nih, y[j][3], sr[j]);
-            sr[j] = MFMA(nil, y[j][2], sr[j]);
-            si[j] = MFMA(x.rh, y[j][2], si[j]);
-            si[j] = MFMA(x.rh, y[j][3], si[j]);
-            si[j] = MFMA(x.rl, y[j][2], si[j]);
-            si[j] = MFMA(x.ih, y[j][0], si[j]);
-            si[j] = MFMA(x.ih, y[j][1], si[j]);
-            si[j] = MFMA(x.il, y[j][0], si[j]);
-        }
-        if (more) {
-            put_y(nx1.y, buf ^ 1);
-            x = leg_frag(nx1.x, ku, nx1.a);
-        }
-        nx1 = nx2;
-        buf ^= 1;
-        __syncthreads();
-    }
-    // D layout: register e of lane l is row 8 (e / 4) + 4 (l / 32) + e % 4
-    // (a Tx row of this wavefront's block), column l % 32 (an Rx column)
+            for (int e = 0; e < 8; e++) {
+                const int sp = (int)sv[e];
+                a[e] = (!PER_EL || ((sp < 0) | (sp == t))) ? __uint_as_float(av[e]) : 0.0f;
+            }
+            const Frag x = leg_frag(raw_of(b, 4 * i), ku, a);
+            const uint4 nih = neg(x.ih), nil = neg(x.il);
 #pragma unroll
-    for (int j = 0; j < FQ_W; j++)
-#pragma unroll
-        for (int e = 0; e < 16; e++) {
-            const int to = ti * FQ_TILE + w * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-            const int ro = ri * FQ_TILE + j * 32 + (lane & 31);
-            if (to < A.T && ro < A.R) {
-                const float2 v = make_float2(sr[j][e], si[j][e]);
-                if (A.partial)
-                    A.out[((((int64_t)s * A.M + m) * A.K + k) * A.T + to) * A.R + ro] = v;
-                else
-                    A.out[(((int64_t)to * A.R + ro) * A.M + m) * A.K + k] = v;
+            for (int j = 0; j < 3; j++) {
+                // re += Xr Yr - Xi Yi, im += Xr Yi + Xi Yr (hi*hi + hi*lo + lo*hi)
+                sr[i][j] = MFMA(x.rh, y[j].rh, sr[i][j]);
+                si[i][j] = MFMA(x.rh, y[j].ih, si[i][j]);
+                sr[i][j] = MFMA(x.rh, y[j].rl, sr[i][j]);
+                si[i][j] = MFMA(x.rh, y[j].il, si[i][j]);
+                sr[i][j] = MFMA(x.rl, y[j].rh, sr[i][j]);
+                si[i][j] = MFMA(x.rl, y[j].ih, si[i][j]);
+                sr[i][j] = MFMA(nih, y[j].ih, sr[i][j]);
+                si[i][j] = MFMA(x.ih, y[j].rh, si[i][j]);
+                sr[i][j] = MFMA(nih, y[j].il, sr[i][j]);
+                si[i][j] = MFMA(x.ih, y[j].rl, si[i][j]);
+                sr[i][j] = MFMA(nil, y[j].ih, sr[i][j]);
+                si[i][j] = MFMA(x.il, y[j].rh, si[i][j]);
             }
         }
+        if (st + 1 < nsteps) FQ_STASH(b ^ 1);
+        __syncthreads();
+        FQ_FETCH(st + 2 < nsteps ? pbeg + (st + 2) * FQ_KS : pbeg);
+    }
+#undef FQ_FETCH
+#undef FQ_STASH
+    // D layout: register e of lane l is row 8 (e / 4) + 4 (l / 32) + e % 4
+    // (a Tx row of block i), column l % 32 (an Rx column of block j)
+    if (!kv) return;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                const int to = t0 + 32 * i + 8 * (e >> 2) + 4 * half + (e & 3);
+                const int ro = r0 + 32 * j + (lane & 31);
+                if (to < A.T && ro < A.R) {
+                    const float2 v = make_float2(sr[i][j][e], si[i][j][e]);
+                    if (A.partial)
+                        A.out[((((int64_t)s * A.M + m) * A.K + kw) * A.T + to) * A.R + ro] = v;
+                    else
+                        A.out[(((int64_t)to * A.R + ro) * A.M + m) * A.K + kw] = v;
+                }
+            }
 }
 
 // cube[(t R + r) M + m][k] = sum over splits, in split order
@@ -344,6 +373,7 @@ __global__ void k_freq_reduce(const float2 *part, int n_split, int T, int R, int
 }  // namespace
 
 int freq_k_step() { return FQ_KS; }
+int freq_k_group() { return FQ_G; }
 
 hipError_t launch_freq_prep(const SynPath *paths, int64_t n, int64_t Ppad, int M, double t_rep,
                             const double *tx, int T, const double *rx, int R, double f0c, double dfc,
@@ -362,7 +392,7 @@ hipError_t launch_freq_prep(const SynPath *paths, int64_t n, int64_t Ppad, int M
 
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
-                            float2 *partial, float2 *cube, hipStream_t s)
+                            int per_element, float2 *partial, float2 *cube, hipStream_t s)
 {
     if ((int64_t)n_split * split_len < Ppad || split_len % FQ_KS || Ppad % FQ_KS || Ppad <= 0)
         return hipErrorInvalidValue;
@@ -378,13 +408,17 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     A.Ppad = Ppad;
     A.tt = (T + FQ_TILE - 1) / FQ_TILE;
     A.rt = (R + FQ_TILE - 1) / FQ_TILE;
+    A.kg = (K + FQ_G - 1) / FQ_G;
     A.n_split = n_split;
     A.split_len = split_len;
     A.partial = n_split > 1;
     A.out = n_split > 1 ? partial : cube;
-    const int64_t blocks = (int64_t)n_split * M * A.tt * A.rt * K;
+    const int64_t blocks = (int64_t)n_split * M * A.tt * A.rt * A.kg;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_freq_gemm, dim3((unsigned)blocks), dim3(FQ_W * 64), 0, s, A);
+    if (per_element)
+        hipLaunchKernelGGL(k_freq_gemm<true>, dim3((unsigned)blocks), dim3(FQ_G * 64), 0, s, A);
+    else
+        hipLaunchKernelGGL(k_freq_gemm<false>, dim3((unsigned)blocks), dim3(FQ_G * 64), 0, s, A);
     if (n_split > 1) {
         const int64_t per = (int64_t)M * K * T * R;
         hipLaunchKernelGGL(k_freq_reduce, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s,

@@ -905,9 +905,11 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
     const int64_t ks = freq_k_step();
     const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
     const int T = c->ntx, R = c->nrx, M = A.M, K = A.K;
-    const int64_t tiles = (int64_t)M * K * ((T + 95) / 96) * ((R + 95) / 96);
-    // enough workgroups to fill the chip, at least 16 steps of paths each
-    int64_t n_split = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
+    const int64_t kg = (K + freq_k_group() - 1) / freq_k_group();
+    const int64_t tiles = (int64_t)M * kg * ((T + 95) / 96) * ((R + 95) / 96);
+    // enough workgroups to fill the chip four times over (one per CU at a
+    // time), at least 16 steps of paths each
+    int64_t n_split = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
     n_split = std::min<int64_t>(n_split, std::max<int64_t>(1, Ppad / (16 * ks)));
     int64_t split_len = (Ppad + n_split - 1) / n_split;
     split_len = (split_len + ks - 1) / ks * ks;
@@ -926,7 +928,8 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
                             c->stream));
     HIPCHK(launch_freq_gemm(c->fq_xt.as<const uint2>(), c->fq_yt.as<const uint2>(),
                             c->fq_amp.as<const float>(), c->fq_src.as<const int32_t>(), T, R, M, K,
-                            Ppad, (int)n_split, split_len, c->fq_part.as<float2>(), A.cube,
+                            Ppad, (int)n_split, split_len, c->mode != RR_TX_SHARED,
+                            c->fq_part.as<float2>(), A.cube,
                             c->stream));
     return RR_OK;
 }

@@ -172,12 +172,14 @@ hipError_t launch_bp_mfma(const float2 *cube, int64_t stride, const double *tx, 
                           uint4 *Sf, float2 *image, hipStream_t s);
 int64_t bp_mfma_frag_bytes(int K);
 int freq_k_step();
+int freq_k_group();   // samples per exact-GEMM workgroup
 hipError_t launch_freq_prep(const SynPath *paths, int64_t n, int64_t Ppad, int M, double t_rep,
                             const double *tx, int T, const double *rx, int R, double f0c, double dfc,
                             double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
                             hipStream_t s);
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
+                            int per_element,
                             float2 *partial, float2 *cube, hipStream_t s);
 hipError_t launch_refit(float4 *nodes, float *ubox, const int32_t *order,
                         const int64_t *level_start, int n_levels, float4 *ltris, int64_t n_tris,

@@ -30,7 +30,8 @@ def _exact(gpu):
 
 
 @pytest.mark.parametrize("n_tx,n_rx,K,M", [(3, 7, 32, 2), (33, 97, 16, 1), (96, 96, 8, 1),
-                                           (97, 5, 12, 3), (1, 1, 40, 1)])
+                                           (97, 5, 12, 3), (1, 1, 40, 1), (5, 9, 13, 2),
+                                           (2, 3, 3, 1)])
 def test_tile_edges(gpu, orc, n_tx, n_rx, K, M):
     w = sg.workload_tiny(1)
     w.array = sg.array_sparse_grid(n_tx, n_rx, 3, grid=128, mode=sg.MODE_SHARED)
