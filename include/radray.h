@@ -134,26 +134,6 @@ int rr_scene_set_alpha(rr_ctx *ctx, const float *alpha, int64_t n, int32_t per);
 int rr_set_array(rr_ctx *ctx, const double *tx, int32_t n_tx, const double *rx, int32_t n_rx,
                  double rx_radius, int32_t tx_mode);
 
-/* Pieces of the RR_PER_TRIANGLE launch (Sec. III casts rays towards every
- * triangle; a coarse mesh with a large near triangle gets its rays spread by
- * cutting it).  Every triangle, in upload order, is cut by midpoint
- * subdivision into four while the piece subtends more than max_solid_angle
- * steradians from the Tx phase centre (Van Oosterom-Strackee formula, FP64)
- * and its depth is below max_depth; the children of (a, b, c) are
- * (a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca), depth first.
- * max_solid_angle = 0 (the default, with max_depth 8) casts at the triangles
- * themselves.  Takes effect at the next per-triangle trace; the pieces are
- * rebuilt on the host after a change of these parameters, the scene, its
- * vertices or the array.  Errors: RR_EINVAL (negative or non-finite angle,
- * max_depth outside [0, 20]). */
-int rr_set_casting(rr_ctx *ctx, double max_solid_angle, int32_t max_depth);
-
-/* Number of pieces the next RR_PER_TRIANGLE trace casts at (builds them if
- * needed); a per-triangle trace launches n_pieces * n_rays rays per source.
- * Errors: RR_ESTATE (no scene or array), RR_EOVERFLOW (more than 2^26
- * pieces), RR_EINVAL (NULL). */
-int rr_casting_pieces(rr_ctx *ctx, int64_t *n_pieces);
-
 /* FMCW chirp: start frequency f0, sweep bandwidth B over t_chirp, chirp
  * repetition t_rep, n_samples fast-time samples per chirp (sample k at
  * frequency f0 + B k / n_samples), n_chirps chirps.  Errors: RR_EINVAL. */
@@ -173,8 +153,9 @@ int rr_set_chirp(rr_ctx *ctx, const rr_chirp *chirp);
  *   sampler     RR_UNIFORM, or RR_PROPOSAL (bins of the proposal table set by
  *               rr_proposal_set_cdf or rr_proposal_build, weight p0/q), or
  *               RR_PER_TRIANGLE (Sec. III: rays cast towards every mesh
- *               triangle): each triangle is first cut into pieces (see
- *               rr_set_casting; by default a piece is the triangle itself);
+ *               triangle): each triangle is first cut into pieces, and
+ *               pieces out of view are dropped (see rr_set_casting; by
+ *               default the pieces are the triangles in view);
  *               ray k of piece f (virtual ray f g^2 + k of its source) aims at
  *               a point uniform in cell (k mod g, k / g) of a g x g grid,
  *               mapped area-preservingly onto the piece, with weight
@@ -205,6 +186,32 @@ typedef struct {
  * reported as RR_EOVERFLOW there).  Errors: RR_ESTATE (no scene or array),
  * RR_EINVAL, RR_ENOMEM, RR_EHIP. */
 int rr_trace(rr_ctx *ctx, const rr_trace_params *params, int64_t *n_paths_out);
+
+/* Pieces of the RR_PER_TRIANGLE launch (Sec. III casts rays towards every
+ * triangle; a coarse mesh with a large near triangle gets its rays spread by
+ * cutting it).  Every triangle, in upload order, is cut by midpoint
+ * subdivision into four while the piece subtends more than max_solid_angle
+ * steradians from the Tx phase centre (Van Oosterom-Strackee formula, FP64)
+ * and its depth is below max_depth; the children of (a, b, c) are
+ * (a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca), depth first.
+ * Pieces none of whose rays can enter the trace's field of view are dropped:
+ * all three vertices beyond the same bounding plane of the azimuth wedge, or
+ * inside the same excluded elevation cone where that cone is convex (below
+ * el_min <= 0, above el_max >= 0), by a margin of 1e-9 of their distance, as
+ * seen from every source (the Tx phase centre, or each Tx element).
+ * max_solid_angle = 0 (the default, with max_depth 8) casts at the triangles
+ * in view.  Takes effect at the next per-triangle trace; the pieces are
+ * rebuilt on the host after a change of these parameters, the field of view,
+ * the scene, its vertices or the array.  Errors: RR_EINVAL (negative or
+ * non-finite angle, max_depth outside [0, 20]). */
+int rr_set_casting(rr_ctx *ctx, double max_solid_angle, int32_t max_depth);
+
+/* Number of pieces a RR_PER_TRIANGLE trace with the field of view of params
+ * casts at (only az/el of params are read; builds the pieces if needed); such
+ * a trace launches n_pieces * n_rays rays per source.  Errors: RR_ESTATE (no
+ * scene or array), RR_EOVERFLOW (more than 2^26 pieces), RR_EINVAL (NULL, or
+ * a field of view per-triangle casting does not take). */
+int rr_casting_pieces(rr_ctx *ctx, const rr_trace_params *params, int64_t *n_pieces);
 
 /* Trace caller-supplied rays instead of the launch (Sec. III-A sends rays
  * out from each transmitter; here the caller chooses them, e.g. for another

@@ -91,7 +91,7 @@ def lib():
         L.orc_backproject.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p,
                                       C.c_void_p, C.c_int64, C.c_void_p]
         L.orc_pieces.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p,
-                                 C.c_void_p, C.c_int64]
+                                 C.c_void_p, C.c_void_p, C.c_int64]
         L.orc_pieces.restype = C.c_int64
         L.orc_release.argtypes = []
         _lib = L
@@ -216,29 +216,39 @@ def tri_grid(tp) -> int:
     return g
 
 
-def pieces(scene, array, omega_max=0.0, depth_max=8):
+def pieces(scene, array, omega_max=0.0, depth_max=8, fov=None):
     """The per-triangle launch's pieces: (vertices float64 [n][3][3], parent
-    triangle int64 [n])."""
+    triangle int64 [n]).  fov = (az_min, az_max, el_min, el_max) drops the
+    pieces no ray of which can enter that field of view (None: keep all)."""
     keep = _Keep()
     sc = _scene(scene, keep)
     ar = _array(array, keep)
-    n = lib().orc_pieces(C.addressof(sc), C.addressof(ar), float(omega_max), int(depth_max),
+    fv = None
+    if fov is not None:
+        fv = np.ascontiguousarray(fov, dtype=np.float64)
+        keep.bufs.append(fv)
+    fp = fv.ctypes.data if fv is not None else None
+    n = lib().orc_pieces(C.addressof(sc), C.addressof(ar), float(omega_max), int(depth_max), fp,
                          None, None, 0)
     if n < 0:
         raise RuntimeError("orc_pieces failed")
     v = np.zeros((max(n, 1), 3, 3))
     par = np.zeros(max(n, 1), dtype=np.int64)
-    lib().orc_pieces(C.addressof(sc), C.addressof(ar), float(omega_max), int(depth_max),
+    lib().orc_pieces(C.addressof(sc), C.addressof(ar), float(omega_max), int(depth_max), fp,
                      v.ctypes.data, par.ctypes.data, n)
     return v[:n], par[:n]
+
+
+def fov_of(tp):
+    """(az_min, az_max, el_min, el_max) of trace parameters."""
+    return (tp.az_min, tp.az_max, tp.el_min, tp.el_max)
 
 
 def n_per_src(scene, array, tp) -> int:
     g = tri_grid(tp)
     if g:
         om = float(getattr(tp, "tri_omega_max", 0.0) or 0.0)
-        n = scene.n_tris if om <= 0.0 else len(pieces(scene, array, om,
-                                                          int(getattr(tp, "tri_depth_max", 8)))[1])
+        n = len(pieces(scene, array, om, int(getattr(tp, "tri_depth_max", 8)), fov_of(tp))[1])
         return n * g * g
     return int(tp.n_rays) if array.mode == 1 else int(tp.n_rays) // array.n_tx
 

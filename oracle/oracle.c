@@ -525,8 +525,10 @@ static void setup(const orc_scene *sc, const orc_array *ar, const orc_trace_para
  * by midpoint subdivision into four while the piece subtends more than
  * omega_max steradians from the Tx phase centre o (and depth < depth_max);
  * children in the order (v0, m01, m20), (m01, v1, m12), (m20, m12, v2),
- * (m01, m12, m20), depth first.  A piece keeps its parent triangle, the one
- * its rays must hit first.  With omega_max = 0 the pieces are the triangles.
+ * (m01, m12, m20), depth first; pieces no ray of which can enter the field
+ * of view are dropped (below).  A piece keeps its parent triangle, the one
+ * its rays must hit first.  With omega_max = 0 the pieces are the triangles
+ * in view.
  * Any subdivision leaves the estimate unbiased (every ray is weighted by its
  * own piece's area); it only moves rays towards the triangles that fill the
  * most solid angle, where area-uniform points on a large triangle would be
@@ -558,35 +560,99 @@ static int push_piece(vec3 a, vec3 b, vec3 c, int64_t parent)
     return 0;
 }
 
+/* The field of view as seen from the launch's sources (the Tx phase centre,
+ * or every Tx element), to drop pieces none of whose rays can count: a ray
+ * outside the field of view is not traced, so a piece whose every point lies
+ * outside it, from every source, only takes up ray indices.  The test is
+ * conservative: all three vertices beyond the same bounding plane of the
+ * azimuth wedge, or inside the same excluded elevation cone where that cone
+ * is convex (below el_min <= 0, above el_max >= 0), by a margin of 1e-9 of
+ * their distance (far above the rounding of a ray's direction); the excluded
+ * regions are convex, so then every point of the piece is outside. */
+typedef struct {
+    const double *src;
+    int32_t n_src;
+    double c0, s0, c1, s1;           /* cos, sin of the azimuth bounds */
+    double slo, shi;                 /* sin of the elevation bounds */
+} fov_cull;
+
+#define CULL_EPS 1e-9
+
+static int beyond_fov(vec3 a, vec3 b, vec3 c, vec3 src, const fov_cull *f)
+{
+    vec3 r[3] = {vsub(a, src), vsub(b, src), vsub(c, src)};
+    int n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+    for (int k = 0; k < 3; k++) {
+        double l = vlen(r[k]);
+        if (f->c0 * r[k].y - f->s0 * r[k].x < -CULL_EPS * l) n0++;
+        if (f->c1 * r[k].y - f->s1 * r[k].x > CULL_EPS * l) n1++;
+        if (r[k].z < f->slo * l - CULL_EPS * l) n2++;
+        if (r[k].z > f->shi * l + CULL_EPS * l) n3++;
+    }
+    return n0 == 3 || n1 == 3 || (f->slo <= 0.0 && n2 == 3) || (f->shi >= 0.0 && n3 == 3);
+}
+
+static int outside_fov(vec3 a, vec3 b, vec3 c, const fov_cull *f)
+{
+    for (int32_t t = 0; t < f->n_src; t++)
+        if (!beyond_fov(a, b, c, mk(f->src[3 * t], f->src[3 * t + 1], f->src[3 * t + 2]), f))
+            return 0;
+    return 1;
+}
+
 static int cut(vec3 a, vec3 b, vec3 c, int64_t parent, vec3 o, double omega_max, int depth,
-               int depth_max)
+               int depth_max, const fov_cull *fov)
 {
     if (omega_max > 0.0 && depth < depth_max && tri_solid_angle(a, b, c, o) > omega_max) {
         vec3 ab = mid(a, b), bc = mid(b, c), ca = mid(c, a);
-        if (cut(a, ab, ca, parent, o, omega_max, depth + 1, depth_max)) return -1;
-        if (cut(ab, b, bc, parent, o, omega_max, depth + 1, depth_max)) return -1;
-        if (cut(ca, bc, c, parent, o, omega_max, depth + 1, depth_max)) return -1;
-        return cut(ab, bc, ca, parent, o, omega_max, depth + 1, depth_max);
+        if (cut(a, ab, ca, parent, o, omega_max, depth + 1, depth_max, fov)) return -1;
+        if (cut(ab, b, bc, parent, o, omega_max, depth + 1, depth_max, fov)) return -1;
+        if (cut(ca, bc, c, parent, o, omega_max, depth + 1, depth_max, fov)) return -1;
+        return cut(ab, bc, ca, parent, o, omega_max, depth + 1, depth_max, fov);
     }
+    if (fov && outside_fov(a, b, c, fov)) return 0;
     return push_piece(a, b, c, parent);
 }
 
-static int build_pieces(const orc_scene *sc, vec3 o, double omega_max, int depth_max)
+/* fov: NULL keeps every piece */
+static int build_pieces(const orc_scene *sc, vec3 o, double omega_max, int depth_max,
+                        const fov_cull *fov)
 {
     g_n_pieces = 0;
     for (int64_t f = 0; f < sc->nt; f++) {
         vec3 v0, v1, v2;
         tri_verts(sc, f, &v0, &v1, &v2);
-        if (cut(v0, v1, v2, f, o, omega_max, 0, depth_max)) return -1;
+        if (cut(v0, v1, v2, f, o, omega_max, 0, depth_max, fov)) return -1;
     }
     return 0;
 }
 
-/* exposed for the tests: number of pieces and the vertices / parent of each */
-int64_t orc_pieces(const orc_scene *sc, const orc_array *ar, double omega_max, int32_t depth_max,
-                   double *verts, int64_t *parent, int64_t cap)
+/* the culling of a launch with field of view (az_min, az_max, el_min, el_max)
+ * from the array's sources; o: the Tx phase centre (the shared source) */
+static void make_cull(const orc_array *ar, const double *o, double az_min, double az_max,
+                      double el_min, double el_max, fov_cull *f)
 {
-    if (build_pieces(sc, centroid(ar->tx, ar->ntx), omega_max, depth_max)) return -1;
+    f->src = ar->shared ? o : ar->tx;
+    f->n_src = ar->shared ? 1 : ar->ntx;
+    f->c0 = cos(az_min);
+    f->s0 = sin(az_min);
+    f->c1 = cos(az_max);
+    f->s1 = sin(az_max);
+    f->slo = sin(el_min);
+    f->shi = sin(el_max);
+}
+
+/* exposed for the tests: number of pieces and the vertices / parent of each;
+ * fov = (az_min, az_max, el_min, el_max) of the launch, or NULL for no
+ * culling */
+int64_t orc_pieces(const orc_scene *sc, const orc_array *ar, double omega_max, int32_t depth_max,
+                   const double *fov, double *verts, int64_t *parent, int64_t cap)
+{
+    vec3 o = centroid(ar->tx, ar->ntx);
+    double oc[3] = {o.x, o.y, o.z};
+    fov_cull f;
+    if (fov) make_cull(ar, oc, fov[0], fov[1], fov[2], fov[3], &f);
+    if (build_pieces(sc, o, omega_max, depth_max, fov ? &f : NULL)) return -1;
     for (int64_t i = 0; i < g_n_pieces && i < cap; i++) {
         for (int k = 0; k < 3; k++) {
             verts[9 * i + 3 * k] = g_pieces[i].v[k].x;
@@ -749,9 +815,13 @@ int orc_trace(const orc_scene *sc, const orc_array *ar, const orc_trace_params *
     if (tp->tri_g < 0 || (tp->tri_g > 0 && !(tp->az_max - tp->az_min <= ORC_PI))) return -1;
     if (tp->tri_g > 0 && (tp->tri_omega_max < 0.0 || tp->tri_depth_max < 0 || tp->tri_depth_max > 20))
         return -1;
-    if (tp->tri_g > 0 &&
-        build_pieces(sc, centroid(ar->tx, ar->ntx), tp->tri_omega_max, tp->tri_depth_max))
-        return -2;
+    if (tp->tri_g > 0) {
+        vec3 o = centroid(ar->tx, ar->ntx);
+        double oc[3] = {o.x, o.y, o.z};
+        fov_cull f;
+        make_cull(ar, oc, tp->az_min, tp->az_max, tp->el_min, tp->el_max, &f);
+        if (build_pieces(sc, o, tp->tri_omega_max, tp->tri_depth_max, &f)) return -2;
+    }
     trace_setup s;
     setup(sc, ar, tp, &s);
     if (use_bvh && g_bvh_scene != sc && bvh_build(sc) != 0) return -2;

@@ -86,7 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.rr_get_bvh_nodes.argtypes = [vp, vp, i64, C.POINTER(i64)]
     L.rr_set_array.argtypes = [vp, vp, i32, vp, i32, f64, i32]
     L.rr_set_casting.argtypes = [vp, f64, i32]
-    L.rr_casting_pieces.argtypes = [vp, C.POINTER(i64)]
+    L.rr_casting_pieces.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
     L.rr_set_chirp.argtypes = [vp, C.POINTER(Chirp)]
     L.rr_trace.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
     L.rr_trace_rays.argtypes = [vp, vp, vp, vp, vp, i64, C.c_int32, C.c_uint64, C.c_int32,
@@ -198,10 +198,12 @@ class Context:
         """Subdivision of the per-triangle launch's triangles into pieces."""
         self._check(self.lib.rr_set_casting(self.h, float(max_solid_angle), int(max_depth)))
 
-    def casting_pieces(self) -> int:
-        """Number of pieces a per-triangle trace casts at."""
+    def casting_pieces(self, az_min=-math.pi / 2, az_max=math.pi / 2, el_min=-math.pi / 2,
+                       el_max=math.pi / 2) -> int:
+        """Number of pieces a per-triangle trace with this field of view casts at."""
+        tp = TraceParams(0, 1, 0, az_min, az_max, el_min, el_max, PER_TRIANGLE, 0, 0)
         n = C.c_int64()
-        self._check(self.lib.rr_casting_pieces(self.h, C.byref(n)))
+        self._check(self.lib.rr_casting_pieces(self.h, C.byref(tp), C.byref(n)))
         return n.value
 
     def set_chirp(self, f0, bandwidth, t_chirp, t_rep, n_samples, n_chirps):
@@ -220,7 +222,7 @@ class Context:
         self.n_paths = n.value
         n_src = 1 if self.mode == TX_SHARED else self.n_tx
         if sampler == PER_TRIANGLE:
-            per = self.casting_pieces() * int(n_rays)
+            per = self.casting_pieces(az_min, az_max, el_min, el_max) * int(n_rays)
         else:
             per = int(n_rays) if self.mode == TX_SHARED else int(n_rays) // self.n_tx
         self.n_traced = n_src * per

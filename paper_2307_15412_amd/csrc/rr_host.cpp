@@ -155,6 +155,7 @@ struct rr_ctx {
     DevBuf pieces_v, pieces_p;
     double cast_omega = 0.0;
     int cast_depth = 8;
+    double cast_fov[4] = {0, 0, 0, 0};   // field of view the pieces were built for
     bool pieces_valid = false;
     int64_t n_pieces = 0;
     std::vector<float> h_verts;
@@ -479,16 +480,27 @@ int rr_scene_set_alpha(rr_ctx *c, const float *alpha, int64_t n, int32_t per)
 
 namespace {
 
-// the per-triangle launch's pieces for the current scene, array and casting
-// parameters (rebuilt when any of them changed)
-int ensure_pieces(rr_ctx *c)
+// the per-triangle launch's pieces for the current scene, array, casting
+// parameters and field of view (rebuilt when any of them changed)
+int ensure_pieces(rr_ctx *c, const rr_trace_params *tp)
 {
-    if (c->pieces_valid) return RR_OK;
+    const double fov[4] = {tp->az_min, tp->az_max, tp->el_min, tp->el_max};
+    if (c->pieces_valid && std::equal(fov, fov + 4, c->cast_fov)) return RR_OK;
+    RrFov f;
+    const int shared = c->mode == RR_TX_SHARED;
+    f.src = shared ? c->oT : c->h_tx.data();
+    f.n_src = shared ? 1 : c->ntx;
+    f.c0 = std::cos(tp->az_min);
+    f.s0 = std::sin(tp->az_min);
+    f.c1 = std::cos(tp->az_max);
+    f.s1 = std::sin(tp->az_max);
+    f.slo = std::sin(tp->el_min);
+    f.shi = std::sin(tp->el_max);
     std::vector<double> pv;
     std::vector<int32_t> par;
     const int64_t limit = (int64_t)1 << 26;
     int rc = rr_build_pieces(c->h_verts.data(), c->h_tris.data(), c->n_tris, c->oT, c->cast_omega,
-                             c->cast_depth, limit, pv, par);
+                             c->cast_depth, &f, limit, pv, par);
     if (rc) return fail(rc, "more than %lld pieces: raise the solid-angle limit", (long long)limit);
     HIPCHK(hipStreamSynchronize(c->stream));
     if ((rc = c->pieces_v.ensure(pv.size() * 8 + 8))) return rc;
@@ -498,6 +510,7 @@ int ensure_pieces(rr_ctx *c)
         HIPCHK(hipMemcpy(c->pieces_p.p, par.data(), par.size() * 4, hipMemcpyHostToDevice));
     }
     c->n_pieces = (int64_t)par.size();
+    std::copy(fov, fov + 4, c->cast_fov);
     c->pieces_valid = true;
     return RR_OK;
 }
@@ -517,12 +530,15 @@ int rr_set_casting(rr_ctx *c, double max_solid_angle, int32_t max_depth)
     return RR_OK;
 }
 
-int rr_casting_pieces(rr_ctx *c, int64_t *n_pieces)
+int rr_casting_pieces(rr_ctx *c, const rr_trace_params *tp, int64_t *n_pieces)
 {
-    if (!c || !n_pieces) return fail(RR_EINVAL, "NULL argument");
+    if (!c || !tp || !n_pieces) return fail(RR_EINVAL, "NULL argument");
     if (!c->has_scene || !c->has_array) return fail(RR_ESTATE, "scene and array must be set");
+    if (!(tp->az_max > tp->az_min) || !(tp->az_max - tp->az_min <= M_PI) ||
+        !(tp->el_max > tp->el_min) || !std::isfinite(tp->az_min) || !std::isfinite(tp->el_min))
+        return fail(RR_EINVAL, "invalid field of view for per-triangle casting");
     HIPCHK(hipSetDevice(c->device));
-    int rc = ensure_pieces(c);
+    int rc = ensure_pieces(c, tp);
     if (rc) return rc;
     *n_pieces = c->n_pieces;
     g_err.clear();
@@ -614,7 +630,7 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
     const int shared = c->mode == RR_TX_SHARED;
     const int64_t n_src = shared ? 1 : c->ntx;
     if (tri_g) {
-        const int rp = ensure_pieces(c);
+        const int rp = ensure_pieces(c, tp);
         if (rp) return rp;
     }
     const int64_t n_per_src = tri_g ? c->n_pieces * tp->n_rays

@@ -45,9 +45,17 @@ struct HostBvh {
     int depth = 0;
 };
 
+// Field of view of a per-triangle launch as seen from its sources (the Tx
+// phase centre, or every Tx element): cosines and sines of the azimuth
+// bounds, sines of the elevation bounds.
+struct RrFov {
+    const double *src;
+    int32_t n_src;
+    double c0, s0, c1, s1, slo, shi;
+};
 int rr_build_pieces(const float *verts, const int32_t *tris, int64_t n_tris, const double *o,
-                    double omega_max, int depth_max, int64_t limit, std::vector<double> &pverts,
-                    std::vector<int32_t> &parent);
+                    double omega_max, int depth_max, const RrFov *fov, int64_t limit,
+                    std::vector<double> &pverts, std::vector<int32_t> &parent);
 int rr_build_bvh(const float *verts, int64_t nv, const int32_t *tris, const int32_t *tri_obj,
                  const float *obj_alpha, int64_t nt, HostBvh &out, std::string &err);
 

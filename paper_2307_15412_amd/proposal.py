@@ -67,24 +67,30 @@ def evaluate(ctx, workloads, budget, ref_rays, beta=0.1):
         p_l = ctx.trace(budget, seed=tp.seed, sampler=B.PROPOSAL, **kw)
         t_l = ctx.kernel_ms(0)
         el = float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30)
-        # per-triangle casting with at most the same number of rays
-        g = int(math.isqrt(budget // max(w.scene.n_tris, 1)))
+        # per-triangle casting (the triangles in view) with at most the same
+        # number of rays
+        fov = (tp.az_min, tp.az_max, tp.el_min, tp.el_max)
+        ctx.set_casting(0.0, 8)
+        n_in = ctx.casting_pieces(*fov)
+        g = int(math.isqrt(budget // max(n_in, 1)))
         rec = dict(seed=tp.seed, err_uniform=eu, err_learned=el, ms_uniform=t_u, ms_learned=t_l,
                    paths_uniform=p_u, paths_learned=p_l)
         if g >= 1:
             p_t = ctx.trace(g * g, seed=tp.seed, sampler=B.PER_TRIANGLE, **kw)
             # an empty cube scores exactly 1: read it with paths_tri
             rec.update(err_tri=float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30),
-                       ms_tri=ctx.kernel_ms(0), rays_tri=g * g * w.scene.n_tris, paths_tri=p_t)
-        # the same with the triangles cut into pieces by solid angle, 4 rays
-        # per piece, the threshold raised until the pieces fit the budget
+                       ms_tri=ctx.kernel_ms(0), rays_tri=g * g * n_in, paths_tri=p_t)
+        # the same with the triangles cut into pieces by solid angle (up to 16
+        # levels: a piece of the 2e4 m^2 ground half a metre below the radar
+        # needs about 13 to come down to the threshold), 4 rays per piece, the
+        # threshold raised until the pieces fit the budget
         om_fov = (tp.az_max - tp.az_min) * (math.sin(tp.el_max) - math.sin(tp.el_min))
         om = om_fov * 4.0 / budget
-        ctx.set_casting(om, 12)
-        while ctx.casting_pieces() * 4 > budget:
+        ctx.set_casting(om, 16)
+        while ctx.casting_pieces(*fov) * 4 > budget:
             om *= 1.25
-            ctx.set_casting(om, 12)
-        n_pc = ctx.casting_pieces()
+            ctx.set_casting(om, 16)
+        n_pc = ctx.casting_pieces(*fov)
         p_c = ctx.trace(4, seed=tp.seed, sampler=B.PER_TRIANGLE, **kw)
         rec.update(err_cut=float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30),
                    ms_cut=ctx.kernel_ms(0), rays_cut=4 * n_pc, paths_cut=p_c, omega_cut=om)

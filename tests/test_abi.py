@@ -96,7 +96,7 @@ def test_new_entry_points_reject_null_handles():
     assert lib.rr_backproject(None, None, 0, None, None, 0, 0) == E
     assert lib.rr_max_projection(None, None, None, None, C.c_float(-15.0)) == E
     assert lib.rr_set_casting(None, 1e-3, 4) == E
-    assert lib.rr_casting_pieces(None, C.byref(n)) == E
+    assert lib.rr_casting_pieces(None, None, C.byref(n)) == E
     pkg.binding._declare_batch(lib)
     assert lib.rr_batch_set_alpha(None, 0, None, 0, 0) == E
     assert lib.rr_last_error() != b""

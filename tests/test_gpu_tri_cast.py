@@ -75,22 +75,29 @@ def test_occluding_pair_and_street(gpu, orc):
 
 
 def test_subdivided_pieces(gpu, orc):
-    """Triangles cut into pieces by solid angle: the piece count and every hit
-    and path bitwise against the oracle, on the reduced street (its ground
-    and facades fill most of the view) and on the occluding pair; changing
-    the parameters, the vertices or the array rebuilds the pieces."""
+    """Triangles cut into pieces by solid angle, pieces out of view dropped:
+    the piece count and every hit and path bitwise against the oracle, on the
+    reduced street (its ground and facades fill most of the view) and on the
+    occluding pair; changing the parameters, the field of view or the
+    vertices rebuilds the pieces."""
     st = sg.Workload("street", sg.scene_street(3, scale=0.05, n_cars=5, n_poles=6),
                      sg.array_ula(2, 4, mode=sg.MODE_PER_TX), sg.Chirp(n_samples=64, n_chirps=8),
                      sg.TraceParams(n_rays=0, max_bounces=2, seed=8, rays_per_tri=4,
                                     tri_omega_max=2e-3, tri_depth_max=6))
-    n_orc = len(orc.pieces(st.scene, st.array, 2e-3, 6)[1])
+    fov = orc.fov_of(st.trace)
+    n_orc = len(orc.pieces(st.scene, st.array, 2e-3, 6, fov)[1])
     assert n_orc > st.scene.n_tris
     _compare(gpu, orc, st)
-    assert gpu.casting_pieces() == n_orc
+    assert gpu.casting_pieces(*fov) == n_orc
     gpu.set_casting(2e-3, 2)
-    assert gpu.casting_pieces() == len(orc.pieces(st.scene, st.array, 2e-3, 2)[1])
+    assert gpu.casting_pieces(*fov) == len(orc.pieces(st.scene, st.array, 2e-3, 2, fov)[1])
     gpu.set_casting(0.0, 8)
-    assert gpu.casting_pieces() == st.scene.n_tris
+    assert gpu.casting_pieces(*fov) == len(orc.pieces(st.scene, st.array, 0.0, 8, fov)[1])
+    # a narrower view drops more pieces; no culling keeps every triangle
+    deg = math.pi / 180
+    narrow = (-20 * deg, 35 * deg, -15 * deg, 10 * deg)
+    assert (gpu.casting_pieces(*narrow) == len(orc.pieces(st.scene, st.array, 0.0, 8, narrow)[1])
+            < len(orc.pieces(st.scene, st.array, 0.0, 8)[1]) == st.scene.n_tris)
     v = np.array([[4.0, -0.2, -0.1], [4.0, 0.3, -0.1], [4.0, 0.0, 0.3],
                   [6.0, -1.0, -1.0], [6.0, 1.5, -0.8], [6.0, -0.2, 1.4]], np.float32)
     sc = sg.Scene(v, np.arange(6, dtype=np.int32).reshape(2, 3), np.zeros(2, np.int32),
@@ -105,7 +112,8 @@ def test_subdivided_pieces(gpu, orc):
     v2 = v - np.array([1.5, 0.0, 0.0], np.float32)
     gpu.update_vertices(v2)
     w2 = sg.Workload("pair2", sg.with_verts(sc, v2), w.array, w.chirp, w.trace)
-    assert gpu.casting_pieces() == len(orc.pieces(w2.scene, w2.array, 5e-3, 5)[1]) != n0
+    assert gpu.casting_pieces() == len(orc.pieces(w2.scene, w2.array, 5e-3, 5,
+                                                  orc.fov_of(w2.trace))[1]) != n0
     n = gpu.trace_workload(w2, record_hits=True)
     oh, op = orc.trace(w2.scene, w2.array, w2.trace)
     assert np.array_equal(gpu.hits().cpu().numpy(), oh[traced_rows(orc, w2.scene, w2.array,

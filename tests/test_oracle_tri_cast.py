@@ -206,3 +206,48 @@ def test_subdivided_launch_keeps_the_estimate():
     _, paths = oracle.trace(pl, ar, tp)
     assert abs(paths["amp"].sum() / want - 1) < 0.01
     assert np.allclose(paths["p"][:, 0, 0], R, atol=1e-12)
+
+
+# ------------------------------------------------------------ field of view
+def test_pieces_outside_the_view_are_dropped():
+    """Triangles behind the array, or beyond an azimuth or elevation bound,
+    take no ray indices; the launch's sum of weights is unchanged (p0 times
+    the solid angle of what is in view); a triangle that straddles a bound
+    is kept, and so is one that only another source of a per-element launch
+    sees."""
+    front = [[6.0, -1.0, -1.0], [6.0, 1.5, -0.8], [6.0, -0.2, 1.4]]
+    behind = [[-5.0, -1.0, -1.0], [-5.0, 1.0, -1.0], [-5.0, 0.0, 1.0]]
+    straddle = [[-0.5, 3.0, 0.0], [2.0, 3.0, 0.0], [1.0, 3.0, 1.0]]
+    sc = _scene(front + behind + straddle)
+    tris = sc.verts.astype(np.float64).reshape(3, 3, 3)
+    fov = (-math.pi / 2, math.pi / 2, -math.pi / 2, math.pi / 2)
+    v, par = oracle.pieces(sc, _mono(), 0.0, 8, fov)
+    assert par.tolist() == [0, 2]
+    assert len(oracle.pieces(sc, _mono(), 0.0, 8)[1]) == 3      # no culling asked
+    hits, paths = oracle.trace(sc, _mono(), _tp(32, b=1))
+    assert hits.shape[0] == 2 * 32 * 32
+    # the straddling triangle's rays behind the array are not traced; the
+    # front one returns its full solid angle (specular, normal incidence)
+    front_amp = paths["amp"][paths["ray"] < 32 * 32].sum()
+    assert abs(front_amp / (_solid_angle(tris[0], np.zeros(3)) / (2 * math.pi)) - 1) < 1e-3
+    # elevation: a floor far below a +-10 degree band is dropped, and so is a
+    # triangle beyond the azimuth bound of a narrow wedge
+    deg = math.pi / 180
+    floor = [[3.0, -1.0, -4.0], [6.0, 1.0, -4.0], [6.0, -1.0, -4.0]]
+    side = [[3.0, 4.0, 0.0], [3.0, 5.0, 0.2], [4.0, 4.5, -0.2]]
+    sc2 = _scene(front + floor + side)
+    band = (-30 * deg, 30 * deg, -10 * deg, 10 * deg)
+    assert oracle.pieces(sc2, _mono(), 0.0, 8, band)[1].tolist() == [0]
+    # el_min > 0: the region below it is not convex, so the floor is kept
+    # (conservative); the side triangle is still beyond the azimuth bound
+    up = (-30 * deg, 30 * deg, 20 * deg, 60 * deg)
+    assert oracle.pieces(sc2, _mono(), 0.0, 8, up)[1].tolist() == [0, 1]
+    # per-element sources: seen at positive azimuth only from the Tx at y = -1
+    tri = [[5.0, -0.6, -0.1], [5.0, -0.4, -0.1], [5.0, -0.5, 0.2]]
+    sc3 = _scene(tri)
+    tx = np.array([[0.0, 1.0, 0.0], [0.0, -1.0, 0.0]])
+    right = (0.0, math.pi / 2, -math.pi / 2, math.pi / 2)
+    per_el = sg.Array(tx, np.zeros((1, 3)), 1e3, sg.MODE_PER_TX)
+    shared = sg.Array(tx, np.zeros((1, 3)), 1e3, sg.MODE_SHARED)
+    assert oracle.pieces(sc3, per_el, 0.0, 8, right)[1].tolist() == [0]
+    assert oracle.pieces(sc3, shared, 0.0, 8, right)[1].tolist() == []
