@@ -14,14 +14,15 @@
 // Both legs are reduced in FP64 per (chirp, element, path) to 32-bit
 // fixed-point turns: beta = frac(f0 d / c), gamma = frac(B d / (K c)), so the
 // phase at sample k is beta + k gamma modulo 2^32, exact in integer
-// arithmetic.  A workgroup of three wavefronts computes a 96 x 96 (Tx x Rx)
-// output tile of one (chirp, sample) over one split of the paths, 16 paths per
-// step: each wavefront generates its own 32 rows of X straight into A-operand
-// registers, the three together generate the 16 x 96 Y tile into LDS (double
-// buffered), and each wavefront issues 36 v_mfma_f32_32x32x16_bf16 per step.
-// Operands are split bf16 hi + lo, products hi*hi + hi*lo + lo*hi, FP32
-// accumulation (as the separable GEMM).  Several path splits write partial
-// tiles that a second kernel adds in split order (deterministic).
+// arithmetic.  A workgroup of four wavefronts computes a 96 x 96 (Tx x Rx)
+// output tile of four consecutive samples of one chirp over one split of the
+// paths, 16 paths per step, one sample per wavefront: the four share the
+// step's table words (loaded once per workgroup, passed through LDS), and
+// each wavefront generates its own X and Y fragments straight into operand
+// registers and issues 108 v_mfma_f32_32x32x16_bf16 per step.  Operands are
+// split bf16 hi + lo, products hi*hi + hi*lo + lo*hi, FP32 accumulation (as
+// the separable GEMM).  Several path splits write partial tiles that a second
+// kernel adds in split order (deterministic).
 #include "rr_internal.h"
 
 namespace {
