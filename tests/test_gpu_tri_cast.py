@@ -122,6 +122,21 @@ def test_subdivided_pieces(gpu, orc):
     assert_paths_equal(gpu_soa_np(gpu), oracle_to_soa(op))
 
 
+def test_nothing_in_view(gpu, orc):
+    """A field of view that holds no triangle: every piece is dropped, the
+    launch traces nothing and returns no path, on both sides."""
+    v = np.array([[4.0, -0.2, -0.1], [4.0, 0.3, -0.1], [4.0, 0.0, 0.3]], np.float32)
+    sc = sg.Scene(v, np.arange(3, dtype=np.int32).reshape(1, 3), np.zeros(1, np.int32),
+                  np.array([0.5], np.float32), np.zeros((1, 3))).checked()
+    o = np.zeros((1, 3))
+    w = sg.Workload("aside", sc, sg.Array(o, o.copy(), 1e3, sg.MODE_PER_TX), sg.Chirp(),
+                    sg.TraceParams(n_rays=0, max_bounces=2, seed=1, az_min=-1.2, az_max=-0.6,
+                                   rays_per_tri=16, tri_omega_max=1e-3, tri_depth_max=4))
+    n, hits, _ = _compare(gpu, orc, w)
+    assert n == 0 and hits.shape == (0, 3)
+    assert gpu.casting_pieces(*orc.fov_of(w.trace)) == 0
+
+
 def test_invalid_grids(gpu):
     import paper_2307_15412_amd as rr
     w = sg.workload_tiny()
