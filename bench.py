@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle rel-err check")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (hardware-counter calibration)")
+    ap.add_argument("--mfma-calibration", action="store_true",
+                    help="only time vendor-library bf16 and fp32 GEMMs (reachable matrix peak)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--workload", choices=["large_mimo", "batch", "proposal", "hand", "alpha_sweep",
                                            "tri_cast", "hand_motion"],
@@ -421,6 +423,46 @@ def run_hand_motion(args):
                                   f"frame{n_frames // 2}": d[2]}}))
 
 
+def mfma_calibration():
+    """The matrix peak reachable on this GPU, measured with the vendor BLAS:
+    square bf16 GEMMs (FP32 accumulation) of 8192 and 16384 and a device copy
+    of 1 GiB, timed with events after a warm-up; the published dense peaks
+    (2.5 PFLOP/s bf16, 8 TB/s) are what the bench's roofline divides by."""
+    import torch
+    out = {}
+    for n in (8192, 16384):
+        a = torch.randn(n, n, dtype=torch.bfloat16, device="cuda:0")
+        b = torch.randn(n, n, dtype=torch.bfloat16, device="cuda:0")
+        c = torch.empty(n, n, dtype=torch.bfloat16, device="cuda:0")
+        for _ in range(3):
+            torch.matmul(a, b, out=c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20 if n == 8192 else 5
+        e0.record()
+        for _ in range(reps):
+            torch.matmul(a, b, out=c)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"bf16_gemm_{n}"] = {"ms": ms, "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
+        del a, b, c
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    out["copy_1gib"] = {"ms": ms, "gb_per_s": 2.0 * (1 << 30) / (ms * 1e-3) / 1e9}
+    print(json.dumps(out))
+
+
 def copy_calibration():
     """A plain device-to-device copy of exactly 1 GiB, five times: the
     FETCH_SIZE / WRITE_SIZE counters of this kernel calibrate the byte counts
@@ -467,6 +509,9 @@ def cpu_model():
 
 def main():
     args = parse()
+    if args.mfma_calibration:
+        mfma_calibration()
+        return
     if args.copy_calibration:
         copy_calibration()
         return
