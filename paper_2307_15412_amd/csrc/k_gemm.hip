@@ -389,12 +389,12 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
 #ifndef GM_FREE_SCHED
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
 #pragma unroll
-        for (int g = 0; g < 4 * GM_NCB; g++) {
-            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // 6 VALU
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // 1 LDS write
+        for (int g = 0; g < 16; g++) {
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // 3 VALU
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // up to 1 LDS write
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, 23 - 4 * GM_NCB, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 23 - 16, 0);
 #endif
         __builtin_amdgcn_sched_barrier(0);
         r0 = load_a(nx, 0);
