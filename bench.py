@@ -123,7 +123,7 @@ def run_proposal(args):
     for ref_rays in (100_000, 1_000_000):
         res = proposal.experiment(ctx, train_seeds=range(1, 201), eval_seeds=range(1001, 1051),
                                   train_rays=50_000, budget=12_500, ref_rays=ref_rays, steps=600,
-                                  batch=16, lr=2e-3, log=log)
+                                  batch=16, lr=2e-3, power=0.5, alt_power=1.0, log=log)
         log(f"reference {ref_rays}: done")
         out[f"ref_{ref_rays}"] = {k: v for k, v in res.items() if k != "per_scene"}
     # equal cube error on the 3072-channel array: learned launch + GEMM

@@ -361,9 +361,15 @@ int rr_proposal_train(rr_ctx *ctx, const float *codes_dev, const float *hist_dev
                       int32_t steps, int32_t batch, float lr, uint64_t seed, float *loss_out);
 
 /* Build the sampling table of one scene from the network: q = (1 - beta)
- * softmax(z) + beta / n_bins, CDF in FP64.  code16_dev: that scene's code
- * (device).  Afterwards rr_trace with sampler RR_PROPOSAL draws from it. */
-int rr_proposal_build(rr_ctx *ctx, const float *code16_dev, float beta);
+ * softmax(power z) + beta / n_bins, CDF in FP64.  The network is trained
+ * towards the returned power per bin; power = 1 samples proportionally to it,
+ * power = 1/2 proportionally to its square root, the density of least cube
+ * variance for a given number of rays when every return carries the same
+ * weight (importance sampling: q proportional to the root second moment of
+ * a bin).  code16_dev: that scene's code (device).  Afterwards rr_trace with
+ * sampler RR_PROPOSAL draws from it.  Errors: RR_ESTATE (no network),
+ * RR_EINVAL (beta outside [0, 1], power outside (0, 2]). */
+int rr_proposal_build(rr_ctx *ctx, const float *code16_dev, float beta, float power);
 
 /* ------------------------------------------------------------------------
  * Batched launch: many scenes of uneven size (triangles, rays, channels,

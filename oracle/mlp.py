@@ -117,8 +117,10 @@ def adam_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return params - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def mixture(z, beta):
-    return (1.0 - beta) * softmax(z) + beta / len(z)
+def mixture(z, beta, power=1.0):
+    """(1 - beta) softmax(power z) + beta / n: the sampling density of a
+    network output z (power < 1 flattens the fitted density)."""
+    return (1.0 - beta) * softmax(power * np.asarray(z, dtype=np.float64)) + beta / len(z)
 
 
 def cdf_of(q):

@@ -403,7 +403,7 @@ def _declare_proposal(L):
     L.rr_mlp_forward.argtypes = [vp, vp, i32, vp]
     L.rr_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp]
     L.rr_proposal_train.argtypes = [vp, vp, vp, i32, i32, i32, C.c_float, C.c_uint64, vp]
-    L.rr_proposal_build.argtypes = [vp, vp, C.c_float]
+    L.rr_proposal_build.argtypes = [vp, vp, C.c_float, C.c_float]
     _PROP_DECLARED = True
 
 
@@ -487,9 +487,9 @@ class _ProposalMixin:
                                                   int(seed) & (2**64 - 1), loss.ctypes.data))
         return loss[: int(steps)]
 
-    def proposal_build(self, code, beta=0.1):
+    def proposal_build(self, code, beta=0.1, power=0.5):
         code = code.to(self.device, self.torch.float32).contiguous().reshape(16)
-        self._check(self._pl().rr_proposal_build(self.h, _ptr(code), float(beta)))
+        self._check(self._pl().rr_proposal_build(self.h, _ptr(code), float(beta), float(power)))
         self._keep_code = code
 
 

@@ -267,9 +267,11 @@ __global__ void k_adam(float *P, const float *G, float *m, float *v, int n, floa
     P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// sampling table for one scene: q_mix = (1 - beta) softmax(z) + beta / NBINS,
-// cdf[0] = 0, cdf[b + 1] = cdf[b] + q_mix[b] (FP64, block scan), normalised
-__global__ __launch_bounds__(1024) void k_build_cdf(const float *z, float beta, double *cdf)
+// sampling table for one scene: q_mix = (1 - beta) softmax(power z) + beta /
+// NBINS, cdf[0] = 0, cdf[b + 1] = cdf[b] + q_mix[b] (FP64, block scan),
+// normalised
+__global__ __launch_bounds__(1024) void k_build_cdf(const float *z, float beta, float power,
+                                                    double *cdf)
 {
     __shared__ double red[1024];
     __shared__ float fred[1024];
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(1024) void k_build_cdf(const float *z, float beta, 
     double e[8];
     double s = 0.0;
     for (int k = 0; k < 8; k++) {
-        e[k] = exp((double)z[t * 8 + k] - (double)mx);
+        e[k] = exp((double)power * ((double)z[t * 8 + k] - (double)mx));
         s += e[k];
     }
     red[t] = s;
@@ -374,8 +376,8 @@ hipError_t launch_adam(float *P, const float *G, float *m, float *v, float lr, i
     return hipGetLastError();
 }
 
-hipError_t launch_build_cdf(const float *z, float beta, double *cdf, hipStream_t s)
+hipError_t launch_build_cdf(const float *z, float beta, float power, double *cdf, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_build_cdf, dim3(1), dim3(1024), 0, s, z, beta, cdf);
+    hipLaunchKernelGGL(k_build_cdf, dim3(1), dim3(1024), 0, s, z, beta, power, cdf);
     return hipGetLastError();
 }

@@ -47,9 +47,11 @@ def _cube(ctx):
     return ctx.synthesize(model=B.EXACT, engine=B.DIRECT_FP32).reshape(-1)
 
 
-def evaluate(ctx, workloads, budget, ref_rays, beta=0.1):
+def evaluate(ctx, workloads, budget, ref_rays, beta=0.1, power=0.5, alt_power=None):
     """Per held-out scene: relative cube error of uniform and learned launches
-    of `budget` rays against a `ref_rays` uniform cube, and their trace times."""
+    of `budget` rays against a `ref_rays` uniform cube, and their trace times;
+    the learned table with softmax power `power` (and, for comparison, with
+    `alt_power`)."""
     out = []
     for w in workloads:
         ctx.setup(w)
@@ -63,7 +65,13 @@ def evaluate(ctx, workloads, budget, ref_rays, beta=0.1):
         t_u = ctx.kernel_ms(0)
         eu = float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30)
         code = ctx.proposal_probe(tp.az_min, tp.az_max)
-        ctx.proposal_build(code, beta)
+        alt = {}
+        if alt_power is not None:
+            ctx.proposal_build(code, beta, alt_power)
+            p_a = ctx.trace(budget, seed=tp.seed, sampler=B.PROPOSAL, **kw)
+            alt = dict(err_learned_alt=float((_cube(ctx) - ref).abs().pow(2).sum().sqrt())
+                       / max(nref, 1e-30), paths_learned_alt=p_a)
+        ctx.proposal_build(code, beta, power)
         p_l = ctx.trace(budget, seed=tp.seed, sampler=B.PROPOSAL, **kw)
         t_l = ctx.kernel_ms(0)
         el = float((_cube(ctx) - ref).abs().pow(2).sum().sqrt()) / max(nref, 1e-30)
@@ -74,7 +82,7 @@ def evaluate(ctx, workloads, budget, ref_rays, beta=0.1):
         n_in = ctx.casting_pieces(*fov)
         g = int(math.isqrt(budget // max(n_in, 1)))
         rec = dict(seed=tp.seed, err_uniform=eu, err_learned=el, ms_uniform=t_u, ms_learned=t_l,
-                   paths_uniform=p_u, paths_learned=p_l)
+                   paths_uniform=p_u, paths_learned=p_l, **alt)
         if g >= 1:
             p_t = ctx.trace(g * g, seed=tp.seed, sampler=B.PER_TRIANGLE, **kw)
             # an empty cube scores exactly 1: read it with paths_tri
@@ -114,7 +122,7 @@ def _loglog(xs, ys, y):
 
 def equal_error(ctx, eval_seeds, budget=12_500, uniform_budgets=(12_500, 25_000, 50_000, 100_000,
                                                                    200_000),
-                ref_rays=1_000_000, beta=0.1, log=None):
+                ref_rays=1_000_000, beta=0.1, power=0.5, log=None):
     """Wall time at equal cube error on the large-MIMO array (3072 channels,
     512 samples x 256 chirps) over box-family scenes, with the network as
     trained in `ctx`.
@@ -146,7 +154,7 @@ def equal_error(ctx, eval_seeds, budget=12_500, uniform_budgets=(12_500, 25_000,
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         code = ctx.proposal_probe(tp.az_min, tp.az_max)
-        ctx.proposal_build(code, beta)
+        ctx.proposal_build(code, beta, power)
         n_l = ctx.trace(budget, seed=tp.seed, sampler=B.PROPOSAL, **kw)
         ctx.synthesize(model=B.SEPARABLE, engine=B.GEMM_BF16X3, out=work)
         torch.cuda.synchronize()
@@ -202,7 +210,7 @@ def _loglog_time(xs, ts, x):
 
 
 def experiment(ctx, train_seeds, eval_seeds, train_rays=50_000, budget=12_500, ref_rays=100_000,
-               steps=300, batch=16, lr=1e-3, beta=0.1, log=None):
+               steps=300, batch=16, lr=1e-3, beta=0.1, power=0.5, alt_power=None, log=None):
     import scenegen as sg
     t0 = time.time()
     tw = [sg.workload_box_family(s, train_rays, points=False) for s in train_seeds]
@@ -213,7 +221,7 @@ def experiment(ctx, train_seeds, eval_seeds, train_rays=50_000, budget=12_500, r
     losses = train(ctx, codes, hists, steps=steps, batch=batch, lr=lr, log=log)
     t2 = time.time()
     ew = [sg.workload_box_family(s, budget, points=False) for s in eval_seeds]
-    res = evaluate(ctx, ew, budget, ref_rays, beta)
+    res = evaluate(ctx, ew, budget, ref_rays, beta, power, alt_power)
     if log:
         log(f"evaluated {len(res)} held-out scenes in {time.time() - t2:.1f} s")
     eu = np.array([r["err_uniform"] for r in res])
@@ -235,6 +243,11 @@ def experiment(ctx, train_seeds, eval_seeds, train_rays=50_000, budget=12_500, r
                    wins_cut=int((ec < eu).sum()),
                    rays_cut_mean=float(np.mean([r["rays_cut"] for r in res])),
                    paths_cut_mean=float(np.mean([r["paths_cut"] for r in res])))
+    if alt_power is not None:
+        ea = np.array([r["err_learned_alt"] for r in res])
+        out.update(alt_power=alt_power, err_learned_alt_mean=float(ea.mean()),
+                   err_ratio_alt_mean=float(np.mean(ea / eu)), wins_alt=int((ea < eu).sum()),
+                   paths_learned_alt_mean=float(np.mean([r["paths_learned_alt"] for r in res])))
     out.update(paths_uniform_mean=float(np.mean([r["paths_uniform"] for r in res])),
                paths_learned_mean=float(np.mean([r["paths_learned"] for r in res])))
     return out

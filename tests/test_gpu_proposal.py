@@ -122,12 +122,17 @@ def test_sampling_table(gpu):
     gpu.mlp_init(9)
     p = gpu.mlp_get_params()
     code = np.random.default_rng(1).random(16).astype(np.float32) * 0.3
-    gpu.proposal_build(torch.from_numpy(code).cuda(), 0.1)
-    cdf = gpu.proposal_get_cdf()
     zr, _ = mlp.forward(_f16(p), mlp.features(_f16(code[None, :])))
-    ref = mlp.cdf_of(mlp.mixture(zr, 0.1))
-    assert cdf[0] == 0.0 and cdf[-1] == 1.0 and np.all(np.diff(cdf) >= 0)
-    assert np.abs(cdf - ref).max() < 2e-4
+    for power in (1.0, 0.5):
+        gpu.proposal_build(torch.from_numpy(code).cuda(), 0.1, power)
+        cdf = gpu.proposal_get_cdf()
+        ref = mlp.cdf_of(mlp.mixture(zr, 0.1, power))
+        assert cdf[0] == 0.0 and cdf[-1] == 1.0 and np.all(np.diff(cdf) >= 0)
+        assert np.abs(cdf - ref).max() < 2e-4
+    # power 1/2 is the square root of the power-1 density, renormalised
+    q1 = np.diff(mlp.cdf_of(mlp.mixture(zr, 0.0, 1.0)))
+    qh = np.diff(mlp.cdf_of(mlp.mixture(zr, 0.0, 0.5)))
+    assert np.allclose(qh, np.sqrt(q1) / np.sqrt(q1).sum(), rtol=1e-9, atol=0)
 
 
 def _splitmix_batches(seed, n, batch, steps):
