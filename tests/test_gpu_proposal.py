@@ -133,6 +133,11 @@ def test_sampling_table(gpu):
     q1 = np.diff(mlp.cdf_of(mlp.mixture(zr, 0.0, 1.0)))
     qh = np.diff(mlp.cdf_of(mlp.mixture(zr, 0.0, 0.5)))
     assert np.allclose(qh, np.sqrt(q1) / np.sqrt(q1).sum(), rtol=1e-9, atol=0)
+    import paper_2307_15412_amd as rr
+    for beta, power in ((0.1, 0.0), (0.1, 2.5), (0.1, float("nan")), (1.5, 0.5)):
+        with pytest.raises(rr.RadrayError) as e:
+            gpu.proposal_build(torch.from_numpy(code).cuda(), beta, power)
+        assert e.value.code == rr.binding.RR_EINVAL
 
 
 def _splitmix_batches(seed, n, batch, steps):
