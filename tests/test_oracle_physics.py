@@ -296,3 +296,208 @@ def test_proposal_launch_unbiased(orc):
     # weights are 1 / (nb q_b) of the sampled bin
     w = paths["amp"] * N
     assert np.all(w > 0) and w.max() < 1.0
+
+
+# ------------------------------------------------- multi-bounce path lengths
+
+_CORNER = np.array([6.0, -1.5, -1.0])   # trihedral corner; FP32-exact coordinates
+_SIDE = 3.0
+
+
+def _corner_scene(vel=((0.0, 0.0, 0.0),) * 3, alpha=0.0):
+    """Three mutually perpendicular square plates meeting at _CORNER, opening
+    towards the radar at the origin side: plate 0 in the plane x = 6, plate 1
+    in y = -1.5, plate 2 in z = -1 (one object each, so that each may move
+    with its own velocity).  Plate i's triangles are 2 i and 2 i + 1."""
+    mb = sg._MeshBuilder()
+    X, Y, Z = _CORNER
+    a = _SIDE
+    mb.grid_quad((X, Y, Z), (0, a, 0), (0, 0, a), 1, 1, 0)
+    mb.grid_quad((X - a, Y, Z), (a, 0, 0), (0, 0, a), 1, 1, 1)
+    mb.grid_quad((X - a, Y, Z), (a, 0, 0), (0, a, 0), 1, 1, 2)
+    return mb.build([alpha] * 3, list(vel))
+
+
+def _mirror(pt, plate):
+    """Mirror image of a point through the plane of plate 0, 1 or 2."""
+    q = np.array(pt, float).copy()
+    q[plate] = 2.0 * _CORNER[plate] - q[plate]
+    return q
+
+
+def _corner_paths(orc, n_rays=600_000, seed=1, vel=((0.0, 0.0, 0.0),) * 3):
+    S = [0.0, 0.0, 0.5]
+    rx = [[0.0, -0.05, 0.5], [0.0, 0.0, 0.45], [0.0, 0.07, 0.52]]
+    ar = _array(S, rx, radius=0.5)
+    sc = _corner_scene(vel)
+    _, paths = orc.trace(sc, ar, _tp(n_rays, bounces=3, seed=seed))
+    return sc, ar, paths
+
+
+def test_multibounce_lengths_method_of_images(orc):
+    """Specular (alpha = 0) trihedral: a path that reflects off the planes of
+    hits 1 .. K-1 travels, from the source to its last hit p_K, exactly the
+    straight distance from the source's image through those planes (taken in
+    hit order) to p_K (method of images).  So every K = 1, 2, 3 path's length
+    L = |p_K - S_(K-1)|, every hit lies on its plate's plane, and the cube of a
+    single path is a exp(-j 2 pi f_k (|p_K - S_(K-1)| + |rx - p_K|) / c) for every
+    receiver: this fixes the multi-bounce inner length of Eq. 4's path length
+    without reference to the oracle's own sum over hit points."""
+    sc, ar, paths = _corner_paths(orc)
+    Ks = np.bincount(paths["K"], minlength=4)
+    assert Ks[2] > 200 and Ks[3] > 100, Ks
+    S = ar.tx[0]
+    ch = sg.Chirp(n_samples=8, n_chirps=1)
+    fk = ch.f0 + ch.bandwidth * np.arange(8) / 8
+    for p in paths:
+        K = int(p["K"])
+        plates = [int(p["tri"][j]) // 2 for j in range(K)]
+        img = np.array(S, float)
+        for j in range(K):
+            assert abs(p["p"][j][plates[j]] - _CORNER[plates[j]]) < 1e-12
+            if j < K - 1:
+                img = _mirror(img, plates[j])
+        pK = p["p"][K - 1]
+        Lref = np.linalg.norm(pK - img)
+        assert abs(p["L"] - Lref) < 1e-12 * Lref, (K, p["L"], Lref)
+    # synthesis of single paths, every receiver (K >= 2 only: the inner sum)
+    for p in paths[paths["K"] >= 2][::7]:
+        K = int(p["K"])
+        img = np.array(S, float)
+        for j in range(K - 1):
+            img = _mirror(img, int(p["tri"][j]) // 2)
+        pK = p["p"][K - 1]
+        d = np.linalg.norm(pK - img) + np.linalg.norm(ar.rx - pK, axis=1)
+        ref = p["amp"] * np.exp(-2j * np.pi * fk[None, :] * d[:, None] / C0)
+        cube = orc.synth(p[None], sc, ar, ch)[:, 0, :]
+        assert np.abs(cube - ref).max() < 1e-9 * p["amp"], (K, np.abs(cube - ref).max())
+
+
+def test_triple_bounce_retroreflects(orc):
+    """Three perpendicular mirrors send a ray back antiparallel: a K = 3 path
+    that meets all three plates leaves its last hit along -d0 (d0 = its launch
+    direction), and its image source is the source inverted through the
+    corner.  Checks the K = 3 geometry of Eq. 2 applied three times."""
+    sc, ar, paths = _corner_paths(orc, n_rays=300_000)
+    S = ar.tx[0]
+    p3 = paths[(paths["K"] == 3)]
+    n_all = 0
+    for p in p3:
+        plates = sorted(int(t) // 2 for t in p["tri"][:3])
+        if plates != [0, 1, 2]:
+            continue
+        n_all += 1
+        d0 = (p["p"][0] - S) / np.linalg.norm(p["p"][0] - S)
+        img = 2.0 * _CORNER - S
+        # the last segment continues the line from the triple image through p3
+        u = (p["p"][2] - img) / np.linalg.norm(p["p"][2] - img)
+        assert np.abs(u + d0).max() < 1e-12 or np.abs(u - (-d0)).max() < 1e-12
+        assert abs(p["L"] - np.linalg.norm(p["p"][2] - img)) < 1e-12 * p["L"]
+    assert n_all > 50
+
+
+def test_motion_galilean_shift(orc):
+    """Every object (plates and a point reflector) moving with one velocity v:
+    in the exact model, the cube at chirp m equals the chirp-0 cube of the
+    static scene with every Tx and Rx moved by -v m T_rep (only relative
+    positions enter a path length).  Covers the motion of the first, inner and
+    last hit points of K = 1, 2, 3 paths."""
+    v = (2.5, -1.25, 0.75)
+    sc, ar, paths = _corner_paths(orc, n_rays=200_000, vel=(v,) * 3)
+    assert (paths["K"] >= 2).sum() > 50
+    sc.pt_pos = np.array([[4.0, 1.0, 0.3]])
+    sc.pt_vel = np.array([v])
+    sc.pt_aperture = np.array([0.02])
+    _, ppt = orc.trace(sc, ar, _tp(10))
+    pts = ppt[ppt["tri"][:, 0] == -1]
+    assert len(pts) == 1
+    allp = np.concatenate([paths, pts])
+    ch = sg.Chirp(n_samples=16, n_chirps=6)
+    moving = orc.synth(allp, sc, ar, ch, model=0)
+    static = sg.Scene(sc.verts, sc.tris, sc.tri_obj, sc.obj_alpha, np.zeros((3, 3)),
+                      sc.pt_pos, np.zeros((1, 3)), sc.pt_aperture).checked()
+    ch1 = sg.Chirp(n_samples=16, n_chirps=1)
+    for m in range(6):
+        sh = -np.array(v) * m * ch.t_rep
+        ar_m = _array(ar.tx + sh, ar.rx + sh, radius=ar.rx_radius)
+        ref = orc.synth(allp, static, ar_m, ch1, model=0)[:, 0, :]
+        err = np.abs(moving[:, m, :] - ref).max() / np.abs(ref).max()
+        assert err < 1e-9, (m, err)
+    # and the motion is really there: chirp 5 differs from chirp 0
+    assert np.abs(moving[:, 5, :] - moving[:, 0, :]).max() > 0.1 * np.abs(moving).max()
+
+
+def test_motion_per_object_hit_points(orc):
+    """Each plate moving with its own velocity (reading R17: a hit point moves
+    with the object it lies on, the path's topology is frozen at chirp 0): the
+    cube at chirp m equals the chirp-0 cube of a static scene whose path
+    records have every hit point p_j advanced by v_obj(j) m T_rep.  The inner
+    segments of K = 2, 3 paths then change length, so a hit point that is not
+    moved, or moved with another hit's object, fails."""
+    vel = ((3.0, 0.5, -0.25), (-1.0, 2.0, 0.5), (0.25, -0.75, 1.5))
+    sc, ar, paths = _corner_paths(orc, n_rays=200_000, vel=vel)
+    multi = paths[paths["K"] >= 2]
+    mixed = [len({int(t) // 2 for t in p["tri"][:p["K"]]}) > 1 for p in multi]
+    assert sum(mixed) > 50
+    ch = sg.Chirp(n_samples=16, n_chirps=5)
+    moving = orc.synth(paths, sc, ar, ch, model=0)
+    static = sg.Scene(sc.verts, sc.tris, sc.tri_obj, sc.obj_alpha, np.zeros((3, 3))).checked()
+    ch1 = sg.Chirp(n_samples=16, n_chirps=1)
+    V = np.array(vel)
+    for m in range(5):
+        tau = m * ch.t_rep
+        q = paths.copy()
+        for j in range(3):
+            live = q["K"] > j
+            q["p"][live, j, :] += V[q["vid"][live, j]] * tau
+        ref = orc.synth(q, static, ar, ch1, model=0)[:, 0, :]
+        err = np.abs(moving[:, m, :] - ref).max() / np.abs(ref).max()
+        assert err < 1e-9, (m, err)
+    # a frozen inner point would change the answer: check the relation is sharp
+    tau = 4 * ch.t_rep
+    q = paths.copy()
+    for j in (0,):
+        q["p"][:, j, :] += V[q["vid"][:, j]] * tau
+    last = q["K"] - 1
+    sel = last > 0
+    q["p"][sel, last[sel], :] += V[q["vid"][sel, last[sel]]] * tau
+    wrong = orc.synth(q, static, ar, ch1, model=0)[:, 0, :]
+    three = q["K"] == 3
+    assert three.sum() > 0
+    assert np.abs(moving[:, 4, :] - wrong).max() > 1e-3 * np.abs(wrong).max()
+
+
+# ------------------------------------------------------- proposal scene code
+
+def test_probe_code_closed_form(orc):
+    """Scene code of the learned proposal: 16 azimuth sectors of 8 rays at
+    elevation 0 from the Tx phase centre, ray i of sector s at azimuth
+    az_min + (8 s + i + 1/2) / 128 (az_max - az_min); each ray scores
+    exp(-t / 10 m) if its closest hit belongs to an object other than object 0,
+    else 0.  Object 0 here is a wall covering the left half (y > 0) in front of
+    a plate of object 1 at x = R, so rays that meet the wall score 0 and the
+    others that meet the plate score exp(-R' / (10 cos az)), R' = R - x_radar."""
+    R, R0, W = 12.0, 6.0, 30.0
+    mb = sg._MeshBuilder()
+    mb.grid_quad((R0, 0.0, -5.0), (0.0, W, 0.0), (0.0, 0.0, 10.0), 1, 1, 0)
+    mb.grid_quad((R, -W, -5.0), (0.0, 2 * W, 0.0), (0.0, 0.0, 10.0), 1, 1, 1)
+    sc = mb.build([0.5, 0.5], [[0, 0, 0], [0, 0, 0]])
+    o = np.array([0.5, 0.25, 0.5])
+    ar = _array([o - [0, 0.01, 0], o + [0, 0.01, 0]], [o, o], mode=sg.MODE_SHARED)
+    for az_lo, az_hi in ((-math.pi / 2, math.pi / 2), (-1.0, 0.6)):
+        tp = sg.TraceParams(n_rays=10, max_bounces=1, seed=0, az_min=az_lo, az_max=az_hi)
+        code = orc.probe_code(sc, ar, tp)
+        ref = np.zeros(16)
+        for s in range(16):
+            acc = 0.0
+            for i in range(8):
+                az = az_lo + (8 * s + i + 0.5) / 128 * (az_hi - az_lo)
+                y0 = o[1] + (R0 - o[0]) * math.tan(az)
+                if 0.0 <= y0 <= W:
+                    continue                       # object 0 (the wall) is hit first
+                y = o[1] + (R - o[0]) * math.tan(az)
+                if -W <= y <= W:
+                    acc += math.exp(-(R - o[0]) / (10.0 * math.cos(az)))
+            ref[s] = acc / 8
+        assert np.abs(code - ref).max() < 1e-12, (az_lo, np.abs(code - ref).max())
+        assert (code > 0).any() and (code == 0).any()
