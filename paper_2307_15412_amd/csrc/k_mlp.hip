@@ -195,15 +195,22 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const float *P, const float *dz
 }
 
 // weight gradients as outer-product reductions over rows:
-//   G[a][c] += sum_r D[r][a] V[r][c],  Gb[a] += sum_r D[r][a]
+//   G[a][c] = sum_r D[r][a] V[r][c],  Gb[a] = sum_r D[r][a]
 // V is either the FP16 activation (mode 0, width 64) or the layer-1 input
 // (mode 1, width 18, rebuilt from the bin and the scene code).
+// Block b sums its own rows in row order and writes its partial sums to row b
+// of the partial table (stride NPARAMS, at the layer's parameter offsets);
+// k_wgrad_sum then adds the rows of that table in block order, so the
+// gradient is the same bits on every run.
 // 256 threads: thread t owns output row a = t / 4, 16 columns from (t % 4) * 16.
 #define WG_ROWS 64
 __global__ __launch_bounds__(256) void k_wgrad(const float *D, int da, const __half *V,
                                                const float *codes, int vc, int64_t n,
-                                               int64_t rows_per_block, float *G, float *Gb)
+                                               int64_t rows_per_block, float *part, int off_g,
+                                               int off_b)
 {
+    float *G = part + (int64_t)blockIdx.x * NPARAMS + off_g;
+    float *Gb = part + (int64_t)blockIdx.x * NPARAMS + off_b;
     __shared__ float sD[WG_ROWS][NH + 1];
     __shared__ float sV[WG_ROWS][NH + 1];
     const int t = threadIdx.x;
@@ -248,9 +255,19 @@ __global__ __launch_bounds__(256) void k_wgrad(const float *D, int da, const __h
     if (a < da) {
 #pragma unroll
         for (int k = 0; k < 16; k++)
-            if (c0 + k < vc) atomicAdd(&G[a * vc + c0 + k], acc[k]);
-        if ((t & 3) == 0) atomicAdd(&Gb[a], accb);
+            if (c0 + k < vc) G[a * vc + c0 + k] = acc[k];
+        if ((t & 3) == 0) Gb[a] = accb;
     }
+}
+
+// G[i] = sum over blocks b = 0, 1, ... of part[b][i], in that order
+__global__ __launch_bounds__(256) void k_wgrad_sum(const float *part, int nb, float *G)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAMS) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; b++) s += part[(int64_t)b * NPARAMS + i];
+    G[i] = s;
 }
 
 // Adam (Kingma & Ba): FP32 master parameters and moments
@@ -346,24 +363,27 @@ hipError_t launch_softmax_grad(const float *z, const float *H, int n_scenes, flo
     return hipGetLastError();
 }
 
+int64_t mlp_wgrad_blocks(int64_t n) { return (n + MLP_WGRAD_ROWS - 1) / MLP_WGRAD_ROWS; }
+
 hipError_t launch_mlp_backward(const float *P, const float *dz, int64_t n, const __half *acts,
-                               float *d1, float *d2, float *d3, const float *codes, float *grad,
-                               hipStream_t s)
+                               float *d1, float *d2, float *d3, const float *codes, float *part,
+                               float *grad, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, dz, n, acts,
                        d1, d2, d3);
-    const int64_t rpb = 4096;
-    const unsigned nb = (unsigned)((n + rpb - 1) / rpb);
+    const int64_t rpb = MLP_WGRAD_ROWS;
+    const int nb = (int)mlp_wgrad_blocks(n);
     // layer 4: dz (width 1) x h3; layer 3: d3 x h2; layer 2: d2 x h1; layer 1: d1 x input
     hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, dz, 1, acts + 2 * n * NH, codes, NH, n, rpb,
-                       grad + OFF_W4, grad + OFF_B4);
+                       part, OFF_W4, OFF_B4);
     hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d3, NH, acts + 1 * n * NH, codes, NH, n, rpb,
-                       grad + OFF_W3, grad + OFF_B3);
+                       part, OFF_W3, OFF_B3);
     hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d2, NH, acts + 0 * n * NH, codes, NH, n, rpb,
-                       grad + OFF_W2, grad + OFF_B2);
+                       part, OFF_W2, OFF_B2);
     hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d1, NH, (const __half *)nullptr, codes, NIN,
-                       n, rpb, grad + OFF_W1, grad + OFF_B1);
+                       n, rpb, part, OFF_W1, OFF_B1);
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((NPARAMS + 255) / 256), dim3(256), 0, s, part, nb, grad);
     return hipGetLastError();
 }
 

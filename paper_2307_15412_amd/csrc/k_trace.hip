@@ -589,8 +589,11 @@ __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_probe(TraceArgs A, float *co
 // Training target of the proposal from a uniform trace: per direction bin the
 // sum over its rays of (returned power = number of received paths, since
 // w = 1) + 0.1 x (first segment hit an object other than object 0).
+// Every ray adds a whole number of tenths, so the bins count tenths in 32-bit
+// integers (the sum does not depend on the order of the atomic adds) and
+// k_hist_finish turns the counts into values in place.
 __global__ void k_hist(TraceArgs A, int64_t n_traced, const int32_t *hits, const int32_t *tri_obj,
-                       int n_az, int n_el, float *H)
+                       int n_az, int n_el, unsigned *H)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_traced) return;
@@ -603,9 +606,16 @@ __global__ void k_hist(TraceArgs A, int64_t n_traced, const int32_t *hits, const
     ia = min(ia, n_az - 1);
     ie = min(ie, n_el - 1);
     const int h0 = hits[g * (A.bmax + 1)];
-    const float hit = (h0 >= 0 && tri_obj[h0] != 0) ? 0.1f : 0.0f;
-    const float val = (float)A.counts[v] + hit;
-    if (val != 0.0f) atomicAdd(&H[ie * n_az + ia], val);
+    const unsigned tenths = 10u * (unsigned)A.counts[v] + ((h0 >= 0 && tri_obj[h0] != 0) ? 1u : 0u);
+    if (tenths != 0u) atomicAdd(&H[ie * n_az + ia], tenths);
+}
+
+__global__ void k_hist_finish(float *H, int nb)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const unsigned u = reinterpret_cast<const unsigned *>(H)[b];
+    H[b] = (float)((double)u / 10.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -795,7 +805,9 @@ hipError_t launch_hist(const TraceArgs &a, int64_t n_traced, const int32_t *hits
 {
     if (n_traced <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_hist, dim3((unsigned)((n_traced + 255) / 256)), dim3(256), 0, s, a,
-                       n_traced, hits, tri_obj, n_az, n_el, H);
+                       n_traced, hits, tri_obj, n_az, n_el, reinterpret_cast<unsigned *>(H));
+    hipLaunchKernelGGL(k_hist_finish, dim3((unsigned)((n_az * n_el + 255) / 256)), dim3(256), 0, s, H,
+                       n_az * n_el);
     return hipGetLastError();
 }
 

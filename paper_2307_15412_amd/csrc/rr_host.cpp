@@ -170,7 +170,7 @@ struct rr_ctx {
     TraceArgs last{};          // arguments of the last trace (histogram)
     int64_t last_traced = 0;
     int last_sampler = -1;
-    DevBuf mlp_p, mlp_m, mlp_v, mlp_g, mlp_acts, mlp_z, mlp_dz, mlp_d, mlp_loss;
+    DevBuf mlp_p, mlp_m, mlp_v, mlp_g, mlp_acts, mlp_z, mlp_dz, mlp_d, mlp_loss, mlp_part;
     DevBuf tr_codes, tr_hist, tr_loss;   // minibatch staging of rr_proposal_train
     DevBuf bp_peak;                      // peak of the last maximum projection
     bool mlp_ready = false;
@@ -272,7 +272,7 @@ void rr_destroy(rr_ctx *c)
                       &c->counter, &c->total, &c->err_flag, &c->hits, &c->cdf, &c->syn,
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
-                      &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss,
+                      &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss, &c->mlp_part,
                       &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->pieces_v, &c->pieces_p, &c->tris_dev, &c->verts_dev,
                       &c->refit_order, &c->ubox,
                       &c->fq_pm, &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part, &c->bp_sf};
@@ -1323,6 +1323,7 @@ static int mlp_buffers(rr_ctx *c, int64_t rows, int n_scenes)
     if ((rc = c->mlp_dz.ensure((size_t)rows * 4))) return rc;
     if ((rc = c->mlp_d.ensure((size_t)rows * 3 * 64 * 4))) return rc;
     if ((rc = c->mlp_loss.ensure((size_t)n_scenes * 4 + 4))) return rc;
+    if ((rc = c->mlp_part.ensure((size_t)mlp_wgrad_blocks(rows) * RR_MLP_PARAMS * 4))) return rc;
     return RR_OK;
 }
 
@@ -1351,10 +1352,9 @@ static int mlp_step(rr_ctx *c, const float *codes, const float *hist, int32_t n_
                               c->stream));
     HIPCHK(launch_softmax_grad(c->mlp_z.as<const float>(), hist, n_scenes, c->mlp_dz.as<float>(),
                                c->mlp_loss.as<float>(), c->stream));
-    HIPCHK(hipMemsetAsync(c->mlp_g.p, 0, RR_MLP_PARAMS * 4, c->stream));
     HIPCHK(launch_mlp_backward(c->mlp_p.as<const float>(), c->mlp_dz.as<const float>(), rows, acts,
-                               d, d + rows * 64, d + 2 * rows * 64, codes, c->mlp_g.as<float>(),
-                               c->stream));
+                               d, d + rows * 64, d + 2 * rows * 64, codes, c->mlp_part.as<float>(),
+                               c->mlp_g.as<float>(), c->stream));
     if (grad_out)
         HIPCHK(hipMemcpyAsync(grad_out, c->mlp_g.p, RR_MLP_PARAMS * 4, hipMemcpyDeviceToDevice,
                               c->stream));

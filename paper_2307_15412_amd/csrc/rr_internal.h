@@ -232,9 +232,14 @@ hipError_t launch_mlp_forward(const float *P, const float *codes, int64_t n, __h
                               hipStream_t s);
 hipError_t launch_softmax_grad(const float *z, const float *H, int n_scenes, float *dz, float *loss,
                                hipStream_t s);
+// weight gradients: blocks of MLP_WGRAD_ROWS rows write partial sums into
+// part ([mlp_wgrad_blocks(n)][RR_MLP_PARAMS] floats), then one pass adds them
+// in block order into grad (every entry written)
+#define MLP_WGRAD_ROWS 4096
+int64_t mlp_wgrad_blocks(int64_t n);
 hipError_t launch_mlp_backward(const float *P, const float *dz, int64_t n, const __half *acts,
-                               float *d1, float *d2, float *d3, const float *codes, float *grad,
-                               hipStream_t s);
+                               float *d1, float *d2, float *d3, const float *codes, float *part,
+                               float *grad, hipStream_t s);
 hipError_t launch_adam(float *P, const float *G, float *m, float *v, float lr, int step, hipStream_t s);
 hipError_t launch_build_cdf(const float *z, float beta, float power, double *cdf, hipStream_t s);
 hipError_t launch_batch_trace(const TraceArgs *scenes, const int64_t *chunk_start, int S,
