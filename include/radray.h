@@ -181,11 +181,25 @@ typedef struct {
  * bounce): for source s, its rays 0..N_s-1 then its point reflectors.  With
  * n_paths_out != NULL the stream is synchronised and the number of stored
  * paths written; the internal path buffer grows as needed.  With NULL the
- * call does not synchronise (path count stays on the device; a later
- * rr_get_path_count reports it, and overflow of the current capacity is
- * reported as RR_EOVERFLOW there).  Errors: RR_ESTATE (no scene or array),
- * RR_EINVAL, RR_ENOMEM, RR_EHIP. */
+ * call does not synchronise: the path count stays on the device until a call
+ * that needs it on the host (rr_get_path_count, rr_get_paths, rr_get_hits,
+ * rr_synthesize, rr_proposal_histogram) reads it back with one
+ * synchronisation; if the paths overflowed the current temporary buffer, that
+ * call returns RR_EOVERFLOW, the buffer grows and the trace must be repeated.
+ * Errors: RR_ESTATE (no scene or array), RR_EINVAL, RR_ENOMEM, RR_EHIP,
+ * RR_EUNSUPPORTED (a BVH deeper than the traversal stack; the builder keeps
+ * depth <= 31, so this is not expected). */
 int rr_trace(rr_ctx *ctx, const rr_trace_params *params, int64_t *n_paths_out);
+
+/* rr_trace run by a variant of the tracing kernel that also counts its work
+ * (the same hits and paths bit for bit, somewhat slower): the data behind the
+ * tracer's memory roofline (Sec. IV: the tracer's cost grows with the mesh).
+ * work_out[0] rays traced (point reflectors excluded), [1] closest-hit
+ * queries (segments), [2] BVH nodes fetched (64 B each), [3] leaf triangle
+ * records fetched (48 B each).  n_paths_out is required (the call
+ * synchronises).  Errors as rr_trace. */
+int rr_trace_work(rr_ctx *ctx, const rr_trace_params *params, int64_t *n_paths_out,
+                  int64_t work_out[4]);
 
 /* Pieces of the RR_PER_TRIANGLE launch (Sec. III casts rays towards every
  * triangle; a coarse mesh with a large near triangle gets its rays spread by
@@ -465,8 +479,10 @@ int rr_max_projection(rr_ctx *ctx, const void *image_dev, const rr_volume *vol, 
 
 /* Kernel timing of the last rr_trace / rr_synthesize / rr_backproject call,
  * in milliseconds, measured with HIP events on the context stream
- * (synchronises).  which: 0 = trace (all trace kernels), 1 = synthesis main
- * kernel, 2 = back-projection. */
+ * (synchronises).  which: 0 = trace (all trace kernels, scan and scatter
+ * included), 1 = synthesis main kernel, 2 = back-projection, 3 = the tracing
+ * kernels of the last trace alone (rays and point reflectors, before the
+ * scan). */
 int rr_last_kernel_ms(rr_ctx *ctx, int32_t which, double *ms_out);
 
 #ifdef __cplusplus

@@ -30,7 +30,7 @@ EXPORTED = [
     "rr_set_chirp", "rr_trace", "rr_trace_rays", "rr_get_path_count", "rr_get_hits",
     "rr_get_paths", "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms", "rr_backproject",
     "rr_max_projection", "rr_scene_set_alpha", "rr_scene_update_vertices", "rr_get_bvh_nodes",
-    "rr_set_casting", "rr_casting_pieces",
+    "rr_set_casting", "rr_casting_pieces", "rr_trace_work",
 ]
 
 
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     L.rr_casting_pieces.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
     L.rr_set_chirp.argtypes = [vp, C.POINTER(Chirp)]
     L.rr_trace.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64)]
+    L.rr_trace_work.argtypes = [vp, C.POINTER(TraceParams), C.POINTER(i64), vp]
     L.rr_trace_rays.argtypes = [vp, vp, vp, vp, vp, i64, C.c_int32, C.c_uint64, C.c_int32,
                                 C.POINTER(i64)]
     L.rr_get_path_count.argtypes = [vp, C.POINTER(i64)]
@@ -214,12 +215,15 @@ class Context:
     # -------------------------------------------------------------- trace
     def trace(self, n_rays, max_bounces=2, seed=0, az_min=-math.pi / 2, az_max=math.pi / 2,
               el_min=-math.pi / 2, el_max=math.pi / 2, sampler=UNIFORM, record_hits=True,
-              path_cap=0) -> int:
+              path_cap=0, sync=True):
+        """Returns the number of stored paths; with sync=False the call does
+        not wait for the GPU and returns None (the count stays on the device
+        until path_count() or a synthesis needs it)."""
         tp = TraceParams(int(n_rays), int(max_bounces), int(seed) & (2**64 - 1), az_min, az_max,
                          el_min, el_max, int(sampler), int(bool(record_hits)), int(path_cap))
         n = C.c_int64()
-        self._check(self.lib.rr_trace(self.h, C.byref(tp), C.byref(n)))
-        self.n_paths = n.value
+        self._check(self.lib.rr_trace(self.h, C.byref(tp), C.byref(n) if sync else None))
+        self.n_paths = n.value if sync else None
         n_src = 1 if self.mode == TX_SHARED else self.n_tx
         if sampler == PER_TRIANGLE:
             per = self.casting_pieces(az_min, az_max, el_min, el_max) * int(n_rays)
@@ -262,6 +266,30 @@ class Context:
         self._check(self.lib.rr_get_hits(self.h, C.c_void_p(out.data_ptr()), out.numel()))
         self.stream.synchronize()
         return out
+
+    def trace_work(self, n_rays, max_bounces=2, seed=0, az_min=-math.pi / 2, az_max=math.pi / 2,
+                   el_min=-math.pi / 2, el_max=math.pi / 2, sampler=UNIFORM, record_hits=False,
+                   path_cap=0):
+        """trace() through the counting kernel: returns (paths, work) with work
+        = dict(rays, queries, nodes, tris) summed over the launch."""
+        tp = TraceParams(int(n_rays), int(max_bounces), int(seed) & (2**64 - 1), az_min, az_max,
+                         el_min, el_max, int(sampler), int(bool(record_hits)), int(path_cap))
+        n = C.c_int64()
+        w = (C.c_int64 * 4)()
+        self._check(self.lib.rr_trace_work(self.h, C.byref(tp), C.byref(n), w))
+        self.n_paths = n.value
+        n_src = 1 if self.mode == TX_SHARED else self.n_tx
+        self.n_traced = n_src * (int(n_rays) if self.mode == TX_SHARED else int(n_rays) // self.n_tx)
+        self.max_bounces = int(max_bounces)
+        self.record_hits = bool(record_hits)
+        return n.value, dict(rays=w[0], queries=w[1], nodes=w[2], tris=w[3])
+
+    def path_count(self) -> int:
+        """Stored paths of the last trace (waits for a trace run with sync=False)."""
+        n = C.c_int64()
+        self._check(self.lib.rr_get_path_count(self.h, C.byref(n)))
+        self.n_paths = n.value
+        return n.value
 
     def paths(self):
         """Context paths as device tensors: src, K, ray [n]; tri, vid [KMAX][n];

@@ -124,12 +124,21 @@ __device__ __forceinline__ float safe_inv(double d)
     return 1.0f / f;
 }
 
+// Work counters of the counting tracer (k_trace_count): BVH nodes fetched,
+// leaf triangle records fetched, closest-hit queries.
+struct TraceCount {
+    unsigned nodes, tris, queries;
+};
+
 // Closest hit of the ray (o, d) over every triangle except `skip`: smallest
 // t > RR_TMIN, lowest id on ties.  Returns the triangle id (-1: miss), its t
-// and its position in the leaf-ordered triangle array.
-__device__ int closest_hit(const TraceArgs &A, d3 o, d3 d, int skip, double &tbest, int &lbest,
-                           int *stk)
+// and its position in the leaf-ordered triangle array.  CNT: also count the
+// work into *cn.
+template <bool CNT>
+__device__ int closest_hit_t(const TraceArgs &A, d3 o, d3 d, int skip, double &tbest, int &lbest,
+                             int *stk, TraceCount *cn)
 {
+    if (CNT) cn->queries++;
     int best = -1;
     tbest = __builtin_huge_val();
     lbest = -1;
@@ -142,6 +151,7 @@ __device__ int closest_hit(const TraceArgs &A, d3 o, d3 d, int skip, double &tbe
     int ref = 0;
     while (true) {
         if (ref >= 0) {
+            if (CNT) cn->nodes++;
             const float4 *N = A.nodes + 4 * (int64_t)ref;
             float4 n0 = N[0], n1 = N[1], n2 = N[2], n3 = N[3];
             float a0 = fmaf(n0.x, ix, -oix), a1 = fmaf(n0.w, ix, -oix);
@@ -173,6 +183,7 @@ __device__ int closest_hit(const TraceArgs &A, d3 o, d3 d, int skip, double &tbe
         } else {
             int x = ~ref;
             int first = x >> 3, cnt = (x & 7) + 1;
+            if (CNT) cn->tris += (unsigned)cnt;
             for (int k = 0; k < cnt; k++) {
                 const float4 *T = A.ltris + 3 * (int64_t)(first + k);
                 float4 t0 = T[0], t1 = T[1], t2 = T[2];
@@ -195,6 +206,12 @@ __device__ int closest_hit(const TraceArgs &A, d3 o, d3 d, int skip, double &tbe
         ref = stk[sp * RR_TRACE_BLOCK];
     }
     return best;
+}
+
+__device__ __forceinline__ int closest_hit(const TraceArgs &A, d3 o, d3 d, int skip, double &tbest,
+                                           int &lbest, int *stk)
+{
+    return closest_hit_t<false>(A, o, d, skip, tbest, lbest, stk, nullptr);
 }
 
 // Eqs. (1)-(3): n is the unit normal facing the incident direction d.
@@ -267,8 +284,10 @@ __device__ __forceinline__ void append(const TraceArgs &A, bool rec, int32_t src
 }
 
 // one launched ray g (source-major) through all of its bounces
+template <bool CNT = false>
 __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, int64_t i, int64_t t, int64_t v,
-                           double amp, int32_t srcid, int32_t *hrow, int *stk, int64_t target);
+                           double amp, int32_t srcid, int32_t *hrow, int *stk, int64_t target,
+                           TraceCount *cn = nullptr);
 
 // Per-triangle casting: ray i of a source aims at piece f = i / g^2 (a
 // triangle, or part of one cut by the host's subdivision), at a point drawn
@@ -278,8 +297,9 @@ __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, i
 // p0 A |cos| / d^2 (A |cos| = |area normal . dir| / 2) over g^2 rays; only
 // rays inside the field of view are traced, and they count only when the
 // piece's triangle is their first hit.
+template <bool CNT = false>
 __device__ void trace_tri(const TraceArgs &A, int64_t g, int64_t t, int64_t i, int64_t v, d3 src,
-                          int *stk)
+                          int *stk, TraceCount *cn = nullptr)
 {
     const int64_t gs = A.tri_g, gg = gs * gs;
     const int64_t f = i / gg, k = i - f * gg;
@@ -309,11 +329,12 @@ __device__ void trace_tri(const TraceArgs &A, int64_t g, int64_t t, int64_t i, i
         A.counts[v] = 0;
         return;
     }
-    trace_from(A, src, d, i, t, v, w / (double)gg, A.shared ? -1 : (int32_t)t, hrow, stk,
-               A.piece_parent[f]);
+    trace_from<CNT>(A, src, d, i, t, v, w / (double)gg, A.shared ? -1 : (int32_t)t, hrow, stk,
+                    A.piece_parent[f], cn);
 }
 
-__device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
+template <bool CNT = false>
+__device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk, TraceCount *cn = nullptr)
 {
     int64_t t = g / A.n_per_src;
     int64_t i = g - t * A.n_per_src;
@@ -321,7 +342,7 @@ __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
     d3 src = A.shared ? mk3(A.oT[0], A.oT[1], A.oT[2])
                       : mk3(A.tx[3 * t], A.tx[3 * t + 1], A.tx[3 * t + 2]);
     if (A.sampler == RR_PER_TRIANGLE) {
-        trace_tri(A, g, t, i, v, src, stk);
+        trace_tri<CNT>(A, g, t, i, v, src, stk, cn);
         return;
     }
     uint64_t r[4];
@@ -348,7 +369,7 @@ __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk)
     const double amp = w / (double)A.n_per_src;
     const int32_t srcid = A.shared ? -1 : (int32_t)t;
     int32_t *hrow = A.hits ? A.hits + g * (A.bmax + 1) : nullptr;
-    trace_from(A, src, dir, i, t, v, amp, srcid, hrow, stk, -1);
+    trace_from<CNT>(A, src, dir, i, t, v, amp, srcid, hrow, stk, -1, cn);
 }
 
 // Caller-supplied ray g: origin, direction (normalised here), amplitude and
@@ -374,8 +395,10 @@ __device__ void trace_user(const TraceArgs &A, const UserRays &U, int64_t g, int
 // at each hit with the random numbers of counter (i, t, j + 1); paths carry
 // source srcid, virtual ray v and amplitude amp.  target >= 0: the ray is
 // dropped (hit row all -1, no paths) unless its first hit is that triangle.
+template <bool CNT>
 __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, int64_t i, int64_t t, int64_t v,
-                           double amp, int32_t srcid, int32_t *hrow, int *stk, int64_t target)
+                           double amp, int32_t srcid, int32_t *hrow, int *stk, int64_t target,
+                           TraceCount *cn)
 {
     Rec R;
 #pragma unroll
@@ -392,7 +415,7 @@ __device__ __forceinline__ void trace_from(const TraceArgs &A, d3 src, d3 dir, i
     for (int j = 0; j <= A.bmax; j++) {
         double th;
         int lidx;
-        int h = closest_hit(A, o, dir, prev, th, lidx, stk);
+        int h = closest_hit_t<CNT>(A, o, dir, prev, th, lidx, stk, cn);
         if (j == 0 && target >= 0 && h != target) {
             // cast towards a triangle that is not its first hit: not counted
             if (hrow)
@@ -484,6 +507,29 @@ __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace(TraceArgs A, int64_t n
     __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
     const int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
     if (g < n_traced) trace_ray(A, g, lds_stack + threadIdx.x);
+}
+
+// k_trace with work counters: the same rays, hits and paths, plus the sums
+// over all rays of BVH nodes fetched, leaf triangle records fetched and
+// closest-hit queries (stats[0..2], integer atomics: exact, order-free)
+__global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace_count(TraceArgs A, int64_t n_traced,
+                                                                unsigned long long *stats)
+{
+    __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
+    const int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
+    TraceCount cn = {0u, 0u, 0u};
+    if (g < n_traced) trace_ray<true>(A, g, lds_stack + threadIdx.x, &cn);
+    unsigned long long a = cn.nodes, b = cn.tris, q = cn.queries;
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        q += __shfl_xor(q, off);
+    }
+    if (__lane_id() == 0) {
+        atomicAdd(stats + 0, a);
+        atomicAdd(stats + 1, b);
+        atomicAdd(stats + 2, q);
+    }
 }
 
 __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace_user(TraceArgs A, UserRays U)
@@ -753,6 +799,16 @@ hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s)
     if (n_traced <= 0) return hipSuccess;
     int64_t blocks = (n_traced + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
     hipLaunchKernelGGL(k_trace, dim3((unsigned)blocks), dim3(RR_TRACE_BLOCK), 0, s, a, n_traced);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_count(const TraceArgs &a, int64_t n_traced, unsigned long long *stats,
+                              hipStream_t s)
+{
+    if (n_traced <= 0) return hipSuccess;
+    int64_t blocks = (n_traced + RR_TRACE_BLOCK - 1) / RR_TRACE_BLOCK;
+    hipLaunchKernelGGL(k_trace_count, dim3((unsigned)blocks), dim3(RR_TRACE_BLOCK), 0, s, a, n_traced,
+                       stats);
     return hipGetLastError();
 }
 

@@ -112,7 +112,9 @@ bool finite3(const double *p, int64_t n)
 struct rr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // [0, 1] trace stage, [2, 3] synthesis, [4, 5] imaging, [6] end of the
+    // tracing kernels within the trace stage
+    hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool trace_timed = false, synth_timed = false, image_timed = false;
 
     // scene
@@ -140,6 +142,8 @@ struct rr_ctx {
     int64_t tmp_cap = 0;
     PathStore paths;
     int64_t n_paths = -1;          // -1: none
+    bool paths_pending = false;    // a trace without a host count: n_paths not read back yet
+    int64_t pending_keep = 0;      // at most this many paths kept by that trace
     int64_t hits_elems = 0;
     bool hits_recorded = false;
     int n_az = 0, n_el = 0;        // proposal grid (cdf set)
@@ -173,6 +177,7 @@ struct rr_ctx {
     DevBuf mlp_p, mlp_m, mlp_v, mlp_g, mlp_acts, mlp_z, mlp_dz, mlp_d, mlp_loss, mlp_part;
     DevBuf tr_codes, tr_hist, tr_loss;   // minibatch staging of rr_proposal_train
     DevBuf bp_peak;                      // peak of the last maximum projection
+    DevBuf trace_stats;                  // work counters of rr_trace_work
     bool mlp_ready = false;
     int mlp_step = 0;
 };
@@ -182,22 +187,53 @@ namespace {
 // The trace stage of rr_trace / rr_trace_rays: tracing kernels, scan of the
 // per-ray counts, scatter into (ray, bounce) order; grows the temporary
 // buffer and re-runs once if it overflowed.
+// With n_paths_out == NULL nothing waits for the GPU: the scatter reads the
+// path count on the device and keeps at most min(path_cap, buffer) paths;
+// resolve_paths reads the count back when the host first needs it.
 template <class Kernels>
 int run_trace(rr_ctx *c, TraceArgs &A, int64_t V, int64_t nb, int64_t path_cap, Kernels kernels,
               int64_t *n_paths_out)
 {
     int rc;
+    c->paths_pending = false;
+    if (!n_paths_out) {
+        A.tmp = c->tmp.soa;
+        HIPCHK(hipMemsetAsync(c->counter.p, 0, 8, c->stream));
+        HIPCHK(hipMemsetAsync(c->err_flag.p, 0, 4, c->stream));
+        HIPCHK(hipEventRecord(c->ev[0], c->stream));
+        HIPCHK(kernels(A));
+        HIPCHK(hipEventRecord(c->ev[6], c->stream));
+        HIPCHK(launch_scan_u8(A.counts, V, c->offsets.as<uint32_t>(), c->bsums.as<uint32_t>(),
+                              nb + 1, c->total.as<unsigned long long>(), c->stream));
+        const int64_t keep = path_cap > 0 ? std::min(path_cap, c->tmp_cap) : c->tmp_cap;
+        if ((rc = c->paths.alloc(std::max<int64_t>(keep, 1)))) return rc;
+        HIPCHK(launch_scatter(c->tmp.soa, A.counter, c->tmp_cap, c->offsets.as<uint32_t>(),
+                              c->paths.soa, keep, c->stream));
+        HIPCHK(hipEventRecord(c->ev[1], c->stream));
+        c->n_paths = -1;
+        c->paths_pending = true;
+        c->pending_keep = keep;
+        c->trace_timed = true;
+        c->last = A;
+        g_err.clear();
+        return RR_OK;
+    }
     for (int attempt = 0; attempt < 2; attempt++) {
         A.tmp = c->tmp.soa;
         HIPCHK(hipMemsetAsync(c->counter.p, 0, 8, c->stream));
         HIPCHK(hipMemsetAsync(c->err_flag.p, 0, 4, c->stream));
         HIPCHK(hipEventRecord(c->ev[0], c->stream));
         HIPCHK(kernels(A));
+        HIPCHK(hipEventRecord(c->ev[6], c->stream));
         HIPCHK(launch_scan_u8(A.counts, V, c->offsets.as<uint32_t>(), c->bsums.as<uint32_t>(),
                               nb + 1, c->total.as<unsigned long long>(), c->stream));
         unsigned long long cnt = 0;
+        int errf = 0;
         HIPCHK(hipMemcpyAsync(&cnt, c->counter.p, 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(&errf, c->err_flag.p, 4, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        if (errf)
+            return fail(RR_EUNSUPPORTED, "traversal stack overflow (BVH depth %d)", c->bvh_depth);
         if ((int64_t)cnt > c->tmp_cap) {
             c->tmp_cap = (int64_t)cnt + cnt / 4 + 1024;
             if ((rc = c->tmp.alloc(c->tmp_cap))) return rc;
@@ -209,10 +245,6 @@ int run_trace(rr_ctx *c, TraceArgs &A, int64_t V, int64_t nb, int64_t path_cap, 
         HIPCHK(launch_scatter(c->tmp.soa, A.counter, c->tmp_cap, c->offsets.as<uint32_t>(),
                               c->paths.soa, keep, c->stream));
         HIPCHK(hipEventRecord(c->ev[1], c->stream));
-        int errf = 0;
-        HIPCHK(hipMemcpyAsync(&errf, c->err_flag.p, 4, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (errf) return fail(RR_EHIP, "traversal stack overflow (BVH depth %d)", c->bvh_depth);
         c->n_paths = keep;
         c->trace_timed = true;
         c->last = A;
@@ -221,6 +253,31 @@ int run_trace(rr_ctx *c, TraceArgs &A, int64_t V, int64_t nb, int64_t path_cap, 
         return RR_OK;
     }
     return fail(RR_EOVERFLOW, "temporary path buffer overflow persisted");
+}
+
+// The path count of a trace that did not read it back: one synchronisation.
+// A count beyond the temporary buffer means records were dropped: the buffer
+// grows for the next trace and RR_EOVERFLOW is returned.
+int resolve_paths(rr_ctx *c)
+{
+    if (!c->paths_pending) return RR_OK;
+    c->paths_pending = false;
+    HIPCHK(hipSetDevice(c->device));
+    unsigned long long cnt = 0;
+    int errf = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, c->counter.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&errf, c->err_flag.p, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (errf)
+        return fail(RR_EUNSUPPORTED, "traversal stack overflow (BVH depth %d)", c->bvh_depth);
+    if ((int64_t)cnt > c->tmp_cap) {
+        const int64_t need = (int64_t)cnt;
+        c->tmp_cap = need + need / 4 + 1024;
+        return fail(RR_EOVERFLOW, "%lld paths overflowed the path buffer; it has grown, trace again",
+                    (long long)need);
+    }
+    c->n_paths = std::min<int64_t>((int64_t)cnt, c->pending_keep);
+    return RR_OK;
 }
 
 }  // namespace
@@ -273,7 +330,7 @@ void rr_destroy(rr_ctx *c)
                       &c->ranges, &c->tmp.buf, &c->paths.buf, &c->gT, &c->gR, &c->gA,
                       &c->gB, &c->tri_obj, &c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_g,
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss, &c->mlp_part,
-                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->tri_alpha, &c->pieces_v, &c->pieces_p, &c->tris_dev, &c->verts_dev,
+                      &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->trace_stats, &c->tri_alpha, &c->pieces_v, &c->pieces_p, &c->tris_dev, &c->verts_dev,
                       &c->refit_order, &c->ubox,
                       &c->fq_pm, &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part, &c->bp_sf};
     for (DevBuf *b : bufs) b->release();
@@ -318,6 +375,7 @@ int rr_scene_upload(rr_ctx *c, const float *verts, int64_t n_verts, const int32_
     if (rc) return fail(rc, "BVH build: %s", err.c_str());
     c->has_scene = false;
     c->n_paths = -1;
+    c->paths_pending = false;
     HIPCHK(hipStreamSynchronize(c->stream));
     if ((rc = c->nodes.ensure(bvh.nodes.size() * 4 + 64))) return rc;
     if ((rc = c->ltris.ensure(bvh.tris.size() * 4 + 64))) return rc;
@@ -582,6 +640,7 @@ int rr_set_array(rr_ctx *c, const double *tx, int32_t n_tx, const double *rx, in
     c->mode = tx_mode;
     c->has_array = true;
     c->n_paths = -1;
+    c->paths_pending = false;
     g_err.clear();
     return RR_OK;
 }
@@ -602,7 +661,9 @@ int rr_set_chirp(rr_ctx *c, const rr_chirp *ch)
 // defined below; also used by the proposal code
 int rr_set_proposal_cdf_internal(rr_ctx *c, const double *cdf_dev, int n_az, int n_el);
 
-int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
+// rr_trace, with the counting kernel when stats (device, 3 x u64) is given
+static int trace_impl(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out,
+                      unsigned long long *stats)
 {
     if (!c || !tp) return fail(RR_EINVAL, "NULL argument");
     if (!c->has_scene || !c->has_array) return fail(RR_ESTATE, "scene and array must be set");
@@ -700,13 +761,42 @@ int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
     A.err_flag = c->err_flag.as<int>();
 
     auto kernels = [&](const TraceArgs &a) -> hipError_t {
-        hipError_t e = launch_trace(a, n_traced, c->stream);
+        hipError_t e;
+        if (stats) {
+            e = hipMemsetAsync(stats, 0, 3 * sizeof(unsigned long long), c->stream);
+            if (e == hipSuccess) e = launch_trace_count(a, n_traced, stats, c->stream);
+        } else {
+            e = launch_trace(a, n_traced, c->stream);
+        }
         return e == hipSuccess ? launch_points(a, c->stream) : e;
     };
     int rc2 = run_trace(c, A, V, nb, tp->path_cap, kernels, n_paths_out);
     if (rc2) return rc2;
     c->last_traced = n_traced;
     c->last_sampler = tp->record_hits ? tp->sampler : -1;
+    return RR_OK;
+}
+
+int rr_trace(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out)
+{
+    return trace_impl(c, tp, n_paths_out, nullptr);
+}
+
+int rr_trace_work(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out, int64_t work_out[4])
+{
+    if (!c || !tp || !n_paths_out || !work_out) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_scene || !c->has_array) return fail(RR_ESTATE, "scene and array must be set");
+    HIPCHK(hipSetDevice(c->device));
+    int rc = c->trace_stats.ensure(64);
+    if (rc) return rc;
+    if ((rc = trace_impl(c, tp, n_paths_out, c->trace_stats.as<unsigned long long>()))) return rc;
+    unsigned long long st[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(st, c->trace_stats.p, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    work_out[0] = c->last_traced;
+    work_out[1] = (int64_t)st[2];
+    work_out[2] = (int64_t)st[0];
+    work_out[3] = (int64_t)st[1];
     return RR_OK;
 }
 
@@ -789,6 +879,7 @@ int rr_trace_rays(rr_ctx *c, const double *orig, const double *dir, const double
 int rr_get_path_count(rr_ctx *c, int64_t *n_out)
 {
     if (!c || !n_out) return fail(RR_EINVAL, "NULL argument");
+    if (int rc = resolve_paths(c)) return rc;
     if (c->n_paths < 0) return fail(RR_ESTATE, "no paths");
     *n_out = c->n_paths;
     return RR_OK;
@@ -797,6 +888,7 @@ int rr_get_path_count(rr_ctx *c, int64_t *n_out)
 int rr_get_hits(rr_ctx *c, int32_t *dst, int64_t cap_elems)
 {
     if (!c) return fail(RR_EINVAL, "NULL argument");
+    if (int rc = resolve_paths(c)) return rc;
     if (c->n_paths < 0 || !c->hits_recorded) return fail(RR_ESTATE, "no hit list recorded");
     if (c->hits_elems == 0) return RR_OK;
     if (!dst) return fail(RR_EINVAL, "NULL argument");
@@ -819,6 +911,7 @@ static hipError_t copy_planes(void *dst, int64_t dstride, const void *src, int64
 int rr_get_paths(rr_ctx *c, const rr_paths *d, int64_t *n_out)
 {
     if (!c || !d || !n_out) return fail(RR_EINVAL, "NULL argument");
+    if (int rc = resolve_paths(c)) return rc;
     if (c->n_paths < 0) return fail(RR_ESTATE, "no paths");
     int64_t n = c->n_paths;
     *n_out = n;
@@ -845,6 +938,7 @@ int rr_set_paths(rr_ctx *c, const rr_paths *s, int64_t n)
     if (n > 0 && (!s->src || !s->K || !s->vid || !s->p || !s->amp))
         return fail(RR_EINVAL, "src, K, vid, p and amp are required");
     HIPCHK(hipSetDevice(c->device));
+    c->paths_pending = false;
     int rc = c->paths.alloc(std::max<int64_t>(n, 1));
     if (rc) return rc;
     const PathSoA &d = c->paths.soa;
@@ -955,6 +1049,7 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
 {
     if (!c || !cube) return fail(RR_EINVAL, "NULL argument");
     if (!c->has_array || !c->has_chirp) return fail(RR_ESTATE, "array and chirp must be set");
+    if (int rc = resolve_paths(c)) return rc;
     if (c->n_paths < 0) return fail(RR_ESTATE, "no paths (trace or rr_set_paths first)");
     if (model != RR_EXACT && model != RR_SEPARABLE) return fail(RR_EINVAL, "unknown model");
     if (engine == RR_ENGINE_AUTO) {
@@ -1065,11 +1160,11 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
 int rr_last_kernel_ms(rr_ctx *c, int32_t which, double *ms)
 {
     if (!c || !ms) return fail(RR_EINVAL, "NULL argument");
-    if (which < 0 || which > 2 || (which == 0 && !c->trace_timed) ||
+    if (which < 0 || which > 3 || ((which == 0 || which == 3) && !c->trace_timed) ||
         (which == 1 && !c->synth_timed) || (which == 2 && !c->image_timed))
         return fail(RR_ESTATE, "nothing timed");
     HIPCHK(hipSetDevice(c->device));
-    hipEvent_t a = c->ev[which * 2], b = c->ev[which * 2 + 1];
+    hipEvent_t a = c->ev[which == 3 ? 0 : which * 2], b = c->ev[which == 3 ? 6 : which * 2 + 1];
     HIPCHK(hipEventSynchronize(b));
     float f = 0;
     HIPCHK(hipEventElapsedTime(&f, a, b));
@@ -1239,6 +1334,7 @@ int rr_proposal_probe(rr_ctx *c, double az_min, double az_max, float *code16)
 int rr_proposal_histogram(rr_ctx *c, float *hist)
 {
     if (!c || !hist) return fail(RR_EINVAL, "NULL argument");
+    if (int rc = resolve_paths(c)) return rc;
     if (c->n_paths < 0 || c->last_sampler != RR_UNIFORM || !c->hits_recorded)
         return fail(RR_ESTATE, "needs a uniform trace with record_hits");
     HIPCHK(hipSetDevice(c->device));

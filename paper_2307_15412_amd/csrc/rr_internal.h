@@ -171,6 +171,10 @@ struct BatchRangeInfo {
 // launchers (defined in the .hip files)
 hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s);
 hipError_t launch_points(const TraceArgs &a, hipStream_t s);
+// k_trace plus exact work counters: stats[0] BVH nodes fetched, stats[1] leaf
+// triangle records fetched, stats[2] closest-hit queries (summed, not cleared)
+hipError_t launch_trace_count(const TraceArgs &a, int64_t n_traced, unsigned long long *stats,
+                              hipStream_t s);
 hipError_t launch_trace_user(const TraceArgs &a, const UserRays &u, hipStream_t s);
 hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alpha,
                             const float *obj_alpha, hipStream_t s);

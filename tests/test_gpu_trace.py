@@ -96,3 +96,55 @@ def test_street_full_size_sampled(gpu, orc):
     sel = np.isin(gp["ray"], vids)
     g = {k: (v[..., sel]) for k, v in gp.items()}
     assert_paths_equal(g, oracle_to_soa(op))
+
+
+def test_trace_without_host_count(gpu, orc):
+    """rr_trace with no count pointer does not wait for the GPU: the path
+    count is read back by the first call that needs it, and the paths, hit
+    list and cube equal those of a trace that read it back at once."""
+    import paper_2307_15412_amd as rr
+    w = sg.workload_tiny(2)
+    w.trace.n_rays = 40_000
+    gpu.setup(w)
+    n_sync = gpu.trace_workload(w, record_hits=True)
+    ref_paths = gpu_soa_np(gpu)
+    ref_hits = gpu.hits().cpu().numpy()
+    ref_cube = gpu.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32).cpu().numpy()
+    assert gpu.trace_workload(w, record_hits=True, sync=False) is None
+    cube = gpu.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32).cpu().numpy()
+    assert np.array_equal(cube, ref_cube)
+    assert gpu.path_count() == n_sync
+    assert_paths_equal(gpu_soa_np(gpu), ref_paths)
+    assert np.array_equal(gpu.hits().cpu().numpy(), ref_hits)
+    # and against the oracle, path cap included
+    w.path_cap = n_sync // 3
+    gpu.trace_workload(w, record_hits=False, sync=False)
+    assert gpu.path_count() == n_sync // 3
+    _, op = orc.trace(w.scene, w.array, w.trace)
+    assert_paths_equal(gpu_soa_np(gpu), oracle_to_soa(op[: n_sync // 3]))
+
+
+def test_trace_without_host_count_overflow(orc):
+    """More paths than the temporary buffer holds, without a host count: the
+    first call that needs the count reports RR_EOVERFLOW (the dropped records
+    are never read), the buffer has grown, and the repeated trace is exact."""
+    import paper_2307_15412_amd as rr
+    ctx = rr.Context(0)
+    try:
+        sc = sg.plate(2.0, 50.0, alpha=1.0)
+        arr = sg.Array(np.array([[0, 0, 0.5]]), np.array([[0, 0, 0.5]]), 60.0, sg.MODE_PER_TX)
+        w = sg.Workload("plate", sc, arr, sg.Chirp(), sg.TraceParams(n_rays=400_000, max_bounces=2))
+        ctx.setup(w)
+        ctx.trace_workload(w, record_hits=False, sync=False)
+        with pytest.raises(rr.RadrayError) as e:
+            ctx.path_count()
+        assert e.value.code == rr.binding.RR_EOVERFLOW
+        with pytest.raises(rr.RadrayError):
+            ctx.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32)
+        ctx.trace_workload(w, record_hits=False, sync=False)
+        n = ctx.path_count()
+        _, op = orc.trace(w.scene, w.array, w.trace)
+        assert n == len(op) > 65536
+        assert_paths_equal(gpu_soa_np(ctx), oracle_to_soa(op))
+    finally:
+        ctx.close()
