@@ -313,6 +313,30 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
 int rr_synthesize(rr_ctx *ctx, int32_t model, int32_t engine, void *cube_dev, int64_t cube_elems,
                   const int64_t *sample_idx_dev, int64_t n_sample);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the full
+ * cube of rr_synthesize with the direct FP32 engine (either model), computed
+ * without any hipMalloc, hipFree or allocating library call.  Its temporary
+ * data (one synthesis record per path and the path range of each transmitter
+ * group) live in a fixed scratch area of the library: at most
+ * RR_NOALLOC_MAX_PATHS paths and RR_NOALLOC_MAX_TX transmitters (per-element
+ * launch), about 13.7 MB that every GPU the library runs on holds from the
+ * first rr_create on it until the process ends.  Inputs are the context's
+ * paths, array, chirp and object velocities; cube_dev (caller-owned,
+ * complex64 [n_ch][n_chirps][n_samples], cube_elems complex elements) is
+ * overwritten.  The result equals rr_synthesize with RR_DIRECT_FP32 (same
+ * kernels).  Paths whose source does not match the array's launch mode are
+ * not summed (rr_synthesize rejects them).  All calls on one GPU share its
+ * scratch and each call rewrites what it reads: calls on one stream are
+ * ordered, calls that overlap in time on one GPU (other streams, other
+ * contexts, other threads) race.  If the last trace left its path count on
+ * the device, this call reads it back (one synchronisation, no allocation).
+ * Errors: RR_ESTATE (no paths, array, chirp or scene), RR_EINVAL,
+ * RR_EUNSUPPORTED (over either limit, or too many samples per chirp). */
+#define RR_NOALLOC_MAX_PATHS 65536
+#define RR_NOALLOC_MAX_TX 4096
+int rr_synthesize_noalloc(rr_ctx *ctx, int32_t model, void *cube_dev, int64_t cube_elems);
+
 /* ------------------------------------------------------------------------
  * Learned ray proposal (an importance-sampling density for the launch of
  * Sec. III-A).  Directions are binned on a grid of RR_PROP_NAZ azimuth x

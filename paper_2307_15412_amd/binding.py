@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libradray.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EHIP, RR_ESTATE, RR_EOVERFLOW, RR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_MAX_PATHS, NOALLOC_MAX_TX = 65536, 4096
 TX_PER_ELEMENT, TX_SHARED = 0, 1
 UNIFORM, PROPOSAL, PER_TRIANGLE = 0, 1, 2
 EXACT, SEPARABLE = 0, 1
@@ -30,7 +31,7 @@ EXPORTED = [
     "rr_set_chirp", "rr_trace", "rr_trace_rays", "rr_get_path_count", "rr_get_hits",
     "rr_get_paths", "rr_set_paths", "rr_synthesize", "rr_last_kernel_ms", "rr_backproject",
     "rr_max_projection", "rr_scene_set_alpha", "rr_scene_update_vertices", "rr_get_bvh_nodes",
-    "rr_set_casting", "rr_casting_pieces", "rr_trace_work",
+    "rr_set_casting", "rr_casting_pieces", "rr_trace_work", "rr_synthesize_noalloc",
 ]
 
 
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     L.rr_get_paths.argtypes = [vp, C.POINTER(Paths), C.POINTER(i64)]
     L.rr_set_paths.argtypes = [vp, C.POINTER(Paths), i64]
     L.rr_synthesize.argtypes = [vp, i32, i32, vp, i64, vp, i64]
+    L.rr_synthesize_noalloc.argtypes = [vp, i32, vp, i64]
     L.rr_last_kernel_ms.argtypes = [vp, i32, C.POINTER(f64)]
     _lib = L
     return L
@@ -349,6 +351,18 @@ class Context:
                                            C.c_void_p(out.data_ptr()), out.numel(),
                                            C.c_void_p(idx.data_ptr()), idx.numel()))
         self._keep_idx = idx
+        return out
+
+    def synthesize_noalloc(self, model=EXACT, out=None):
+        """Full cube through rr_synthesize_noalloc (direct engine, no device
+        allocation in the library; `out` must be given to avoid one here)."""
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.n_ch, self.M, self.K), dtype=torch.complex64,
+                              device=self.device)
+        check_out(out, self.device, torch.complex64, self.n_ch * self.M * self.K, "cube")
+        self._check(self.lib.rr_synthesize_noalloc(self.h, int(model), C.c_void_p(out.data_ptr()),
+                                                   out.numel()))
         return out
 
     # ------------------------------------------------------------ imaging

@@ -291,14 +291,17 @@ __global__ void k_syn_prep(PathSoA P, int64_t n, const double *obj_vel, int nobj
 }
 
 // ranges[g] = first path with src >= g (paths sorted by src); g in [0, n_groups]
-__global__ void k_ranges(const int32_t *src, int64_t n, int n_groups, int64_t *ranges)
+// ranges[g] = first path whose source is >= g0 + g, g = 0 .. n_groups (src
+// sorted): per-Tx groups with g0 = 0, the single group of a shared launch
+// (every src = -1) with g0 = -1
+__global__ void k_ranges(const int32_t *src, int64_t n, int n_groups, int g0, int64_t *ranges)
 {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g > n_groups) return;
     int64_t lo = 0, hi = n;
     while (lo < hi) {
         int64_t mid = (lo + hi) / 2;
-        if (src[mid] < g) lo = mid + 1; else hi = mid;
+        if (src[mid] < g0 + g) lo = mid + 1; else hi = mid;
     }
     ranges[g] = lo;
 }
@@ -416,11 +419,11 @@ hipError_t launch_syn_prep(const PathSoA &paths, int64_t n, const double *obj_ve
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const int32_t *src, int64_t n, int n_groups, int64_t *ranges,
+hipError_t launch_ranges(const int32_t *src, int64_t n, int n_groups, int g0, int64_t *ranges,
                          hipStream_t s)
 {
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_groups + 1 + 255) / 256)), dim3(256), 0, s,
-                       src, n, n_groups, ranges);
+                       src, n, n_groups, g0, ranges);
     return hipGetLastError();
 }
 

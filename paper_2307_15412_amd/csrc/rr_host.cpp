@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "rr_internal.h"
@@ -107,6 +108,36 @@ bool finite3(const double *p, int64_t n)
     return true;
 }
 
+}  // namespace
+
+// Scratch of rr_synthesize_noalloc: synthesis records of up to
+// RR_NOALLOC_MAX_PATHS paths, then the path ranges of up to RR_NOALLOC_MAX_TX
+// transmitter groups.  Each GPU holds its own copy from module load until the
+// process ends.  Host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the current device (g_scratch_dev), never
+// through the array's name.
+#define NOALLOC_RANGES_OFF (((size_t)RR_NOALLOC_MAX_PATHS * sizeof(SynPath) + 255) / 256 * 256)
+#define NOALLOC_BYTES (NOALLOC_RANGES_OFF + (size_t)(RR_NOALLOC_MAX_TX + 2) * 8)
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+// once per device, with that device current
+int scratch_init(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(RR_EUNSUPPORTED, "device index %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[dev]) return RR_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(RR_EHIP, "scratch symbol address: %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+    return RR_OK;
+}
 }  // namespace
 
 struct rr_ctx {
@@ -297,6 +328,7 @@ int rr_create(int hip_device, void *hip_stream, rr_ctx **out)
     if (hip_device < 0 || hip_device >= ndev)
         return fail(RR_EINVAL, "device %d out of range (%d devices)", hip_device, ndev);
     HIPCHK(hipSetDevice(hip_device));
+    if (int rc = scratch_init(hip_device)) return rc;
     rr_ctx *c = new rr_ctx();
     c->device = hip_device;
     c->stream = (hipStream_t)hip_stream;
@@ -1112,7 +1144,7 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
         HIPCHK(hipMemcpyAsync(c->ranges.p, r, 16, hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
     } else {
-        HIPCHK(launch_ranges(c->paths.soa.src, n, n_groups, c->ranges.as<int64_t>(), c->stream));
+        HIPCHK(launch_ranges(c->paths.soa.src, n, n_groups, 0, c->ranges.as<int64_t>(), c->stream));
     }
     SynthArgs A{};
     A.paths = sp;
@@ -1151,6 +1183,72 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
         if (e == hipErrorInvalidValue) return fail(RR_EUNSUPPORTED, "n_samples too large");
         HIPCHK(e);
     }
+    HIPCHK(hipEventRecord(c->ev[3], c->stream));
+    c->synth_timed = true;
+    g_err.clear();
+    return RR_OK;
+}
+
+// rr_synthesize with the direct engine over the full cube, allocating
+// nothing: the synthesis records and path ranges live in this device's
+// scratch; every entry read is written first by this call (no clearing
+// needed).  Paths whose source does not belong to the launch mode fall
+// outside every range and are not summed.
+int rr_synthesize_noalloc(rr_ctx *c, int32_t model, void *cube, int64_t cube_elems)
+{
+    if (!c || !cube) return fail(RR_EINVAL, "NULL argument");
+    if (!c->has_array || !c->has_chirp) return fail(RR_ESTATE, "array and chirp must be set");
+    if (!c->has_scene) return fail(RR_ESTATE, "scene must be set (velocities)");
+    if (int rc = resolve_paths(c)) return rc;
+    if (c->n_paths < 0) return fail(RR_ESTATE, "no paths (trace or rr_set_paths first)");
+    if (model != RR_EXACT && model != RR_SEPARABLE) return fail(RR_EINVAL, "unknown model");
+    const int64_t C = (int64_t)c->ntx * c->nrx, M = c->chirp.n_chirps, K = c->chirp.n_samples;
+    if (cube_elems < C * M * K)
+        return fail(RR_EINVAL, "cube needs %lld complex elements", (long long)(C * M * K));
+    if (C * M > (int64_t)1 << 31) return fail(RR_EUNSUPPORTED, "too many rows");
+    const int64_t n = c->n_paths;
+    const int shared = c->mode == RR_TX_SHARED;
+    const int n_groups = shared ? 1 : c->ntx;
+    if (n > RR_NOALLOC_MAX_PATHS)
+        return fail(RR_EUNSUPPORTED, "%lld paths exceed the scratch limit of %d", (long long)n,
+                    RR_NOALLOC_MAX_PATHS);
+    if (n_groups > RR_NOALLOC_MAX_TX)
+        return fail(RR_EUNSUPPORTED, "%d transmitters exceed the scratch limit of %d", n_groups,
+                    RR_NOALLOC_MAX_TX);
+    HIPCHK(hipSetDevice(c->device));
+    unsigned char *base = static_cast<unsigned char *>(g_scratch_dev[c->device]);
+    if (!base) return fail(RR_ESTATE, "scratch not initialised on device %d", c->device);
+    SynPath *sp = reinterpret_cast<SynPath *>(base);
+    int64_t *ranges = reinterpret_cast<int64_t *>(base + NOALLOC_RANGES_OFF);
+    HIPCHK(launch_syn_prep(c->paths.soa, n, c->obj_vel.as<const double>(), c->nobj,
+                           c->pt_vel.as<const double>(), c->npts, sp, c->stream));
+    HIPCHK(launch_ranges(c->paths.soa.src, n, n_groups, shared ? -1 : 0, ranges, c->stream));
+    SynthArgs A{};
+    A.paths = sp;
+    A.ranges = ranges;
+    A.n_paths = n;
+    A.tx = c->tx.as<const double>();
+    A.rx = c->rx.as<const double>();
+    A.ntx = c->ntx;
+    A.nrx = c->nrx;
+    for (int a = 0; a < 3; a++) {
+        A.oT[a] = c->oT[a];
+        A.oR[a] = c->oR[a];
+    }
+    A.shared = shared;
+    A.model = model;
+    A.f0 = c->chirp.f0;
+    A.bw = c->chirp.bandwidth;
+    A.t_rep = c->chirp.t_rep;
+    A.inv_c = 1.0 / 299792458.0;
+    A.M = (int)M;
+    A.K = (int)K;
+    A.cube = static_cast<float2 *>(cube);
+    HIPCHK(hipEventRecord(c->ev[2], c->stream));
+    const int rows = (int)(shared ? C * M : (int64_t)c->nrx * M);
+    hipError_t e = launch_synth_direct(A, n_groups, rows, c->stream);
+    if (e == hipErrorInvalidValue) return fail(RR_EUNSUPPORTED, "n_samples too large");
+    HIPCHK(e);
     HIPCHK(hipEventRecord(c->ev[3], c->stream));
     c->synth_timed = true;
     g_err.clear();

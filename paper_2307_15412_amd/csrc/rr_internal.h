@@ -209,7 +209,7 @@ hipError_t launch_scatter(const PathSoA &tmp, const unsigned long long *counter,
 
 hipError_t launch_syn_prep(const PathSoA &paths, int64_t n, const double *obj_vel, int nobj,
                            const double *pt_vel, int npts, SynPath *out, hipStream_t s);
-hipError_t launch_ranges(const int32_t *src, int64_t n, int n_groups, int64_t *ranges,
+hipError_t launch_ranges(const int32_t *src, int64_t n, int n_groups, int g0, int64_t *ranges,
                          hipStream_t s);
 hipError_t launch_synth_direct(const SynthArgs &a, int n_groups, int rows_per_group,
                                hipStream_t s);
