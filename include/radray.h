@@ -300,9 +300,17 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
  *          sample) factor), which allows the complex-GEMM engine.
  *   engine RR_DIRECT_FP32 (either model), RR_GEMM_BF16X3 (separable only:
  *          split-bf16 hi+lo complex GEMM on MFMA, FP32 accumulation; each
- *          chirp's samples are computed in whole tiles of 64), or
- *          RR_ENGINE_AUTO (GEMM for the separable model when the 64-sample
- *          tiling pads a chirp by at most a quarter, direct otherwise).
+ *          chirp's samples are computed in whole tiles of 64; relative error
+ *          bar 1e-3), RR_GEMM_EXACT (exact model only, full cube: one
+ *          split-bf16 complex product per (chirp, sample) of FP64-reduced Tx
+ *          and Rx leg phasors, held to the exact model's 1e-4 bar), or
+ *          RR_ENGINE_AUTO: the separable model takes RR_GEMM_BF16X3 when the
+ *          64-sample tiling pads a chirp by at most a quarter; the exact model
+ *          takes RR_GEMM_EXACT for a shared launch whose 96 x 96 Tx x Rx
+ *          tiles are at least half filled and whose leg tables fit its
+ *          budget; everything else, and sampled entries, the direct engine.
+ *          AUTO never changes the model, and each engine it picks meets that
+ *          model's error bar.
  *   cube_dev complex64 [n_ch][n_chirps][n_samples], cube_elems = its complex
  *          element count; the cube is overwritten.
  *   sample_idx_dev int64 [n_sample] flat entry indices (c*M*K + m*K + k):

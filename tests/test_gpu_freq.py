@@ -1,6 +1,7 @@
 """Exact-model synthesis as one split-bf16 complex product per (chirp,
-sample) against the FP64 oracle (relative error <= 1e-3, the split-bf16
-tolerance): full cubes at Tx / Rx counts around the 32-row blocks and 96-wide
+sample) against the FP64 oracle.  ENGINE_AUTO sends the exact model here, so
+the engine is held to the exact model's FP32 bar (relative error <= 1e-4, the
+direct engine's), not the split-bf16 GEMM's 1e-3; it measures ~5e-7: full cubes at Tx / Rx counts around the 32-row blocks and 96-wide
 tiles, several chirps of a moving scene, the per-element launch (paths feed
 only their own Tx), path counts around the 16-path steps and the split
 boundaries, an empty path list; the hand set-up against the direct FP32 engine
@@ -16,7 +17,7 @@ from helpers import oracle_to_soa, rel_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-3
+TOL = 1e-4
 
 
 def _upload(gpu, op):
