@@ -96,6 +96,34 @@ def run_batch(args):
     dt = (time.perf_counter() - t0) / args.steps
     ps = sum(float(n) * np.prod(s) for n, s in zip(counts, B.shapes))
     rays = sum(w.trace.n_rays for w in ws)
+    # sampled entries of the timed launch's cubes against the FP64 oracle
+    # (exact model): the slot with the most channels, the one with the most
+    # triangles and four seeded others, 256 entries each
+    check = None
+    if not args.no_check:
+        import oracle
+        slots = [int(np.argmax([w.array.n_ch for w in ws])), int(np.argmax([w.scene.n_tris for w in ws]))]
+        for s in np.random.default_rng(5).permutation(len(ws)):
+            if len(slots) >= 6:
+                break
+            if int(s) not in slots:
+                slots.append(int(s))
+        errs, ratios, t0 = [], [], time.perf_counter()
+        for s in slots:
+            w = ws[s]
+            _, op = oracle.trace(w.scene, w.array, w.trace, want_hits=False)
+            if len(op) != counts[s]:
+                raise SystemExit(f"slot {s}: {counts[s]} paths, oracle {len(op)}")
+            flat = cubes[s].reshape(-1)
+            idx = np.random.default_rng(100 + s).choice(flat.numel(), 256, replace=False)
+            got = flat[torch.from_numpy(idx).to(flat.device)].cpu().numpy()
+            ref = oracle.synth(op, w.scene, w.array, w.chirp, model=0, idx=idx)
+            errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+            ratios.append(float(np.abs(got - ref).max() / np.abs(ref).max()))
+            log(f"slot {s}: {w.array.n_ch} ch, {w.scene.n_tris} tris, rel err {errs[-1]:.2e}")
+        check = {"slots": slots, "rel_err": errs, "max_err_ratio": ratios,
+                 "rel_err_max": max(errs), "oracle_s": time.perf_counter() - t0,
+                 "entries_per_slot": 256}
     print(json.dumps({
         "metric": "batched Gpath-samples/s (64 uneven scenes, one captured launch)",
         "value": ps / dt / 1e9, "unit": "Gpath-samples/s", "n_gpus": 1, "steps": args.steps,
@@ -106,7 +134,8 @@ def run_batch(args):
         "scenes": len(ws), "rays": rays, "paths": int(np.sum(counts)),
         "cube_gb": sum(np.prod(s) for s in B.shapes) * 8 / 1e9,
         "mrays_per_s_incl_synth": rays / dt / 1e6, "tiles": tiles.tolist(),
-        "scene_gen_s": gen_s, "bvh_upload_s": upload_s, "graph_ms": B.stats()["ms_total"]}))
+        "scene_gen_s": gen_s, "bvh_upload_s": upload_s, "graph_ms": B.stats()["ms_total"],
+        "oracle_check": check}))
 
 
 def run_proposal(args):

@@ -102,3 +102,38 @@ def test_batch_against_oracle(gpu, orc):
         ref = orc.synth(op, w.scene, w.array, w.chirp, model=0, idx=idx)
         assert rel_err(got, ref) < 1e-4, i
     B.close()
+
+
+def test_batch_full_size_slot(gpu, orc):
+    """A slot at the batched configuration's largest size: a street of 5.1e5
+    triangles seen by 3072 channels (48 Tx x 64 Rx shared launch), 512 samples
+    x 64 chirps, 1e6 rays, 3 bounces, among two uneven scenes.  The slot
+    equals the single-scene launch bit for bit and 1024 seeded entries are
+    within 1e-4 of the FP64 oracle (exact model)."""
+    import paper_2307_15412_amd as rr
+    big = sg.Workload("street_3072", sg.scene_street(7), sg.array_sparse_grid(48, 64, 24,
+                      mode=sg.MODE_SHARED), sg.Chirp(n_samples=512, n_chirps=64),
+                      sg.TraceParams(n_rays=1_000_000, max_bounces=3, seed=7))
+    assert big.scene.n_tris >= 500_000 and big.array.n_ch == 3072
+    ws = [sg.workload_batch(n_scenes=1, seed0=2010, rays=200_000, tri_hi=1e5, ch_hi=64)[0], big,
+          sg.workload_box_family(4, 50_000)]
+    B = rr.Batch(gpu, len(ws))
+    for i, w in enumerate(ws):
+        B.set_workload(i, w)
+    cubes = B.alloc_cubes()
+    counts = B.launch(cubes)
+    flat = cubes[1].reshape(-1)
+    idx = np.random.default_rng(17).choice(flat.numel(), 1024, replace=False)
+    got = flat[torch.from_numpy(idx).to(flat.device)].cpu().numpy()
+    n, ref_cube = _single(gpu, big)
+    assert counts[1] == n > 10_000
+    assert torch.equal(cubes[1], ref_cube)
+    del ref_cube
+    B.close()
+    _, op = orc.trace(big.scene, big.array, big.trace, want_hits=False)
+    assert len(op) == n
+    ref = orc.synth(op, big.scene, big.array, big.chirp, model=0, idx=idx)
+    err = rel_err(got, ref)
+    print(f"3072-channel slot: {n} paths, relative error {err:.2e}, max ratio "
+          f"{np.abs(got - ref).max() / np.abs(ref).max():.2e}")
+    assert err < 1e-4
