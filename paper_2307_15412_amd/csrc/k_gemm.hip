@@ -8,17 +8,24 @@
 //     B[p, n] = exp(-j 2 pi (f0 + B k / K) D_p(m) / c).
 // Phases are formed and reduced modulo one cycle in FP64 (prep kernels).  The
 // GEMM runs in bf16 on v_mfma_f32_32x32x16_bf16 with each operand split into
-// hi + lo bf16 parts (x = hi + lo to ~16 bits); the product keeps hi*hi,
-// hi*lo and lo*hi, accumulated in FP32.  A complex product is four real ones,
-// so each 16-path step issues 12 MFMAs per 32x32 output block.
+// hi + lo bf16 parts (x = hi + lo to ~16 bits); each real product keeps
+// hi*hi, hi*lo and lo*hi, accumulated in FP32.  The complex product uses
+// three real products instead of four (Gauss's method, whose rounding Higham
+// analysed in "Stability of a method for multiplying complex matrices with
+// three real matrix multiplications", 1992):
+//     P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi),
+//     Re = P1 - P2,  Im = P3 - P1 - P2,
+// so each 16-path step issues 9 MFMAs per 32x32 output block (12 with four
+// real products), and both operands carry a third pair of planes for the
+// sums Ar + Ai and Br + Bi, formed in FP32 before the split.
 //
 // A (channels x paths) is prepared once in the MFMA fragment layout, so a
 // wavefront loads each 32x16 operand fragment as one contiguous 1 KiB read.
 // B (paths x samples, up to 1.3e10 entries) is never stored: each workgroup
-// generates its 16 x 128 tile per step into LDS from two 32-bit fixed-point
+// generates its 16 x 64 tile per step into LDS from two 32-bit fixed-point
 // phases per (path, chirp) -- start phase beta and per-sample step gamma,
 // exact modulo 2^32 in integer arithmetic -- one hardware sin/cos per path
-// and lane and complex rotations by a precomputed exp(-j 2 pi 32 gamma).
+// and lane and a complex rotation by a precomputed exp(-j 2 pi 32 gamma).
 #include "rr_internal.h"
 
 namespace {
@@ -26,20 +33,19 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-#ifndef GM_TM
-#define GM_TM 512          // output rows (channels) per workgroup
-#endif
-#ifndef GM_TN
+#define GM_TM 256          // output rows (channels) per workgroup
 #define GM_TN 64           // output columns (chirp, sample) per workgroup
-#endif
 #define GM_KS 16           // paths per MFMA step
-#define GM_THREADS 256     // 4 wavefronts, one per SIMD, 128 x 64 each
-#define GM_WR 4            // 32-row blocks per wavefront
-#define GM_WC 2            // 32-column blocks per wavefront
-#define GM_NCB (GM_TN / 32)             // column blocks per tile
-#define GM_WAVES_C (GM_NCB / GM_WC)     // wavefronts across the columns
-static_assert((GM_TM / 32 / GM_WR) * GM_WAVES_C == GM_THREADS / 64, "wavefront grid");
+#define GM_THREADS 256     // 4 wavefronts, one per SIMD, 64 x 64 each
+#define GM_WR 2            // 32-row blocks per wavefront
+#define GM_NCB (GM_TN / 32)             // 32-column blocks per tile (each wavefront: all)
+#define GM_PL 6            // operand planes: re hi, re lo, im hi, im lo, (re+im) hi, (re+im) lo
+#define GM_NBUF 3          // B tiles in LDS: read one step ahead, generated two ahead
+static_assert((GM_TM / 32 / GM_WR) == GM_THREADS / 64, "wavefront grid");
 #define BFRAG_U4 72        // one B fragment in LDS: 64 lanes + 8 padding (uint4 units)
+#ifndef GM_VPM
+#define GM_VPM 2           // vector instructions scheduled beside each MFMA
+#endif
 
 
 __device__ __forceinline__ double dist3(const double *a, const double *b)
@@ -108,9 +114,9 @@ __device__ __forceinline__ float bf16_float(unsigned short b)
 }
 
 // A[c][p] = T[t][p] R[r][p] split into bf16 hi/lo, in fragment order:
-// uint4 index ((rb * KB + kb) * 4 + plane) * 64 + lane holds rows
+// uint4 index ((rb * KB + kb) * 6 + plane) * 64 + lane holds rows
 // rb*32 + lane%32, paths kb*16 + (lane/32)*8 + 0..7 of plane
-// (0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo).
+// (0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo, 4 (re+im)_hi, 5 (re+im)_lo).
 __global__ void k_prep_a(const float2 *T, const float2 *R, int nrx, int C, int RB, int KB, int Ppad,
                          uint4 *Af)
 {
@@ -122,7 +128,7 @@ __global__ void k_prep_a(const float2 *T, const float2 *R, int nrx, int C, int R
     const int rb = (int)(frag / KB);
     const int row = rb * 32 + (lane & 31);
     const int64_t p0 = (int64_t)kb * GM_KS + (lane >> 5) * 8;
-    unsigned short h[4][8];
+    unsigned short h[GM_PL][8];
     for (int e = 0; e < 8; e++) {
         float re = 0.0f, im = 0.0f;
         if (row < C) {
@@ -131,19 +137,22 @@ __global__ void k_prep_a(const float2 *T, const float2 *R, int nrx, int C, int R
             re = a.x * b.x - a.y * b.y;
             im = a.x * b.y + a.y * b.x;
         }
-        unsigned short rh = bf16_bits(re), ih = bf16_bits(im);
+        const float sm = re + im;
+        unsigned short rh = bf16_bits(re), ih = bf16_bits(im), sh = bf16_bits(sm);
         h[0][e] = rh;
         h[1][e] = bf16_bits(re - bf16_float(rh));
         h[2][e] = ih;
         h[3][e] = bf16_bits(im - bf16_float(ih));
+        h[4][e] = sh;
+        h[5][e] = bf16_bits(sm - bf16_float(sh));
     }
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < GM_PL; q++) {
         uint4 v;
         v.x = h[q][0] | ((unsigned)h[q][1] << 16);
         v.y = h[q][2] | ((unsigned)h[q][3] << 16);
         v.z = h[q][4] | ((unsigned)h[q][5] << 16);
         v.w = h[q][6] | ((unsigned)h[q][7] << 16);
-        Af[(frag * 4 + q) * 64 + lane] = v;
+        Af[(frag * GM_PL + q) * 64 + lane] = v;
     }
 }
 
@@ -203,36 +212,31 @@ __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf1
 
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a), as_bf(b), c, 0, 0, 0)
 
-// One workgroup computes a 512 x 64 output tile with four wavefronts, one
-// per SIMD, stacked along the rows and each owning 128 x 64 (4 x 2 blocks of
-// 32 x 32, accumulators in the AGPR half of the register file).  Per 16-path
-// step a wavefront issues 96 MFMAs.  The tall tile shares each generated B
-// value among 512 rows and gives every A fragment to exactly one wavefront.
+// One workgroup computes a 256 x 64 output tile with four wavefronts, one
+// per SIMD, stacked along the rows and each owning 64 x 64 (2 x 2 blocks of
+// 32 x 32 with three accumulators each, P1, P2, P3: 192 accumulator
+// registers).  Per 16-path step a wavefront issues 36 MFMAs.
 //
 // A fragments go from global memory (L2) straight into registers: each is
-// one contiguous 1 KiB, and the fragments of row block i for step kb + 2 are
-// requested as soon as the MFMAs of row i of step kb have been issued, two
-// steps before they are needed (two register sets alternate).  Only B passes through LDS (two buffers):
-//   first half of step kb: MFMAs of rows 0-1, interleaved with the
-//     generation of B(kb + 1);
-//   barrier (B(kb + 1) complete);
-//   second half: MFMAs of rows 2-3 while the B fragments of step kb + 1 are
-//     read into registers.
+// one contiguous 1 KiB, and the six fragments of row block i for step kb + 2
+// are requested as soon as the MFMAs of row block i of step kb have been
+// issued (two register sets alternate).  B passes through LDS in three
+// buffers, so one barrier per step suffices: in step kb a wavefront reads
+// the fragments of B(kb + 1) into registers while the workgroup generates
+// B(kb + 2); both are spread over the step's MFMAs.
 __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict__ Af,
                                                         const uint4 *__restrict__ Bp, int RB,
                                                         int KB, int Ppad, int C, int M, int K,
                                                         int n_col_tiles, float2 *__restrict__ cube)
 {
-    // B: two buffers x 4 planes (re_hi, re_lo, im_hi, im_lo) x column blocks,
-    // each fragment 64 lanes x 16 B with 128 B of padding after lane 31, so
-    // that the generator's 32-bit writes of both lane halves land in distinct
-    // banks.
-    __shared__ uint4 Bs[2][4 * GM_NCB * BFRAG_U4];
+    // B: three buffers x 6 planes x column blocks, each fragment 64 lanes x
+    // 16 B with 128 B of padding after lane 31, so that the generator's
+    // 32-bit writes of both lane halves land in distinct banks.
+    __shared__ uint4 Bs[GM_NBUF][GM_PL * GM_NCB * BFRAG_U4];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     // wavefront index, uniform by construction (kept in scalar registers)
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wr = w / GM_WAVES_C, wc = w % GM_WAVES_C;
     // XCD-aware order: workgroup b runs on XCD b % 8; each XCD walks its own
     // contiguous run of (row tile, column tile) pairs, row tile slowest, so
     // the workgroups resident on one XCD share A through that XCD's L2.
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
     if (total % 8 == 0) q = (int64_t)(blockIdx.x % 8) * (total / 8) + blockIdx.x / 8;
     const int rt = (int)(q / n_col_tiles);
     const int ct = (int)(q - (int64_t)rt * n_col_tiles);
-    const int rb0 = rt * (GM_TM / 32) + wr * GM_WR;
+    const int rb0 = rt * (GM_TM / 32) + w * GM_WR;
 
     // B generator: path pair (2 pp, 2 pp + 1), columns nb + 32 h, h < GM_NCB
     const int pp = tid & 7;
@@ -257,188 +261,201 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
     const int flane = (p0 >> 3) * 32 + nb;
     // 32-bit word index of (fragment 0, this lane, slots p0 & 7 and +1)
     const int wofs = (flane * 16 + (flane >= 32 ? 128 : 0) + (p0 & 7) * 2) / 4;
-    const uint4 *bprow = Bp + (int64_t)m * Ppad + p0;
+    const uint4 *bprow = Bp + (int64_t)m * Ppad;   // + p0 per lane
+    // words per plane (all column blocks)
+    constexpr int PS = GM_NCB * BFRAG_U4 * 4;
 
-    auto gen = [&](uint4 pa, uint4 pb, uint4 *Bs) {
-        unsigned *bsw = reinterpret_cast<unsigned *>(Bs);
-        float ar, ai, br, bi;
+    // generator state: the phasors of the two paths at the current column
+    struct Gen {
+        float ar, ai, br, bi, rar, rai, rbr, rbi;
+    };
+    // start phasors at column block 0 from the (beta, gamma) words
+    auto gen_start = [&](uint4 pa, uint4 pb) -> Gen {
+        Gen g;
         {
             const float u = (float)(int)(pa.x + kbase * pa.y) * 2.3283064365386963e-10f;
-            ar = __builtin_amdgcn_cosf(u);
-            ai = -__builtin_amdgcn_sinf(u);
+            g.ar = __builtin_amdgcn_cosf(u);
+            g.ai = -__builtin_amdgcn_sinf(u);
         }
         {
             const float u = (float)(int)(pb.x + kbase * pb.y) * 2.3283064365386963e-10f;
-            br = __builtin_amdgcn_cosf(u);
-            bi = -__builtin_amdgcn_sinf(u);
+            g.br = __builtin_amdgcn_cosf(u);
+            g.bi = -__builtin_amdgcn_sinf(u);
         }
-        const float rar = __uint_as_float(pa.z), rai = __uint_as_float(pa.w);
-        const float rbr = __uint_as_float(pb.z), rbi = __uint_as_float(pb.w);
-#pragma unroll
-        for (int h = 0; h < GM_NCB; h++) {
-            if (h > 0) {
-                // advance both phasors by 32 columns
-                float t0 = ar * rar - ai * rai, t1 = ar * rai + ai * rar;
-                ar = t0; ai = t1;
-                t0 = br * rbr - bi * rbi; t1 = br * rbi + bi * rbr;
-                br = t0; bi = t1;
-            }
-            unsigned rh, rl, ih, il;
-            split_bf16(ar, br, rh, rl);
-            split_bf16(ai, bi, ih, il);
-            // word offset of (plane 0, column block h)
-            const int f = h * (BFRAG_U4 * 4);
-            const int ps = GM_NCB * BFRAG_U4 * 4;
-            bsw[f + wofs] = rh;
-            bsw[f + ps + wofs] = rl;
-            bsw[f + 2 * ps + wofs] = ih;
-            bsw[f + 3 * ps + wofs] = il;
+        g.rar = __uint_as_float(pa.z); g.rai = __uint_as_float(pa.w);
+        g.rbr = __uint_as_float(pb.z); g.rbi = __uint_as_float(pb.w);
+        return g;
+    };
+    // the six planes of column block h (after advancing by 32 columns for h > 0)
+    auto gen_block = [&](Gen &g, int h, uint4 *B) {
+        unsigned *bsw = reinterpret_cast<unsigned *>(B);
+        if (h > 0) {
+            float t0 = g.ar * g.rar - g.ai * g.rai, t1 = g.ar * g.rai + g.ai * g.rar;
+            g.ar = t0; g.ai = t1;
+            t0 = g.br * g.rbr - g.bi * g.rbi; t1 = g.br * g.rbi + g.bi * g.rbr;
+            g.br = t0; g.bi = t1;
         }
+        unsigned rh, rl, ih, il, sh, sl;
+        split_bf16(g.ar, g.br, rh, rl);
+        split_bf16(g.ai, g.bi, ih, il);
+        split_bf16(g.ar + g.ai, g.br + g.bi, sh, sl);
+        const int f = h * (BFRAG_U4 * 4) + wofs;
+        bsw[f] = rh;
+        bsw[f + PS] = rl;
+        bsw[f + 2 * PS] = ih;
+        bsw[f + 3 * PS] = il;
+        bsw[f + 4 * PS] = sh;
+        bsw[f + 5 * PS] = sl;
     };
     // A fragments of this wavefront's row blocks: fragment (rb, kb, plane)
-    // is the 1 KiB at Af + ((rb KB + kb) 4 + plane) 64
-    const uint4 *arow = Af + (int64_t)rb0 * KB * 256 + lane;
+    // is the 1 KiB at Af + ((rb KB + kb) 6 + plane) 64; the step's address is
+    // uniform (scalar registers), the lane adds its own 16 bytes
+    const uint4 *arow = Af + (int64_t)rb0 * KB * (GM_PL * 64);
 
-    f32x16 sr[GM_WR][GM_WC], si[GM_WR][GM_WC];
+    f32x16 p1[GM_WR][GM_NCB], p2[GM_WR][GM_NCB], p3[GM_WR][GM_NCB];
 #pragma unroll
     for (int i = 0; i < GM_WR; i++)
 #pragma unroll
-        for (int j = 0; j < GM_WC; j++)
+        for (int j = 0; j < GM_NCB; j++)
 #pragma unroll
-            for (int e = 0; e < 16; e++) { sr[i][j][e] = 0.0f; si[i][j][e] = 0.0f; }
+            for (int e = 0; e < 16; e++) {
+                p1[i][j][e] = 0.0f;
+                p2[i][j][e] = 0.0f;
+                p3[i][j][e] = 0.0f;
+            }
 
     struct ARow {
-        uint4 q[4];
+        uint4 q[GM_PL];
     };
-    // B fragments of two column blocks: planes (re_hi, re_lo, im_hi, im_lo)
-    // in q, the negated imaginary planes for the real part of the product in n
     struct BCols {
-        uint4 q[GM_WC][4];
-        uint4 n[GM_WC][2];
+        uint4 q[GM_NCB][GM_PL];
     };
     auto load_a = [&](int kb, int i) -> ARow {
         ARow a;
-        const uint4 *src = arow + ((int64_t)i * KB + kb) * 256;
+        const uint4 *src = arow + ((int64_t)i * KB + kb) * (GM_PL * 64);
 #pragma unroll
-        for (int p = 0; p < 4; p++) a.q[p] = src[p * 64];
+        for (int p = 0; p < GM_PL; p++) a.q[p] = src[p * 64 + lane];
         return a;
     };
     const int lofs = lane + (lane >= 32 ? 8 : 0);
-    auto load_b = [&](const uint4 *Bs) -> BCols {
+    auto load_b = [&](const uint4 *B) -> BCols {
         BCols b;
 #pragma unroll
-        for (int j = 0; j < GM_WC; j++)
+        for (int j = 0; j < GM_NCB; j++)
 #pragma unroll
-            for (int p = 0; p < 4; p++) b.q[j][p] = Bs[(p * GM_NCB + wc * GM_WC + j) * BFRAG_U4 + lofs];
+            for (int p = 0; p < GM_PL; p++) b.q[j][p] = B[(p * GM_NCB + j) * BFRAG_U4 + lofs];
         return b;
     };
-    // sign flip of the imaginary planes (bf16 negation is exact); applied
-    // well after the LDS reads, so that it never waits for them
-    auto negate = [&](BCols &b) {
+    // P1 += Ar Br, P2 += Ai Bi, P3 += (Ar + Ai)(Br + Bi), each hi*hi + hi*lo + lo*hi
+    // (slot-major over both column blocks: consecutive MFMAs never share an
+    // accumulator, the same one recurs every sixth)
+    auto mma_row = [&](const ARow &a, const BCols &b, int i) {
 #pragma unroll
-        for (int j = 0; j < GM_WC; j++)
+        for (int s = 0; s < 3; s++) {
+            const int ah = s == 2 ? 1 : 0, bl = s == 1 ? 1 : 0;   // hi*hi, hi*lo, lo*hi
 #pragma unroll
-            for (int p = 0; p < 2; p++) {
-                const uint4 v = b.q[j][2 + p];
-                b.n[j][p] = make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u,
-                                       v.w ^ 0x80008000u);
+            for (int j = 0; j < GM_NCB; j++) {
+                p1[i][j] = MFMA(a.q[0 + ah], b.q[j][0 + bl], p1[i][j]);
+                p2[i][j] = MFMA(a.q[2 + ah], b.q[j][2 + bl], p2[i][j]);
+                p3[i][j] = MFMA(a.q[4 + ah], b.q[j][4 + bl], p3[i][j]);
             }
-    };
-    // re += Ar Br + Ai (-Bi) ; im += Ar Bi + Ai Br  (hi*hi + hi*lo + lo*hi)
-    auto mma_row = [&](const ARow a, const BCols &b, int i) {
-#pragma unroll
-        for (int j = 0; j < GM_WC; j++) {
-            sr[i][j] = MFMA(a.q[0], b.q[j][0], sr[i][j]);
-            si[i][j] = MFMA(a.q[0], b.q[j][2], si[i][j]);
-            sr[i][j] = MFMA(a.q[0], b.q[j][1], sr[i][j]);
-            si[i][j] = MFMA(a.q[0], b.q[j][3], si[i][j]);
-            sr[i][j] = MFMA(a.q[1], b.q[j][0], sr[i][j]);
-            si[i][j] = MFMA(a.q[1], b.q[j][2], si[i][j]);
-            sr[i][j] = MFMA(a.q[2], b.n[j][0], sr[i][j]);
-            si[i][j] = MFMA(a.q[2], b.q[j][0], si[i][j]);
-            sr[i][j] = MFMA(a.q[2], b.n[j][1], sr[i][j]);
-            si[i][j] = MFMA(a.q[2], b.q[j][1], si[i][j]);
-            sr[i][j] = MFMA(a.q[3], b.n[j][0], sr[i][j]);
-            si[i][j] = MFMA(a.q[3], b.q[j][0], si[i][j]);
         }
     };
 
-    // prologue: B(0) in LDS, the B parameters of step 1 and the A fragments
-    // of steps 0 and 1 in registers
+    // prologue: B(0) and B(1) in LDS, the B parameters of step 2 and the A
+    // fragments of steps 0 and 1 in registers
     const int last = KB - 1;
-    gen(bprow[0], bprow[1], Bs[0]);
-    uint4 pna = bprow[(int64_t)min(1, last) * GM_KS];
-    uint4 pnb = bprow[(int64_t)min(1, last) * GM_KS + 1];
-    ARow x0 = load_a(0, 0), x1 = load_a(0, 1), x2 = load_a(0, 2), x3 = load_a(0, 3);
+    {
+        Gen g0 = gen_start(bprow[p0], bprow[p0 + 1]);
+#pragma unroll
+        for (int h = 0; h < GM_NCB; h++) gen_block(g0, h, Bs[0]);
+        const int s1 = min(1, last);
+        Gen g1 = gen_start(bprow[(int64_t)s1 * GM_KS + p0], bprow[(int64_t)s1 * GM_KS + p0 + 1]);
+#pragma unroll
+        for (int h = 0; h < GM_NCB; h++) gen_block(g1, h, Bs[1]);
+    }
+    uint4 pna = bprow[(int64_t)min(2, last) * GM_KS + p0];
+    uint4 pnb = bprow[(int64_t)min(2, last) * GM_KS + p0 + 1];
+    ARow x0 = load_a(0, 0), x1 = load_a(0, 1);
     ARow y0 = load_a(min(1, last), 0), y1 = load_a(min(1, last), 1);
-    ARow y2 = load_a(min(1, last), 2), y3 = load_a(min(1, last), 3);
     __syncthreads();
     BCols b0 = load_b(Bs[0]), b1;
-    negate(b0);
 
-    // One step kb on A fragments r0..r3 (of step kb, loaded two steps
-    // earlier) and B fragments bc; refills r0..r3 with step kb + 2 and
-    // returns the B fragments of step kb + 1.
-    auto step = [&](int kb, ARow &r0, ARow &r1, ARow &r2, ARow &r3, const BCols &bc) -> BCols {
+    // One step kb on A fragments r0, r1 (of step kb, loaded two steps
+    // earlier) and B fragments bc; refills r0, r1 with step kb + 2, writes
+    // B(kb + 2) into LDS and returns the B fragments of step kb + 1.
+    auto step = [&](int kb, ARow &r0, ARow &r1, const BCols &bc, const uint4 *Br,
+                    uint4 *Bg) -> BCols {
         const int nx = min(kb + 2, last);
-        uint4 *Bn = Bs[(kb + 1) & 1];
-        const uint4 pca = pna, pcb = pnb;
-        // rows 0-1 with the generation of B(kb + 1) interleaved
-        gen(pca, pcb, Bn);
+        __syncthreads();        // B(kb + 1) complete; the buffer of B(kb + 2) is free
+        BCols bn = load_b(Br);
+        Gen g = gen_start(pna, pnb);
+        // parameters of the next step's generation, a whole step ahead
+        const int nb3 = min(kb + 3, last);
+        pna = bprow[(int64_t)nb3 * GM_KS + p0];
+        pnb = bprow[(int64_t)nb3 * GM_KS + p0 + 1];
+        gen_block(g, 0, Bg);
         mma_row(r0, bc, 0);
 #ifndef GM_FREE_SCHED
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);      // the two parameter loads
 #pragma unroll
-        for (int g = 0; g < 16; g++) {
-            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // 3 VALU
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // up to 1 LDS write
+        for (int t = 0; t < 18; t++) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, GM_VPM, 0);  // GM_VPM VALU
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // up to 1 LDS read
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // up to 1 LDS write
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, 23 - 16, 0);
 #endif
         __builtin_amdgcn_sched_barrier(0);
         r0 = load_a(nx, 0);
-        pna = bprow[(int64_t)nx * GM_KS];
-        pnb = bprow[(int64_t)nx * GM_KS + 1];
+        gen_block(g, 1, Bg);
         mma_row(r1, bc, 1);
+#ifndef GM_FREE_SCHED
+#pragma unroll
+        for (int t = 0; t < 18; t++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, GM_VPM, 0);  // GM_VPM VALU
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // up to 1 LDS write
+        }
+#endif
         __builtin_amdgcn_sched_barrier(0);
         r1 = load_a(nx, 1);
-        __syncthreads();
-        BCols bn = load_b(Bn);
-        mma_row(r2, bc, 2);
-        __builtin_amdgcn_sched_barrier(0);
-        r2 = load_a(nx, 2);
-        negate(bn);
-        mma_row(r3, bc, 3);
-        __builtin_amdgcn_sched_barrier(0);
-        r3 = load_a(nx, 3);
         return bn;
     };
-    // KB is even: the two register sets alternate
-    for (int kb = 0; kb < KB; kb += 2) {
-        b1 = step(kb, x0, x1, x2, x3, b0);
-        b0 = step(kb + 1, y0, y1, y2, y3, b1);
+    // KB is a multiple of 6: the two A register sets and the three B buffers
+    // return to the same places every six steps (constant LDS offsets)
+    for (int kb = 0; kb < KB; kb += 6) {
+        b1 = step(kb, x0, x1, b0, Bs[1], Bs[2]);
+        b0 = step(kb + 1, y0, y1, b1, Bs[2], Bs[0]);
+        b1 = step(kb + 2, x0, x1, b0, Bs[0], Bs[1]);
+        b0 = step(kb + 3, y0, y1, b1, Bs[1], Bs[2]);
+        b1 = step(kb + 4, x0, x1, b0, Bs[2], Bs[0]);
+        b0 = step(kb + 5, y0, y1, b1, Bs[0], Bs[1]);
     }
-    // D layout: register e of lane l is row 8*(e/4) + 4*(l/32) + e%4, column l%32
+    // Re = P1 - P2, Im = P3 - P1 - P2.  D layout: register e of lane l is
+    // row 8*(e/4) + 4*(l/32) + e%4, column l%32
 #pragma unroll
     for (int i = 0; i < GM_WR; i++)
 #pragma unroll
-        for (int j = 0; j < GM_WC; j++)
+        for (int j = 0; j < GM_NCB; j++)
 #pragma unroll
             for (int e = 0; e < 16; e++) {
                 const int row = (rb0 + i) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                const int k = k0 + (wc * GM_WC + j) * 32 + (lane & 31);
+                const int k = k0 + j * 32 + (lane & 31);
+                const float a = p1[i][j][e], b = p2[i][j][e];
                 if (row < C && k < K)
-                    cube[((int64_t)row * M + m) * K + k] = make_float2(sr[i][j][e], si[i][j][e]);
+                    cube[((int64_t)row * M + m) * K + k] = make_float2(a - b, p3[i][j][e] - a - b);
             }
 }
 
 }  // namespace
 
 int gemm_row_pad() { return GM_TM; }
+// bytes of the prepared A operand per (row, path): six bf16 planes
+int gemm_a_bytes() { return 2 * GM_PL; }
 int gemm_col_tile() { return GM_TN; }
-// paths are padded to two steps (the A register sets alternate)
-int gemm_k_step() { return 2 * GM_KS; }
+// paths are padded to six steps (two A register sets, three B buffers)
+int gemm_k_step() { return 6 * GM_KS; }
 
 hipError_t launch_gemm_prep_tr(const SynthArgs &a, int Ppad, float2 *T, float2 *R, hipStream_t s)
 {

@@ -1018,7 +1018,7 @@ static int rr_synth_gemm(rr_ctx *c, const SynthArgs &A)
     int rc;
     if ((rc = c->gT.ensure((size_t)c->ntx * Ppad * 8))) return rc;
     if ((rc = c->gR.ensure((size_t)c->nrx * Ppad * 8))) return rc;
-    if ((rc = c->gA.ensure((size_t)Cpad * Ppad * 8))) return rc;
+    if ((rc = c->gA.ensure((size_t)Cpad * Ppad * gemm_a_bytes()))) return rc;
     if ((rc = c->gB.ensure((size_t)A.M * Ppad * 16))) return rc;
     HIPCHK(launch_gemm_prep_tr(A, (int)Ppad, c->gT.as<float2>(), c->gR.as<float2>(), c->stream));
     HIPCHK(launch_gemm_prep_a(c->gT.as<const float2>(), c->gR.as<const float2>(), c->nrx, C, Cpad,

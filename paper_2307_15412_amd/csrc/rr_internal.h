@@ -218,6 +218,7 @@ hipError_t launch_synth_sampled(const SynthArgs &a, const int64_t *idx, int64_t 
 
 // split-bf16 complex GEMM engine (k_gemm.hip)
 int gemm_row_pad();
+int gemm_a_bytes();
 int gemm_col_tile();
 int gemm_k_step();
 hipError_t launch_gemm_prep_tr(const SynthArgs &a, int Ppad, float2 *T, float2 *R, hipStream_t s);

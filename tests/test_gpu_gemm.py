@@ -1,7 +1,7 @@
 """Split-bf16 complex-GEMM synthesis (separable model) against the FP64
 oracle: relative error <= 1e-3 on the full cube or on seeded sampled
-entries; edge cases of the tiling (channel counts below one 512-row tile or
-just above it, one or three 64-column tiles per chirp, sample counts that end
+entries; edge cases of the tiling (channel counts below one 256-row tile,
+exactly one, just above one or two, one or three 64-column tiles per chirp, sample counts that end
 inside a column tile, odd chirp counts, path counts not divisible by the
 32-path padding, empty path list)."""
 import numpy as np
@@ -65,7 +65,8 @@ def test_ragged_path_counts(gpu, orc, n_keep):
 
 @pytest.mark.parametrize("n_tx,n_rx,K,M,n_keep", [(3, 7, 64, 3, 33), (8, 65, 192, 2, 47),
                                                   (1, 1, 64, 1, 1), (3, 7, 96, 3, 33),
-                                                  (8, 65, 200, 2, 47), (2, 3, 5, 2, 9)])
+                                                  (8, 65, 200, 2, 47), (2, 3, 5, 2, 9),
+                                                  (4, 64, 64, 2, 40), (1, 257, 64, 1, 20)])
 def test_tile_edges(gpu, orc, n_tx, n_rx, K, M, n_keep):
     """Full cubes at channel, column and path counts around the tile sizes;
     the paths of a shared launch feed every channel."""
