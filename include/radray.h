@@ -417,6 +417,20 @@ int rr_proposal_train(rr_ctx *ctx, const float *codes_dev, const float *hist_dev
  * RR_EINVAL (beta outside [0, 1], power outside (0, 2]). */
 int rr_proposal_build(rr_ctx *ctx, const float *code16_dev, float beta, float power);
 
+/* The sampling table of least cube variance per unit of work when both rays
+ * and returned paths cost time (importance sampling: the variance goes as
+ * sum_b m_b / q_b, the work as N (c_ray + c_path sum_b q_b rho_b); with every
+ * return carrying about the same weight, m_b ~ rho_b, and Cauchy-Schwarz gives
+ * q_b ~ sqrt(rho_b / (c_ray + c_path rho_b))).  The network's softmax is read
+ * as the returns density: x_b = n_bins softmax(z)_b (1 on average), and
+ *     q_b ~ sqrt(x_b / (kappa + x_b)),  kappa = c_ray / (c_path rho_mean),
+ * rho_mean the mean returns per ray of a uniform launch; then mixed with the
+ * uniform density as rr_proposal_build does.  A large kappa (rays dominate)
+ * gives the square-root table (power 1/2); a small one (paths dominate) a
+ * table flat over every direction that returns.  Errors as rr_proposal_build,
+ * RR_EINVAL for kappa <= 0. */
+int rr_proposal_build_cost(rr_ctx *ctx, const float *code16_dev, float beta, float kappa);
+
 /* ------------------------------------------------------------------------
  * Batched launch: many scenes of uneven size (triangles, rays, channels,
  * chirps, samples) traced and synthesised (exact model, direct FP32 engine)

@@ -123,6 +123,17 @@ def mixture(z, beta, power=1.0):
     return (1.0 - beta) * softmax(power * np.asarray(z, dtype=np.float64)) + beta / len(z)
 
 
+def mixture_cost(z, beta, kappa):
+    """(1 - beta) d / sum d + beta / n with d = sqrt(x / (kappa + x)) and
+    x = n softmax(z): the density of least variance x work when a ray costs
+    kappa mean returns (importance sampling: variance sum_b x_b / q_b, work
+    kappa + sum_b q_b x_b per ray, minimised together by Cauchy-Schwarz)."""
+    z = np.asarray(z, dtype=np.float64)
+    x = len(z) * softmax(z)
+    d = np.sqrt(x / (kappa + x))
+    return (1.0 - beta) * d / d.sum() + beta / len(z)
+
+
 def cdf_of(q):
     c = np.concatenate([[0.0], np.cumsum(q)])
     c /= c[-1]

@@ -446,6 +446,7 @@ def _declare_proposal(L):
     L.rr_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp]
     L.rr_proposal_train.argtypes = [vp, vp, vp, i32, i32, i32, C.c_float, C.c_uint64, vp]
     L.rr_proposal_build.argtypes = [vp, vp, C.c_float, C.c_float]
+    L.rr_proposal_build_cost.argtypes = [vp, vp, C.c_float, C.c_float]
     _PROP_DECLARED = True
 
 
@@ -529,6 +530,12 @@ class _ProposalMixin:
                                                   int(seed) & (2**64 - 1), loss.ctypes.data))
         return loss[: int(steps)]
 
+    def proposal_build_cost(self, code, beta=0.1, kappa=1.0):
+        """Cost-aware sampling table: q ~ sqrt(x / (kappa + x)), x = n_bins softmax(z)."""
+        code = code.to(self.device, self.torch.float32).contiguous().reshape(16)
+        self._check(self._pl().rr_proposal_build_cost(self.h, _ptr(code), float(beta), float(kappa)))
+        self._keep_code = code
+
     def proposal_build(self, code, beta=0.1, power=0.5):
         code = code.to(self.device, self.torch.float32).contiguous().reshape(16)
         self._check(self._pl().rr_proposal_build(self.h, _ptr(code), float(beta), float(power)))
@@ -540,7 +547,8 @@ for _name, _fn in list(vars(_ProposalMixin).items()):
         setattr(Context, _name, _fn)
 EXPORTED += ["rr_proposal_set_cdf", "rr_proposal_get_cdf", "rr_proposal_probe",
              "rr_proposal_histogram", "rr_mlp_init", "rr_mlp_set_params", "rr_mlp_get_params",
-             "rr_mlp_forward", "rr_mlp_train_step", "rr_proposal_train", "rr_proposal_build"]
+             "rr_mlp_forward", "rr_mlp_train_step", "rr_proposal_train", "rr_proposal_build",
+             "rr_proposal_build_cost"]
 
 
 # --------------------------------------------------------------------------

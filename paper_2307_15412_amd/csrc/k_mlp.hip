@@ -284,11 +284,14 @@ __global__ void k_adam(float *P, const float *G, float *m, float *v, int n, floa
     P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// sampling table for one scene: q_mix = (1 - beta) softmax(power z) + beta /
-// NBINS, cdf[0] = 0, cdf[b + 1] = cdf[b] + q_mix[b] (FP64, block scan),
-// normalised
+// sampling table for one scene: q_mix = (1 - beta) d / sum d + beta / NBINS
+// with d = exp(power z) (kappa = 0: the softmax of power z), or, with kappa >
+// 0, d = sqrt(x / (kappa + x)) where x = NBINS softmax(z) is a bin's fitted
+// return density relative to the mean (the density of least variance x cost
+// when a ray costs kappa mean returns); cdf[0] = 0, cdf[b + 1] = cdf[b] +
+// q_mix[b] (FP64, block scan), normalised
 __global__ __launch_bounds__(1024) void k_build_cdf(const float *z, float beta, float power,
-                                                    double *cdf)
+                                                    float kappa, double *cdf)
 {
     __shared__ double red[1024];
     __shared__ float fred[1024];
@@ -304,10 +307,11 @@ __global__ __launch_bounds__(1024) void k_build_cdf(const float *z, float beta, 
     mx = fred[0];
     __syncthreads();
     // each thread owns 8 consecutive bins
+    const double pw = kappa > 0.0f ? 1.0 : (double)power;
     double e[8];
     double s = 0.0;
     for (int k = 0; k < 8; k++) {
-        e[k] = exp((double)power * ((double)z[t * 8 + k] - (double)mx));
+        e[k] = exp(pw * ((double)z[t * 8 + k] - (double)mx));
         s += e[k];
     }
     red[t] = s;
@@ -316,8 +320,25 @@ __global__ __launch_bounds__(1024) void k_build_cdf(const float *z, float beta, 
         if (t < o) red[t] += red[t + o];
         __syncthreads();
     }
-    const double tot = red[0];
+    double tot = red[0];
     __syncthreads();
+    if (kappa > 0.0f) {
+        // x = NBINS e / tot; d = sqrt(x / (kappa + x)); then normalise d
+        double s2 = 0.0;
+        for (int k = 0; k < 8; k++) {
+            const double x = (double)NBINS * e[k] / tot;
+            e[k] = sqrt(x / ((double)kappa + x));
+            s2 += e[k];
+        }
+        red[t] = s2;
+        __syncthreads();
+        for (int o = 512; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        tot = red[0];
+        __syncthreads();
+    }
     double loc = 0.0;
     double q[8];
     for (int k = 0; k < 8; k++) {
@@ -396,8 +417,9 @@ hipError_t launch_adam(float *P, const float *G, float *m, float *v, float lr, i
     return hipGetLastError();
 }
 
-hipError_t launch_build_cdf(const float *z, float beta, float power, double *cdf, hipStream_t s)
+hipError_t launch_build_cdf(const float *z, float beta, float power, float kappa, double *cdf,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_build_cdf, dim3(1), dim3(1024), 0, s, z, beta, power, cdf);
+    hipLaunchKernelGGL(k_build_cdf, dim3(1), dim3(1024), 0, s, z, beta, power, kappa, cdf);
     return hipGetLastError();
 }

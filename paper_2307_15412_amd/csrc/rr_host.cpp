@@ -1649,12 +1649,8 @@ int rr_proposal_train(rr_ctx *c, const float *codes, const float *hist, int32_t 
     return RR_OK;
 }
 
-int rr_proposal_build(rr_ctx *c, const float *code16, float beta, float power)
+static int proposal_table(rr_ctx *c, const float *code16, float beta, float power, float kappa)
 {
-    if (!c || !code16) return fail(RR_EINVAL, "NULL argument");
-    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
-    if (!(beta >= 0.0f && beta <= 1.0f)) return fail(RR_EINVAL, "beta must be in [0, 1]");
-    if (!(power > 0.0f && power <= 2.0f)) return fail(RR_EINVAL, "power must be in (0, 2]");
     HIPCHK(hipSetDevice(c->device));
     const int nb = RR_PROP_NAZ * RR_PROP_NEL;
     int rc;
@@ -1662,11 +1658,29 @@ int rr_proposal_build(rr_ctx *c, const float *code16, float beta, float power)
     if ((rc = c->cdf.ensure((size_t)(nb + 1) * 8))) return rc;
     HIPCHK(launch_mlp_forward(c->mlp_p.as<const float>(), code16, nb, nullptr, c->mlp_z.as<float>(),
                               c->stream));
-    HIPCHK(launch_build_cdf(c->mlp_z.as<const float>(), beta, power, c->cdf.as<double>(),
+    HIPCHK(launch_build_cdf(c->mlp_z.as<const float>(), beta, power, kappa, c->cdf.as<double>(),
                             c->stream));
     c->n_az = RR_PROP_NAZ;
     c->n_el = RR_PROP_NEL;
     return RR_OK;
+}
+
+int rr_proposal_build(rr_ctx *c, const float *code16, float beta, float power)
+{
+    if (!c || !code16) return fail(RR_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
+    if (!(beta >= 0.0f && beta <= 1.0f)) return fail(RR_EINVAL, "beta must be in [0, 1]");
+    if (!(power > 0.0f && power <= 2.0f)) return fail(RR_EINVAL, "power must be in (0, 2]");
+    return proposal_table(c, code16, beta, power, 0.0f);
+}
+
+int rr_proposal_build_cost(rr_ctx *c, const float *code16, float beta, float kappa)
+{
+    if (!c || !code16) return fail(RR_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(RR_ESTATE, "network not initialised");
+    if (!(beta >= 0.0f && beta <= 1.0f)) return fail(RR_EINVAL, "beta must be in [0, 1]");
+    if (!(kappa > 0.0f) || !std::isfinite(kappa)) return fail(RR_EINVAL, "kappa must be positive");
+    return proposal_table(c, code16, beta, 1.0f, kappa);
 }
 
 // --------------------------------------------------------------------------

@@ -246,7 +246,8 @@ hipError_t launch_mlp_backward(const float *P, const float *dz, int64_t n, const
                                float *d1, float *d2, float *d3, const float *codes, float *part,
                                float *grad, hipStream_t s);
 hipError_t launch_adam(float *P, const float *G, float *m, float *v, float lr, int step, hipStream_t s);
-hipError_t launch_build_cdf(const float *z, float beta, float power, double *cdf, hipStream_t s);
+hipError_t launch_build_cdf(const float *z, float beta, float power, float kappa, double *cdf,
+                            hipStream_t s);
 hipError_t launch_batch_trace(const TraceArgs *scenes, const int64_t *chunk_start, int S,
                               int64_t n_chunks, unsigned long long *work, hipStream_t s);
 hipError_t launch_batch_synth(const SynthArgs *scenes, const BatchSynthInfo *info,

@@ -136,10 +136,21 @@ def test_sampling_table(gpu):
     q1 = np.diff(mlp.cdf_of(mlp.mixture(zr, 0.0, 1.0)))
     qh = np.diff(mlp.cdf_of(mlp.mixture(zr, 0.0, 0.5)))
     assert np.allclose(qh, np.sqrt(q1) / np.sqrt(q1).sum(), rtol=1e-9, atol=0)
+    # the cost-aware table
+    for kappa in (0.003, 1.0, 300.0):
+        gpu.proposal_build_cost(torch.from_numpy(code).cuda(), 0.1, kappa)
+        cdf = gpu.proposal_get_cdf()
+        ref = mlp.cdf_of(mlp.mixture_cost(zr, 0.1, kappa))
+        assert cdf[0] == 0.0 and cdf[-1] == 1.0 and np.all(np.diff(cdf) >= 0)
+        assert np.abs(cdf - ref).max() < 2e-4, kappa
     import paper_2307_15412_amd as rr
     for beta, power in ((0.1, 0.0), (0.1, 2.5), (0.1, float("nan")), (1.5, 0.5)):
         with pytest.raises(rr.RadrayError) as e:
             gpu.proposal_build(torch.from_numpy(code).cuda(), beta, power)
+        assert e.value.code == rr.binding.RR_EINVAL
+    for beta, kappa in ((0.1, 0.0), (0.1, -1.0), (0.1, float("inf")), (-0.1, 1.0)):
+        with pytest.raises(rr.RadrayError) as e:
+            gpu.proposal_build_cost(torch.from_numpy(code).cuda(), beta, kappa)
         assert e.value.code == rr.binding.RR_EINVAL
 
 
@@ -201,16 +212,51 @@ def test_train_loop_equals_single_steps(gpu, batch):
     assert np.array_equal(got, ref)
 
 
+def test_reference_metric(gpu):
+    """The error against the expectation: from two independent references the
+    zero cube scores exactly 1, an independent third launch of the same size
+    scores about the references' own error, and a launch of 16 times more
+    rays about a quarter of it."""
+    import paper_2307_15412_amd as rr
+    from paper_2307_15412_amd import proposal
+    w = sg.workload_box_family(1003, 200_000, points=False)
+    gpu.setup(w)
+    cube = lambda: gpu.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32).reshape(-1).clone()
+    kw = dict(max_bounces=2, record_hits=False)
+    gpu.trace(200_000, seed=1, **kw)
+    a = cube()
+    gpu.trace(200_000, seed=2, **kw)
+    ref = proposal.Reference(a, cube())
+    assert ref.mse(torch.zeros_like(a)) == pytest.approx(1.0, abs=1e-12)
+    e_same = []
+    for sd in range(3, 11):
+        gpu.trace(200_000, seed=sd, **kw)
+        e_same.append(ref.mse(cube()))
+    gpu.trace(3_200_000, seed=99, **kw)
+    e_big = ref.mse(cube())
+    r2 = ref.ref_err() ** 2
+    # a launch like A and B has mean squared error 2 var(R) = 2 r2
+    print(f"reference metric: ref {r2 ** .5:.3f}, same-size {np.mean(e_same) ** .5:.3f}, "
+          f"16x {max(e_big, 0) ** .5:.3f}")
+    assert 0.5 * 2 * r2 < np.mean(e_same) < 2.0 * 2 * r2
+    assert e_big < 0.5 * np.mean(e_same)
+
+
 def test_learned_proposal_gain(gpu):
     """Train on uniform traces of 60 scenes of the box family, then on 10
-    held-out scenes draw 1.25e4 rays from the learned density: the traced
-    part of the cube is closer to a 1e6-ray uniform reference than the cube
-    from 1.25e4 uniform rays."""
+    held-out scenes draw 1e6 rays from the learned density: its cube error
+    against the expectation (two independent 8e6-ray uniform launches, their
+    own noise subtracted; 2 seeds per estimator) is below 0.8 of that of 1e6
+    uniform rays, in at least 7 of 10 scenes.  The budget puts the uniform
+    error below 1 (it falls as ~600 / sqrt(rays) on this family), so that an
+    empty cube (error exactly 1, the negative control) fails the same test."""
     from paper_2307_15412_amd import proposal
     res = proposal.experiment(gpu, train_seeds=range(1, 61), eval_seeds=range(1001, 1011),
-                              train_rays=50_000, budget=12_500, ref_rays=1_000_000, steps=200,
-                              batch=16, lr=2e-3)
+                              train_rays=50_000, budget=1_000_000, ref_rays=8_000_000, steps=200,
+                              batch=16, lr=2e-3, n_seeds=2)
     print({k: v for k, v in res.items() if k != "per_scene"})
     assert res["loss_last"] < res["loss_first"]
-    assert res["err_learned_mean"] < 0.8 * res["err_uniform_mean"]
-    assert res["wins"] >= 7
+    assert res["err_uniform_mean"] < 1.0
+    passes = lambda err: err < 0.8 * res["err_uniform_mean"]
+    assert passes(res["err_learned_mean"]) and res["wins"] >= 7
+    assert not passes(res["err_zero"])

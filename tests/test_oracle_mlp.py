@@ -97,3 +97,33 @@ def test_histogram_definition(orc):
     H = orc.histogram(sc2, arr, tp, hits, paths)
     n_hit = int((hits[:, 0] >= 0).sum())
     assert abs(H.sum() - (len(paths) + 0.1 * n_hit)) < 1e-6
+
+
+def test_cost_aware_density_limits_and_optimality():
+    """The cost-aware table: for a large ray cost it is the square-root
+    table, for a vanishing one the uniform density, and in between it
+    minimises variance x work, V(q) C(q) with V = sum_b x_b / q_b and
+    C = kappa + sum_b q_b x_b: checked against the closed-form minimiser of a
+    two-bin problem and against random perturbations on the simplex."""
+    rng = np.random.default_rng(7)
+    z = rng.normal(0, 2.0, mlp.N_BINS)
+    q_sqrt = mlp.mixture(z, 0.0, 0.5)
+    assert np.abs(mlp.mixture_cost(z, 0.0, 1e12) / q_sqrt - 1).max() < 1e-9
+    assert np.abs(mlp.mixture_cost(z, 0.0, 1e-300) * mlp.N_BINS - 1).max() < 1e-12
+    # two bins, x = (x1, x2): minimise (x1/q + x2/(1-q)) (k + q x1 + (1-q) x2) over q
+    for x1, x2, k in ((3.0, 0.2, 0.5), (1.0, 4.0, 10.0), (0.01, 2.0, 0.001)):
+        qs = np.linspace(1e-6, 1 - 1e-6, 2_000_001)
+        f = (x1 / qs + x2 / (1 - qs)) * (k + qs * x1 + (1 - qs) * x2)
+        q_best = qs[np.argmin(f)]
+        d1, d2 = math.sqrt(x1 / (k + x1)), math.sqrt(x2 / (k + x2))
+        assert abs(q_best - d1 / (d1 + d2)) < 2e-6
+    # random perturbations of the full table never lower V C
+    x = mlp.N_BINS * mlp.softmax(z)
+    for kappa in (0.01, 1.0, 100.0):
+        q = mlp.mixture_cost(z, 0.0, kappa)
+        vc = lambda p: float(np.sum(x / p) * (kappa + np.sum(p * x)))
+        base = vc(q)
+        for _ in range(20):
+            d = rng.normal(size=q.size) * q * 0.05
+            d -= q * d.sum() / q.sum()
+            assert vc(q + d) >= base * (1 - 1e-12)
