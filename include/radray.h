@@ -306,9 +306,9 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
  *          and Rx leg phasors, held to the exact model's 1e-4 bar), or
  *          RR_ENGINE_AUTO: the separable model takes RR_GEMM_BF16X3 when the
  *          64-sample tiling pads a chirp by at most a quarter; the exact model
- *          takes RR_GEMM_EXACT for a shared launch whose 96 x 96 Tx x Rx
- *          tiles are at least half filled and whose leg tables fit its
- *          budget; everything else, and sampled entries, the direct engine.
+ *          takes RR_GEMM_EXACT for a shared launch whose Tx x Rx product
+ *          tiles (32, 64 or 96 square, whichever pads least) are at least
+ *          half filled and whose leg tables fit its budget; everything else, and sampled entries, the direct engine.
  *          AUTO never changes the model, and each engine it picks meets that
  *          model's error bar.
  *   cube_dev complex64 [n_ch][n_chirps][n_samples], cube_elems = its complex

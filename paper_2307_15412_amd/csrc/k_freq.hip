@@ -28,9 +28,9 @@
 namespace {
 
 #define FQ_G 4            // samples per workgroup, one per wavefront
-#define FQ_TILE 96        // Tx and Rx extent of a workgroup tile
 #define FQ_KS 16          // paths per step
-#define FQ_CH 24          // 1 KiB table chunks per step (X and Y, 3 blocks, 4 pieces)
+// a workgroup tile is NB x NB blocks of 32 x 32 (Tx x Rx), NB = 1, 2, 3; per
+// step its table words are 8 NB chunks of 1 KiB (X and Y, NB blocks, 4 pieces)
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -50,12 +50,39 @@ __device__ __forceinline__ double dist3(const double *a, const double *b)
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+// The paths of a synthesis: n records from `paths`, or, with rng given, the
+// records rng[0] .. rng[1] of `paths` (read on the device; a batched launch
+// knows its scenes' path ranges only there), at most Ppad of them (more set
+// *overflow).
+struct PathRange {
+    const SynPath *paths;
+    int64_t n;
+    const int64_t *rng_lo, *rng_hi;
+    int *overflow;
+};
+
+__device__ __forceinline__ void path_range(const PathRange &R, int64_t Ppad, const SynPath *&p,
+                                           int64_t &n)
+{
+    if (R.rng_lo) {
+        const int64_t lo = *R.rng_lo, hi = *R.rng_hi;
+        p = R.paths + lo;
+        n = min(hi - lo, Ppad);
+    } else {
+        p = R.paths;
+        n = R.n;
+    }
+}
+
 // Per (chirp, path): first and last hit point at chirp time and the length
 // between them.  Layout [M][Ppad] of 8 doubles: p1.xyz, pK.xyz, inner, amp.
-__global__ void k_freq_paths(const SynPath *paths, int64_t n, int64_t Ppad, int M, double t_rep,
-                             double *pm)
+__global__ void k_freq_paths(PathRange PR, int64_t Ppad, int M, double t_rep, double *pm)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const SynPath *paths;
+    int64_t n;
+    path_range(PR, Ppad, paths, n);
+    if (g == 0 && PR.rng_lo && PR.overflow && *PR.rng_hi - *PR.rng_lo > Ppad) *PR.overflow = 1;
     if (g >= (int64_t)M * Ppad) return;
     const int m = (int)(g / Ppad);
     const int64_t p = g - (int64_t)m * Ppad;
@@ -86,11 +113,14 @@ __global__ void k_freq_paths(const SynPath *paths, int64_t n, int64_t Ppad, int 
 // Leg tables: xt[m][t][p] for dX = |p1 - tx_t| + inner and yt[m][r][p] for
 // dY = |rx_r - pK|, each (beta, gamma) in fixed-point turns; and per path the
 // amplitude (0 beyond the path count) and source.
-__global__ void k_freq_tables(const double *pm, const SynPath *paths, int64_t n, int64_t Ppad, int M,
-                              const double *tx, int T, const double *rx, int R, double f0c,
-                              double dfc, uint2 *xt, uint2 *yt, float *amp, int32_t *src)
+__global__ void k_freq_tables(const double *pm, PathRange PR, int64_t Ppad, int M, const double *tx,
+                              int T, const double *rx, int R, double f0c, double dfc, uint2 *xt,
+                              uint2 *yt, float *amp, int32_t *src)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const SynPath *paths;
+    int64_t n;
+    path_range(PR, Ppad, paths, n);
     const int64_t per_m = (int64_t)(T + R) * Ppad;
     if (g >= (int64_t)M * per_m) return;
     const int m = (int)(g / per_m);
@@ -189,21 +219,24 @@ struct FreqArgs {
     int partial;
 };
 
-// One workgroup: a 96 x 96 (Tx x Rx) tile of FQ_G consecutive samples of one
-// chirp over one path split; wavefront w owns sample k0 + w and the whole
-// tile (3 x 3 blocks of 32 x 32, real and imaginary accumulators: 288
-// registers, one wavefront per SIMD).  The samples of a workgroup share the
-// table words of every step: the 24 KiB of (beta, gamma) words of the 96 Tx
-// and 96 Rx rows and 16 paths, plus the paths' amplitudes and sources, are
-// loaded once per workgroup (each lane fetching six 16-byte pieces a step
-// ahead into registers) and passed through LDS (two buffers), already in the
-// fragment lane order so that every read is a contiguous 1 KiB.  Each
-// wavefront generates its own X and Y fragments for its sample.  Rows beyond
-// the array's Tx and Rx counts read row 0's words and are never stored.
-template <bool PER_EL>
-__global__ __launch_bounds__(FQ_G * 64, 1) void k_freq_gemm(FreqArgs A)
+// One workgroup: a 32 NB x 32 NB (Tx x Rx) tile of FQ_G consecutive samples
+// of one chirp over one path split; wavefront w owns sample k0 + w and the
+// whole tile (NB x NB blocks of 32 x 32, real and imaginary accumulators:
+// 32 NB^2 registers).  The samples of a workgroup share the table words of
+// every step: the (beta, gamma) words of the tile's Tx and Rx rows and 16
+// paths, plus the paths' amplitudes and sources, are loaded once per
+// workgroup (each lane fetching 2 NB 16-byte pieces a step ahead into
+// registers) and passed through LDS (two buffers), already in the fragment
+// lane order so that every read is a contiguous 1 KiB.  Each wavefront
+// generates its own X and Y fragments for its sample.  Rows beyond the
+// array's Tx and Rx counts read row 0's words and are never stored.
+template <bool PER_EL, int NB>
+__global__ __launch_bounds__(FQ_G * 64, NB == 3 ? 1 : (NB == 2 ? 2 : 4)) void k_freq_gemm(FreqArgs A)
 {
-    __shared__ uint4 Ls[2][FQ_CH + 1][64];
+    constexpr int CH = 8 * NB;            // table chunks per step
+    constexpr int PL = CH / FQ_G;         // pieces per lane
+    constexpr int TILE = 32 * NB;
+    __shared__ uint4 Ls[2][CH + 1][64];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // the sample group fastest: the workgroups that share one split's tables
@@ -223,42 +256,40 @@ __global__ __launch_bounds__(FQ_G * 64, 1) void k_freq_gemm(FreqArgs A)
     const int64_t pbeg = (int64_t)s * A.split_len;
     const int64_t pend = min(A.Ppad, pbeg + A.split_len);
     const int64_t nsteps = (pend - pbeg) / FQ_KS;
-    const int t0 = ti * FQ_TILE, r0 = ri * FQ_TILE;
+    const int t0 = ti * TILE, r0 = ri * TILE;
     const int half = lane >> 5;
 
     // loader: this wavefront fetches chunks q = w + 4 j; chunk q is table
-    // q / 12 (X, Y), block (q % 12) / 4, piece q % 4 (paths 2 (q % 4) and
-    // 2 (q % 4) + 1 of the lane's half); lane l reads row 32 block + l % 32
-    auto piece_ptr = [&](int j) -> const uint4 * {
+    // q / (4 NB) (X, Y), block (q % (4 NB)) / 4, piece q % 4 (paths 2 (q % 4)
+    // and 2 (q % 4) + 1 of the lane's half); lane l reads row 32 block + l % 32
+    const uint4 *lp[PL];
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
         const int q = w + FQ_G * j;
-        const int tab = q / 12, blk = (q % 12) >> 2, c = q & 3;
+        const int tab = q / (4 * NB), blk = (q % (4 * NB)) >> 2, c = q & 3;
         int row = (tab ? r0 : t0) + 32 * blk + (lane & 31);
         if (row >= (tab ? A.R : A.T)) row = 0;    // any valid row: masked later
         const uint2 *base = tab ? A.yt + ((int64_t)m * A.R + row) * A.Ppad
                                 : A.xt + ((int64_t)m * A.T + row) * A.Ppad;
-        return reinterpret_cast<const uint4 *>(base + 8 * half + 2 * c);
-    };
-    static_assert(FQ_CH / FQ_G == 6, "six pieces per lane");
-    const uint4 *lp0 = piece_ptr(0), *lp1 = piece_ptr(1), *lp2 = piece_ptr(2);
-    const uint4 *lp3 = piece_ptr(3), *lp4 = piece_ptr(4), *lp5 = piece_ptr(5);
+        lp[j] = reinterpret_cast<const uint4 *>(base + 8 * half + 2 * c);
+    }
     // amplitudes and sources: wavefront 0, lanes 0-3 (amp) and 4-7 (src)
     const bool aload = w == 0 && lane < 8;
     const uint4 *ap = lane < 4 ? reinterpret_cast<const uint4 *>(A.amp) + (lane & 3)
                                : reinterpret_cast<const uint4 *>(A.src) + (lane & 3);
     // one step's pieces of this lane, fetched a step ahead
-    uint4 P0, P1, P2, P3, P4, P5, PA = make_uint4(0u, 0u, 0u, 0u);
-#define FQ_FETCH(p0)                                                                              \
-    do {                                                                                          \
-        const int64_t h_ = (p0) >> 1;                                                             \
-        P0 = lp0[h_]; P1 = lp1[h_]; P2 = lp2[h_]; P3 = lp3[h_]; P4 = lp4[h_]; P5 = lp5[h_];       \
-        if (aload) PA = ap[(p0) >> 2];                                                            \
-    } while (0)
-#define FQ_STASH(b)                                                                               \
-    do {                                                                                          \
-        Ls[b][w][lane] = P0; Ls[b][w + 4][lane] = P1; Ls[b][w + 8][lane] = P2;                    \
-        Ls[b][w + 12][lane] = P3; Ls[b][w + 16][lane] = P4; Ls[b][w + 20][lane] = P5;             \
-        if (aload) Ls[b][FQ_CH][lane] = PA;                                                       \
-    } while (0)
+    uint4 P[PL], PA = make_uint4(0u, 0u, 0u, 0u);
+    auto fetch = [&](int64_t p0) {
+        const int64_t h = p0 >> 1;
+#pragma unroll
+        for (int j = 0; j < PL; j++) P[j] = lp[j][h];
+        if (aload) PA = ap[p0 >> 2];
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int j = 0; j < PL; j++) Ls[b][w + FQ_G * j][lane] = P[j];
+        if (aload) Ls[b][CH][lane] = PA;
+    };
     auto raw_of = [&](int b, int q0) -> Raw {
         Raw r;
 #pragma unroll
@@ -266,35 +297,35 @@ __global__ __launch_bounds__(FQ_G * 64, 1) void k_freq_gemm(FreqArgs A)
         return r;
     };
 
-    f32x16 sr[3][3], si[3][3];
+    f32x16 sr[NB][NB], si[NB][NB];
 #pragma unroll
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < NB; i++)
 #pragma unroll
-        for (int j = 0; j < 3; j++)
+        for (int j = 0; j < NB; j++)
 #pragma unroll
             for (int e = 0; e < 16; e++) {
                 sr[i][j][e] = 0.0f;
                 si[i][j][e] = 0.0f;
             }
 
-    FQ_FETCH(pbeg);
-    FQ_STASH(0);
-    FQ_FETCH(nsteps > 1 ? pbeg + FQ_KS : pbeg);
+    fetch(pbeg);
+    stash(0);
+    fetch(nsteps > 1 ? pbeg + FQ_KS : pbeg);
     __syncthreads();
     for (int64_t st = 0; st < nsteps; st++) {
         const int b = (int)(st & 1);
-        // Y fragments of the three Rx blocks (zero beyond the array)
-        Frag y[3];
+        // Y fragments of the Rx blocks (zero beyond the array)
+        Frag y[NB];
 #pragma unroll
-        for (int j = 0; j < 3; j++) y[j] = leg_frag(raw_of(b, 12 + 4 * j), ku, nullptr);
+        for (int j = 0; j < NB; j++) y[j] = leg_frag(raw_of(b, 4 * NB + 4 * j), ku, nullptr);
         // amplitudes of the lane's 8 paths; in a per-element launch a path
         // feeds only its own transmitter's rows
-        const uint4 a0 = Ls[b][FQ_CH][2 * half], a1 = Ls[b][FQ_CH][2 * half + 1];
-        const uint4 s0 = Ls[b][FQ_CH][4 + 2 * half], s1 = Ls[b][FQ_CH][5 + 2 * half];
+        const uint4 a0 = Ls[b][CH][2 * half], a1 = Ls[b][CH][2 * half + 1];
+        const uint4 s0 = Ls[b][CH][4 + 2 * half], s1 = Ls[b][CH][5 + 2 * half];
         const unsigned av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
         const unsigned sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
 #pragma unroll
-        for (int i = 0; i < 3; i++) {
+        for (int i = 0; i < NB; i++) {
             const int t = t0 + 32 * i + (lane & 31);
             float a[8];
 #pragma unroll
@@ -305,7 +336,7 @@ __global__ __launch_bounds__(FQ_G * 64, 1) void k_freq_gemm(FreqArgs A)
             const Frag x = leg_frag(raw_of(b, 4 * i), ku, a);
             const uint4 nih = neg(x.ih), nil = neg(x.il);
 #pragma unroll
-            for (int j = 0; j < 3; j++) {
+            for (int j = 0; j < NB; j++) {
                 // re += Xr Yr - Xi Yi, im += Xr Yi + Xi Yr (hi*hi + hi*lo + lo*hi)
                 sr[i][j] = MFMA(x.rh, y[j].rh, sr[i][j]);
                 si[i][j] = MFMA(x.rh, y[j].ih, si[i][j]);
@@ -321,19 +352,17 @@ __global__ __launch_bounds__(FQ_G * 64, 1) void k_freq_gemm(FreqArgs A)
                 si[i][j] = MFMA(x.il, y[j].rh, si[i][j]);
             }
         }
-        if (st + 1 < nsteps) FQ_STASH(b ^ 1);
+        if (st + 1 < nsteps) stash(b ^ 1);
         __syncthreads();
-        FQ_FETCH(st + 2 < nsteps ? pbeg + (st + 2) * FQ_KS : pbeg);
+        fetch(st + 2 < nsteps ? pbeg + (st + 2) * FQ_KS : pbeg);
     }
-#undef FQ_FETCH
-#undef FQ_STASH
     // D layout: register e of lane l is row 8 (e / 4) + 4 (l / 32) + e % 4
     // (a Tx row of block i), column l % 32 (an Rx column of block j)
     if (!kv) return;
 #pragma unroll
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < NB; i++)
 #pragma unroll
-        for (int j = 0; j < 3; j++)
+        for (int j = 0; j < NB; j++)
 #pragma unroll
             for (int e = 0; e < 16; e++) {
                 const int to = t0 + 32 * i + 8 * (e >> 2) + 4 * half + (e & 3);
@@ -376,27 +405,46 @@ __global__ void k_freq_reduce(const float2 *part, int n_split, int T, int R, int
 int freq_k_step() { return FQ_KS; }
 int freq_k_group() { return FQ_G; }
 
-hipError_t launch_freq_prep(const SynPath *paths, int64_t n, int64_t Ppad, int M, double t_rep,
+hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_lo,
+                            const int64_t *rng_hi, int *overflow, int64_t Ppad, int M, double t_rep,
                             const double *tx, int T, const double *rx, int R, double f0c, double dfc,
                             double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
                             hipStream_t s)
 {
     const int64_t n1 = (int64_t)M * Ppad;
     if (n1 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_freq_paths, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, paths, n,
-                       Ppad, M, t_rep, pm);
+    PathRange PR{paths, n, rng_lo, rng_hi, overflow};
+    hipLaunchKernelGGL(k_freq_paths, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, PR, Ppad,
+                       M, t_rep, pm);
     const int64_t n2 = (int64_t)M * (T + R) * Ppad;
-    hipLaunchKernelGGL(k_freq_tables, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, pm, paths,
-                       n, Ppad, M, tx, T, rx, R, f0c, dfc, xt, yt, amp, src);
+    hipLaunchKernelGGL(k_freq_tables, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, pm, PR,
+                       Ppad, M, tx, T, rx, R, f0c, dfc, xt, yt, amp, src);
     return hipGetLastError();
+}
+
+// workgroup tile of NB blocks of 32 (1, 2 or 3) that wastes the least
+// padding on a T x R array (ties: the larger tile)
+int freq_tile_blocks(int T, int R)
+{
+    int best = 3;
+    int64_t best_area = -1;
+    for (int nb = 3; nb >= 1; nb--) {
+        const int64_t t = 32 * nb, area = ((T + t - 1) / t * t) * ((R + t - 1) / t * t);
+        if (best_area < 0 || area < best_area) {
+            best_area = area;
+            best = nb;
+        }
+    }
+    return best;
 }
 
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
-                            int per_element, float2 *partial, float2 *cube, hipStream_t s)
+                            int per_element, int nb, float2 *partial, float2 *cube, hipStream_t s)
 {
     if ((int64_t)n_split * split_len < Ppad || split_len % FQ_KS || Ppad % FQ_KS || Ppad <= 0)
         return hipErrorInvalidValue;
+    if (nb < 1 || nb > 3) return hipErrorInvalidValue;
     FreqArgs A;
     A.xt = xt;
     A.yt = yt;
@@ -407,8 +455,8 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     A.M = M;
     A.K = K;
     A.Ppad = Ppad;
-    A.tt = (T + FQ_TILE - 1) / FQ_TILE;
-    A.rt = (R + FQ_TILE - 1) / FQ_TILE;
+    A.tt = (T + 32 * nb - 1) / (32 * nb);
+    A.rt = (R + 32 * nb - 1) / (32 * nb);
     A.kg = (K + FQ_G - 1) / FQ_G;
     A.n_split = n_split;
     A.split_len = split_len;
@@ -416,10 +464,15 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     A.out = n_split > 1 ? partial : cube;
     const int64_t blocks = (int64_t)n_split * M * A.tt * A.rt * A.kg;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    if (per_element)
-        hipLaunchKernelGGL(k_freq_gemm<true>, dim3((unsigned)blocks), dim3(FQ_G * 64), 0, s, A);
-    else
-        hipLaunchKernelGGL(k_freq_gemm<false>, dim3((unsigned)blocks), dim3(FQ_G * 64), 0, s, A);
+    const dim3 g((unsigned)blocks), t(FQ_G * 64);
+    switch (nb * 2 + (per_element ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_freq_gemm<false, 1>), g, t, 0, s, A); break;
+    case 3: hipLaunchKernelGGL((k_freq_gemm<true, 1>), g, t, 0, s, A); break;
+    case 4: hipLaunchKernelGGL((k_freq_gemm<false, 2>), g, t, 0, s, A); break;
+    case 5: hipLaunchKernelGGL((k_freq_gemm<true, 2>), g, t, 0, s, A); break;
+    case 6: hipLaunchKernelGGL((k_freq_gemm<false, 3>), g, t, 0, s, A); break;
+    default: hipLaunchKernelGGL((k_freq_gemm<true, 3>), g, t, 0, s, A); break;
+    }
     if (n_split > 1) {
         const int64_t per = (int64_t)M * K * T * R;
         hipLaunchKernelGGL(k_freq_reduce, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s,

@@ -1047,8 +1047,9 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
     const int64_t ks = freq_k_step();
     const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
     const int T = c->ntx, R = c->nrx, M = A.M, K = A.K;
+    const int nb = freq_tile_blocks(T, R), tile = 32 * nb;
     const int64_t kg = (K + freq_k_group() - 1) / freq_k_group();
-    const int64_t tiles = (int64_t)M * kg * ((T + 95) / 96) * ((R + 95) / 96);
+    const int64_t tiles = (int64_t)M * kg * ((T + tile - 1) / tile) * ((R + tile - 1) / tile);
     // enough workgroups to fill the chip four times over (one per CU at a
     // time), at least 16 steps of paths each
     int64_t n_split = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
@@ -1064,15 +1065,15 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
     if ((rc = c->fq_src.ensure((size_t)Ppad * 4))) return rc;
     if (n_split > 1 && (rc = c->fq_part.ensure((size_t)n_split * M * K * T * R * 8))) return rc;
     HIPCHK(hipEventRecord(c->ev[2], c->stream));
-    HIPCHK(launch_freq_prep(A.paths, n, Ppad, M, A.t_rep, A.tx, T, A.rx, R, A.f0 * A.inv_c,
+    HIPCHK(launch_freq_prep(A.paths, n, nullptr, nullptr, nullptr, Ppad, M, A.t_rep, A.tx, T, A.rx, R,
+                            A.f0 * A.inv_c,
                             A.bw / (double)K * A.inv_c, c->fq_pm.as<double>(), c->fq_xt.as<uint2>(),
                             c->fq_yt.as<uint2>(), c->fq_amp.as<float>(), c->fq_src.as<int32_t>(),
                             c->stream));
     HIPCHK(launch_freq_gemm(c->fq_xt.as<const uint2>(), c->fq_yt.as<const uint2>(),
                             c->fq_amp.as<const float>(), c->fq_src.as<const int32_t>(), T, R, M, K,
-                            Ppad, (int)n_split, split_len, c->mode != RR_TX_SHARED,
-                            c->fq_part.as<float2>(), A.cube,
-                            c->stream));
+                            Ppad, (int)n_split, split_len, c->mode != RR_TX_SHARED, nb,
+                            c->fq_part.as<float2>(), A.cube, c->stream));
     return RR_OK;
 }
 
@@ -1092,9 +1093,11 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
         engine = (model == RR_SEPARABLE && !idx && 4 * Kp <= 5 * K) ? RR_GEMM_BF16X3
                                                                      : RR_DIRECT_FP32;
         // the exact model as per-sample products: for a shared launch whose
-        // 96 x 96 tiles are well filled and whose leg tables fit the budget
+        // product tiles are at least half filled and whose leg tables fit the
+        // budget
         if (model == RR_EXACT && !idx && c->mode == RR_TX_SHARED && c->n_paths > 0) {
-            const int64_t tp = (int64_t)((c->ntx + 95) / 96) * 96, rp = (int64_t)((c->nrx + 95) / 96) * 96;
+            const int64_t tl = 32 * freq_tile_blocks(c->ntx, c->nrx);
+            const int64_t tp = (c->ntx + tl - 1) / tl * tl, rp = (c->nrx + tl - 1) / tl * tl;
             if (2 * (int64_t)c->ntx * c->nrx >= tp * rp && freq_table_bytes(c, c->n_paths) <= FREQ_TABLE_MAX)
                 engine = RR_GEMM_EXACT;
         }
