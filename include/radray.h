@@ -433,11 +433,18 @@ int rr_proposal_build_cost(rr_ctx *ctx, const float *code16_dev, float beta, flo
 
 /* ------------------------------------------------------------------------
  * Batched launch: many scenes of uneven size (triangles, rays, channels,
- * chirps, samples) traced and synthesised (exact model, direct FP32 engine)
- * by one persistent trace kernel and one persistent synthesis kernel that
- * pull (scene, chunk) and (scene, tile) items from device counters.  The
- * whole stage sequence is captured once as a hipGraph and replayed; the
- * per-scene synthesis tile (samples per lane) comes from rr_batch_tune.
+ * chirps, samples) traced and synthesised (exact model) in one captured
+ * launch.  One persistent trace kernel pulls (scene, chunk) items from a
+ * device counter; synthesis runs per scene on one of two engines: the direct
+ * FP32 engine (one persistent kernel over (scene, tile) items of every scene
+ * that uses it) or the exact product engine of rr_synthesize's
+ * RR_GEMM_EXACT (split-bf16 Tx x Rx products per sample on MFMA, kernels of
+ * their own per scene, one scene after another on shared leg tables, each
+ * reading its path range on the device).  Both meet the exact model's FP32
+ * bar (relative error <= 1e-4).  The whole stage sequence is captured once as
+ * a hipGraph and replayed; the engine, the product tile and the direct
+ * engine's tile (samples per lane) per scene come from rr_batch_tune, or
+ * from rr_batch_set_engine.
  * ------------------------------------------------------------------------ */
 typedef struct rr_batch rr_batch;
 
@@ -464,20 +471,39 @@ int rr_batch_set_alpha(rr_batch *batch, int32_t slot, const float *alpha, int64_
 
 /* Run the batch: cubes[s] is scene s's complex64 [n_ch][n_chirps][n_samples]
  * device buffer.  The first launch (or the first after a change) captures the
- * pipeline as a hipGraph; later launches replay it (new cube pointers only
- * update a device table).  The call waits for completion and checks the path
- * pool, growing it and re-running if it overflowed.  n_paths_out (host
- * int64 [n_scenes], may be NULL) receives each scene's path count. */
+ * pipeline as a hipGraph; later launches replay it (new cube pointers update
+ * a device table, or re-capture when a scene uses the product engine).  The
+ * call waits for completion and checks the path pool and the product
+ * engine's leg-table capacity of every scene using it (sized from the
+ * previous launch's count, else from the ray budget), growing them and
+ * re-running if one overflowed.  n_paths_out (host int64 [n_scenes], may be
+ * NULL) receives each scene's path count. */
 int rr_batch_launch(rr_batch *batch, void *const *cubes, int64_t *n_paths_out);
 
-/* Autotune the synthesis tile: run the batch once into `cubes` for its paths,
- * then for every distinct sample count time each candidate samples-per-lane
- * value on the scenes with that count, over at most the first 2048 paths of
- * each path group (synthesis time is linear in the path count), and keep the
- * fastest.  Afterwards the cubes hold partial sums: run rr_batch_launch to
- * fill them.  rr_batch_get_tiles reports the choice per scene. */
+/* Autotune the synthesis: run the batch once into `cubes` for its paths,
+ * then, over at most the first 2048 paths of each path group (synthesis time
+ * is linear in the path count): for every distinct sample count time each
+ * candidate samples-per-lane value of the direct engine on the scenes with
+ * that count and keep the fastest; then per scene left to RR_ENGINE_AUTO
+ * time the direct engine against the product engine at every tile (32, 64,
+ * 96) that pads at most twice the least padding (shared launches only), and
+ * keep the product engine if it is faster by a tenth and 20 us.  Afterwards
+ * the cubes hold partial sums: run rr_batch_launch to fill them.
+ * rr_batch_get_tiles reports the direct engine's samples per lane per scene;
+ * rr_batch_get_plan the engine each scene runs on (RR_DIRECT_FP32 or
+ * RR_GEMM_EXACT, both host int32 [n_scenes]) and its tile (samples per lane,
+ * or the product tile's Tx and Rx extent).  Untuned scenes left to AUTO take
+ * rr_synthesize's rule (the product engine for a shared launch whose tiles
+ * are at least half filled, tables within 16 GiB). */
 int rr_batch_tune(rr_batch *batch, void *const *cubes);
 int rr_batch_get_tiles(rr_batch *batch, int32_t *samples_per_lane_out);
+int rr_batch_get_plan(rr_batch *batch, int32_t *engine_out, int32_t *tile_out);
+
+/* Pin slot `slot`'s synthesis engine: RR_ENGINE_AUTO (default: the tuner's
+ * or the rule's choice), RR_DIRECT_FP32, or RR_GEMM_EXACT with tile 32, 64
+ * or 96 (0: least padding).  Invalidates the captured graph.
+ * Errors: RR_EINVAL (slot, engine, tile). */
+int rr_batch_set_engine(rr_batch *batch, int32_t slot, int32_t engine, int32_t tile);
 
 /* Timing (ms, HIP events around the graph launch) of the last launch, the
  * synthesis stage of the last autotuner run, and the last total path count. */

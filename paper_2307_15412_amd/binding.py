@@ -568,6 +568,8 @@ def _declare_batch(L):
     L.rr_batch_launch.argtypes = [vp, vp, vp]
     L.rr_batch_tune.argtypes = [vp, vp]
     L.rr_batch_get_tiles.argtypes = [vp, vp]
+    L.rr_batch_get_plan.argtypes = [vp, vp, vp]
+    L.rr_batch_set_engine.argtypes = [vp, i32, i32, i32]
     L.rr_batch_stats.argtypes = [vp, C.POINTER(f64), C.POINTER(f64), C.POINTER(i64)]
     L._batch_declared = True
 
@@ -655,6 +657,19 @@ class Batch:
         self.ctx._check(self.lib.rr_batch_get_tiles(self.h, tiles.ctypes.data))
         return tiles
 
+    def set_engine(self, slot, engine=ENGINE_AUTO, tile=0):
+        """Pin slot's synthesis engine (ENGINE_AUTO, DIRECT_FP32, or
+        GEMM_EXACT with product tile 32, 64 or 96; 0 = least padding)."""
+        self.ctx._check(self.lib.rr_batch_set_engine(self.h, int(slot), int(engine), int(tile)))
+
+    def plan(self):
+        """(engine, tile) per scene: DIRECT_FP32 with its samples per lane, or
+        GEMM_EXACT with its product tile."""
+        e = np.zeros(self.n, dtype=np.int32)
+        t = np.zeros(self.n, dtype=np.int32)
+        self.ctx._check(self.lib.rr_batch_get_plan(self.h, e.ctypes.data, t.ctypes.data))
+        return e, t
+
     def stats(self):
         a, b, n = C.c_double(), C.c_double(), C.c_int64()
         self.ctx._check(self.lib.rr_batch_stats(self.h, C.byref(a), C.byref(b), C.byref(n)))
@@ -663,4 +678,5 @@ class Batch:
 
 EXPORTED += ["rr_batch_create", "rr_batch_destroy", "rr_batch_set_scene", "rr_batch_set_alpha",
              "rr_batch_launch",
-             "rr_batch_tune", "rr_batch_get_tiles", "rr_batch_stats"]
+             "rr_batch_tune", "rr_batch_get_tiles", "rr_batch_get_plan", "rr_batch_set_engine",
+             "rr_batch_stats"]

@@ -36,6 +36,7 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double frac(double x) { return x - floor(x); }
 
@@ -50,27 +51,30 @@ __device__ __forceinline__ double dist3(const double *a, const double *b)
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
-// The paths of a synthesis: n records from `paths`, or, with rng given, the
-// records rng[0] .. rng[1] of `paths` (read on the device; a batched launch
-// knows its scenes' path ranges only there), at most Ppad of them (more set
-// *overflow).
+// The paths of a synthesis: n records from `paths`, or, with rng_lo given,
+// the records *rng_lo .. *rng_hi of `paths`, read on the device (a batched
+// launch knows its scenes' path ranges only there), at most Ppad of them (the
+// caller checks the count against its capacity afterwards).
 struct PathRange {
     const SynPath *paths;
     int64_t n;
     const int64_t *rng_lo, *rng_hi;
-    int *overflow;
 };
 
+// the path records and count of a synthesis, and the padded count the
+// product reads (a multiple of FQ_KS; table entries beyond it are not needed)
 __device__ __forceinline__ void path_range(const PathRange &R, int64_t Ppad, const SynPath *&p,
-                                           int64_t &n)
+                                           int64_t &n, int64_t &used)
 {
     if (R.rng_lo) {
         const int64_t lo = *R.rng_lo, hi = *R.rng_hi;
         p = R.paths + lo;
-        n = min(hi - lo, Ppad);
+        n = min(max(hi - lo, (int64_t)0), Ppad);
+        used = (n + FQ_KS - 1) / FQ_KS * FQ_KS;
     } else {
         p = R.paths;
         n = R.n;
+        used = Ppad;
     }
 }
 
@@ -80,12 +84,12 @@ __global__ void k_freq_paths(PathRange PR, int64_t Ppad, int M, double t_rep, do
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const SynPath *paths;
-    int64_t n;
-    path_range(PR, Ppad, paths, n);
-    if (g == 0 && PR.rng_lo && PR.overflow && *PR.rng_hi - *PR.rng_lo > Ppad) *PR.overflow = 1;
+    int64_t n, used;
+    path_range(PR, Ppad, paths, n, used);
     if (g >= (int64_t)M * Ppad) return;
     const int m = (int)(g / Ppad);
     const int64_t p = g - (int64_t)m * Ppad;
+    if (p >= used) return;
     double *o = pm + 8 * g;
     if (p >= n) {
         for (int q = 0; q < 8; q++) o[q] = 0.0;
@@ -119,14 +123,15 @@ __global__ void k_freq_tables(const double *pm, PathRange PR, int64_t Ppad, int 
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const SynPath *paths;
-    int64_t n;
-    path_range(PR, Ppad, paths, n);
+    int64_t n, used;
+    path_range(PR, Ppad, paths, n, used);
     const int64_t per_m = (int64_t)(T + R) * Ppad;
     if (g >= (int64_t)M * per_m) return;
     const int m = (int)(g / per_m);
     const int64_t rem = g - (int64_t)m * per_m;
     const int i = (int)(rem / Ppad);
     const int64_t p = rem - (int64_t)i * Ppad;
+    if (p >= used) return;
     const double *o = pm + 8 * ((int64_t)m * Ppad + p);
     uint2 v = make_uint2(0u, 0u);
     if (p < n) {
@@ -217,6 +222,9 @@ struct FreqArgs {
     int64_t split_len;        // paths per split (multiple of FQ_KS)
     float2 *out;              // cube (one split) or partial tiles [split][m][k][T][R]
     int partial;
+    // with rng_lo: the path count is *rng_hi - *rng_lo (at most Ppad), read
+    // on the device, and the splits divide its padded count evenly
+    const int64_t *rng_lo, *rng_hi;
 };
 
 // One workgroup: a 32 NB x 32 NB (Tx x Rx) tile of FQ_G consecutive samples
@@ -231,7 +239,8 @@ struct FreqArgs {
 // generates its own X and Y fragments for its sample.  Rows beyond the
 // array's Tx and Rx counts read row 0's words and are never stored.
 template <bool PER_EL, int NB>
-__global__ __launch_bounds__(FQ_G * 64, NB == 3 ? 1 : (NB == 2 ? 2 : 4)) void k_freq_gemm(FreqArgs A)
+__global__ __launch_bounds__(FQ_G * 64, NB == 3 || (NB == 2 && PER_EL) ? 1 : (NB == 2 ? 2 : 4)) void
+k_freq_gemm(FreqArgs A)
 {
     constexpr int CH = 8 * NB;            // table chunks per step
     constexpr int PL = CH / FQ_G;         // pieces per lane
@@ -253,16 +262,23 @@ __global__ __launch_bounds__(FQ_G * 64, NB == 3 ? 1 : (NB == 2 ? 2 : 4)) void k_
     const int kw = kq * FQ_G + w;
     const bool kv = kw < A.K;
     const unsigned ku = (unsigned)(kv ? kw : A.K - 1);
-    const int64_t pbeg = (int64_t)s * A.split_len;
-    const int64_t pend = min(A.Ppad, pbeg + A.split_len);
-    const int64_t nsteps = (pend - pbeg) / FQ_KS;
+    int64_t used = A.Ppad, split_len = A.split_len;
+    if (A.rng_lo) {
+        const int64_t n = min(max(*A.rng_hi - *A.rng_lo, (int64_t)0), A.Ppad);
+        used = (n + FQ_KS - 1) / FQ_KS * FQ_KS;
+        split_len = ((used + A.n_split - 1) / A.n_split + FQ_KS - 1) / FQ_KS * FQ_KS;
+    }
+    const int64_t pstart = (int64_t)s * split_len;
+    const int64_t nsteps = max(min(used, pstart + split_len) - pstart, (int64_t)0) / FQ_KS;
+    // an empty split still writes its (zero) tile; its loads stay at path 0
+    const int64_t pbeg = nsteps > 0 ? pstart : 0;
     const int t0 = ti * TILE, r0 = ri * TILE;
     const int half = lane >> 5;
 
     // loader: this wavefront fetches chunks q = w + 4 j; chunk q is table
     // q / (4 NB) (X, Y), block (q % (4 NB)) / 4, piece q % 4 (paths 2 (q % 4)
     // and 2 (q % 4) + 1 of the lane's half); lane l reads row 32 block + l % 32
-    const uint4 *lp[PL];
+    const u32x4 *lp[PL];
 #pragma unroll
     for (int j = 0; j < PL; j++) {
         const int q = w + FQ_G * j;
@@ -271,25 +287,26 @@ __global__ __launch_bounds__(FQ_G * 64, NB == 3 ? 1 : (NB == 2 ? 2 : 4)) void k_
         if (row >= (tab ? A.R : A.T)) row = 0;    // any valid row: masked later
         const uint2 *base = tab ? A.yt + ((int64_t)m * A.R + row) * A.Ppad
                                 : A.xt + ((int64_t)m * A.T + row) * A.Ppad;
-        lp[j] = reinterpret_cast<const uint4 *>(base + 8 * half + 2 * c);
+        lp[j] = reinterpret_cast<const u32x4 *>(base + 8 * half + 2 * c);
     }
     // amplitudes and sources: wavefront 0, lanes 0-3 (amp) and 4-7 (src)
     const bool aload = w == 0 && lane < 8;
-    const uint4 *ap = lane < 4 ? reinterpret_cast<const uint4 *>(A.amp) + (lane & 3)
-                               : reinterpret_cast<const uint4 *>(A.src) + (lane & 3);
+    const u32x4 *ap = lane < 4 ? reinterpret_cast<const u32x4 *>(A.amp) + (lane & 3)
+                               : reinterpret_cast<const u32x4 *>(A.src) + (lane & 3);
     // one step's pieces of this lane, fetched a step ahead
-    uint4 P[PL], PA = make_uint4(0u, 0u, 0u, 0u);
-    auto fetch = [&](int64_t p0) {
-        const int64_t h = p0 >> 1;
-#pragma unroll
-        for (int j = 0; j < PL; j++) P[j] = lp[j][h];
-        if (aload) PA = ap[p0 >> 2];
-    };
-    auto stash = [&](int b) {
-#pragma unroll
-        for (int j = 0; j < PL; j++) Ls[b][w + FQ_G * j][lane] = P[j];
-        if (aload) Ls[b][CH][lane] = PA;
-    };
+    u32x4 P[PL], PA = {0u, 0u, 0u, 0u};
+#define FQ_FETCH(p0)                                                                              \
+    do {                                                                                          \
+        const int64_t h_ = (p0) >> 1;                                                             \
+        _Pragma("unroll") for (int j_ = 0; j_ < PL; j_++) P[j_] = lp[j_][h_];                     \
+        if (aload) PA = ap[(p0) >> 2];                                                            \
+    } while (0)
+#define FQ_STASH(b_)                                                                              \
+    do {                                                                                          \
+        _Pragma("unroll") for (int j_ = 0; j_ < PL; j_++)                                         \
+            *reinterpret_cast<u32x4 *>(&Ls[b_][w + FQ_G * j_][lane]) = P[j_];                     \
+        if (aload) *reinterpret_cast<u32x4 *>(&Ls[b_][CH][lane]) = PA;                            \
+    } while (0)
     auto raw_of = [&](int b, int q0) -> Raw {
         Raw r;
 #pragma unroll
@@ -308,9 +325,9 @@ __global__ __launch_bounds__(FQ_G * 64, NB == 3 ? 1 : (NB == 2 ? 2 : 4)) void k_
                 si[i][j][e] = 0.0f;
             }
 
-    fetch(pbeg);
-    stash(0);
-    fetch(nsteps > 1 ? pbeg + FQ_KS : pbeg);
+    FQ_FETCH(pbeg);
+    FQ_STASH(0);
+    FQ_FETCH(nsteps > 1 ? pbeg + FQ_KS : pbeg);
     __syncthreads();
     for (int64_t st = 0; st < nsteps; st++) {
         const int b = (int)(st & 1);
@@ -352,10 +369,12 @@ __global__ __launch_bounds__(FQ_G * 64, NB == 3 ? 1 : (NB == 2 ? 2 : 4)) void k_
                 si[i][j] = MFMA(x.il, y[j].rh, si[i][j]);
             }
         }
-        if (st + 1 < nsteps) stash(b ^ 1);
+        if (st + 1 < nsteps) FQ_STASH(b ^ 1);
         __syncthreads();
-        fetch(st + 2 < nsteps ? pbeg + (st + 2) * FQ_KS : pbeg);
+        FQ_FETCH(st + 2 < nsteps ? pbeg + (st + 2) * FQ_KS : pbeg);
     }
+#undef FQ_FETCH
+#undef FQ_STASH
     // D layout: register e of lane l is row 8 (e / 4) + 4 (l / 32) + e % 4
     // (a Tx row of block i), column l % 32 (an Rx column of block j)
     if (!kv) return;
@@ -406,14 +425,14 @@ int freq_k_step() { return FQ_KS; }
 int freq_k_group() { return FQ_G; }
 
 hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_lo,
-                            const int64_t *rng_hi, int *overflow, int64_t Ppad, int M, double t_rep,
+                            const int64_t *rng_hi, int64_t Ppad, int M, double t_rep,
                             const double *tx, int T, const double *rx, int R, double f0c, double dfc,
                             double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
                             hipStream_t s)
 {
     const int64_t n1 = (int64_t)M * Ppad;
     if (n1 <= 0) return hipSuccess;
-    PathRange PR{paths, n, rng_lo, rng_hi, overflow};
+    PathRange PR{paths, n, rng_lo, rng_hi};
     hipLaunchKernelGGL(k_freq_paths, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, PR, Ppad,
                        M, t_rep, pm);
     const int64_t n2 = (int64_t)M * (T + R) * Ppad;
@@ -440,7 +459,8 @@ int freq_tile_blocks(int T, int R)
 
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
-                            int per_element, int nb, float2 *partial, float2 *cube, hipStream_t s)
+                            int per_element, int nb, const int64_t *rng_lo, const int64_t *rng_hi,
+                            float2 *partial, float2 *cube, hipStream_t s)
 {
     if ((int64_t)n_split * split_len < Ppad || split_len % FQ_KS || Ppad % FQ_KS || Ppad <= 0)
         return hipErrorInvalidValue;
@@ -462,6 +482,8 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     A.split_len = split_len;
     A.partial = n_split > 1;
     A.out = n_split > 1 ? partial : cube;
+    A.rng_lo = rng_lo;
+    A.rng_hi = rng_hi;
     const int64_t blocks = (int64_t)n_split * M * A.tt * A.rt * A.kg;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const dim3 g((unsigned)blocks), t(FQ_G * 64);

@@ -1065,15 +1065,15 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
     if ((rc = c->fq_src.ensure((size_t)Ppad * 4))) return rc;
     if (n_split > 1 && (rc = c->fq_part.ensure((size_t)n_split * M * K * T * R * 8))) return rc;
     HIPCHK(hipEventRecord(c->ev[2], c->stream));
-    HIPCHK(launch_freq_prep(A.paths, n, nullptr, nullptr, nullptr, Ppad, M, A.t_rep, A.tx, T, A.rx, R,
-                            A.f0 * A.inv_c,
-                            A.bw / (double)K * A.inv_c, c->fq_pm.as<double>(), c->fq_xt.as<uint2>(),
+    HIPCHK(launch_freq_prep(A.paths, n, nullptr, nullptr, Ppad, M, A.t_rep, A.tx, T, A.rx, R,
+                            A.f0 * A.inv_c, A.bw / (double)K * A.inv_c, c->fq_pm.as<double>(),
+                            c->fq_xt.as<uint2>(),
                             c->fq_yt.as<uint2>(), c->fq_amp.as<float>(), c->fq_src.as<int32_t>(),
                             c->stream));
     HIPCHK(launch_freq_gemm(c->fq_xt.as<const uint2>(), c->fq_yt.as<const uint2>(),
                             c->fq_amp.as<const float>(), c->fq_src.as<const int32_t>(), T, R, M, K,
-                            Ppad, (int)n_split, split_len, c->mode != RR_TX_SHARED, nb,
-                            c->fq_part.as<float2>(), A.cube, c->stream));
+                            Ppad, (int)n_split, split_len, c->mode != RR_TX_SHARED, nb, nullptr,
+                            nullptr, c->fq_part.as<float2>(), A.cube, c->stream));
     return RR_OK;
 }
 
@@ -1704,6 +1704,18 @@ struct BatchScene {
     rr_trace_params tp{};
     int64_t n_src = 0, n_per_src = 0, n_vps = 0, V = 0;
     int kr = 0;
+    // synthesis engine: requested (RR_ENGINE_AUTO, RR_DIRECT_FP32 or
+    // RR_GEMM_EXACT, tile 0 or 32/64/96), the autotuner's choice for AUTO
+    // (-1: not tuned), and the plan of the current graph
+    int req_engine = RR_ENGINE_AUTO, req_tile = 0;
+    int tuned_engine = -1, tuned_nb = 0;
+    int try_engine = -1, try_nb = 0;      // forced plan while the tuner times a candidate
+    bool use_freq = false;
+    int nb = 0;                           // exact engine: tile blocks (tile 32 nb)
+    int64_t fq_cap = 0;                   // exact engine: leg table capacity (paths)
+    int fq_split = 1;
+    int64_t fq_ppad = 0, fq_split_len = 0;  // table stride and split length of the graph
+    int64_t n_last = -1;                  // path count of the last launch
     void release()
     {
         DevBuf *b[] = {&nodes, &ltris, &obj_alpha, &obj_vel, &pt_pos, &pt_vel, &pt_ap, &tx, &rx};
@@ -1730,7 +1742,9 @@ struct rr_batch {
     DevBuf counts, offsets, bsums, total, counter, work;
     PathStore tmp, fin;
     DevBuf syn, alpha_tmp;
+    DevBuf fq_pm, fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact engine, shared by its scenes
     int64_t cap = 0, V_total = 0, n_chunks = 0, n_items = 0, n_ranges = 0, nb = 0;
+    std::vector<char> synth_on;           // scenes the synthesis stage computes
     std::vector<int64_t> range_base;
     std::vector<void *> cubes;
     hipGraph_t graph = nullptr;
@@ -1751,10 +1765,55 @@ void batch_drop_graph(rr_batch *b)
     b->dirty = true;
 }
 
+// leg table bytes of the exact engine for a scene at a path capacity
+int64_t batch_freq_bytes(const BatchScene &x, int64_t cap)
+{
+    return (int64_t)x.chirp.n_chirps * cap * (8 * (x.ntx + x.nrx) + 64);
+}
+
+// the exact engine's table budget for AUTO in a batch (the tables are shared
+// by the scenes that use it, one after the other)
+const int64_t BATCH_FREQ_TABLE_MAX = (int64_t)16 << 30;
+
+// the synthesis plan of scene x: the exact product engine (and its tile) or
+// the direct engine, and the exact engine's table capacity
+void batch_plan(BatchScene &x)
+{
+    const int64_t ks = freq_k_step();
+    const int64_t est = x.n_src * x.n_per_src / 16 + x.n_src * x.npts;
+    const int64_t want = x.n_last >= 0 ? x.n_last + x.n_last / 4 + 1024 : est;
+    // start from the estimate; follow the last launch's count down when the
+    // capacity is more than twice what it needs (growth comes from overflow)
+    if (x.fq_cap <= 0 || x.fq_cap > 2 * want) x.fq_cap = want;
+    x.fq_cap = std::max<int64_t>((x.fq_cap + ks - 1) / ks * ks, ks);
+    int eng = x.req_engine, nb = x.req_tile / 32;
+    if (x.try_engine >= 0) {
+        eng = x.try_engine;
+        nb = x.try_nb;
+    } else if (eng == RR_ENGINE_AUTO && x.tuned_engine >= 0) {
+        eng = x.tuned_engine;
+        nb = x.tuned_nb;
+    }
+    if (nb <= 0) nb = freq_tile_blocks(x.ntx, x.nrx);
+    if (eng == RR_ENGINE_AUTO) {
+        // untuned: the single-scene rule (a shared launch whose product
+        // tiles are at least half filled), within the table budget
+        const int64_t tl = 32 * nb;
+        const int64_t tp = (x.ntx + tl - 1) / tl * tl, rp = (x.nrx + tl - 1) / tl * tl;
+        eng = x.mode == RR_TX_SHARED && 2 * (int64_t)x.ntx * x.nrx >= tp * rp &&
+                      batch_freq_bytes(x, x.fq_cap) <= BATCH_FREQ_TABLE_MAX
+                  ? RR_GEMM_EXACT
+                  : RR_DIRECT_FP32;
+    }
+    x.use_freq = eng == RR_GEMM_EXACT;
+    x.nb = nb;
+}
+
 // per-scene tables and global buffers for the current scene set and cubes;
-// only_K > 0 gives synthesis work to the scenes with that sample count alone
-// and p_limit > 0 caps the paths of each group (both for tile timing)
-int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0)
+// only_K > 0 gives synthesis work to the scenes with that sample count alone,
+// only_scene >= 0 to that scene alone, and p_limit > 0 caps the paths of each
+// group (all three for the autotuner's timing)
+int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0, int only_scene = -1)
 {
     const int S = b->S;
     std::vector<TraceArgs> ta(S);
@@ -1764,6 +1823,7 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0)
     std::vector<BatchRangeInfo> ri(S);
     std::vector<int64_t> chunk(S + 1, 0), items(S + 1, 0), vr(S + 1, 0);
     b->range_base.assign(S + 1, 0);
+    b->synth_on.assign(S, 0);
     int64_t V = 0, est = 0;
     for (int s = 0; s < S; s++) {
         BatchScene &x = b->sc[s];
@@ -1790,8 +1850,10 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0)
         info[s].rows_per_group = rows;
         info[s].rc = RC;
         info[s].bpg = (rows + RPB - 1) / RPB;
-        const bool synth = only_K <= 0 || K == only_K;
-        items[s + 1] = items[s] + (synth ? (int64_t)info[s].bpg * n_groups : 0);
+        batch_plan(x);
+        const bool synth = (only_K <= 0 || K == only_K) && (only_scene < 0 || s == only_scene);
+        b->synth_on[s] = synth;
+        items[s + 1] = items[s] + (synth && !x.use_freq ? (int64_t)info[s].bpg * n_groups : 0);
         b->range_base[s + 1] = b->range_base[s] + (shared ? 2 : n_groups + 1);
     }
     vr[S] = V;
@@ -1821,6 +1883,42 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0)
     if ((rc = b->d_items.ensure(8 * (S + 1)))) return rc;
     if ((rc = b->d_vr.ensure(8 * (S + 1)))) return rc;
     if ((rc = b->d_ranges.ensure(8 * (b->n_ranges + 1)))) return rc;
+    // exact engine: per scene the table stride (capacity, or the timing cap)
+    // and path splits; one set of tables serves its scenes in turn
+    {
+        const int64_t ks = freq_k_step();
+        size_t pm = 0, xt = 0, yt = 0, pp = 0, part = 0;
+        for (int s = 0; s < S; s++) {
+            BatchScene &x = b->sc[s];
+            if (!x.use_freq || !b->synth_on[s]) continue;
+            int64_t P = x.fq_cap;
+            if (p_limit > 0) P = std::min<int64_t>(P, std::max<int64_t>((p_limit + ks - 1) / ks * ks, ks));
+            x.fq_ppad = P;
+            const int M = x.chirp.n_chirps, K = x.chirp.n_samples, tl = 32 * x.nb;
+            const int64_t kg = (K + freq_k_group() - 1) / freq_k_group();
+            const int64_t tiles = (int64_t)M * kg * ((x.ntx + tl - 1) / tl) * ((x.nrx + tl - 1) / tl);
+            int64_t n_split = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+            n_split = std::min<int64_t>(n_split, std::max<int64_t>(1, P / (16 * ks)));
+            int64_t split_len = (P + n_split - 1) / n_split;
+            split_len = (split_len + ks - 1) / ks * ks;
+            x.fq_split = (int)((P + split_len - 1) / split_len);
+            x.fq_split_len = split_len;
+            pm = std::max(pm, (size_t)M * P * 64);
+            xt = std::max(xt, (size_t)M * x.ntx * P * 8);
+            yt = std::max(yt, (size_t)M * x.nrx * P * 8);
+            pp = std::max(pp, (size_t)P * 4);
+            if (x.fq_split > 1)
+                part = std::max(part, (size_t)x.fq_split * M * K * x.ntx * x.nrx * 8);
+        }
+        if (pm) {
+            if ((rc = b->fq_pm.ensure(pm))) return rc;
+            if ((rc = b->fq_xt.ensure(xt))) return rc;
+            if ((rc = b->fq_yt.ensure(yt))) return rc;
+            if ((rc = b->fq_amp.ensure(pp))) return rc;
+            if ((rc = b->fq_src.ensure(pp))) return rc;
+            if (part && (rc = b->fq_part.ensure(part))) return rc;
+        }
+    }
     const double INV_2PI = 0.15915494309189535;
     for (int s = 0; s < S; s++) {
         BatchScene &x = b->sc[s];
@@ -1937,20 +2035,62 @@ int batch_enqueue_synth(rr_batch *b, bool timed)
     if (timed) HIPCHK(hipEventRecord(b->ev[2], st));
     HIPCHK(launch_batch_synth(b->d_sargs.as<const SynthArgs>(), b->d_info.as<const BatchSynthInfo>(),
                               b->d_items.as<const int64_t>(), b->S, b->n_items, work + 1, st));
+    // the exact product engine's scenes, one after the other on the shared
+    // tables; each reads its path range from the device
+    const int64_t *rg = b->d_ranges.as<const int64_t>();
+    for (int s = 0; s < b->S; s++) {
+        const BatchScene &x = b->sc[s];
+        if (!x.use_freq || !b->synth_on[s]) continue;
+        const int64_t *lo = rg + b->range_base[s], *hi = rg + b->range_base[s + 1] - 1;
+        const int M = x.chirp.n_chirps, K = x.chirp.n_samples;
+        const double inv_c = 1.0 / 299792458.0;
+        HIPCHK(launch_freq_prep(b->syn.as<const SynPath>(), 0, lo, hi, x.fq_ppad, M, x.chirp.t_rep,
+                                x.tx.as<const double>(), x.ntx, x.rx.as<const double>(), x.nrx,
+                                x.chirp.f0 * inv_c, x.chirp.bandwidth / (double)K * inv_c,
+                                b->fq_pm.as<double>(), b->fq_xt.as<uint2>(), b->fq_yt.as<uint2>(),
+                                b->fq_amp.as<float>(), b->fq_src.as<int32_t>(), st));
+        HIPCHK(launch_freq_gemm(b->fq_xt.as<const uint2>(), b->fq_yt.as<const uint2>(),
+                                b->fq_amp.as<const float>(), b->fq_src.as<const int32_t>(), x.ntx,
+                                x.nrx, M, K, x.fq_ppad, x.fq_split, x.fq_split_len,
+                                x.mode != RR_TX_SHARED, x.nb, lo, hi, b->fq_part.as<float2>(),
+                                static_cast<float2 *>(b->cubes[s]), st));
+    }
     if (timed) HIPCHK(hipEventRecord(b->ev[3], st));
     return RR_OK;
 }
 
+// after a launch: the path pool and every exact-engine scene's table
+// capacity against the counts; a shortfall grows the capacity and asks for a
+// re-run (*overflow).  Records each scene's path count.
 int batch_check(rr_batch *b, bool *overflow)
 {
     unsigned long long cnt = 0, tot = 0;
+    std::vector<int64_t> r(b->n_ranges + 1);
     HIPCHK(hipMemcpyAsync(&cnt, b->counter.p, 8, hipMemcpyDeviceToHost, b->st));
     HIPCHK(hipMemcpyAsync(&tot, b->total.p, 8, hipMemcpyDeviceToHost, b->st));
+    HIPCHK(hipMemcpyAsync(r.data(), b->d_ranges.p, 8 * b->n_ranges, hipMemcpyDeviceToHost, b->st));
     HIPCHK(hipStreamSynchronize(b->st));
     *overflow = (int64_t)cnt > b->cap;
     if (*overflow) b->cap = (int64_t)cnt + (int64_t)cnt / 4 + 4096;
     b->last_total = (int64_t)tot;
+    if (*overflow) return RR_OK;   // counts are cut short: re-run first
+    for (int s = 0; s < b->S; s++) {
+        BatchScene &x = b->sc[s];
+        const int64_t n = r[b->range_base[s + 1] - 1] - r[b->range_base[s]];
+        x.n_last = n;
+        if (x.use_freq && b->synth_on[s] && n > x.fq_ppad) {
+            x.fq_cap = n + n / 4 + 1024;
+            *overflow = true;
+        }
+    }
     return RR_OK;
+}
+
+bool batch_any_freq(const rr_batch *b)
+{
+    for (const auto &x : b->sc)
+        if (x.use_freq) return true;
+    return false;
 }
 
 }  // namespace
@@ -2075,6 +2215,9 @@ int rr_batch_set_scene(rr_batch *b, int32_t slot, const float *verts, int64_t n_
     x.chirp = *chirp;
     x.tp = *tp;
     x.kr = 0;
+    x.tuned_engine = -1;
+    x.n_last = -1;
+    x.fq_cap = 0;
     x.set = true;
     batch_drop_graph(b);
     return RR_OK;
@@ -2105,6 +2248,8 @@ int rr_batch_launch(rr_batch *b, void *const *cubes, int64_t *n_paths_out)
     bool new_cubes = b->cubes.size() != (size_t)b->S ||
                      !std::equal(b->cubes.begin(), b->cubes.end(), cubes);
     b->cubes.assign(cubes, cubes + b->S);
+    // the exact engine's kernels take their cube as an argument: re-capture
+    if (new_cubes && batch_any_freq(b)) b->dirty = true;
     for (int attempt = 0; attempt < 3; attempt++) {
         if (b->dirty || new_cubes) {
             int rc = batch_prepare(b);
@@ -2142,14 +2287,8 @@ int rr_batch_launch(rr_batch *b, void *const *cubes, int64_t *n_paths_out)
         if (attempt == 2) return fail(RR_EOVERFLOW, "batched path pool overflow persisted");
     }
     HIPCHK(hipEventElapsedTime(&b->ms_total, b->ev[0], b->ev[5]));
-    if (n_paths_out) {
-        std::vector<int64_t> r(b->n_ranges + 1);
-        HIPCHK(hipMemcpy(r.data(), b->d_ranges.p, 8 * b->n_ranges, hipMemcpyDeviceToHost));
-        for (int s = 0; s < b->S; s++) {
-            const int64_t lo = r[b->range_base[s]], hi = r[b->range_base[s + 1] - 1];
-            n_paths_out[s] = hi - lo;
-        }
-    }
+    if (n_paths_out)
+        for (int s = 0; s < b->S; s++) n_paths_out[s] = b->sc[s].n_last;
     return RR_OK;
 }
 
@@ -2164,6 +2303,18 @@ int rr_batch_tune(rr_batch *b, void *const *cubes)
     std::vector<int> Ks;
     for (auto &x : b->sc)
         if (std::find(Ks.begin(), Ks.end(), x.chirp.n_samples) == Ks.end()) Ks.push_back(x.chirp.n_samples);
+    // the candidates run eagerly on a bounded prefix of the paths of the last
+    // launch (time is linear in the path count)
+    auto time_synth = [&](int only_K, int only_scene, float *ms) -> int {
+        int r = batch_prepare(b, only_K, TUNE_PATHS, only_scene);
+        if (r) return r;
+        if ((r = batch_enqueue_synth(b, true))) return r;
+        HIPCHK(hipStreamSynchronize(b->st));
+        HIPCHK(hipEventElapsedTime(ms, b->ev[2], b->ev[3]));
+        return RR_OK;
+    };
+    // 1. the direct engine's tile, per sample count, on every scene with it
+    for (auto &x : b->sc) x.try_engine = RR_DIRECT_FP32;
     for (int K : Ks) {
         float best_ms = 3.0e38f;
         int best = 0;
@@ -2171,23 +2322,87 @@ int rr_batch_tune(rr_batch *b, void *const *cubes)
             if (cand > RR_BATCH_MAX_KR || K % cand != 0 || K / cand > 256) continue;
             for (auto &x : b->sc)
                 if (x.chirp.n_samples == K) x.kr = cand;
-            // the candidate runs eagerly on a bounded prefix of the paths of
-            // the last launch (time is linear in the path count), for the
-            // scenes with this sample count only
-            if ((rc = batch_prepare(b, K, TUNE_PATHS))) return rc;
-            if ((rc = batch_enqueue_synth(b, true))) return rc;
-            HIPCHK(hipStreamSynchronize(b->st));
             float ms = 0.0f;
-            HIPCHK(hipEventElapsedTime(&ms, b->ev[2], b->ev[3]));
+            if ((rc = time_synth(K, -1, &ms))) break;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = cand;
             }
         }
+        if (rc) break;
         for (auto &x : b->sc)
             if (x.chirp.n_samples == K) x.kr = best;
     }
+    // 2. per scene left to AUTO: the direct engine against the exact product
+    // engine at each tile that pads at most twice the least padding (shared
+    // launches; a per-element launch wastes the product on other Tx rows).
+    // The product engine's scene runs as separate kernels: it has to win by
+    // a tenth and 20 us.
+    for (int s = 0; s < b->S && !rc; s++) {
+        BatchScene &x = b->sc[s];
+        if (x.req_engine != RR_ENGINE_AUTO) continue;
+        float t_direct = 0.0f;
+        x.try_engine = RR_DIRECT_FP32;
+        if ((rc = time_synth(0, s, &t_direct))) break;
+        int best_eng = RR_DIRECT_FP32, best_nb = 0;
+        float best_ms = t_direct;
+        if (x.mode == RR_TX_SHARED) {
+            int64_t least = -1;
+            int64_t area[4] = {0, 0, 0, 0};
+            for (int nb = 1; nb <= 3; nb++) {
+                const int64_t tl = 32 * nb;
+                area[nb] = ((x.ntx + tl - 1) / tl * tl) * ((x.nrx + tl - 1) / tl * tl);
+                if (least < 0 || area[nb] < least) least = area[nb];
+            }
+            for (int nb = 1; nb <= 3; nb++) {
+                if (area[nb] > 2 * least) continue;
+                if (batch_freq_bytes(x, std::max(x.fq_cap, x.n_last)) > BATCH_FREQ_TABLE_MAX) continue;
+                x.try_engine = RR_GEMM_EXACT;
+                x.try_nb = nb;
+                float ms = 0.0f;
+                if ((rc = time_synth(0, s, &ms))) break;
+                if (ms * 1.1f + 0.02f < best_ms) {
+                    best_ms = ms;
+                    best_eng = RR_GEMM_EXACT;
+                    best_nb = nb;
+                }
+            }
+        }
+        x.tuned_engine = best_eng;
+        x.tuned_nb = best_nb;
+    }
+    for (auto &x : b->sc) x.try_engine = -1;
     batch_drop_graph(b);
+    return rc;
+}
+
+int rr_batch_set_engine(rr_batch *b, int32_t slot, int32_t engine, int32_t tile)
+{
+    if (!b) return fail(RR_EINVAL, "NULL batch");
+    if (slot < 0 || slot >= b->S) return fail(RR_EINVAL, "slot out of range");
+    if (engine != RR_ENGINE_AUTO && engine != RR_DIRECT_FP32 && engine != RR_GEMM_EXACT)
+        return fail(RR_EINVAL, "batched scenes use RR_ENGINE_AUTO, RR_DIRECT_FP32 or RR_GEMM_EXACT");
+    if (tile != 0 && (engine != RR_GEMM_EXACT || (tile != 32 && tile != 64 && tile != 96)))
+        return fail(RR_EINVAL, "tile 32, 64 or 96 with RR_GEMM_EXACT, else 0");
+    BatchScene &x = b->sc[slot];
+    x.req_engine = engine;
+    x.req_tile = tile;
+    batch_drop_graph(b);
+    return RR_OK;
+}
+
+int rr_batch_get_plan(rr_batch *b, int32_t *engine_out, int32_t *tile_out)
+{
+    if (!b || !engine_out || !tile_out) return fail(RR_EINVAL, "NULL argument");
+    if (b->dirty) {
+        HIPCHK(hipSetDevice(b->c->device));
+        if (int rc = batch_prepare(b)) return rc;
+    }
+    for (int s = 0; s < b->S; s++) {
+        BatchScene &x = b->sc[s];
+        engine_out[s] = x.use_freq ? RR_GEMM_EXACT : RR_DIRECT_FP32;
+        tile_out[s] = x.use_freq ? 32 * x.nb : x.kr;
+    }
     return RR_OK;
 }
 

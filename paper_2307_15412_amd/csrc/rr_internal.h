@@ -186,16 +186,19 @@ int64_t bp_mfma_frag_bytes(int K);
 int freq_k_step();
 int freq_k_group();   // samples per exact-GEMM workgroup
 // leg tables of n paths, or (rng_lo != NULL) of the records *rng_lo ..
-// *rng_hi of `paths` read on the device, at most Ppad (more set *overflow)
+// *rng_hi of `paths` read on the device, at most Ppad of them
 hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_lo,
-                            const int64_t *rng_hi, int *overflow, int64_t Ppad, int M, double t_rep,
+                            const int64_t *rng_hi, int64_t Ppad, int M, double t_rep,
                             const double *tx, int T, const double *rx, int R, double f0c, double dfc,
                             double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
                             hipStream_t s);
 int freq_tile_blocks(int T, int R);   // exact-GEMM tile: NB blocks of 32 per side
+// rng_lo / rng_hi (may be NULL): the path count read on the device, as for
+// launch_freq_prep; the splits then divide that count evenly
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
-                            int per_element, int nb, float2 *partial, float2 *cube, hipStream_t s);
+                            int per_element, int nb, const int64_t *rng_lo, const int64_t *rng_hi,
+                            float2 *partial, float2 *cube, hipStream_t s);
 hipError_t launch_refit(float4 *nodes, float *ubox, const int32_t *order,
                         const int64_t *level_start, int n_levels, float4 *ltris, int64_t n_tris,
                         const int32_t *tris, const float *verts, double pad, hipStream_t s);

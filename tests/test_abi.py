@@ -83,8 +83,9 @@ def test_output_tensors_checked_before_the_library_sees_them():
 
 
 def test_new_entry_points_reject_null_handles():
-    """Per-face alpha, vertex update, BVH export, imaging, casting pieces and
-    batch alpha refuse a NULL context before touching HIP."""
+    """Per-face alpha, vertex update, BVH export, imaging, casting pieces,
+    batch alpha and the batch's engine plan refuse a NULL handle before
+    touching HIP."""
     import ctypes as C
     import paper_2307_15412_amd as pkg
     lib = pkg.load_library()
@@ -99,4 +100,6 @@ def test_new_entry_points_reject_null_handles():
     assert lib.rr_casting_pieces(None, None, C.byref(n)) == E
     pkg.binding._declare_batch(lib)
     assert lib.rr_batch_set_alpha(None, 0, None, 0, 0) == E
+    assert lib.rr_batch_set_engine(None, 0, 0, 0) == E
+    assert lib.rr_batch_get_plan(None, None, None) == E
     assert lib.rr_last_error() != b""

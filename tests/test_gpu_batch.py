@@ -1,8 +1,9 @@
-"""Batched launch (persistent trace and synthesis kernels captured as one
-hipGraph): every scene's path count and cube must equal the single-scene
-launch of the same workload (bitwise with the same tile shape, within float
-rounding after autotuning), replays must reproduce the result, and sampled
-entries must match the FP64 oracle."""
+"""Batched launch (a persistent trace kernel, the direct engine's persistent
+synthesis kernel and the exact product engine's per-scene kernels captured
+as one hipGraph): every scene's path count and cube must equal the
+single-scene launch of the same workload on the same engine (bitwise with
+the same tile shape, within float rounding after autotuning), replays must
+reproduce the result, and sampled entries must match the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -30,11 +31,20 @@ def _workloads():
     return ws
 
 
-def _single(gpu, w):
+def _single(gpu, w, engine=None):
     import paper_2307_15412_amd as rr
     gpu.setup(w)
     n = gpu.trace_workload(w, record_hits=False)
-    return n, gpu.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32).clone()
+    eng = rr.DIRECT_FP32 if engine is None else engine
+    return n, gpu.synthesize(model=rr.EXACT, engine=eng).clone()
+
+
+def _sampled_oracle_err(orc, w, cube, seed, n=512):
+    _, op = orc.trace(w.scene, w.array, w.trace, want_hits=False)
+    flat = cube.reshape(-1)
+    idx = np.random.default_rng(seed).choice(flat.numel(), n, replace=False)
+    got = flat[torch.from_numpy(idx).to(flat.device)].cpu().numpy()
+    return rel_err(got, orc.synth(op, w.scene, w.array, w.chirp, model=0, idx=idx))
 
 
 def test_batch_matches_single_scene(gpu):
@@ -43,6 +53,7 @@ def test_batch_matches_single_scene(gpu):
     B = rr.Batch(gpu, len(ws))
     for i, w in enumerate(ws):
         B.set_workload(i, w)
+        B.set_engine(i, rr.DIRECT_FP32)
     cubes = B.alloc_cubes()
     counts = B.launch(cubes)
     st = B.stats()
@@ -67,6 +78,93 @@ def test_batch_matches_single_scene(gpu):
     B.close()
 
 
+def _exact_workloads():
+    """Shared launches around the product tiles (32, 64, 96 and ragged), a
+    moving street, a per-element launch and a points-only scene; the slots
+    left at the least padding tile have enough (chirp, sample, tile) work
+    items that neither side splits the paths."""
+    def wl(name, scene, arr, K, M, rays, seed):
+        return sg.Workload(name, scene, arr, sg.Chirp(n_samples=K, n_chirps=M),
+                           sg.TraceParams(n_rays=rays, max_bounces=2, seed=seed))
+    c1 = sg.scene_c1(4)
+    street = sg.scene_street(2, scale=0.05, n_cars=5, n_poles=6)
+    return [
+        (wl("tiny33x70", c1, sg.array_sparse_grid(33, 70, 5), 64, 16, 60_000, 1), 0),
+        (wl("street40", street, sg.array_sparse_grid(40, 40, 6), 96, 8, 120_000, 2), 64),
+        (wl("tiny96", c1, sg.array_sparse_grid(96, 96, 7, grid=128), 16, 2, 40_000, 3), 96),
+        (wl("street7x9", street, sg.array_sparse_grid(7, 9, 8), 128, 16, 100_000, 4), 32),
+        (wl("perel", c1, sg.array_ula(6, 8, mode=sg.MODE_PER_TX), 128, 32, 60_000, 5), 0),
+        (sg.Workload("points", sg.point_only([[8.0, 1.0, 0.5], [15.0, -2.0, 0.6]],
+                                             vel=[[1.0, 0.0, 0.0], [-2.0, 0.5, 0.0]]),
+                     sg.array_sparse_grid(5, 6, 9), sg.Chirp(n_samples=64, n_chirps=8),
+                     sg.TraceParams(n_rays=1000, max_bounces=2, seed=3)), 0),
+    ]
+
+
+def test_batch_exact_engine(gpu, orc):
+    """Every slot pinned to the product engine (tiles 32 / 64 / 96 forced or
+    least padding): counts equal the single-scene launch; a slot at the least
+    padding tile equals the single-scene product engine bit for bit (same
+    tile, one path split on both sides), forced tiles agree with it to float
+    rounding; sampled entries within 1e-4 of the FP64 oracle; replays, and a
+    re-capture for new cube buffers, reproduce the cubes bit for bit."""
+    import paper_2307_15412_amd as rr
+    cases = _exact_workloads()
+    B = rr.Batch(gpu, len(cases))
+    for i, (w, tile) in enumerate(cases):
+        B.set_workload(i, w)
+        B.set_engine(i, rr.GEMM_EXACT, tile)
+    eng, tiles = B.plan()
+    assert (eng == rr.GEMM_EXACT).all()
+    assert [int(t) for t in tiles[1:4]] == [64, 96, 32]
+    cubes = B.alloc_cubes()
+    counts = B.launch(cubes)
+    for i, (w, tile) in enumerate(cases):
+        n, ref = _single(gpu, w, rr.GEMM_EXACT)
+        assert counts[i] == n, (i, counts[i], n)
+        got = cubes[i]
+        if tile == 0:
+            assert torch.equal(got, ref), (i, rel_err(got.cpu().numpy(), ref.cpu().numpy()))
+        else:
+            assert rel_err(got.cpu().numpy(), ref.cpu().numpy()) < 2e-6, i
+        if n:
+            assert _sampled_oracle_err(orc, w, got, 40 + i) < 1e-4, i
+        else:
+            assert not got.any()
+    first = [c.clone() for c in cubes]
+    for c in cubes:
+        c.zero_()
+    assert np.array_equal(B.launch(cubes), counts)
+    for a, b in zip(first, cubes):
+        assert torch.equal(a, b)
+    other = B.alloc_cubes()
+    B.launch(other)
+    for a, b in zip(first, other):
+        assert torch.equal(a, b)
+    B.close()
+
+
+def test_batch_exact_capacity_grows(gpu):
+    """A reception sphere of 3 m makes far more rays return than the leg
+    tables' first capacity (1 in 16 rays) holds: the launch grows the tables
+    and re-runs, and the cube equals the single-scene product engine."""
+    import paper_2307_15412_amd as rr
+    w = sg.workload_tiny(6)
+    w.array = sg.array_sparse_grid(8, 8, 11)
+    w.array.rx_radius = 3.0
+    w.trace.n_rays = 40_000
+    w.chirp = sg.Chirp(n_samples=64, n_chirps=4)
+    B = rr.Batch(gpu, 1)
+    B.set_workload(0, w)
+    B.set_engine(0, rr.GEMM_EXACT)
+    cubes = B.alloc_cubes()
+    counts = B.launch(cubes)
+    n, ref = _single(gpu, w, rr.GEMM_EXACT)
+    assert counts[0] == n > w.trace.n_rays // 16 + 3
+    assert torch.equal(cubes[0], ref)
+    B.close()
+
+
 def test_batch_autotune(gpu):
     import paper_2307_15412_amd as rr
     ws = _workloads()
@@ -78,11 +176,43 @@ def test_batch_autotune(gpu):
     for t, w in zip(tiles, ws):
         K = w.chirp.n_samples
         assert t in (4, 8, 16, 32) and K % t == 0 and K // t <= 256
+    eng, pt = B.plan()
+    for e, t, tl, w in zip(eng, pt, tiles, ws):
+        if e == rr.GEMM_EXACT:
+            assert w.array.mode == sg.MODE_SHARED and t in (32, 64, 96)
+        else:
+            assert e == rr.DIRECT_FP32 and t == tl
     counts = B.launch(cubes)
     for i, w in enumerate(ws):
         n, ref = _single(gpu, w)
         assert counts[i] == n
         assert rel_err(cubes[i].cpu().numpy(), ref.cpu().numpy()) < 2e-5
+    B.close()
+
+
+def test_batch_autotune_picks_product_engine(gpu):
+    """Two shared 48 x 64 street scenes (3072 channels) beside a small one:
+    the tuner runs them on the product engine, the small one on the direct
+    engine; the cubes agree with the single-scene launches."""
+    import paper_2307_15412_amd as rr
+    street = sg.scene_street(3, scale=0.1, n_cars=8, n_poles=10)
+    big = [sg.Workload(f"big{i}", street, sg.array_sparse_grid(48, 64, 30 + i),
+                       sg.Chirp(n_samples=256, n_chirps=8),
+                       sg.TraceParams(n_rays=200_000, max_bounces=3, seed=30 + i)) for i in range(2)]
+    small = sg.workload_tiny(7)
+    ws = [big[0], small, big[1]]
+    B = rr.Batch(gpu, len(ws))
+    for i, w in enumerate(ws):
+        B.set_workload(i, w)
+    cubes = B.alloc_cubes()
+    B.tune(cubes)
+    eng, tiles = B.plan()
+    assert list(eng) == [rr.GEMM_EXACT, rr.DIRECT_FP32, rr.GEMM_EXACT], (eng, tiles)
+    counts = B.launch(cubes)
+    for i, w in enumerate(ws):
+        n, ref = _single(gpu, w)
+        assert counts[i] == n
+        assert rel_err(cubes[i].cpu().numpy(), ref.cpu().numpy()) < 2e-5, i
     B.close()
 
 
@@ -105,35 +235,42 @@ def test_batch_against_oracle(gpu, orc):
 
 
 def test_batch_full_size_slot(gpu, orc):
-    """A slot at the batched configuration's largest size: a street of 5.1e5
+    """Slots at the batched configuration's largest size: a street of 5.1e5
     triangles seen by 3072 channels (48 Tx x 64 Rx shared launch), 512 samples
-    x 64 chirps, 1e6 rays, 3 bounces, among two uneven scenes.  The slot
-    equals the single-scene launch bit for bit and 1024 seeded entries are
-    within 1e-4 of the FP64 oracle (exact model)."""
+    x 64 chirps, 1e6 rays, 3 bounces, twice among two uneven scenes: once left
+    to AUTO (the product engine, 64 x 64 tiles) and once pinned to the direct
+    engine.  Each equals the single-scene launch on its engine bit for bit,
+    and 1024 seeded entries of each are within 1e-4 of the FP64 oracle (exact
+    model)."""
     import paper_2307_15412_amd as rr
     big = sg.Workload("street_3072", sg.scene_street(7), sg.array_sparse_grid(48, 64, 24,
                       mode=sg.MODE_SHARED), sg.Chirp(n_samples=512, n_chirps=64),
                       sg.TraceParams(n_rays=1_000_000, max_bounces=3, seed=7))
     assert big.scene.n_tris >= 500_000 and big.array.n_ch == 3072
     ws = [sg.workload_batch(n_scenes=1, seed0=2010, rays=200_000, tri_hi=1e5, ch_hi=64)[0], big,
-          sg.workload_box_family(4, 50_000)]
+          sg.workload_box_family(4, 50_000), big]
     B = rr.Batch(gpu, len(ws))
     for i, w in enumerate(ws):
         B.set_workload(i, w)
+    B.set_engine(3, rr.DIRECT_FP32)
+    eng, tiles = B.plan()
+    assert eng[1] == rr.GEMM_EXACT and tiles[1] == 64 and eng[3] == rr.DIRECT_FP32
     cubes = B.alloc_cubes()
     counts = B.launch(cubes)
-    flat = cubes[1].reshape(-1)
-    idx = np.random.default_rng(17).choice(flat.numel(), 1024, replace=False)
-    got = flat[torch.from_numpy(idx).to(flat.device)].cpu().numpy()
-    n, ref_cube = _single(gpu, big)
-    assert counts[1] == n > 10_000
-    assert torch.equal(cubes[1], ref_cube)
-    del ref_cube
+    idx = np.random.default_rng(17).choice(cubes[1].numel(), 1024, replace=False)
+    ti = torch.from_numpy(idx).to(cubes[1].device)
+    got = {s: cubes[s].reshape(-1)[ti].cpu().numpy() for s in (1, 3)}
+    for s, e in ((1, rr.GEMM_EXACT), (3, rr.DIRECT_FP32)):
+        n, ref_cube = _single(gpu, big, e)
+        assert counts[s] == n > 10_000
+        assert torch.equal(cubes[s], ref_cube), s
+        del ref_cube
     B.close()
     _, op = orc.trace(big.scene, big.array, big.trace, want_hits=False)
     assert len(op) == n
     ref = orc.synth(op, big.scene, big.array, big.chirp, model=0, idx=idx)
-    err = rel_err(got, ref)
-    print(f"3072-channel slot: {n} paths, relative error {err:.2e}, max ratio "
-          f"{np.abs(got - ref).max() / np.abs(ref).max():.2e}")
-    assert err < 1e-4
+    for s in (1, 3):
+        err = rel_err(got[s], ref)
+        print(f"3072-channel slot {s}: {n} paths, relative error {err:.2e}, max ratio "
+              f"{np.abs(got[s] - ref).max() / np.abs(ref).max():.2e}")
+        assert err < 1e-4
