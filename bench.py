@@ -63,7 +63,8 @@ def parse():
 def run_batch(args):
     """64 procedural scenes (1e4-1e6 triangles, 4-3072 channels, 128-512
     samples, 64-256 chirps, 1e6 rays each, 3 bounces) traced and synthesised
-    (exact model, FP32 cubes) by one captured launch after autotuning."""
+    (exact model, FP32 cubes) by one captured launch after autotuning (per
+    scene the direct engine or the exact product engine, and its tile)."""
     import torch
     import scenegen as sg
     import paper_2307_15412_amd as rr
@@ -83,7 +84,13 @@ def run_batch(args):
     cubes = B.alloc_cubes()
     t0 = time.time()
     tiles = B.tune(cubes)
-    log(f"autotune {time.time() - t0:.1f} s, tiles {sorted(set(tiles.tolist()))}")
+    tune_s = time.time() - t0
+    eng, ptile = B.plan()
+    # per scene: "x<tile>" on the exact product engine, "d<samples per lane>"
+    # on the direct engine
+    plan = [("x" if e == rr.GEMM_EXACT else "d") + str(int(t)) for e, t in zip(eng, ptile)]
+    n_prod = int(np.sum(eng == rr.GEMM_EXACT))
+    log(f"autotune {tune_s:.1f} s: {n_prod} scenes on the product engine, plan {plan}")
     for _ in range(args.warmup):
         B.launch(cubes, want_counts=False)
         log("warmup launch done")
@@ -133,7 +140,8 @@ def run_batch(args):
                                "64-256 chirps, 1e6 rays each, <=3 bounces, exact model"},
         "scenes": len(ws), "rays": rays, "paths": int(np.sum(counts)),
         "cube_gb": sum(np.prod(s) for s in B.shapes) * 8 / 1e9,
-        "mrays_per_s_incl_synth": rays / dt / 1e6, "tiles": tiles.tolist(),
+        "mrays_per_s_incl_synth": rays / dt / 1e6, "plan": plan, "product_engine_scenes": n_prod,
+        "autotune_s": tune_s,
         "scene_gen_s": gen_s, "bvh_upload_s": upload_s, "graph_ms": B.stats()["ms_total"],
         "oracle_check": check}))
 

@@ -307,7 +307,7 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
  *          RR_ENGINE_AUTO: the separable model takes RR_GEMM_BF16X3 when the
  *          64-sample tiling pads a chirp by at most a quarter; the exact model
  *          takes RR_GEMM_EXACT for a shared launch whose Tx x Rx product
- *          tiles (32, 64 or 96 square, whichever pads least) are at least
+ *          tiles (16 to 96 square, the tile of least modelled cost) are at least
  *          half filled and whose leg tables fit its budget; everything else, and sampled entries, the direct engine.
  *          AUTO never changes the model, and each engine it picks meets that
  *          model's error bar.
@@ -485,9 +485,10 @@ int rr_batch_launch(rr_batch *batch, void *const *cubes, int64_t *n_paths_out);
  * is linear in the path count): for every distinct sample count time each
  * candidate samples-per-lane value of the direct engine on the scenes with
  * that count and keep the fastest; then per scene left to RR_ENGINE_AUTO
- * time the direct engine against the product engine at every tile (32, 64,
- * 96) that pads at most twice the least padding (shared launches only), and
- * keep the product engine if it is faster by a tenth and 20 us.  Afterwards
+ * time the direct engine against the product engine at every tile (16, 32,
+ * 48, 64, 96) whose modelled cost (padded outputs over the tile's measured
+ * throughput) is within 1.5x of the least (shared launches only), and keep
+ * the product engine if it is faster by a tenth and 20 us.  Afterwards
  * the cubes hold partial sums: run rr_batch_launch to fill them.
  * rr_batch_get_tiles reports the direct engine's samples per lane per scene;
  * rr_batch_get_plan the engine each scene runs on (RR_DIRECT_FP32 or
@@ -500,8 +501,9 @@ int rr_batch_get_tiles(rr_batch *batch, int32_t *samples_per_lane_out);
 int rr_batch_get_plan(rr_batch *batch, int32_t *engine_out, int32_t *tile_out);
 
 /* Pin slot `slot`'s synthesis engine: RR_ENGINE_AUTO (default: the tuner's
- * or the rule's choice), RR_DIRECT_FP32, or RR_GEMM_EXACT with tile 32, 64
- * or 96 (0: least padding).  Invalidates the captured graph.
+ * or the rule's choice), RR_DIRECT_FP32, or RR_GEMM_EXACT with product tile
+ * 16, 32, 48, 64 or 96 (0: the tile of least modelled cost).  Invalidates the
+ * captured graph.
  * Errors: RR_EINVAL (slot, engine, tile). */
 int rr_batch_set_engine(rr_batch *batch, int32_t slot, int32_t engine, int32_t tile);
 

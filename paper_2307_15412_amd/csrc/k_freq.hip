@@ -14,21 +14,24 @@
 // Both legs are reduced in FP64 per (chirp, element, path) to 32-bit
 // fixed-point turns: beta = frac(f0 d / c), gamma = frac(B d / (K c)), so the
 // phase at sample k is beta + k gamma modulo 2^32, exact in integer
-// arithmetic.  A workgroup of four wavefronts computes a 96 x 96 (Tx x Rx)
+// arithmetic.  A workgroup of four wavefronts computes a square (Tx x Rx)
 // output tile of four consecutive samples of one chirp over one split of the
-// paths, 16 paths per step, one sample per wavefront: the four share the
-// step's table words (loaded once per workgroup, passed through LDS), and
-// each wavefront generates its own X and Y fragments straight into operand
-// registers and issues 108 v_mfma_f32_32x32x16_bf16 per step.  Operands are
-// split bf16 hi + lo, products hi*hi + hi*lo + lo*hi, FP32 accumulation (as
-// the separable GEMM).  Several path splits write partial tiles that a second
-// kernel adds in split order (deterministic).
+// paths, one sample per wavefront: the four share the step's table words
+// (loaded once per workgroup, passed through LDS), and each wavefront
+// generates its own X and Y fragments straight into operand registers.  The
+// tile is 16 or 48 wide in 16 x 16 blocks (v_mfma_f32_16x16x32_bf16, 32 paths
+// a step) or 32, 64 or 96 wide in 32 x 32 blocks (v_mfma_f32_32x32x16_bf16,
+// 16 paths a step), chosen per array to trade padding against the sharing of
+// phasors among products.  Operands are split bf16 hi + lo, products
+// hi*hi + hi*lo + lo*hi, FP32 accumulation (as the separable GEMM).  Several
+// path splits write partial tiles that a second kernel adds in split order
+// (deterministic).
 #include "rr_internal.h"
 
 namespace {
 
 #define FQ_G 4            // samples per workgroup, one per wavefront
-#define FQ_KS 16          // paths per step
+#define FQ_PAD 32         // path granule of the tables and splits (a multiple of every step)
 // a workgroup tile is NB x NB blocks of 32 x 32 (Tx x Rx), NB = 1, 2, 3; per
 // step its table words are 8 NB chunks of 1 KiB (X and Y, NB blocks, 4 pieces)
 
@@ -62,7 +65,7 @@ struct PathRange {
 };
 
 // the path records and count of a synthesis, and the padded count the
-// product reads (a multiple of FQ_KS; table entries beyond it are not needed)
+// product reads (a multiple of FQ_PAD; table entries beyond it are not needed)
 __device__ __forceinline__ void path_range(const PathRange &R, int64_t Ppad, const SynPath *&p,
                                            int64_t &n, int64_t &used)
 {
@@ -70,7 +73,7 @@ __device__ __forceinline__ void path_range(const PathRange &R, int64_t Ppad, con
         const int64_t lo = *R.rng_lo, hi = *R.rng_hi;
         p = R.paths + lo;
         n = min(max(hi - lo, (int64_t)0), Ppad);
-        used = (n + FQ_KS - 1) / FQ_KS * FQ_KS;
+        used = (n + FQ_PAD - 1) / FQ_PAD * FQ_PAD;
     } else {
         p = R.paths;
         n = R.n;
@@ -163,7 +166,25 @@ __device__ __forceinline__ void split_bf16(float x, float y, unsigned &hi, unsig
 
 __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-#define MFMA(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a), as_bf(b), c, 0, 0, 0)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// one split-bf16 product on the matrix cores: 32 x 32 blocks of 16 paths, or
+// 16 x 16 blocks of 32 paths
+template <int BS> struct Mfma;
+template <> struct Mfma<32> {
+    typedef f32x16 acc;
+    static __device__ __forceinline__ acc mma(uint4 a, uint4 b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a), as_bf(b), c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<16> {
+    typedef f32x4 acc;
+    static __device__ __forceinline__ acc mma(uint4 a, uint4 b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a), as_bf(b), c, 0, 0, 0);
+    }
+};
 
 // exp(-j 2 pi u) of fixed-point turns u
 __device__ __forceinline__ void phasor(unsigned u, float &re, float &im)
@@ -173,7 +194,7 @@ __device__ __forceinline__ void phasor(unsigned u, float &re, float &im)
     im = -__builtin_amdgcn_sinf(f);
 }
 
-struct Frag {          // one 32 x 16 operand, split: real hi/lo, imaginary hi/lo
+struct Frag {          // one operand fragment (8 values a lane), split: real hi/lo, imaginary hi/lo
     uint4 rh, rl, ih, il;
 };
 
@@ -219,7 +240,7 @@ struct FreqArgs {
     int tt, rt;               // Tx and Rx tiles
     int kg;                   // groups of FQ_G samples
     int n_split;
-    int64_t split_len;        // paths per split (multiple of FQ_KS)
+    int64_t split_len;        // paths per split (multiple of FQ_PAD)
     float2 *out;              // cube (one split) or partial tiles [split][m][k][T][R]
     int partial;
     // with rng_lo: the path count is *rng_hi - *rng_lo (at most Ppad), read
@@ -227,24 +248,31 @@ struct FreqArgs {
     const int64_t *rng_lo, *rng_hi;
 };
 
-// One workgroup: a 32 NB x 32 NB (Tx x Rx) tile of FQ_G consecutive samples
-// of one chirp over one path split; wavefront w owns sample k0 + w and the
-// whole tile (NB x NB blocks of 32 x 32, real and imaginary accumulators:
-// 32 NB^2 registers).  The samples of a workgroup share the table words of
-// every step: the (beta, gamma) words of the tile's Tx and Rx rows and 16
+// One workgroup: a BS NB x BS NB (Tx x Rx) tile of FQ_G consecutive samples
+// of one chirp over one path split, in NB x NB blocks of BS x BS (BS = 32:
+// v_mfma_f32_32x32x16_bf16, 16 paths a step; BS = 16:
+// v_mfma_f32_16x16x32_bf16, 32 paths a step).  Wavefront w owns sample
+// k0 + w and the whole tile (real and imaginary accumulators: 2 NB^2 BS^2 / 64
+// registers).  The samples of a workgroup share the table words of every
+// step: the (beta, gamma) words of the tile's Tx and Rx rows and the step's
 // paths, plus the paths' amplitudes and sources, are loaded once per
 // workgroup (each lane fetching 2 NB 16-byte pieces a step ahead into
 // registers) and passed through LDS (two buffers), already in the fragment
 // lane order so that every read is a contiguous 1 KiB.  Each wavefront
 // generates its own X and Y fragments for its sample.  Rows beyond the
 // array's Tx and Rx counts read row 0's words and are never stored.
-template <bool PER_EL, int NB>
-__global__ __launch_bounds__(FQ_G * 64, NB == 3 || (NB == 2 && PER_EL) ? 1 : (NB == 2 ? 2 : 4)) void
-k_freq_gemm(FreqArgs A)
+template <bool PER_EL, int BS, int NB>
+__global__ __launch_bounds__(FQ_G * 64, BS == 16 ? (NB == 1 ? 4 : 2)
+                                                 : (NB == 3 || (NB == 2 && PER_EL) ? 1 : (NB == 2 ? 2 : 4)))
+void k_freq_gemm(FreqArgs A)
 {
-    constexpr int CH = 8 * NB;            // table chunks per step
+    typedef typename Mfma<BS>::acc acc;
+    constexpr int GR = 64 / BS;           // lane groups: each holds 8 paths of a fragment row
+    constexpr int STEP = 8 * GR;          // paths per step
+    constexpr int NE = BS * BS / 64;      // accumulator registers of a block
+    constexpr int CH = 8 * NB;            // 1 KiB table chunks per step (X and Y, NB blocks, 4 pieces)
     constexpr int PL = CH / FQ_G;         // pieces per lane
-    constexpr int TILE = 32 * NB;
+    constexpr int TILE = BS * NB;
     __shared__ uint4 Ls[2][CH + 1][64];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -265,35 +293,38 @@ k_freq_gemm(FreqArgs A)
     int64_t used = A.Ppad, split_len = A.split_len;
     if (A.rng_lo) {
         const int64_t n = min(max(*A.rng_hi - *A.rng_lo, (int64_t)0), A.Ppad);
-        used = (n + FQ_KS - 1) / FQ_KS * FQ_KS;
-        split_len = ((used + A.n_split - 1) / A.n_split + FQ_KS - 1) / FQ_KS * FQ_KS;
+        used = (n + FQ_PAD - 1) / FQ_PAD * FQ_PAD;
+        split_len = ((used + A.n_split - 1) / A.n_split + FQ_PAD - 1) / FQ_PAD * FQ_PAD;
     }
     const int64_t pstart = (int64_t)s * split_len;
-    const int64_t nsteps = max(min(used, pstart + split_len) - pstart, (int64_t)0) / FQ_KS;
+    const int64_t nsteps = max(min(used, pstart + split_len) - pstart, (int64_t)0) / STEP;
     // an empty split still writes its (zero) tile; its loads stay at path 0
     const int64_t pbeg = nsteps > 0 ? pstart : 0;
     const int t0 = ti * TILE, r0 = ri * TILE;
-    const int half = lane >> 5;
+    const int grp = lane / BS, lrow = lane % BS;
 
     // loader: this wavefront fetches chunks q = w + 4 j; chunk q is table
     // q / (4 NB) (X, Y), block (q % (4 NB)) / 4, piece q % 4 (paths 2 (q % 4)
-    // and 2 (q % 4) + 1 of the lane's half); lane l reads row 32 block + l % 32
+    // and 2 (q % 4) + 1 of the lane group's 8); lane l reads row
+    // BS block + l % BS
     const u32x4 *lp[PL];
 #pragma unroll
     for (int j = 0; j < PL; j++) {
         const int q = w + FQ_G * j;
         const int tab = q / (4 * NB), blk = (q % (4 * NB)) >> 2, c = q & 3;
-        int row = (tab ? r0 : t0) + 32 * blk + (lane & 31);
+        int row = (tab ? r0 : t0) + BS * blk + lrow;
         if (row >= (tab ? A.R : A.T)) row = 0;    // any valid row: masked later
         const uint2 *base = tab ? A.yt + ((int64_t)m * A.R + row) * A.Ppad
                                 : A.xt + ((int64_t)m * A.T + row) * A.Ppad;
-        lp[j] = reinterpret_cast<const u32x4 *>(base + 8 * half + 2 * c);
+        lp[j] = reinterpret_cast<const u32x4 *>(base + 8 * grp + 2 * c);
     }
-    // amplitudes and sources: wavefront 0, lanes 0-3 (amp) and 4-7 (src)
-    const bool aload = w == 0 && lane < 8;
-    const u32x4 *ap = lane < 4 ? reinterpret_cast<const u32x4 *>(A.amp) + (lane & 3)
-                               : reinterpret_cast<const u32x4 *>(A.src) + (lane & 3);
-    // one step's pieces of this lane, fetched a step ahead
+    // amplitudes and sources of a step: wavefront 0, lanes 0 .. STEP/4 - 1
+    // (amp) and STEP/4 .. STEP/2 - 1 (src)
+    const bool aload = w == 0 && lane < STEP / 2;
+    const u32x4 *ap = lane < STEP / 4 ? reinterpret_cast<const u32x4 *>(A.amp) + lane
+                                      : reinterpret_cast<const u32x4 *>(A.src) + (lane - STEP / 4);
+    // one step's pieces of this lane, fetched a step ahead (native vector
+    // registers: an array of HIP's uint4 would be kept in scratch memory)
     u32x4 P[PL], PA = {0u, 0u, 0u, 0u};
 #define FQ_FETCH(p0)                                                                              \
     do {                                                                                          \
@@ -314,20 +345,20 @@ k_freq_gemm(FreqArgs A)
         return r;
     };
 
-    f32x16 sr[NB][NB], si[NB][NB];
+    acc sr[NB][NB], si[NB][NB];
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
         for (int j = 0; j < NB; j++)
 #pragma unroll
-            for (int e = 0; e < 16; e++) {
+            for (int e = 0; e < NE; e++) {
                 sr[i][j][e] = 0.0f;
                 si[i][j][e] = 0.0f;
             }
 
     FQ_FETCH(pbeg);
     FQ_STASH(0);
-    FQ_FETCH(nsteps > 1 ? pbeg + FQ_KS : pbeg);
+    FQ_FETCH(nsteps > 1 ? pbeg + STEP : pbeg);
     __syncthreads();
     for (int64_t st = 0; st < nsteps; st++) {
         const int b = (int)(st & 1);
@@ -337,13 +368,13 @@ k_freq_gemm(FreqArgs A)
         for (int j = 0; j < NB; j++) y[j] = leg_frag(raw_of(b, 4 * NB + 4 * j), ku, nullptr);
         // amplitudes of the lane's 8 paths; in a per-element launch a path
         // feeds only its own transmitter's rows
-        const uint4 a0 = Ls[b][CH][2 * half], a1 = Ls[b][CH][2 * half + 1];
-        const uint4 s0 = Ls[b][CH][4 + 2 * half], s1 = Ls[b][CH][5 + 2 * half];
+        const uint4 a0 = Ls[b][CH][2 * grp], a1 = Ls[b][CH][2 * grp + 1];
+        const uint4 s0 = Ls[b][CH][STEP / 4 + 2 * grp], s1 = Ls[b][CH][STEP / 4 + 2 * grp + 1];
         const unsigned av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
         const unsigned sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
 #pragma unroll
         for (int i = 0; i < NB; i++) {
-            const int t = t0 + 32 * i + (lane & 31);
+            const int t = t0 + BS * i + lrow;
             float a[8];
 #pragma unroll
             for (int e = 0; e < 8; e++) {
@@ -355,37 +386,38 @@ k_freq_gemm(FreqArgs A)
 #pragma unroll
             for (int j = 0; j < NB; j++) {
                 // re += Xr Yr - Xi Yi, im += Xr Yi + Xi Yr (hi*hi + hi*lo + lo*hi)
-                sr[i][j] = MFMA(x.rh, y[j].rh, sr[i][j]);
-                si[i][j] = MFMA(x.rh, y[j].ih, si[i][j]);
-                sr[i][j] = MFMA(x.rh, y[j].rl, sr[i][j]);
-                si[i][j] = MFMA(x.rh, y[j].il, si[i][j]);
-                sr[i][j] = MFMA(x.rl, y[j].rh, sr[i][j]);
-                si[i][j] = MFMA(x.rl, y[j].ih, si[i][j]);
-                sr[i][j] = MFMA(nih, y[j].ih, sr[i][j]);
-                si[i][j] = MFMA(x.ih, y[j].rh, si[i][j]);
-                sr[i][j] = MFMA(nih, y[j].il, sr[i][j]);
-                si[i][j] = MFMA(x.ih, y[j].rl, si[i][j]);
-                sr[i][j] = MFMA(nil, y[j].ih, sr[i][j]);
-                si[i][j] = MFMA(x.il, y[j].rh, si[i][j]);
+                sr[i][j] = Mfma<BS>::mma(x.rh, y[j].rh, sr[i][j]);
+                si[i][j] = Mfma<BS>::mma(x.rh, y[j].ih, si[i][j]);
+                sr[i][j] = Mfma<BS>::mma(x.rh, y[j].rl, sr[i][j]);
+                si[i][j] = Mfma<BS>::mma(x.rh, y[j].il, si[i][j]);
+                sr[i][j] = Mfma<BS>::mma(x.rl, y[j].rh, sr[i][j]);
+                si[i][j] = Mfma<BS>::mma(x.rl, y[j].ih, si[i][j]);
+                sr[i][j] = Mfma<BS>::mma(nih, y[j].ih, sr[i][j]);
+                si[i][j] = Mfma<BS>::mma(x.ih, y[j].rh, si[i][j]);
+                sr[i][j] = Mfma<BS>::mma(nih, y[j].il, sr[i][j]);
+                si[i][j] = Mfma<BS>::mma(x.ih, y[j].rl, si[i][j]);
+                sr[i][j] = Mfma<BS>::mma(nil, y[j].ih, sr[i][j]);
+                si[i][j] = Mfma<BS>::mma(x.il, y[j].rh, si[i][j]);
             }
         }
         if (st + 1 < nsteps) FQ_STASH(b ^ 1);
         __syncthreads();
-        FQ_FETCH(st + 2 < nsteps ? pbeg + (st + 2) * FQ_KS : pbeg);
+        FQ_FETCH(st + 2 < nsteps ? pbeg + (st + 2) * STEP : pbeg);
     }
 #undef FQ_FETCH
 #undef FQ_STASH
     // D layout: register e of lane l is row 8 (e / 4) + 4 (l / 32) + e % 4
-    // (a Tx row of block i), column l % 32 (an Rx column of block j)
+    // (BS = 32) or 4 (l / 16) + e (BS = 16) of the block, column l % BS
     if (!kv) return;
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
         for (int j = 0; j < NB; j++)
 #pragma unroll
-            for (int e = 0; e < 16; e++) {
-                const int to = t0 + 32 * i + 8 * (e >> 2) + 4 * half + (e & 3);
-                const int ro = r0 + 32 * j + (lane & 31);
+            for (int e = 0; e < NE; e++) {
+                const int br = BS == 32 ? 8 * (e >> 2) + 4 * grp + (e & 3) : 4 * grp + e;
+                const int to = t0 + BS * i + br;
+                const int ro = r0 + BS * j + lrow;
                 if (to < A.T && ro < A.R) {
                     const float2 v = make_float2(sr[i][j][e], si[i][j][e]);
                     if (A.partial)
@@ -421,7 +453,7 @@ __global__ void k_freq_reduce(const float2 *part, int n_split, int T, int R, int
 
 }  // namespace
 
-int freq_k_step() { return FQ_KS; }
+int freq_k_step() { return FQ_PAD; }
 int freq_k_group() { return FQ_G; }
 
 hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_lo,
@@ -443,28 +475,40 @@ hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_
 
 // workgroup tile of NB blocks of 32 (1, 2 or 3) that wastes the least
 // padding on a T x R array (ties: the larger tile)
-int freq_tile_blocks(int T, int R)
+// Product tiles (square, Tx x Rx extent): 16 and 48 in 16 x 16 blocks, 32,
+// 64 and 96 in 32 x 32 blocks.  Measured throughput per padded output
+// (split-bf16 products, relative): bigger tiles share each phasor among more
+// products; the 16 x 16 blocks cost more per output than 32 x 32 at equal
+// tile.  The tile that minimises padded outputs / throughput.
+static const int FQ_TILES[5] = {16, 32, 48, 64, 96};
+static const double FQ_TILE_RATE[5] = {17.8, 30.0, 38.0, 43.0, 42.0};
+
+double freq_tile_cost(int T, int R, int tile)
 {
-    int best = 3;
-    int64_t best_area = -1;
-    for (int nb = 3; nb >= 1; nb--) {
-        const int64_t t = 32 * nb, area = ((T + t - 1) / t * t) * ((R + t - 1) / t * t);
-        if (best_area < 0 || area < best_area) {
-            best_area = area;
-            best = nb;
+    for (int i = 0; i < 5; i++)
+        if (FQ_TILES[i] == tile) {
+            const double tp = (double)((T + tile - 1) / tile * tile), rp = (double)((R + tile - 1) / tile * tile);
+            return tp * rp / FQ_TILE_RATE[i];
         }
-    }
+    return 1e300;
+}
+
+int freq_tile(int T, int R)
+{
+    int best = 96;
+    for (int i = 0; i < 5; i++)
+        if (freq_tile_cost(T, R, FQ_TILES[i]) < freq_tile_cost(T, R, best)) best = FQ_TILES[i];
     return best;
 }
 
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
-                            int per_element, int nb, const int64_t *rng_lo, const int64_t *rng_hi,
+                            int per_element, int tile, const int64_t *rng_lo, const int64_t *rng_hi,
                             float2 *partial, float2 *cube, hipStream_t s)
 {
-    if ((int64_t)n_split * split_len < Ppad || split_len % FQ_KS || Ppad % FQ_KS || Ppad <= 0)
+    if ((int64_t)n_split * split_len < Ppad || split_len % FQ_PAD || Ppad % FQ_PAD || Ppad <= 0)
         return hipErrorInvalidValue;
-    if (nb < 1 || nb > 3) return hipErrorInvalidValue;
+    if (tile != 16 && tile != 32 && tile != 48 && tile != 64 && tile != 96) return hipErrorInvalidValue;
     FreqArgs A;
     A.xt = xt;
     A.yt = yt;
@@ -475,8 +519,8 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     A.M = M;
     A.K = K;
     A.Ppad = Ppad;
-    A.tt = (T + 32 * nb - 1) / (32 * nb);
-    A.rt = (R + 32 * nb - 1) / (32 * nb);
+    A.tt = (T + tile - 1) / tile;
+    A.rt = (R + tile - 1) / tile;
     A.kg = (K + FQ_G - 1) / FQ_G;
     A.n_split = n_split;
     A.split_len = split_len;
@@ -487,14 +531,20 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     const int64_t blocks = (int64_t)n_split * M * A.tt * A.rt * A.kg;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const dim3 g((unsigned)blocks), t(FQ_G * 64);
-    switch (nb * 2 + (per_element ? 1 : 0)) {
-    case 2: hipLaunchKernelGGL((k_freq_gemm<false, 1>), g, t, 0, s, A); break;
-    case 3: hipLaunchKernelGGL((k_freq_gemm<true, 1>), g, t, 0, s, A); break;
-    case 4: hipLaunchKernelGGL((k_freq_gemm<false, 2>), g, t, 0, s, A); break;
-    case 5: hipLaunchKernelGGL((k_freq_gemm<true, 2>), g, t, 0, s, A); break;
-    case 6: hipLaunchKernelGGL((k_freq_gemm<false, 3>), g, t, 0, s, A); break;
-    default: hipLaunchKernelGGL((k_freq_gemm<true, 3>), g, t, 0, s, A); break;
+    const bool pe = per_element != 0;
+#define FQ_LAUNCH(BS, NB)                                                                         \
+    do {                                                                                          \
+        if (pe) hipLaunchKernelGGL((k_freq_gemm<true, BS, NB>), g, t, 0, s, A);                   \
+        else hipLaunchKernelGGL((k_freq_gemm<false, BS, NB>), g, t, 0, s, A);                     \
+    } while (0)
+    switch (tile) {
+    case 16: FQ_LAUNCH(16, 1); break;
+    case 48: FQ_LAUNCH(16, 3); break;
+    case 32: FQ_LAUNCH(32, 1); break;
+    case 64: FQ_LAUNCH(32, 2); break;
+    default: FQ_LAUNCH(32, 3); break;
     }
+#undef FQ_LAUNCH
     if (n_split > 1) {
         const int64_t per = (int64_t)M * K * T * R;
         hipLaunchKernelGGL(k_freq_reduce, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s,

@@ -1047,7 +1047,7 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
     const int64_t ks = freq_k_step();
     const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
     const int T = c->ntx, R = c->nrx, M = A.M, K = A.K;
-    const int nb = freq_tile_blocks(T, R), tile = 32 * nb;
+    const int tile = freq_tile(T, R);
     const int64_t kg = (K + freq_k_group() - 1) / freq_k_group();
     const int64_t tiles = (int64_t)M * kg * ((T + tile - 1) / tile) * ((R + tile - 1) / tile);
     // enough workgroups to fill the chip four times over (one per CU at a
@@ -1072,7 +1072,7 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
                             c->stream));
     HIPCHK(launch_freq_gemm(c->fq_xt.as<const uint2>(), c->fq_yt.as<const uint2>(),
                             c->fq_amp.as<const float>(), c->fq_src.as<const int32_t>(), T, R, M, K,
-                            Ppad, (int)n_split, split_len, c->mode != RR_TX_SHARED, nb, nullptr,
+                            Ppad, (int)n_split, split_len, c->mode != RR_TX_SHARED, tile, nullptr,
                             nullptr, c->fq_part.as<float2>(), A.cube, c->stream));
     return RR_OK;
 }
@@ -1096,7 +1096,7 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
         // product tiles are at least half filled and whose leg tables fit the
         // budget
         if (model == RR_EXACT && !idx && c->mode == RR_TX_SHARED && c->n_paths > 0) {
-            const int64_t tl = 32 * freq_tile_blocks(c->ntx, c->nrx);
+            const int64_t tl = freq_tile(c->ntx, c->nrx);
             const int64_t tp = (c->ntx + tl - 1) / tl * tl, rp = (c->nrx + tl - 1) / tl * tl;
             if (2 * (int64_t)c->ntx * c->nrx >= tp * rp && freq_table_bytes(c, c->n_paths) <= FREQ_TABLE_MAX)
                 engine = RR_GEMM_EXACT;
@@ -1705,13 +1705,13 @@ struct BatchScene {
     int64_t n_src = 0, n_per_src = 0, n_vps = 0, V = 0;
     int kr = 0;
     // synthesis engine: requested (RR_ENGINE_AUTO, RR_DIRECT_FP32 or
-    // RR_GEMM_EXACT, tile 0 or 32/64/96), the autotuner's choice for AUTO
-    // (-1: not tuned), and the plan of the current graph
+    // RR_GEMM_EXACT, product tile 0 or 16/32/48/64/96), the autotuner's
+    // choice for AUTO (-1: not tuned), and the plan of the current graph
     int req_engine = RR_ENGINE_AUTO, req_tile = 0;
-    int tuned_engine = -1, tuned_nb = 0;
-    int try_engine = -1, try_nb = 0;      // forced plan while the tuner times a candidate
+    int tuned_engine = -1, tuned_tile = 0;
+    int try_engine = -1, try_tile = 0;    // forced plan while the tuner times a candidate
     bool use_freq = false;
-    int nb = 0;                           // exact engine: tile blocks (tile 32 nb)
+    int tile = 0;                         // exact engine: product tile
     int64_t fq_cap = 0;                   // exact engine: leg table capacity (paths)
     int fq_split = 1;
     int64_t fq_ppad = 0, fq_split_len = 0;  // table stride and split length of the graph
@@ -1786,19 +1786,19 @@ void batch_plan(BatchScene &x)
     // capacity is more than twice what it needs (growth comes from overflow)
     if (x.fq_cap <= 0 || x.fq_cap > 2 * want) x.fq_cap = want;
     x.fq_cap = std::max<int64_t>((x.fq_cap + ks - 1) / ks * ks, ks);
-    int eng = x.req_engine, nb = x.req_tile / 32;
+    int eng = x.req_engine, tile = x.req_tile;
     if (x.try_engine >= 0) {
         eng = x.try_engine;
-        nb = x.try_nb;
+        tile = x.try_tile;
     } else if (eng == RR_ENGINE_AUTO && x.tuned_engine >= 0) {
         eng = x.tuned_engine;
-        nb = x.tuned_nb;
+        tile = x.tuned_tile;
     }
-    if (nb <= 0) nb = freq_tile_blocks(x.ntx, x.nrx);
+    if (tile <= 0) tile = freq_tile(x.ntx, x.nrx);
     if (eng == RR_ENGINE_AUTO) {
         // untuned: the single-scene rule (a shared launch whose product
         // tiles are at least half filled), within the table budget
-        const int64_t tl = 32 * nb;
+        const int64_t tl = tile;
         const int64_t tp = (x.ntx + tl - 1) / tl * tl, rp = (x.nrx + tl - 1) / tl * tl;
         eng = x.mode == RR_TX_SHARED && 2 * (int64_t)x.ntx * x.nrx >= tp * rp &&
                       batch_freq_bytes(x, x.fq_cap) <= BATCH_FREQ_TABLE_MAX
@@ -1806,7 +1806,7 @@ void batch_plan(BatchScene &x)
                   : RR_DIRECT_FP32;
     }
     x.use_freq = eng == RR_GEMM_EXACT;
-    x.nb = nb;
+    x.tile = tile;
 }
 
 // per-scene tables and global buffers for the current scene set and cubes;
@@ -1894,7 +1894,7 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0, int only_sce
             int64_t P = x.fq_cap;
             if (p_limit > 0) P = std::min<int64_t>(P, std::max<int64_t>((p_limit + ks - 1) / ks * ks, ks));
             x.fq_ppad = P;
-            const int M = x.chirp.n_chirps, K = x.chirp.n_samples, tl = 32 * x.nb;
+            const int M = x.chirp.n_chirps, K = x.chirp.n_samples, tl = x.tile;
             const int64_t kg = (K + freq_k_group() - 1) / freq_k_group();
             const int64_t tiles = (int64_t)M * kg * ((x.ntx + tl - 1) / tl) * ((x.nrx + tl - 1) / tl);
             int64_t n_split = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
@@ -2052,7 +2052,7 @@ int batch_enqueue_synth(rr_batch *b, bool timed)
         HIPCHK(launch_freq_gemm(b->fq_xt.as<const uint2>(), b->fq_yt.as<const uint2>(),
                                 b->fq_amp.as<const float>(), b->fq_src.as<const int32_t>(), x.ntx,
                                 x.nrx, M, K, x.fq_ppad, x.fq_split, x.fq_split_len,
-                                x.mode != RR_TX_SHARED, x.nb, lo, hi, b->fq_part.as<float2>(),
+                                x.mode != RR_TX_SHARED, x.tile, lo, hi, b->fq_part.as<float2>(),
                                 static_cast<float2 *>(b->cubes[s]), st));
     }
     if (timed) HIPCHK(hipEventRecord(b->ev[3], st));
@@ -2334,42 +2334,36 @@ int rr_batch_tune(rr_batch *b, void *const *cubes)
             if (x.chirp.n_samples == K) x.kr = best;
     }
     // 2. per scene left to AUTO: the direct engine against the exact product
-    // engine at each tile that pads at most twice the least padding (shared
-    // launches; a per-element launch wastes the product on other Tx rows).
-    // The product engine's scene runs as separate kernels: it has to win by
-    // a tenth and 20 us.
+    // engine at each tile whose modelled cost is within 1.5x of the least
+    // (shared launches; a per-element launch wastes the product on other Tx
+    // rows).  The product engine's scene runs as separate kernels: it has to
+    // win by a tenth and 20 us.
     for (int s = 0; s < b->S && !rc; s++) {
         BatchScene &x = b->sc[s];
         if (x.req_engine != RR_ENGINE_AUTO) continue;
         float t_direct = 0.0f;
         x.try_engine = RR_DIRECT_FP32;
         if ((rc = time_synth(0, s, &t_direct))) break;
-        int best_eng = RR_DIRECT_FP32, best_nb = 0;
+        int best_eng = RR_DIRECT_FP32, best_tile = 0;
         float best_ms = t_direct;
-        if (x.mode == RR_TX_SHARED) {
-            int64_t least = -1;
-            int64_t area[4] = {0, 0, 0, 0};
-            for (int nb = 1; nb <= 3; nb++) {
-                const int64_t tl = 32 * nb;
-                area[nb] = ((x.ntx + tl - 1) / tl * tl) * ((x.nrx + tl - 1) / tl * tl);
-                if (least < 0 || area[nb] < least) least = area[nb];
-            }
-            for (int nb = 1; nb <= 3; nb++) {
-                if (area[nb] > 2 * least) continue;
-                if (batch_freq_bytes(x, std::max(x.fq_cap, x.n_last)) > BATCH_FREQ_TABLE_MAX) continue;
+        if (x.mode == RR_TX_SHARED &&
+            batch_freq_bytes(x, std::max(x.fq_cap, x.n_last)) <= BATCH_FREQ_TABLE_MAX) {
+            const double least = freq_tile_cost(x.ntx, x.nrx, freq_tile(x.ntx, x.nrx));
+            for (int tile : {16, 32, 48, 64, 96}) {
+                if (freq_tile_cost(x.ntx, x.nrx, tile) > 1.5 * least) continue;
                 x.try_engine = RR_GEMM_EXACT;
-                x.try_nb = nb;
+                x.try_tile = tile;
                 float ms = 0.0f;
                 if ((rc = time_synth(0, s, &ms))) break;
                 if (ms * 1.1f + 0.02f < best_ms) {
                     best_ms = ms;
                     best_eng = RR_GEMM_EXACT;
-                    best_nb = nb;
+                    best_tile = tile;
                 }
             }
         }
         x.tuned_engine = best_eng;
-        x.tuned_nb = best_nb;
+        x.tuned_tile = best_tile;
     }
     for (auto &x : b->sc) x.try_engine = -1;
     batch_drop_graph(b);
@@ -2382,8 +2376,9 @@ int rr_batch_set_engine(rr_batch *b, int32_t slot, int32_t engine, int32_t tile)
     if (slot < 0 || slot >= b->S) return fail(RR_EINVAL, "slot out of range");
     if (engine != RR_ENGINE_AUTO && engine != RR_DIRECT_FP32 && engine != RR_GEMM_EXACT)
         return fail(RR_EINVAL, "batched scenes use RR_ENGINE_AUTO, RR_DIRECT_FP32 or RR_GEMM_EXACT");
-    if (tile != 0 && (engine != RR_GEMM_EXACT || (tile != 32 && tile != 64 && tile != 96)))
-        return fail(RR_EINVAL, "tile 32, 64 or 96 with RR_GEMM_EXACT, else 0");
+    if (tile != 0 && (engine != RR_GEMM_EXACT ||
+                      (tile != 16 && tile != 32 && tile != 48 && tile != 64 && tile != 96)))
+        return fail(RR_EINVAL, "tile 16, 32, 48, 64 or 96 with RR_GEMM_EXACT, else 0");
     BatchScene &x = b->sc[slot];
     x.req_engine = engine;
     x.req_tile = tile;
@@ -2401,7 +2396,7 @@ int rr_batch_get_plan(rr_batch *b, int32_t *engine_out, int32_t *tile_out)
     for (int s = 0; s < b->S; s++) {
         BatchScene &x = b->sc[s];
         engine_out[s] = x.use_freq ? RR_GEMM_EXACT : RR_DIRECT_FP32;
-        tile_out[s] = x.use_freq ? 32 * x.nb : x.kr;
+        tile_out[s] = x.use_freq ? x.tile : x.kr;
     }
     return RR_OK;
 }

@@ -192,12 +192,13 @@ hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_
                             const double *tx, int T, const double *rx, int R, double f0c, double dfc,
                             double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
                             hipStream_t s);
-int freq_tile_blocks(int T, int R);   // exact-GEMM tile: NB blocks of 32 per side
+int freq_tile(int T, int R);          // exact-GEMM tile (16, 32, 48, 64 or 96) of least modelled cost
+double freq_tile_cost(int T, int R, int tile);   // modelled time of a tile (relative)
 // rng_lo / rng_hi (may be NULL): the path count read on the device, as for
 // launch_freq_prep; the splits then divide that count evenly
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
-                            int per_element, int nb, const int64_t *rng_lo, const int64_t *rng_hi,
+                            int per_element, int tile, const int64_t *rng_lo, const int64_t *rng_hi,
                             float2 *partial, float2 *cube, hipStream_t s);
 hipError_t launch_refit(float4 *nodes, float *ubox, const int32_t *order,
                         const int64_t *level_start, int n_levels, float4 *ltris, int64_t n_tris,

@@ -79,10 +79,10 @@ def test_batch_matches_single_scene(gpu):
 
 
 def _exact_workloads():
-    """Shared launches around the product tiles (32, 64, 96 and ragged), a
+    """Shared launches around the product tiles (16 to 96, and ragged), a
     moving street, a per-element launch and a points-only scene; the slots
-    left at the least padding tile have enough (chirp, sample, tile) work
-    items that neither side splits the paths."""
+    left at the least cost tile split their paths alike in the batch and in
+    the single-scene launch (the batch sizes its splits by table capacity)."""
     def wl(name, scene, arr, K, M, rays, seed):
         return sg.Workload(name, scene, arr, sg.Chirp(n_samples=K, n_chirps=M),
                            sg.TraceParams(n_rays=rays, max_bounces=2, seed=seed))
@@ -93,6 +93,8 @@ def _exact_workloads():
         (wl("street40", street, sg.array_sparse_grid(40, 40, 6), 96, 8, 120_000, 2), 64),
         (wl("tiny96", c1, sg.array_sparse_grid(96, 96, 7, grid=128), 16, 2, 40_000, 3), 96),
         (wl("street7x9", street, sg.array_sparse_grid(7, 9, 8), 128, 16, 100_000, 4), 32),
+        (wl("tiny12", c1, sg.array_sparse_grid(12, 13, 10), 64, 8, 60_000, 6), 16),
+        (wl("street42", street, sg.array_sparse_grid(42, 42, 12), 32, 4, 80_000, 7), 48),
         (wl("perel", c1, sg.array_ula(6, 8, mode=sg.MODE_PER_TX), 128, 32, 60_000, 5), 0),
         (sg.Workload("points", sg.point_only([[8.0, 1.0, 0.5], [15.0, -2.0, 0.6]],
                                              vel=[[1.0, 0.0, 0.0], [-2.0, 0.5, 0.0]]),
@@ -102,12 +104,13 @@ def _exact_workloads():
 
 
 def test_batch_exact_engine(gpu, orc):
-    """Every slot pinned to the product engine (tiles 32 / 64 / 96 forced or
-    least padding): counts equal the single-scene launch; a slot at the least
-    padding tile equals the single-scene product engine bit for bit (same
-    tile, one path split on both sides), forced tiles agree with it to float
-    rounding; sampled entries within 1e-4 of the FP64 oracle; replays, and a
-    re-capture for new cube buffers, reproduce the cubes bit for bit."""
+    """Every slot pinned to the product engine (tiles 16 / 32 / 48 / 64 / 96
+    forced, or the tile of least modelled cost): counts equal the
+    single-scene launch; a slot at the least cost tile equals the single-scene
+    product engine bit for bit (same tile, same path splits on both sides),
+    forced tiles agree with it to float rounding; sampled entries within 1e-4
+    of the FP64 oracle; replays, and a re-capture for new cube buffers,
+    reproduce the cubes bit for bit."""
     import paper_2307_15412_amd as rr
     cases = _exact_workloads()
     B = rr.Batch(gpu, len(cases))
@@ -116,7 +119,7 @@ def test_batch_exact_engine(gpu, orc):
         B.set_engine(i, rr.GEMM_EXACT, tile)
     eng, tiles = B.plan()
     assert (eng == rr.GEMM_EXACT).all()
-    assert [int(t) for t in tiles[1:4]] == [64, 96, 32]
+    assert [int(t) for t in tiles[1:6]] == [64, 96, 32, 16, 48]
     cubes = B.alloc_cubes()
     counts = B.launch(cubes)
     for i, (w, tile) in enumerate(cases):
@@ -179,7 +182,7 @@ def test_batch_autotune(gpu):
     eng, pt = B.plan()
     for e, t, tl, w in zip(eng, pt, tiles, ws):
         if e == rr.GEMM_EXACT:
-            assert w.array.mode == sg.MODE_SHARED and t in (32, 64, 96)
+            assert w.array.mode == sg.MODE_SHARED and t in (16, 32, 48, 64, 96)
         else:
             assert e == rr.DIRECT_FP32 and t == tl
     counts = B.launch(cubes)

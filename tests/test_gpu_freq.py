@@ -2,8 +2,8 @@
 sample) against the FP64 oracle.  ENGINE_AUTO sends the exact model here, so
 the engine is held to the exact model's FP32 bar (relative error <= 1e-4, the
 direct engine's), not the split-bf16 GEMM's 1e-3; it measures ~5e-7: full
-cubes at Tx / Rx counts around the 32-row blocks and the 32-, 64- and 96-wide
-tiles, several chirps of a moving scene, the per-element launch (paths feed
+cubes at Tx / Rx counts around the 16- and 32-row blocks and the 16-, 32-,
+48-, 64- and 96-wide tiles, several chirps of a moving scene, the per-element launch (paths feed
 only their own Tx), path counts around the 16-path steps and the split
 boundaries, an empty path list; the hand set-up against the direct FP32 engine
 and sampled oracle entries; invalid requests refused."""
@@ -34,7 +34,8 @@ def _exact(gpu):
 @pytest.mark.parametrize("n_tx,n_rx,K,M", [(3, 7, 32, 2), (33, 97, 16, 1), (96, 96, 8, 1),
                                            (97, 5, 12, 3), (1, 1, 40, 1), (5, 9, 13, 2),
                                            (2, 3, 3, 1), (55, 55, 16, 2), (100, 190, 8, 1),
-                                           (190, 95, 8, 1)])
+                                           (190, 95, 8, 1), (15, 15, 24, 2), (42, 42, 8, 1),
+                                           (17, 50, 9, 1), (47, 40, 5, 2)])
 def test_tile_edges(gpu, orc, n_tx, n_rx, K, M):
     w = sg.workload_tiny(1)
     w.array = sg.array_sparse_grid(n_tx, n_rx, 3, grid=128, mode=sg.MODE_SHARED)
