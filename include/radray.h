@@ -301,16 +301,20 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
  *   engine RR_DIRECT_FP32 (either model), RR_GEMM_BF16X3 (separable only:
  *          split-bf16 hi+lo complex GEMM on MFMA, FP32 accumulation; each
  *          chirp's samples are computed in whole tiles of 64; relative error
- *          bar 1e-3), RR_GEMM_EXACT (exact model only, full cube: one
- *          split-bf16 complex product per (chirp, sample) of FP64-reduced Tx
- *          and Rx leg phasors, held to the exact model's 1e-4 bar), or
+ *          bar 1e-3), RR_GEMM_EXACT (exact model only, full cube: split-bf16
+ *          complex products on the matrix cores of FP64-reduced leg phases,
+ *          held to the exact model's 1e-4 bar; either one (Tx x paths) by
+ *          (paths x Rx) product per (chirp, sample) in square tiles of 16,
+ *          32, 48, 64 or 96, or, per (channel, chirp), one (k1 x paths) by
+ *          (paths x k2) product over the samples k = k1 S + k2 (at most 1024
+ *          samples); the layout of least modelled time), or
  *          RR_ENGINE_AUTO: the separable model takes RR_GEMM_BF16X3 when the
  *          64-sample tiling pads a chirp by at most a quarter; the exact model
- *          takes RR_GEMM_EXACT for a shared launch whose Tx x Rx product
- *          tiles (16 to 96 square, the tile of least modelled cost) are at least
- *          half filled and whose leg tables fit its budget; everything else, and sampled entries, the direct engine.
- *          AUTO never changes the model, and each engine it picks meets that
- *          model's error bar.
+ *          takes RR_GEMM_EXACT for a shared launch whose best layout is
+ *          modelled at 1.5x the direct engine's throughput or more and whose
+ *          leg tables fit its budget; everything else, and sampled entries,
+ *          the direct engine.  AUTO never changes the model, and each engine
+ *          it picks meets that model's error bar.
  *   cube_dev complex64 [n_ch][n_chirps][n_samples], cube_elems = its complex
  *          element count; the cube is overwritten.
  *   sample_idx_dev int64 [n_sample] flat entry indices (c*M*K + m*K + k):
@@ -485,25 +489,26 @@ int rr_batch_launch(rr_batch *batch, void *const *cubes, int64_t *n_paths_out);
  * is linear in the path count): for every distinct sample count time each
  * candidate samples-per-lane value of the direct engine on the scenes with
  * that count and keep the fastest; then per scene left to RR_ENGINE_AUTO
- * time the direct engine against the product engine at every tile (16, 32,
- * 48, 64, 96) whose modelled cost (padded outputs over the tile's measured
- * throughput) is within 1.5x of the least (shared launches only), and keep
- * the product engine if it is faster by a tenth and 20 us.  Afterwards
+ * time the direct engine against the product engine at every layout (the
+ * sample split, tiles 16, 32, 48, 64, 96) whose modelled time (padded outputs
+ * over the layout's measured throughput) is within 1.5x of the least (shared
+ * launches only), and keep the product engine if it is faster by a tenth and
+ * 20 us.  Afterwards
  * the cubes hold partial sums: run rr_batch_launch to fill them.
  * rr_batch_get_tiles reports the direct engine's samples per lane per scene;
  * rr_batch_get_plan the engine each scene runs on (RR_DIRECT_FP32 or
  * RR_GEMM_EXACT, both host int32 [n_scenes]) and its tile (samples per lane,
- * or the product tile's Tx and Rx extent).  Untuned scenes left to AUTO take
- * rr_synthesize's rule (the product engine for a shared launch whose tiles
- * are at least half filled, tables within 16 GiB). */
+ * or the product layout as rr_batch_set_engine numbers it).  Untuned scenes
+ * left to AUTO take rr_synthesize's rule (tables within 16 GiB). */
 int rr_batch_tune(rr_batch *batch, void *const *cubes);
 int rr_batch_get_tiles(rr_batch *batch, int32_t *samples_per_lane_out);
 int rr_batch_get_plan(rr_batch *batch, int32_t *engine_out, int32_t *tile_out);
 
 /* Pin slot `slot`'s synthesis engine: RR_ENGINE_AUTO (default: the tuner's
- * or the rule's choice), RR_DIRECT_FP32, or RR_GEMM_EXACT with product tile
- * 16, 32, 48, 64 or 96 (0: the tile of least modelled cost).  Invalidates the
- * captured graph.
+ * or the rule's choice), RR_DIRECT_FP32, or RR_GEMM_EXACT with product
+ * layout `tile`: a square Tx x Rx tile of 16, 32, 48, 64 or 96, 1 for the
+ * per-channel sample split (at most 1024 samples), 0 for the layout of least
+ * modelled time.  Invalidates the captured graph.
  * Errors: RR_EINVAL (slot, engine, tile). */
 int rr_batch_set_engine(rr_batch *batch, int32_t slot, int32_t engine, int32_t tile);
 

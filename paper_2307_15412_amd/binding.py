@@ -659,8 +659,9 @@ class Batch:
 
     def set_engine(self, slot, engine=ENGINE_AUTO, tile=0):
         """Pin slot's synthesis engine (ENGINE_AUTO, DIRECT_FP32, or
-        GEMM_EXACT with product tile 16, 32, 48, 64 or 96; 0 = the tile of
-        least modelled cost)."""
+        GEMM_EXACT with product layout tile: 16, 32, 48, 64 or 96 square
+        Tx x Rx tiles, 1 = per-channel sample split, 0 = least modelled
+        time)."""
         self.ctx._check(self.lib.rr_batch_set_engine(self.h, int(slot), int(engine), int(tile)))
 
     def plan(self):

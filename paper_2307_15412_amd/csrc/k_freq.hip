@@ -32,6 +32,7 @@ namespace {
 
 #define FQ_G 4            // samples per workgroup, one per wavefront
 #define FQ_PAD 32         // path granule of the tables and splits (a multiple of every step)
+#define FQ_KS_KMAX 1024   // most samples of the sample split (2 x 2 blocks of 16 x 16 = 32 x 32)
 // a workgroup tile is NB x NB blocks of 32 x 32 (Tx x Rx), NB = 1, 2, 3; per
 // step its table words are 8 NB chunks of 1 KiB (X and Y, NB blocks, 4 pieces)
 
@@ -186,10 +187,13 @@ template <> struct Mfma<16> {
     }
 };
 
-// exp(-j 2 pi u) of fixed-point turns u
+// exp(-j 2 pi u) of fixed-point turns u: the top 23 bits of u become the
+// mantissa of a float in [1, 2) turns (one funnel shift), which the hardware
+// sine and cosine (arguments in turns) take as they are; the phase keeps
+// 2^-23 turns (7.5e-7 rad)
 __device__ __forceinline__ void phasor(unsigned u, float &re, float &im)
 {
-    const float f = (float)(int)u * 2.3283064365386963e-10f;
+    const float f = __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, u, 9u));
     re = __builtin_amdgcn_cosf(f);
     im = -__builtin_amdgcn_sinf(f);
 }
@@ -246,6 +250,9 @@ struct FreqArgs {
     // with rng_lo: the path count is *rng_hi - *rng_lo (at most Ppad), read
     // on the device, and the splits divide its padded count evenly
     const int64_t *rng_lo, *rng_hi;
+    // sample split (one channel per wavefront): k = k1 S + k2
+    int S;
+    int64_t n_waves;
 };
 
 // One workgroup: a BS NB x BS NB (Tx x Rx) tile of FQ_G consecutive samples
@@ -428,6 +435,153 @@ void k_freq_gemm(FreqArgs A)
             }
 }
 
+// One wavefront per (path split, chirp, channel): the channel's samples as a
+// product over paths.  With beta and gamma of channel (t, r) the sums of its
+// Tx and Rx leg words, the phase of sample k = k1 S + k2 splits exactly (in
+// 32-bit fixed-point turns) as (beta + k1 S gamma) + k2 gamma, so
+//     s[k1 S + k2] = sum_p U[k1, p] V[p, k2],
+//     U[k1, p] = a_p exp(-j 2 pi (beta + k1 S gamma)),  V[p, k2] = exp(-j 2 pi k2 gamma),
+// a (Q x paths) by (paths x S) complex product in QB x SB blocks of 16 x 16
+// (v_mfma_f32_16x16x32_bf16, 32 paths a step, split bf16 as the tile
+// kernels).  Per path and channel it evaluates Q + S phasors instead of the
+// Tx x Rx tiles' (T + R) K / (T R): the better choice for small arrays.  Each
+// lane loads its 8 paths' leg words straight from the tables (the 16 lanes of
+// a row group read the same words).
+template <bool PER_EL, int QB, int SB>
+__global__ __launch_bounds__(FQ_G * 64) void k_freq_ks(FreqArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wv = (int64_t)blockIdx.x * FQ_G + (threadIdx.x >> 6);
+    if (wv >= A.n_waves) return;
+    // wave -> (split, chirp, channel), channel fastest
+    const int C = A.T * A.R;
+    int64_t id = wv;
+    const int c = (int)(id % C);
+    id /= C;
+    const int m = (int)(id % A.M);
+    const int s = (int)(id / A.M);
+    const int t = c / A.R, r = c - t * A.R;
+    int64_t used = A.Ppad, split_len = A.split_len;
+    if (A.rng_lo) {
+        const int64_t n = min(max(*A.rng_hi - *A.rng_lo, (int64_t)0), A.Ppad);
+        used = (n + FQ_PAD - 1) / FQ_PAD * FQ_PAD;
+        split_len = ((used + A.n_split - 1) / A.n_split + FQ_PAD - 1) / FQ_PAD * FQ_PAD;
+    }
+    const int64_t pstart = (int64_t)s * split_len;
+    const int64_t nsteps = max(min(used, pstart + split_len) - pstart, (int64_t)0) / 32;
+    const int grp = lane >> 4, lrow = lane & 15;
+    // the lane's 8 paths of a step: pstart + 32 step + 8 grp + (0 .. 7)
+    const int64_t p0 = nsteps > 0 ? pstart + 8 * grp : 0;
+    const u32x4 *xp = reinterpret_cast<const u32x4 *>(A.xt + ((int64_t)m * A.T + t) * A.Ppad + p0);
+    const u32x4 *yp = reinterpret_cast<const u32x4 *>(A.yt + ((int64_t)m * A.R + r) * A.Ppad + p0);
+    const u32x4 *apn = reinterpret_cast<const u32x4 *>(A.amp + p0);
+    const u32x4 *spn = reinterpret_cast<const u32x4 *>(A.src + p0);
+    unsigned kq[QB], k2[SB];
+#pragma unroll
+    for (int q = 0; q < QB; q++) kq[q] = (unsigned)((16 * q + lrow) * A.S);
+#pragma unroll
+    for (int b = 0; b < SB; b++) k2[b] = (unsigned)(16 * b + lrow);
+    f32x4 sr[QB][SB], si[QB][SB];
+#pragma unroll
+    for (int i = 0; i < QB; i++)
+#pragma unroll
+        for (int j = 0; j < SB; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                sr[i][j][e] = 0.0f;
+                si[i][j][e] = 0.0f;
+            }
+    // a step's words, loaded a step ahead
+    u32x4 X[4], Y[4], AM[2], SR[2];
+#define KS_LOAD(st_)                                                                              \
+    do {                                                                                          \
+        const int64_t o_ = (st_) * 16;                                                            \
+        _Pragma("unroll") for (int q_ = 0; q_ < 4; q_++) {                                        \
+            X[q_] = xp[o_ + q_];                                                                  \
+            Y[q_] = yp[o_ + q_];                                                                  \
+        }                                                                                         \
+        AM[0] = apn[(st_) * 8];                                                                   \
+        AM[1] = apn[(st_) * 8 + 1];                                                               \
+        if (PER_EL) {                                                                             \
+            SR[0] = spn[(st_) * 8];                                                               \
+            SR[1] = spn[(st_) * 8 + 1];                                                           \
+        }                                                                                         \
+    } while (0)
+    if (nsteps > 0) KS_LOAD(0);
+    for (int64_t st = 0; st < nsteps; st++) {
+        Raw ru, rv;   // (beta, gamma) of U, (0, gamma) of V
+        float a[8];
+        {
+            unsigned *wu = reinterpret_cast<unsigned *>(ru.w), *wv2 = reinterpret_cast<unsigned *>(rv.w);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                wu[4 * q] = X[q].x + Y[q].x;
+                wu[4 * q + 1] = X[q].y + Y[q].y;
+                wu[4 * q + 2] = X[q].z + Y[q].z;
+                wu[4 * q + 3] = X[q].w + Y[q].w;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                wv2[2 * e] = 0u;
+                wv2[2 * e + 1] = wu[2 * e + 1];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                a[e] = __uint_as_float(AM[0][e]);
+                a[4 + e] = __uint_as_float(AM[1][e]);
+                if (PER_EL) {
+                    // a path of the per-element launch feeds its own Tx only
+                    const int s0 = (int)SR[0][e], s1 = (int)SR[1][e];
+                    if (s0 >= 0 && s0 != t) a[e] = 0.0f;
+                    if (s1 >= 0 && s1 != t) a[4 + e] = 0.0f;
+                }
+            }
+        }
+        if (st + 1 < nsteps) KS_LOAD(st + 1);
+        Frag v[SB];
+#pragma unroll
+        for (int j = 0; j < SB; j++) v[j] = leg_frag(rv, k2[j], nullptr);
+#pragma unroll
+        for (int i = 0; i < QB; i++) {
+            const Frag x = leg_frag(ru, kq[i], a);
+            const uint4 nih = neg(x.ih), nil = neg(x.il);
+#pragma unroll
+            for (int j = 0; j < SB; j++) {
+                sr[i][j] = Mfma<16>::mma(x.rh, v[j].rh, sr[i][j]);
+                si[i][j] = Mfma<16>::mma(x.rh, v[j].ih, si[i][j]);
+                sr[i][j] = Mfma<16>::mma(x.rh, v[j].rl, sr[i][j]);
+                si[i][j] = Mfma<16>::mma(x.rh, v[j].il, si[i][j]);
+                sr[i][j] = Mfma<16>::mma(x.rl, v[j].rh, sr[i][j]);
+                si[i][j] = Mfma<16>::mma(x.rl, v[j].ih, si[i][j]);
+                sr[i][j] = Mfma<16>::mma(nih, v[j].ih, sr[i][j]);
+                si[i][j] = Mfma<16>::mma(x.ih, v[j].rh, si[i][j]);
+                sr[i][j] = Mfma<16>::mma(nih, v[j].il, sr[i][j]);
+                si[i][j] = Mfma<16>::mma(x.ih, v[j].rl, si[i][j]);
+                sr[i][j] = Mfma<16>::mma(nil, v[j].ih, sr[i][j]);
+                si[i][j] = Mfma<16>::mma(x.il, v[j].rh, si[i][j]);
+            }
+        }
+    }
+#undef KS_LOAD
+    // D layout: register e of lane l is row 4 (l / 16) + e (k1), column
+    // l % 16 (k2) of the block
+#pragma unroll
+    for (int i = 0; i < QB; i++)
+#pragma unroll
+        for (int j = 0; j < SB; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int kk1 = 16 * i + 4 * grp + e, kk2 = 16 * j + lrow;
+                const int k = kk1 * A.S + kk2;
+                if (kk2 >= A.S || k >= A.K) continue;
+                const float2 v = make_float2(sr[i][j][e], si[i][j][e]);
+                if (A.partial)
+                    A.out[((((int64_t)s * A.M + m) * A.K + k) * A.T + t) * A.R + r] = v;
+                else
+                    A.out[((int64_t)c * A.M + m) * A.K + k] = v;
+            }
+}
+
 // cube[(t R + r) M + m][k] = sum over splits, in split order
 __global__ void k_freq_reduce(const float2 *part, int n_split, int T, int R, int M, int K,
                               float2 *cube)
@@ -475,30 +629,86 @@ hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_
 
 // workgroup tile of NB blocks of 32 (1, 2 or 3) that wastes the least
 // padding on a T x R array (ties: the larger tile)
-// Product tiles (square, Tx x Rx extent): 16 and 48 in 16 x 16 blocks, 32,
-// 64 and 96 in 32 x 32 blocks.  Measured throughput per padded output
-// (split-bf16 products, relative): bigger tiles share each phasor among more
-// products; the 16 x 16 blocks cost more per output than 32 x 32 at equal
-// tile.  The tile that minimises padded outputs / throughput.
+// Product layouts: Tx x Rx tiles (square; 16 and 48 in 16 x 16 blocks, 32,
+// 64 and 96 in 32 x 32 blocks), or tile 1: one channel per wavefront with the
+// samples split (k = k1 S + k2).  Measured throughput per padded output
+// (split-bf16 products, 1e12 complex multiply-adds/s on one MI355X): bigger
+// tiles share each phasor among more products; the 16 x 16 blocks cost more
+// per output than 32 x 32 at equal tile; the sample split pads nothing across
+// channels and shares each phasor among ~sqrt(K) samples.  The layout that
+// minimises padded outputs / throughput.
 static const int FQ_TILES[5] = {16, 32, 48, 64, 96};
 static const double FQ_TILE_RATE[5] = {17.8, 30.0, 38.0, 43.0, 42.0};
 
-double freq_tile_cost(int T, int R, int tile)
+// sample split of K samples: QB x SB blocks of 16 x 16, S samples a row
+static void ks_shape(int K, int &qb, int &sb, int &S)
 {
+    if (K <= 256) {
+        qb = sb = 1;
+        S = (K + 15) / 16;
+    } else if (K <= 512) {
+        qb = 1;
+        sb = 2;
+        S = (K + 15) / 16;
+    } else {
+        qb = sb = 2;
+        S = (K + 31) / 32;
+    }
+}
+
+int freq_tile(int T, int R, int K);
+
+static double ks_rate(int K)
+{
+    return K <= 128 ? 9.0 : K <= 256 ? 17.0 : K <= 512 ? 23.0 : 25.0;
+}
+
+double freq_tile_cost(int T, int R, int K, int tile)
+{
+    if (tile == 1) return K <= FQ_KS_KMAX ? (double)T * R * K / ks_rate(K) : 1e300;
     for (int i = 0; i < 5; i++)
         if (FQ_TILES[i] == tile) {
             const double tp = (double)((T + tile - 1) / tile * tile), rp = (double)((R + tile - 1) / tile * tile);
-            return tp * rp / FQ_TILE_RATE[i];
+            return tp * rp * K / FQ_TILE_RATE[i];
         }
     return 1e300;
 }
 
-int freq_tile(int T, int R)
+// the direct FP32 engine's throughput in the same units (measured on the
+// batched streets); the product engine pays at 1.5x that
+static const double DIRECT_RATE = 9.0;
+
+bool freq_pays(int T, int R, int K)
+{
+    const int tile = freq_tile(T, R, K);
+    return (double)T * R * K / freq_tile_cost(T, R, K, tile) >= 1.5 * DIRECT_RATE;
+}
+
+int freq_tile(int T, int R, int K)
 {
     int best = 96;
-    for (int i = 0; i < 5; i++)
-        if (freq_tile_cost(T, R, FQ_TILES[i]) < freq_tile_cost(T, R, best)) best = FQ_TILES[i];
+    for (int tile : {1, 16, 32, 48, 64, 96})
+        if (freq_tile_cost(T, R, K, tile) < freq_tile_cost(T, R, K, best)) best = tile;
     return best;
+}
+
+void freq_splits(int tile, int T, int R, int M, int K, int64_t Ppad, int &n_split, int64_t &split_len)
+{
+    // enough workgroups to fill the chip four times over (one per CU at a
+    // time), at least 16 steps of paths each
+    int64_t groups;
+    if (tile == 1) {
+        groups = ((int64_t)M * T * R + FQ_G - 1) / FQ_G;
+    } else {
+        const int64_t kg = (K + FQ_G - 1) / FQ_G;
+        groups = (int64_t)M * kg * ((T + tile - 1) / tile) * ((R + tile - 1) / tile);
+    }
+    int64_t ns = std::max<int64_t>(1, (1024 + groups - 1) / groups);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, Ppad / (16 * FQ_PAD)));
+    int64_t len = (Ppad + ns - 1) / ns;
+    len = (len + FQ_PAD - 1) / FQ_PAD * FQ_PAD;
+    n_split = (int)((Ppad + len - 1) / len);
+    split_len = len;
 }
 
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
@@ -508,7 +718,9 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
 {
     if ((int64_t)n_split * split_len < Ppad || split_len % FQ_PAD || Ppad % FQ_PAD || Ppad <= 0)
         return hipErrorInvalidValue;
-    if (tile != 16 && tile != 32 && tile != 48 && tile != 64 && tile != 96) return hipErrorInvalidValue;
+    if (tile != 1 && tile != 16 && tile != 32 && tile != 48 && tile != 64 && tile != 96)
+        return hipErrorInvalidValue;
+    if (tile == 1 && K > FQ_KS_KMAX) return hipErrorInvalidValue;
     FreqArgs A;
     A.xt = xt;
     A.yt = yt;
@@ -528,16 +740,30 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     A.out = n_split > 1 ? partial : cube;
     A.rng_lo = rng_lo;
     A.rng_hi = rng_hi;
-    const int64_t blocks = (int64_t)n_split * M * A.tt * A.rt * A.kg;
+    int qb = 1, sb = 1;
+    ks_shape(K, qb, sb, A.S);
+    A.n_waves = (int64_t)n_split * M * T * R;
+    const int64_t blocks = tile == 1 ? (A.n_waves + FQ_G - 1) / FQ_G
+                                     : (int64_t)n_split * M * A.tt * A.rt * A.kg;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const dim3 g((unsigned)blocks), t(FQ_G * 64);
     const bool pe = per_element != 0;
+#define KS_LAUNCH(QB, SB)                                                                         \
+    do {                                                                                          \
+        if (pe) hipLaunchKernelGGL((k_freq_ks<true, QB, SB>), g, t, 0, s, A);                     \
+        else hipLaunchKernelGGL((k_freq_ks<false, QB, SB>), g, t, 0, s, A);                       \
+    } while (0)
 #define FQ_LAUNCH(BS, NB)                                                                         \
     do {                                                                                          \
         if (pe) hipLaunchKernelGGL((k_freq_gemm<true, BS, NB>), g, t, 0, s, A);                   \
         else hipLaunchKernelGGL((k_freq_gemm<false, BS, NB>), g, t, 0, s, A);                     \
     } while (0)
     switch (tile) {
+    case 1:
+        if (qb == 1 && sb == 1) KS_LAUNCH(1, 1);
+        else if (qb == 1) KS_LAUNCH(1, 2);
+        else KS_LAUNCH(2, 2);
+        break;
     case 16: FQ_LAUNCH(16, 1); break;
     case 48: FQ_LAUNCH(16, 3); break;
     case 32: FQ_LAUNCH(32, 1); break;
@@ -545,6 +771,7 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     default: FQ_LAUNCH(32, 3); break;
     }
 #undef FQ_LAUNCH
+#undef KS_LAUNCH
     if (n_split > 1) {
         const int64_t per = (int64_t)M * K * T * R;
         hipLaunchKernelGGL(k_freq_reduce, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s,

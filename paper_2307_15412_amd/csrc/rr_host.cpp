@@ -1047,16 +1047,10 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
     const int64_t ks = freq_k_step();
     const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
     const int T = c->ntx, R = c->nrx, M = A.M, K = A.K;
-    const int tile = freq_tile(T, R);
-    const int64_t kg = (K + freq_k_group() - 1) / freq_k_group();
-    const int64_t tiles = (int64_t)M * kg * ((T + tile - 1) / tile) * ((R + tile - 1) / tile);
-    // enough workgroups to fill the chip four times over (one per CU at a
-    // time), at least 16 steps of paths each
-    int64_t n_split = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
-    n_split = std::min<int64_t>(n_split, std::max<int64_t>(1, Ppad / (16 * ks)));
-    int64_t split_len = (Ppad + n_split - 1) / n_split;
-    split_len = (split_len + ks - 1) / ks * ks;
-    n_split = (Ppad + split_len - 1) / split_len;
+    const int tile = freq_tile(T, R, K);
+    int n_split = 1;
+    int64_t split_len = Ppad;
+    freq_splits(tile, T, R, M, K, Ppad, n_split, split_len);
     int rc;
     if ((rc = c->fq_pm.ensure((size_t)M * Ppad * 64))) return rc;
     if ((rc = c->fq_xt.ensure((size_t)M * T * Ppad * 8))) return rc;
@@ -1092,15 +1086,12 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
         const int64_t Kp = (K + CT - 1) / CT * CT;
         engine = (model == RR_SEPARABLE && !idx && 4 * Kp <= 5 * K) ? RR_GEMM_BF16X3
                                                                      : RR_DIRECT_FP32;
-        // the exact model as per-sample products: for a shared launch whose
-        // product tiles are at least half filled and whose leg tables fit the
-        // budget
-        if (model == RR_EXACT && !idx && c->mode == RR_TX_SHARED && c->n_paths > 0) {
-            const int64_t tl = freq_tile(c->ntx, c->nrx);
-            const int64_t tp = (c->ntx + tl - 1) / tl * tl, rp = (c->nrx + tl - 1) / tl * tl;
-            if (2 * (int64_t)c->ntx * c->nrx >= tp * rp && freq_table_bytes(c, c->n_paths) <= FREQ_TABLE_MAX)
-                engine = RR_GEMM_EXACT;
-        }
+        // the exact model as products on the matrix cores: for a shared
+        // launch whose best product layout is modelled at least 1.5x the
+        // direct engine's throughput and whose leg tables fit the budget
+        if (model == RR_EXACT && !idx && c->mode == RR_TX_SHARED && c->n_paths > 0 &&
+            freq_pays(c->ntx, c->nrx, (int)K) && freq_table_bytes(c, c->n_paths) <= FREQ_TABLE_MAX)
+            engine = RR_GEMM_EXACT;
     }
     if (engine != RR_DIRECT_FP32 && engine != RR_GEMM_BF16X3 && engine != RR_GEMM_EXACT)
         return fail(RR_EINVAL, "unknown engine");
@@ -1794,17 +1785,17 @@ void batch_plan(BatchScene &x)
         eng = x.tuned_engine;
         tile = x.tuned_tile;
     }
-    if (tile <= 0) tile = freq_tile(x.ntx, x.nrx);
+    const int K = x.chirp.n_samples;
+    if (tile <= 0) tile = freq_tile(x.ntx, x.nrx, K);
     if (eng == RR_ENGINE_AUTO) {
         // untuned: the single-scene rule (a shared launch whose product
-        // tiles are at least half filled), within the table budget
-        const int64_t tl = tile;
-        const int64_t tp = (x.ntx + tl - 1) / tl * tl, rp = (x.nrx + tl - 1) / tl * tl;
-        eng = x.mode == RR_TX_SHARED && 2 * (int64_t)x.ntx * x.nrx >= tp * rp &&
+        // layout pays), within the table budget
+        eng = x.mode == RR_TX_SHARED && freq_pays(x.ntx, x.nrx, K) &&
                       batch_freq_bytes(x, x.fq_cap) <= BATCH_FREQ_TABLE_MAX
                   ? RR_GEMM_EXACT
                   : RR_DIRECT_FP32;
     }
+    if (tile == 1 && K > 1024) tile = freq_tile(x.ntx, x.nrx, K);   // no sample split that long
     x.use_freq = eng == RR_GEMM_EXACT;
     x.tile = tile;
 }
@@ -1894,15 +1885,8 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0, int only_sce
             int64_t P = x.fq_cap;
             if (p_limit > 0) P = std::min<int64_t>(P, std::max<int64_t>((p_limit + ks - 1) / ks * ks, ks));
             x.fq_ppad = P;
-            const int M = x.chirp.n_chirps, K = x.chirp.n_samples, tl = x.tile;
-            const int64_t kg = (K + freq_k_group() - 1) / freq_k_group();
-            const int64_t tiles = (int64_t)M * kg * ((x.ntx + tl - 1) / tl) * ((x.nrx + tl - 1) / tl);
-            int64_t n_split = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
-            n_split = std::min<int64_t>(n_split, std::max<int64_t>(1, P / (16 * ks)));
-            int64_t split_len = (P + n_split - 1) / n_split;
-            split_len = (split_len + ks - 1) / ks * ks;
-            x.fq_split = (int)((P + split_len - 1) / split_len);
-            x.fq_split_len = split_len;
+            const int M = x.chirp.n_chirps, K = x.chirp.n_samples;
+            freq_splits(x.tile, x.ntx, x.nrx, M, K, P, x.fq_split, x.fq_split_len);
             pm = std::max(pm, (size_t)M * P * 64);
             xt = std::max(xt, (size_t)M * x.ntx * P * 8);
             yt = std::max(yt, (size_t)M * x.nrx * P * 8);
@@ -2348,9 +2332,10 @@ int rr_batch_tune(rr_batch *b, void *const *cubes)
         float best_ms = t_direct;
         if (x.mode == RR_TX_SHARED &&
             batch_freq_bytes(x, std::max(x.fq_cap, x.n_last)) <= BATCH_FREQ_TABLE_MAX) {
-            const double least = freq_tile_cost(x.ntx, x.nrx, freq_tile(x.ntx, x.nrx));
-            for (int tile : {16, 32, 48, 64, 96}) {
-                if (freq_tile_cost(x.ntx, x.nrx, tile) > 1.5 * least) continue;
+            const int K = x.chirp.n_samples;
+            const double least = freq_tile_cost(x.ntx, x.nrx, K, freq_tile(x.ntx, x.nrx, K));
+            for (int tile : {1, 16, 32, 48, 64, 96}) {
+                if (freq_tile_cost(x.ntx, x.nrx, K, tile) > 1.5 * least) continue;
                 x.try_engine = RR_GEMM_EXACT;
                 x.try_tile = tile;
                 float ms = 0.0f;
@@ -2376,9 +2361,11 @@ int rr_batch_set_engine(rr_batch *b, int32_t slot, int32_t engine, int32_t tile)
     if (slot < 0 || slot >= b->S) return fail(RR_EINVAL, "slot out of range");
     if (engine != RR_ENGINE_AUTO && engine != RR_DIRECT_FP32 && engine != RR_GEMM_EXACT)
         return fail(RR_EINVAL, "batched scenes use RR_ENGINE_AUTO, RR_DIRECT_FP32 or RR_GEMM_EXACT");
-    if (tile != 0 && (engine != RR_GEMM_EXACT ||
-                      (tile != 16 && tile != 32 && tile != 48 && tile != 64 && tile != 96)))
-        return fail(RR_EINVAL, "tile 16, 32, 48, 64 or 96 with RR_GEMM_EXACT, else 0");
+    if (tile != 0 && (engine != RR_GEMM_EXACT || (tile != 1 && tile != 16 && tile != 32 &&
+                                                  tile != 48 && tile != 64 && tile != 96)))
+        return fail(RR_EINVAL, "tile 1, 16, 32, 48, 64 or 96 with RR_GEMM_EXACT, else 0");
+    if (tile == 1 && b->sc[slot].set && b->sc[slot].chirp.n_samples > 1024)
+        return fail(RR_EINVAL, "the sample split takes at most 1024 samples");
     BatchScene &x = b->sc[slot];
     x.req_engine = engine;
     x.req_tile = tile;

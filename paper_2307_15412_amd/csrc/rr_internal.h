@@ -192,8 +192,15 @@ hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_
                             const double *tx, int T, const double *rx, int R, double f0c, double dfc,
                             double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
                             hipStream_t s);
-int freq_tile(int T, int R);          // exact-GEMM tile (16, 32, 48, 64 or 96) of least modelled cost
-double freq_tile_cost(int T, int R, int tile);   // modelled time of a tile (relative)
+// exact product engine layouts: Tx x Rx tile 16, 32, 48, 64 or 96, or 1 (one
+// channel per wavefront, samples split); the layout of least modelled time,
+// the modelled time (relative) of one, and the path splits of a launch
+int freq_tile(int T, int R, int K);
+double freq_tile_cost(int T, int R, int K, int tile);
+void freq_splits(int tile, int T, int R, int M, int K, int64_t Ppad, int &n_split, int64_t &split_len);
+// the exact model's AUTO rule: the best product layout is modelled at least
+// 1.5x the direct engine's throughput
+bool freq_pays(int T, int R, int K);
 // rng_lo / rng_hi (may be NULL): the path count read on the device, as for
 // launch_freq_prep; the splits then divide that count evenly
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,

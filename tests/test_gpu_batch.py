@@ -95,7 +95,8 @@ def _exact_workloads():
         (wl("street7x9", street, sg.array_sparse_grid(7, 9, 8), 128, 16, 100_000, 4), 32),
         (wl("tiny12", c1, sg.array_sparse_grid(12, 13, 10), 64, 8, 60_000, 6), 16),
         (wl("street42", street, sg.array_sparse_grid(42, 42, 12), 32, 4, 80_000, 7), 48),
-        (wl("perel", c1, sg.array_ula(6, 8, mode=sg.MODE_PER_TX), 128, 32, 60_000, 5), 0),
+        (wl("perel", c1, sg.array_ula(6, 8, mode=sg.MODE_PER_TX), 128, 128, 60_000, 5), 0),
+        (wl("street12x16", street, sg.array_sparse_grid(12, 16, 13), 512, 16, 100_000, 8), 1),
         (sg.Workload("points", sg.point_only([[8.0, 1.0, 0.5], [15.0, -2.0, 0.6]],
                                              vel=[[1.0, 0.0, 0.0], [-2.0, 0.5, 0.0]]),
                      sg.array_sparse_grid(5, 6, 9), sg.Chirp(n_samples=64, n_chirps=8),
@@ -105,12 +106,13 @@ def _exact_workloads():
 
 def test_batch_exact_engine(gpu, orc):
     """Every slot pinned to the product engine (tiles 16 / 32 / 48 / 64 / 96
-    forced, or the tile of least modelled cost): counts equal the
-    single-scene launch; a slot at the least cost tile equals the single-scene
-    product engine bit for bit (same tile, same path splits on both sides),
-    forced tiles agree with it to float rounding; sampled entries within 1e-4
-    of the FP64 oracle; replays, and a re-capture for new cube buffers,
-    reproduce the cubes bit for bit."""
+    or the per-channel sample split forced, or the layout of least modelled
+    time): counts equal the single-scene launch; a slot at the least cost
+    layout equals the single-scene product engine bit for bit (same layout,
+    same path splits on both sides), forced layouts agree with it within the
+    operands' rounding (2e-5); sampled entries within 1e-4 of the FP64
+    oracle; replays, and a re-capture for new cube buffers, reproduce the
+    cubes bit for bit."""
     import paper_2307_15412_amd as rr
     cases = _exact_workloads()
     B = rr.Batch(gpu, len(cases))
@@ -119,7 +121,7 @@ def test_batch_exact_engine(gpu, orc):
         B.set_engine(i, rr.GEMM_EXACT, tile)
     eng, tiles = B.plan()
     assert (eng == rr.GEMM_EXACT).all()
-    assert [int(t) for t in tiles[1:6]] == [64, 96, 32, 16, 48]
+    assert [int(t) for t in tiles[1:6]] == [64, 96, 32, 16, 48] and tiles[7] == 1
     cubes = B.alloc_cubes()
     counts = B.launch(cubes)
     for i, (w, tile) in enumerate(cases):
@@ -129,7 +131,10 @@ def test_batch_exact_engine(gpu, orc):
         if tile == 0:
             assert torch.equal(got, ref), (i, rel_err(got.cpu().numpy(), ref.cpu().numpy()))
         else:
-            assert rel_err(got.cpu().numpy(), ref.cpu().numpy()) < 2e-6, i
+            # another layout rounds other split-bf16 operands (each product
+            # term carries ~6e-6 relative rounding): agreement to 2e-5
+            d = rel_err(got.cpu().numpy(), ref.cpu().numpy())
+            assert d < 2e-5, (i, d)
         if n:
             assert _sampled_oracle_err(orc, w, got, 40 + i) < 1e-4, i
         else:
@@ -182,7 +187,7 @@ def test_batch_autotune(gpu):
     eng, pt = B.plan()
     for e, t, tl, w in zip(eng, pt, tiles, ws):
         if e == rr.GEMM_EXACT:
-            assert w.array.mode == sg.MODE_SHARED and t in (16, 32, 48, 64, 96)
+            assert w.array.mode == sg.MODE_SHARED and t in (1, 16, 32, 48, 64, 96)
         else:
             assert e == rr.DIRECT_FP32 and t == tl
     counts = B.launch(cubes)

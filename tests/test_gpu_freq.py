@@ -1,12 +1,15 @@
-"""Exact-model synthesis as one split-bf16 complex product per (chirp,
-sample) against the FP64 oracle.  ENGINE_AUTO sends the exact model here, so
-the engine is held to the exact model's FP32 bar (relative error <= 1e-4, the
-direct engine's), not the split-bf16 GEMM's 1e-3; it measures ~5e-7: full
-cubes at Tx / Rx counts around the 16- and 32-row blocks and the 16-, 32-,
-48-, 64- and 96-wide tiles, several chirps of a moving scene, the per-element launch (paths feed
-only their own Tx), path counts around the 16-path steps and the split
-boundaries, an empty path list; the hand set-up against the direct FP32 engine
-and sampled oracle entries; invalid requests refused."""
+"""Exact-model synthesis as split-bf16 complex products on the matrix cores
+(per (chirp, sample) over Tx x Rx tiles, or per (channel, chirp) over the
+samples split k = k1 S + k2) against the FP64 oracle.  ENGINE_AUTO sends the
+exact model here, so the engine is held to the exact model's FP32 bar
+(relative error <= 1e-4, the direct engine's), not the split-bf16 GEMM's
+1e-3; it measures ~5e-7: full cubes at Tx / Rx counts around the 16- and
+32-row blocks and the 16-, 32-, 48-, 64- and 96-wide tiles, the sample split
+at 1 to 1024 samples (ragged S), several chirps of a moving scene, the
+per-element launch (paths feed only their own Tx), path counts around the
+path steps and the split boundaries, an empty path list; the hand set-up
+against the direct FP32 engine and sampled oracle entries; invalid requests
+refused."""
 import math
 
 import numpy as np
@@ -35,7 +38,8 @@ def _exact(gpu):
                                            (97, 5, 12, 3), (1, 1, 40, 1), (5, 9, 13, 2),
                                            (2, 3, 3, 1), (55, 55, 16, 2), (100, 190, 8, 1),
                                            (190, 95, 8, 1), (15, 15, 24, 2), (42, 42, 8, 1),
-                                           (17, 50, 9, 1), (47, 40, 5, 2)])
+                                           (17, 50, 9, 1), (47, 40, 5, 2), (6, 7, 512, 1),
+                                           (4, 5, 1024, 1), (8, 9, 300, 2), (3, 4, 257, 1)])
 def test_tile_edges(gpu, orc, n_tx, n_rx, K, M):
     w = sg.workload_tiny(1)
     w.array = sg.array_sparse_grid(n_tx, n_rx, 3, grid=128, mode=sg.MODE_SHARED)
