@@ -450,6 +450,7 @@ void k_freq_gemm(FreqArgs A)
 template <bool PER_EL, int QB, int SB>
 __global__ __launch_bounds__(FQ_G * 64) void k_freq_ks(FreqArgs A)
 {
+    typedef f32x4 acc;
     const int lane = threadIdx.x & 63;
     const int64_t wv = (int64_t)blockIdx.x * FQ_G + (threadIdx.x >> 6);
     if (wv >= A.n_waves) return;
@@ -491,9 +492,10 @@ __global__ __launch_bounds__(FQ_G * 64) void k_freq_ks(FreqArgs A)
                 sr[i][j][e] = 0.0f;
                 si[i][j][e] = 0.0f;
             }
-    // a step's words, loaded a step ahead
-    u32x4 X[4], Y[4], AM[2], SR[2];
-#define KS_LOAD(st_)                                                                              \
+    // a step's words, loaded a step ahead into the other of two register
+    // sets (the loop is unrolled by two, so no copies between the sets)
+    u32x4 X0[4], Y0[4], AM0[2], SR0[2], X1[4], Y1[4], AM1[2], SR1[2];
+#define KS_LOAD(st_, X, Y, AM, SR)                                                                \
     do {                                                                                          \
         const int64_t o_ = (st_) * 16;                                                            \
         _Pragma("unroll") for (int q_ = 0; q_ < 4; q_++) {                                        \
@@ -507,62 +509,66 @@ __global__ __launch_bounds__(FQ_G * 64) void k_freq_ks(FreqArgs A)
             SR[1] = spn[(st_) * 8 + 1];                                                           \
         }                                                                                         \
     } while (0)
-    if (nsteps > 0) KS_LOAD(0);
-    for (int64_t st = 0; st < nsteps; st++) {
-        Raw ru, rv;   // (beta, gamma) of U, (0, gamma) of V
-        float a[8];
-        {
-            unsigned *wu = reinterpret_cast<unsigned *>(ru.w), *wv2 = reinterpret_cast<unsigned *>(rv.w);
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                wu[4 * q] = X[q].x + Y[q].x;
-                wu[4 * q + 1] = X[q].y + Y[q].y;
-                wu[4 * q + 2] = X[q].z + Y[q].z;
-                wu[4 * q + 3] = X[q].w + Y[q].w;
-            }
-#pragma unroll
-            for (int e = 0; e < 8; e++) {
-                wv2[2 * e] = 0u;
-                wv2[2 * e + 1] = wu[2 * e + 1];
-            }
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                a[e] = __uint_as_float(AM[0][e]);
-                a[4 + e] = __uint_as_float(AM[1][e]);
-                if (PER_EL) {
-                    // a path of the per-element launch feeds its own Tx only
-                    const int s0 = (int)SR[0][e], s1 = (int)SR[1][e];
-                    if (s0 >= 0 && s0 != t) a[e] = 0.0f;
-                    if (s1 >= 0 && s1 != t) a[4 + e] = 0.0f;
-                }
-            }
-        }
-        if (st + 1 < nsteps) KS_LOAD(st + 1);
-        Frag v[SB];
-#pragma unroll
-        for (int j = 0; j < SB; j++) v[j] = leg_frag(rv, k2[j], nullptr);
-#pragma unroll
-        for (int i = 0; i < QB; i++) {
-            const Frag x = leg_frag(ru, kq[i], a);
-            const uint4 nih = neg(x.ih), nil = neg(x.il);
-#pragma unroll
-            for (int j = 0; j < SB; j++) {
-                sr[i][j] = Mfma<16>::mma(x.rh, v[j].rh, sr[i][j]);
-                si[i][j] = Mfma<16>::mma(x.rh, v[j].ih, si[i][j]);
-                sr[i][j] = Mfma<16>::mma(x.rh, v[j].rl, sr[i][j]);
-                si[i][j] = Mfma<16>::mma(x.rh, v[j].il, si[i][j]);
-                sr[i][j] = Mfma<16>::mma(x.rl, v[j].rh, sr[i][j]);
-                si[i][j] = Mfma<16>::mma(x.rl, v[j].ih, si[i][j]);
-                sr[i][j] = Mfma<16>::mma(nih, v[j].ih, sr[i][j]);
-                si[i][j] = Mfma<16>::mma(x.ih, v[j].rh, si[i][j]);
-                sr[i][j] = Mfma<16>::mma(nih, v[j].il, sr[i][j]);
-                si[i][j] = Mfma<16>::mma(x.ih, v[j].rl, si[i][j]);
-                sr[i][j] = Mfma<16>::mma(nil, v[j].ih, sr[i][j]);
-                si[i][j] = Mfma<16>::mma(x.il, v[j].rh, si[i][j]);
-            }
-        }
+    // one step: U (beta, gamma) and V (0, gamma) words of the channel, the
+    // amplitudes (in a per-element launch a path feeds its own Tx only), the
+    // fragments and the products
+#define KS_STEP(X, Y, AM, SR)                                                                     \
+    do {                                                                                          \
+        Raw ru_, rv_;                                                                             \
+        float a_[8];                                                                              \
+        unsigned *wu_ = reinterpret_cast<unsigned *>(ru_.w);                                      \
+        unsigned *wv_ = reinterpret_cast<unsigned *>(rv_.w);                                      \
+        _Pragma("unroll") for (int q_ = 0; q_ < 4; q_++) {                                        \
+            wu_[4 * q_] = X[q_].x + Y[q_].x;                                                      \
+            wu_[4 * q_ + 1] = X[q_].y + Y[q_].y;                                                  \
+            wu_[4 * q_ + 2] = X[q_].z + Y[q_].z;                                                  \
+            wu_[4 * q_ + 3] = X[q_].w + Y[q_].w;                                                  \
+        }                                                                                         \
+        _Pragma("unroll") for (int e_ = 0; e_ < 8; e_++) {                                        \
+            wv_[2 * e_] = 0u;                                                                     \
+            wv_[2 * e_ + 1] = wu_[2 * e_ + 1];                                                    \
+        }                                                                                         \
+        _Pragma("unroll") for (int e_ = 0; e_ < 4; e_++) {                                        \
+            a_[e_] = __uint_as_float(AM[0][e_]);                                                  \
+            a_[4 + e_] = __uint_as_float(AM[1][e_]);                                              \
+            if (PER_EL) {                                                                         \
+                const int s0_ = (int)SR[0][e_], s1_ = (int)SR[1][e_];                             \
+                if (s0_ >= 0 && s0_ != t) a_[e_] = 0.0f;                                          \
+                if (s1_ >= 0 && s1_ != t) a_[4 + e_] = 0.0f;                                      \
+            }                                                                                     \
+        }                                                                                         \
+        Frag v_[SB];                                                                              \
+        _Pragma("unroll") for (int j_ = 0; j_ < SB; j_++) v_[j_] = leg_frag(rv_, k2[j_], nullptr); \
+        _Pragma("unroll") for (int i_ = 0; i_ < QB; i_++) {                                       \
+            const Frag x_ = leg_frag(ru_, kq[i_], a_);                                            \
+            const uint4 nih_ = neg(x_.ih), nil_ = neg(x_.il);                                     \
+            _Pragma("unroll") for (int j_ = 0; j_ < SB; j_++) {                                   \
+                acc &R_ = sr[i_][j_], &I_ = si[i_][j_];                                           \
+                R_ = Mfma<16>::mma(x_.rh, v_[j_].rh, R_);                                         \
+                I_ = Mfma<16>::mma(x_.rh, v_[j_].ih, I_);                                         \
+                R_ = Mfma<16>::mma(x_.rh, v_[j_].rl, R_);                                         \
+                I_ = Mfma<16>::mma(x_.rh, v_[j_].il, I_);                                         \
+                R_ = Mfma<16>::mma(x_.rl, v_[j_].rh, R_);                                         \
+                I_ = Mfma<16>::mma(x_.rl, v_[j_].ih, I_);                                         \
+                R_ = Mfma<16>::mma(nih_, v_[j_].ih, R_);                                          \
+                I_ = Mfma<16>::mma(x_.ih, v_[j_].rh, I_);                                         \
+                R_ = Mfma<16>::mma(nih_, v_[j_].il, R_);                                          \
+                I_ = Mfma<16>::mma(x_.ih, v_[j_].rl, I_);                                         \
+                R_ = Mfma<16>::mma(nil_, v_[j_].ih, R_);                                          \
+                I_ = Mfma<16>::mma(x_.il, v_[j_].rh, I_);                                         \
+            }                                                                                     \
+        }                                                                                         \
+    } while (0)
+    if (nsteps > 0) KS_LOAD(0, X0, Y0, AM0, SR0);
+    for (int64_t st = 0; st < nsteps; st += 2) {
+        if (st + 1 < nsteps) KS_LOAD(st + 1, X1, Y1, AM1, SR1);
+        KS_STEP(X0, Y0, AM0, SR0);
+        if (st + 1 >= nsteps) break;
+        if (st + 2 < nsteps) KS_LOAD(st + 2, X0, Y0, AM0, SR0);
+        KS_STEP(X1, Y1, AM1, SR1);
     }
 #undef KS_LOAD
+#undef KS_STEP
     // D layout: register e of lane l is row 4 (l / 16) + e (k1), column
     // l % 16 (k2) of the block
 #pragma unroll
