@@ -544,7 +544,8 @@ def street_trace(ctx, scene, args, reps=None):
     (tracing kernel, scan, scatter), and the tracing kernel's memory roofline
     from the work the counting variant of the kernel reports: BVH nodes
     (64 B) + leaf triangle records (48 B) fetched + one count byte per ray +
-    one appended path record per path."""
+    one appended path record per path.  Then the configuration's exact-model
+    cube from those paths, with AUTO's engine and with the direct engine."""
     import torch
     import scenegen as sg
     wc = sg.workload_street(0) if scene is None else sg.Workload(
@@ -580,11 +581,29 @@ def street_trace(ctx, scene, args, reps=None):
             "algorithmic_bytes": alg,
             "note": "the 30 MB BVH of nodes and leaf triangles stays in L2/MALL, so algorithmic "
                     "bytes (every node and triangle fetch counted) can exceed what HBM delivers"}
+    # the configuration's cube (exact model, FP32 bar): AUTO's engine (the
+    # product engine's per-element sample split) and the direct engine; a
+    # path of the per-element launch feeds its own transmitter's 16 channels
+    import paper_2307_15412_amd as rr
+    n = ctx.trace_workload(wc, record_hits=False)
+    cube = torch.empty((a.n_ch, ch.n_chirps, ch.n_samples), dtype=torch.complex64, device="cuda:0")
+    syn = {}
+    for name, eng in (("auto", rr.ENGINE_AUTO), ("direct", rr.DIRECT_FP32)):
+        ts = []
+        for _ in range(3):
+            ctx.synthesize(model=rr.EXACT, engine=eng, out=cube)
+            ts.append(ctx.kernel_ms(1))
+        syn[name] = float(np.median(ts))
+    ps = float(n) * a.rx.shape[0] * ch.n_chirps * ch.n_samples
     return {"workload": "street: 5.1e5 tris, 12 Tx x 16 Rx per-element launch, 1e7 rays, "
                         "<=3 bounces, no path cap",
             "rays": tp.n_rays, "paths": n, "trace_stage_ms": st, "trace_kernel_ms": kt,
             "wall_ms": wall * 1e3, "mrays_per_s": tp.n_rays / (st * 1e-3) / 1e6,
-            "segments_per_s": work["queries"] / (st * 1e-3), "work": work, "roofline": roof}
+            "segments_per_s": work["queries"] / (st * 1e-3), "work": work, "roofline": roof,
+            "synth": {"cube": "192 ch x 128 chirps x 256 samples, exact model",
+                      "path_samples": ps, "auto_ms": syn["auto"], "direct_ms": syn["direct"],
+                      "gpath_samples_per_s_auto": ps / (syn["auto"] * 1e-3) / 1e9,
+                      "gpath_samples_per_s_direct": ps / (syn["direct"] * 1e-3) / 1e9}}
 
 
 def run_street_trace(args):

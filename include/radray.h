@@ -310,10 +310,14 @@ int rr_set_paths(rr_ctx *ctx, const rr_paths *src, int64_t n);
  *          samples); the layout of least modelled time), or
  *          RR_ENGINE_AUTO: the separable model takes RR_GEMM_BF16X3 when the
  *          64-sample tiling pads a chirp by at most a quarter; the exact model
- *          takes RR_GEMM_EXACT for a shared launch whose best layout is
- *          modelled at 1.5x the direct engine's throughput or more and whose
- *          leg tables fit its budget; everything else, and sampled entries,
- *          the direct engine.  AUTO never changes the model, and each engine
+ *          takes RR_GEMM_EXACT when its best layout is modelled at 1.5x
+ *          the direct engine's throughput or more (in a per-element launch
+ *          a path feeds only its own transmitter's channels: the Tx x Rx
+ *          tiles are modelled at the work they waste, the sample split
+ *          reads each transmitter's paths only) and its leg tables (8 bytes
+ *          per chirp, path and element; per-element sample split: the
+ *          path's own transmitter and every receiver) fit 16 GiB;
+ *          everything else, and sampled entries, the direct engine.  AUTO never changes the model, and each engine
  *          it picks meets that model's error bar.
  *   cube_dev complex64 [n_ch][n_chirps][n_samples], cube_elems = its complex
  *          element count; the cube is overwritten.

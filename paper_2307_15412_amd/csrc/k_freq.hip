@@ -44,9 +44,11 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double frac(double x) { return x - floor(x); }
 
+// frac(x) as 32-bit fixed-point turns, rounded to nearest (2^32 wraps to 0)
 __device__ __forceinline__ unsigned turns_u32(double x)
 {
-    return (unsigned)(unsigned long long)llrint(frac(x) * 4294967296.0);
+    const double r = rint(frac(x) * 4294967296.0);
+    return r >= 4294967296.0 ? 0u : (unsigned)r;
 }
 
 __device__ __forceinline__ double dist3(const double *a, const double *b)
@@ -82,73 +84,74 @@ __device__ __forceinline__ void path_range(const PathRange &R, int64_t Ppad, con
     }
 }
 
-// Per (chirp, path): first and last hit point at chirp time and the length
-// between them.  Layout [M][Ppad] of 8 doubles: p1.xyz, pK.xyz, inner, amp.
-__global__ void k_freq_paths(PathRange PR, int64_t Ppad, int M, double t_rep, double *pm)
+// Leg tables, one thread per path over a share of the chirps: the first and
+// last hit point at chirp time and the length between them, then per element
+// the leg in fixed-point turns (beta, gamma): xt[m][t][p] of
+// dX = |p1 - tx_t| + inner and yt[m][r][p] of dY = |rx_r - pK|; and per path
+// the amplitude (0 beyond the path count) and source.  OWN_TX (per-element
+// launch, sample split): the channels of transmitter t read only the paths of
+// t's group, so only each path's own transmitter word is kept, xt[m][0][p].
+template <bool OWN_TX>
+__global__ __launch_bounds__(256) void k_freq_legs(PathRange PR, int64_t Ppad, int M, double t_rep,
+                                                   const double *tx, int T, const double *rx,
+                                                   int R, double f0c, double dfc, uint2 *xt,
+                                                   uint2 *yt, float *amp, int32_t *src)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const SynPath *paths;
     int64_t n, used;
     path_range(PR, Ppad, paths, n, used);
-    if (g >= (int64_t)M * Ppad) return;
-    const int m = (int)(g / Ppad);
-    const int64_t p = g - (int64_t)m * Ppad;
     if (p >= used) return;
-    double *o = pm + 8 * g;
+    const int XR = OWN_TX ? 1 : T;
     if (p >= n) {
-        for (int q = 0; q < 8; q++) o[q] = 0.0;
+        for (int m = blockIdx.y; m < M; m += gridDim.y) {
+            for (int i = 0; i < XR; i++) xt[((int64_t)m * XR + i) * Ppad + p] = make_uint2(0u, 0u);
+            for (int i = 0; i < R; i++) yt[((int64_t)m * R + i) * Ppad + p] = make_uint2(0u, 0u);
+        }
+        if (blockIdx.y == 0) {
+            amp[p] = 0.0f;
+            src[p] = -1;
+        }
         return;
     }
     const SynPath &P = paths[p];
-    const double tau = (double)m * t_rep;
-    double q1[3], qk[3], inner = 0.0;
-    for (int a = 0; a < 3; a++) q1[a] = P.P[0][a] + P.V[0][a] * tau;
-    for (int a = 0; a < 3; a++) qk[a] = q1[a];
-    for (int j = 1; j < P.K; j++) {
-        double q[3];
-        for (int a = 0; a < 3; a++) q[a] = P.P[j][a] + P.V[j][a] * tau;
-        inner += dist3(q, qk);
-        for (int a = 0; a < 3; a++) qk[a] = q[a];
+    const int K = P.K;
+    const int t_own = OWN_TX ? min(max(P.src, 0), T - 1) : 0;
+    double h[RR_KMAX][3], v[RR_KMAX][3];   // the path's points, held over the chirps
+#pragma unroll
+    for (int j = 0; j < RR_KMAX; j++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            h[j][a] = j < K ? P.P[j][a] : 0.0;
+            v[j][a] = j < K ? P.V[j][a] : 0.0;
+        }
+    for (int m = blockIdx.y; m < M; m += gridDim.y) {
+        const double tau = (double)m * t_rep;
+        double q1[3], qk[3], inner = 0.0;
+        for (int a = 0; a < 3; a++) q1[a] = h[0][a] + v[0][a] * tau;
+        for (int a = 0; a < 3; a++) qk[a] = q1[a];
+#pragma unroll
+        for (int j = 1; j < RR_KMAX; j++) {
+            if (j >= K) break;
+            double q[3];
+            for (int a = 0; a < 3; a++) q[a] = h[j][a] + v[j][a] * tau;
+            inner += dist3(q, qk);
+            for (int a = 0; a < 3; a++) qk[a] = q[a];
+        }
+        uint2 *xo = xt + (int64_t)m * XR * Ppad + p;
+        for (int i = 0; i < XR; i++) {
+            const double d = dist3(q1, tx + 3 * (OWN_TX ? t_own : i)) + inner;
+            xo[(int64_t)i * Ppad] = make_uint2(turns_u32(d * f0c), turns_u32(d * dfc));
+        }
+        uint2 *yo = yt + (int64_t)m * R * Ppad + p;
+        for (int i = 0; i < R; i++) {
+            const double d = dist3(rx + 3 * i, qk);
+            yo[(int64_t)i * Ppad] = make_uint2(turns_u32(d * f0c), turns_u32(d * dfc));
+        }
     }
-    for (int a = 0; a < 3; a++) {
-        o[a] = q1[a];
-        o[3 + a] = qk[a];
-    }
-    o[6] = inner;
-    o[7] = P.amp;
-}
-
-// Leg tables: xt[m][t][p] for dX = |p1 - tx_t| + inner and yt[m][r][p] for
-// dY = |rx_r - pK|, each (beta, gamma) in fixed-point turns; and per path the
-// amplitude (0 beyond the path count) and source.
-__global__ void k_freq_tables(const double *pm, PathRange PR, int64_t Ppad, int M, const double *tx,
-                              int T, const double *rx, int R, double f0c, double dfc, uint2 *xt,
-                              uint2 *yt, float *amp, int32_t *src)
-{
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const SynPath *paths;
-    int64_t n, used;
-    path_range(PR, Ppad, paths, n, used);
-    const int64_t per_m = (int64_t)(T + R) * Ppad;
-    if (g >= (int64_t)M * per_m) return;
-    const int m = (int)(g / per_m);
-    const int64_t rem = g - (int64_t)m * per_m;
-    const int i = (int)(rem / Ppad);
-    const int64_t p = rem - (int64_t)i * Ppad;
-    if (p >= used) return;
-    const double *o = pm + 8 * ((int64_t)m * Ppad + p);
-    uint2 v = make_uint2(0u, 0u);
-    if (p < n) {
-        const double d = i < T ? dist3(o, tx + 3 * i) + o[6] : dist3(rx + 3 * (i - T), o + 3);
-        v = make_uint2(turns_u32(d * f0c), turns_u32(d * dfc));
-    }
-    if (i < T)
-        xt[((int64_t)m * T + i) * Ppad + p] = v;
-    else
-        yt[((int64_t)m * R + (i - T)) * Ppad + p] = v;
-    if (m == 0 && i == 0) {
-        amp[p] = p < n ? (float)paths[p].amp : 0.0f;
-        src[p] = p < n ? paths[p].src : -1;
+    if (blockIdx.y == 0) {
+        amp[p] = (float)P.amp;
+        src[p] = P.src;
     }
 }
 
@@ -253,6 +256,10 @@ struct FreqArgs {
     // sample split (one channel per wavefront): k = k1 S + k2
     int S;
     int64_t n_waves;
+    // per-element launch, sample split: groups[t] .. groups[t + 1] are the
+    // paths of transmitter t (path indices of the list the tables were built
+    // from, plus groups[0]); a channel's wavefronts read only those
+    const int64_t *groups;
 };
 
 // One workgroup: a BS NB x BS NB (Tx x Rx) tile of FQ_G consecutive samples
@@ -468,12 +475,26 @@ __global__ __launch_bounds__(FQ_G * 64) void k_freq_ks(FreqArgs A)
         used = (n + FQ_PAD - 1) / FQ_PAD * FQ_PAD;
         split_len = ((used + A.n_split - 1) / A.n_split + FQ_PAD - 1) / FQ_PAD * FQ_PAD;
     }
-    const int64_t pstart = (int64_t)s * split_len;
-    const int64_t nsteps = max(min(used, pstart + split_len) - pstart, (int64_t)0) / 32;
+    // the paths this channel reads: all, or (per-element) its transmitter's
+    // group widened to whole 32-path steps (the paths of neighbouring groups
+    // in the edge steps are masked by their source below)
+    int64_t plo = 0, phi = used;
+    if (PER_EL && A.groups) {
+        const int64_t g0 = A.groups[0];
+        plo = min(max(A.groups[t] - g0, (int64_t)0), used) / 32 * 32;
+        phi = min((max(A.groups[t + 1] - g0, (int64_t)0) + 31) / 32 * 32, used);
+        phi = max(phi, plo);
+        split_len = ((phi - plo + A.n_split - 1) / A.n_split + 31) / 32 * 32;
+    }
+    const int64_t pstart = plo + (int64_t)s * split_len;
+    const int64_t nsteps = max(min(phi, pstart + split_len) - pstart, (int64_t)0) / 32;
     const int grp = lane >> 4, lrow = lane & 15;
     // the lane's 8 paths of a step: pstart + 32 step + 8 grp + (0 .. 7)
     const int64_t p0 = nsteps > 0 ? pstart + 8 * grp : 0;
-    const u32x4 *xp = reinterpret_cast<const u32x4 *>(A.xt + ((int64_t)m * A.T + t) * A.Ppad + p0);
+    // X words: per-element launches with groups keep one row per chirp (each
+    // path's own transmitter), otherwise one per (chirp, transmitter)
+    const int64_t xrow = PER_EL && A.groups ? (int64_t)m : (int64_t)m * A.T + t;
+    const u32x4 *xp = reinterpret_cast<const u32x4 *>(A.xt + xrow * A.Ppad + p0);
     const u32x4 *yp = reinterpret_cast<const u32x4 *>(A.yt + ((int64_t)m * A.R + r) * A.Ppad + p0);
     const u32x4 *apn = reinterpret_cast<const u32x4 *>(A.amp + p0);
     const u32x4 *spn = reinterpret_cast<const u32x4 *>(A.src + p0);
@@ -618,18 +639,23 @@ int freq_k_group() { return FQ_G; }
 
 hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_lo,
                             const int64_t *rng_hi, int64_t Ppad, int M, double t_rep,
-                            const double *tx, int T, const double *rx, int R, double f0c, double dfc,
-                            double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
+                            const double *tx, int T, bool own_tx, const double *rx, int R,
+                            double f0c, double dfc, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
                             hipStream_t s)
 {
-    const int64_t n1 = (int64_t)M * Ppad;
-    if (n1 <= 0) return hipSuccess;
+    if (M <= 0 || Ppad <= 0) return hipSuccess;
     PathRange PR{paths, n, rng_lo, rng_hi};
-    hipLaunchKernelGGL(k_freq_paths, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, PR, Ppad,
-                       M, t_rep, pm);
-    const int64_t n2 = (int64_t)M * (T + R) * Ppad;
-    hipLaunchKernelGGL(k_freq_tables, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, pm, PR,
-                       Ppad, M, tx, T, rx, R, f0c, dfc, xt, yt, amp, src);
+    // one thread per path; the chirps shared over enough workgroups to fill
+    // the chip (each thread keeps its path's points over its chirps)
+    const int64_t bx = (Ppad + 255) / 256;
+    const int by = (int)std::min<int64_t>(M, std::max<int64_t>(1, (4096 + bx - 1) / bx));
+    const dim3 g((unsigned)bx, (unsigned)by);
+    if (own_tx)
+        hipLaunchKernelGGL(k_freq_legs<true>, g, dim3(256), 0, s, PR, Ppad, M, t_rep, tx, T, rx, R,
+                           f0c, dfc, xt, yt, amp, src);
+    else
+        hipLaunchKernelGGL(k_freq_legs<false>, g, dim3(256), 0, s, PR, Ppad, M, t_rep, tx, T, rx, R,
+                           f0c, dfc, xt, yt, amp, src);
     return hipGetLastError();
 }
 
@@ -662,16 +688,27 @@ static void ks_shape(int K, int &qb, int &sb, int &S)
     }
 }
 
-int freq_tile(int T, int R, int K);
+int freq_tile(int T, int R, int K, bool per_element);
 
+// measured at full blocks (256, 512 and 1 024 samples); fewer samples leave
+// the rest of the blocks' products unused
 static double ks_rate(int K)
 {
-    return K <= 128 ? 9.0 : K <= 256 ? 17.0 : K <= 512 ? 23.0 : 25.0;
+    int qb, sb, S;
+    ks_shape(K, qb, sb, S);
+    const double full = qb * sb == 1 ? 17.0 : qb * sb == 2 ? 23.0 : 25.0;
+    return full * K / (256.0 * qb * sb);
 }
 
-double freq_tile_cost(int T, int R, int K, int tile)
+// per path of the launch; in a per-element launch a Tx x Rx tile multiplies
+// every path into all T rows (masked), the sample split only into its own
+// transmitter's channels
+double freq_tile_cost(int T, int R, int K, int tile, bool per_element)
 {
-    if (tile == 1) return K <= FQ_KS_KMAX ? (double)T * R * K / ks_rate(K) : 1e300;
+    if (tile == 1) {
+        if (K > FQ_KS_KMAX) return 1e300;
+        return (double)T * R * K / ks_rate(K) / (per_element ? T : 1);
+    }
     for (int i = 0; i < 5; i++)
         if (FQ_TILES[i] == tile) {
             const double tp = (double)((T + tile - 1) / tile * tile), rp = (double)((R + tile - 1) / tile * tile);
@@ -684,18 +721,31 @@ double freq_tile_cost(int T, int R, int K, int tile)
 // batched streets); the product engine pays at 1.5x that
 static const double DIRECT_RATE = 9.0;
 
-bool freq_pays(int T, int R, int K)
+bool freq_pays(int T, int R, int K, bool per_element)
 {
-    const int tile = freq_tile(T, R, K);
-    return (double)T * R * K / freq_tile_cost(T, R, K, tile) >= 1.5 * DIRECT_RATE;
+    const int tile = freq_tile(T, R, K, per_element);
+    // useful complex multiply-adds per path: T R K (shared) or R K (per element)
+    const double work = (double)T * R * K / (per_element ? T : 1);
+    return work / freq_tile_cost(T, R, K, tile, per_element) >= 1.5 * DIRECT_RATE;
 }
 
-int freq_tile(int T, int R, int K)
+int freq_tile(int T, int R, int K, bool per_element)
 {
     int best = 96;
     for (int tile : {1, 16, 32, 48, 64, 96})
-        if (freq_tile_cost(T, R, K, tile) < freq_tile_cost(T, R, K, best)) best = tile;
+        if (freq_tile_cost(T, R, K, tile, per_element) < freq_tile_cost(T, R, K, best, per_element))
+            best = tile;
     return best;
+}
+
+bool freq_own_tx(int tile, bool per_element, bool has_groups)
+{
+    return tile == 1 && per_element && has_groups;
+}
+
+int64_t freq_table_entries(int T, int R, int M, int64_t Ppad, bool own_tx)
+{
+    return (int64_t)M * ((own_tx ? 1 : T) + R) * Ppad;
 }
 
 void freq_splits(int tile, int T, int R, int M, int K, int64_t Ppad, int &n_split, int64_t &split_len)
@@ -720,7 +770,7 @@ void freq_splits(int tile, int T, int R, int M, int K, int64_t Ppad, int &n_spli
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
                             int per_element, int tile, const int64_t *rng_lo, const int64_t *rng_hi,
-                            float2 *partial, float2 *cube, hipStream_t s)
+                            const int64_t *groups, float2 *partial, float2 *cube, hipStream_t s)
 {
     if ((int64_t)n_split * split_len < Ppad || split_len % FQ_PAD || Ppad % FQ_PAD || Ppad <= 0)
         return hipErrorInvalidValue;
@@ -746,6 +796,7 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     A.out = n_split > 1 ? partial : cube;
     A.rng_lo = rng_lo;
     A.rng_hi = rng_hi;
+    A.groups = tile == 1 && per_element ? groups : nullptr;
     int qb = 1, sb = 1;
     ks_shape(K, qb, sb, A.S);
     A.n_waves = (int64_t)n_split * M * T * R;

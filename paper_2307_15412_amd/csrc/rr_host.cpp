@@ -196,7 +196,7 @@ struct rr_ctx {
     std::vector<float> h_verts;
     // refit of the BVH to moved vertices (rr_scene_update_vertices)
     DevBuf tris_dev, verts_dev, refit_order, ubox;
-    DevBuf fq_pm, fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact-model GEMM engine
+    DevBuf fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact-model GEMM engine
     DevBuf bp_sf;              // cube slices in fragment layout (MFMA back-projection)
     std::vector<double> h_tx, h_rx;
     std::vector<int64_t> refit_levels;   // starts of the levels in refit_order, deepest first
@@ -364,7 +364,7 @@ void rr_destroy(rr_ctx *c)
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss, &c->mlp_part,
                       &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->trace_stats, &c->tri_alpha, &c->pieces_v, &c->pieces_p, &c->tris_dev, &c->verts_dev,
                       &c->refit_order, &c->ubox,
-                      &c->fq_pm, &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part, &c->bp_sf};
+                      &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part, &c->bp_sf};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -1032,13 +1032,15 @@ static int rr_synth_gemm(rr_ctx *c, const SynthArgs &A)
 
 // Exact model as one complex product per (chirp, sample): leg tables per
 // (chirp, element, path), then the split-bf16 MFMA kernel over path splits.
-static const int64_t FREQ_TABLE_MAX = (int64_t)4 << 30;   // AUTO's table budget (bytes)
+static const int64_t FREQ_TABLE_MAX = (int64_t)16 << 30;   // AUTO's table budget (bytes)
 
 static int64_t freq_table_bytes(const rr_ctx *c, int64_t n)
 {
     const int64_t ks = freq_k_step();
     const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
-    return (int64_t)c->chirp.n_chirps * (c->ntx + c->nrx) * Ppad * 8;
+    const bool per_el = c->mode != RR_TX_SHARED;
+    const bool own = freq_own_tx(freq_tile(c->ntx, c->nrx, c->chirp.n_samples, per_el), per_el, true);
+    return 8 * freq_table_entries(c->ntx, c->nrx, c->chirp.n_chirps, Ppad, own);
 }
 
 static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
@@ -1047,27 +1049,28 @@ static int rr_synth_freq(rr_ctx *c, const SynthArgs &A)
     const int64_t ks = freq_k_step();
     const int64_t Ppad = std::max<int64_t>((n + ks - 1) / ks * ks, ks);
     const int T = c->ntx, R = c->nrx, M = A.M, K = A.K;
-    const int tile = freq_tile(T, R, K);
+    const bool per_el = c->mode != RR_TX_SHARED;
+    const int tile = freq_tile(T, R, K, per_el);
     int n_split = 1;
     int64_t split_len = Ppad;
     freq_splits(tile, T, R, M, K, Ppad, n_split, split_len);
+    const bool own = freq_own_tx(tile, per_el, A.ranges != nullptr);
     int rc;
-    if ((rc = c->fq_pm.ensure((size_t)M * Ppad * 64))) return rc;
-    if ((rc = c->fq_xt.ensure((size_t)M * T * Ppad * 8))) return rc;
+    if ((rc = c->fq_xt.ensure((size_t)M * (own ? 1 : T) * Ppad * 8))) return rc;
     if ((rc = c->fq_yt.ensure((size_t)M * R * Ppad * 8))) return rc;
     if ((rc = c->fq_amp.ensure((size_t)Ppad * 4))) return rc;
     if ((rc = c->fq_src.ensure((size_t)Ppad * 4))) return rc;
     if (n_split > 1 && (rc = c->fq_part.ensure((size_t)n_split * M * K * T * R * 8))) return rc;
     HIPCHK(hipEventRecord(c->ev[2], c->stream));
-    HIPCHK(launch_freq_prep(A.paths, n, nullptr, nullptr, Ppad, M, A.t_rep, A.tx, T, A.rx, R,
-                            A.f0 * A.inv_c, A.bw / (double)K * A.inv_c, c->fq_pm.as<double>(),
-                            c->fq_xt.as<uint2>(),
+    HIPCHK(launch_freq_prep(A.paths, n, nullptr, nullptr, Ppad, M, A.t_rep, A.tx, T, own, A.rx, R,
+                            A.f0 * A.inv_c, A.bw / (double)K * A.inv_c, c->fq_xt.as<uint2>(),
                             c->fq_yt.as<uint2>(), c->fq_amp.as<float>(), c->fq_src.as<int32_t>(),
                             c->stream));
     HIPCHK(launch_freq_gemm(c->fq_xt.as<const uint2>(), c->fq_yt.as<const uint2>(),
                             c->fq_amp.as<const float>(), c->fq_src.as<const int32_t>(), T, R, M, K,
-                            Ppad, (int)n_split, split_len, c->mode != RR_TX_SHARED, tile, nullptr,
-                            nullptr, c->fq_part.as<float2>(), A.cube, c->stream));
+                            Ppad, (int)n_split, split_len, per_el, tile, nullptr, nullptr,
+                            per_el ? A.ranges : nullptr, c->fq_part.as<float2>(), A.cube,
+                            c->stream));
     return RR_OK;
 }
 
@@ -1086,11 +1089,12 @@ int rr_synthesize(rr_ctx *c, int32_t model, int32_t engine, void *cube, int64_t 
         const int64_t Kp = (K + CT - 1) / CT * CT;
         engine = (model == RR_SEPARABLE && !idx && 4 * Kp <= 5 * K) ? RR_GEMM_BF16X3
                                                                      : RR_DIRECT_FP32;
-        // the exact model as products on the matrix cores: for a shared
-        // launch whose best product layout is modelled at least 1.5x the
-        // direct engine's throughput and whose leg tables fit the budget
-        if (model == RR_EXACT && !idx && c->mode == RR_TX_SHARED && c->n_paths > 0 &&
-            freq_pays(c->ntx, c->nrx, (int)K) && freq_table_bytes(c, c->n_paths) <= FREQ_TABLE_MAX)
+        // the exact model as products on the matrix cores: where the best
+        // product layout is modelled at least 1.5x the direct engine's
+        // throughput and the leg tables fit the budget
+        if (model == RR_EXACT && !idx && c->n_paths > 0 &&
+            freq_pays(c->ntx, c->nrx, (int)K, c->mode != RR_TX_SHARED) &&
+            freq_table_bytes(c, c->n_paths) <= FREQ_TABLE_MAX)
             engine = RR_GEMM_EXACT;
     }
     if (engine != RR_DIRECT_FP32 && engine != RR_GEMM_BF16X3 && engine != RR_GEMM_EXACT)
@@ -1733,7 +1737,7 @@ struct rr_batch {
     DevBuf counts, offsets, bsums, total, counter, work;
     PathStore tmp, fin;
     DevBuf syn, alpha_tmp;
-    DevBuf fq_pm, fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact engine, shared by its scenes
+    DevBuf fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact engine, shared by its scenes
     int64_t cap = 0, V_total = 0, n_chunks = 0, n_items = 0, n_ranges = 0, nb = 0;
     std::vector<char> synth_on;           // scenes the synthesis stage computes
     std::vector<int64_t> range_base;
@@ -1756,10 +1760,12 @@ void batch_drop_graph(rr_batch *b)
     b->dirty = true;
 }
 
-// leg table bytes of the exact engine for a scene at a path capacity
-int64_t batch_freq_bytes(const BatchScene &x, int64_t cap)
+// leg table bytes of the exact engine for a scene at a path capacity and
+// product layout
+int64_t batch_freq_bytes(const BatchScene &x, int64_t cap, int tile)
 {
-    return (int64_t)x.chirp.n_chirps * cap * (8 * (x.ntx + x.nrx) + 64);
+    const bool own = freq_own_tx(tile, x.mode != RR_TX_SHARED, true);
+    return 8 * freq_table_entries(x.ntx, x.nrx, x.chirp.n_chirps, cap, own);
 }
 
 // the exact engine's table budget for AUTO in a batch (the tables are shared
@@ -1786,16 +1792,16 @@ void batch_plan(BatchScene &x)
         tile = x.tuned_tile;
     }
     const int K = x.chirp.n_samples;
-    if (tile <= 0) tile = freq_tile(x.ntx, x.nrx, K);
+    const bool per_el = x.mode != RR_TX_SHARED;
+    if (tile <= 0) tile = freq_tile(x.ntx, x.nrx, K, per_el);
     if (eng == RR_ENGINE_AUTO) {
-        // untuned: the single-scene rule (a shared launch whose product
-        // layout pays), within the table budget
-        eng = x.mode == RR_TX_SHARED && freq_pays(x.ntx, x.nrx, K) &&
-                      batch_freq_bytes(x, x.fq_cap) <= BATCH_FREQ_TABLE_MAX
+        // untuned: the single-scene rule (the product layout pays), within
+        // the table budget
+        eng = freq_pays(x.ntx, x.nrx, K, per_el) && batch_freq_bytes(x, x.fq_cap, tile) <= BATCH_FREQ_TABLE_MAX
                   ? RR_GEMM_EXACT
                   : RR_DIRECT_FP32;
     }
-    if (tile == 1 && K > 1024) tile = freq_tile(x.ntx, x.nrx, K);   // no sample split that long
+    if (tile == 1 && K > 1024) tile = freq_tile(x.ntx, x.nrx, K, per_el);   // no sample split that long
     x.use_freq = eng == RR_GEMM_EXACT;
     x.tile = tile;
 }
@@ -1878,7 +1884,7 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0, int only_sce
     // and path splits; one set of tables serves its scenes in turn
     {
         const int64_t ks = freq_k_step();
-        size_t pm = 0, xt = 0, yt = 0, pp = 0, part = 0;
+        size_t xt = 0, yt = 0, pp = 0, part = 0;
         for (int s = 0; s < S; s++) {
             BatchScene &x = b->sc[s];
             if (!x.use_freq || !b->synth_on[s]) continue;
@@ -1887,15 +1893,14 @@ int batch_prepare(rr_batch *b, int only_K = 0, int64_t p_limit = 0, int only_sce
             x.fq_ppad = P;
             const int M = x.chirp.n_chirps, K = x.chirp.n_samples;
             freq_splits(x.tile, x.ntx, x.nrx, M, K, P, x.fq_split, x.fq_split_len);
-            pm = std::max(pm, (size_t)M * P * 64);
-            xt = std::max(xt, (size_t)M * x.ntx * P * 8);
+            const bool own = freq_own_tx(x.tile, x.mode != RR_TX_SHARED, true);
+            xt = std::max(xt, (size_t)M * (own ? 1 : x.ntx) * P * 8);
             yt = std::max(yt, (size_t)M * x.nrx * P * 8);
             pp = std::max(pp, (size_t)P * 4);
             if (x.fq_split > 1)
                 part = std::max(part, (size_t)x.fq_split * M * K * x.ntx * x.nrx * 8);
         }
-        if (pm) {
-            if ((rc = b->fq_pm.ensure(pm))) return rc;
+        if (pp) {
             if ((rc = b->fq_xt.ensure(xt))) return rc;
             if ((rc = b->fq_yt.ensure(yt))) return rc;
             if ((rc = b->fq_amp.ensure(pp))) return rc;
@@ -2029,14 +2034,16 @@ int batch_enqueue_synth(rr_batch *b, bool timed)
         const int M = x.chirp.n_chirps, K = x.chirp.n_samples;
         const double inv_c = 1.0 / 299792458.0;
         HIPCHK(launch_freq_prep(b->syn.as<const SynPath>(), 0, lo, hi, x.fq_ppad, M, x.chirp.t_rep,
-                                x.tx.as<const double>(), x.ntx, x.rx.as<const double>(), x.nrx,
-                                x.chirp.f0 * inv_c, x.chirp.bandwidth / (double)K * inv_c,
-                                b->fq_pm.as<double>(), b->fq_xt.as<uint2>(), b->fq_yt.as<uint2>(),
+                                x.tx.as<const double>(), x.ntx,
+                                freq_own_tx(x.tile, x.mode != RR_TX_SHARED, true),
+                                x.rx.as<const double>(), x.nrx, x.chirp.f0 * inv_c,
+                                x.chirp.bandwidth / (double)K * inv_c, b->fq_xt.as<uint2>(),
+                                b->fq_yt.as<uint2>(),
                                 b->fq_amp.as<float>(), b->fq_src.as<int32_t>(), st));
         HIPCHK(launch_freq_gemm(b->fq_xt.as<const uint2>(), b->fq_yt.as<const uint2>(),
                                 b->fq_amp.as<const float>(), b->fq_src.as<const int32_t>(), x.ntx,
                                 x.nrx, M, K, x.fq_ppad, x.fq_split, x.fq_split_len,
-                                x.mode != RR_TX_SHARED, x.tile, lo, hi, b->fq_part.as<float2>(),
+                                x.mode != RR_TX_SHARED, x.tile, lo, hi, lo, b->fq_part.as<float2>(),
                                 static_cast<float2 *>(b->cubes[s]), st));
     }
     if (timed) HIPCHK(hipEventRecord(b->ev[3], st));
@@ -2318,10 +2325,10 @@ int rr_batch_tune(rr_batch *b, void *const *cubes)
             if (x.chirp.n_samples == K) x.kr = best;
     }
     // 2. per scene left to AUTO: the direct engine against the exact product
-    // engine at each tile whose modelled cost is within 1.5x of the least
-    // (shared launches; a per-element launch wastes the product on other Tx
-    // rows).  The product engine's scene runs as separate kernels: it has to
-    // win by a tenth and 20 us.
+    // engine at each layout whose modelled cost is within 1.5x of the least
+    // (in a per-element launch the Tx x Rx tiles waste the product on other
+    // transmitters' rows and model accordingly).  The product engine's scene
+    // runs as separate kernels: it has to win by a tenth and 20 us.
     for (int s = 0; s < b->S && !rc; s++) {
         BatchScene &x = b->sc[s];
         if (x.req_engine != RR_ENGINE_AUTO) continue;
@@ -2330,12 +2337,14 @@ int rr_batch_tune(rr_batch *b, void *const *cubes)
         if ((rc = time_synth(0, s, &t_direct))) break;
         int best_eng = RR_DIRECT_FP32, best_tile = 0;
         float best_ms = t_direct;
-        if (x.mode == RR_TX_SHARED &&
-            batch_freq_bytes(x, std::max(x.fq_cap, x.n_last)) <= BATCH_FREQ_TABLE_MAX) {
+        {
             const int K = x.chirp.n_samples;
-            const double least = freq_tile_cost(x.ntx, x.nrx, K, freq_tile(x.ntx, x.nrx, K));
+            const bool pe = x.mode != RR_TX_SHARED;
+            const double least = freq_tile_cost(x.ntx, x.nrx, K, freq_tile(x.ntx, x.nrx, K, pe), pe);
             for (int tile : {1, 16, 32, 48, 64, 96}) {
-                if (freq_tile_cost(x.ntx, x.nrx, K, tile) > 1.5 * least) continue;
+                if (freq_tile_cost(x.ntx, x.nrx, K, tile, pe) > 1.5 * least) continue;
+                if (batch_freq_bytes(x, std::max(x.fq_cap, x.n_last), tile) > BATCH_FREQ_TABLE_MAX)
+                    continue;
                 x.try_engine = RR_GEMM_EXACT;
                 x.try_tile = tile;
                 float ms = 0.0f;

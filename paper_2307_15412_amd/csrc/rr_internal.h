@@ -186,27 +186,35 @@ int64_t bp_mfma_frag_bytes(int K);
 int freq_k_step();
 int freq_k_group();   // samples per exact-GEMM workgroup
 // leg tables of n paths, or (rng_lo != NULL) of the records *rng_lo ..
-// *rng_hi of `paths` read on the device, at most Ppad of them
+// *rng_hi of `paths` read on the device, at most Ppad of them; own_tx: one X
+// row per chirp, each path's own transmitter (see freq_own_tx)
 hipError_t launch_freq_prep(const SynPath *paths, int64_t n, const int64_t *rng_lo,
                             const int64_t *rng_hi, int64_t Ppad, int M, double t_rep,
-                            const double *tx, int T, const double *rx, int R, double f0c, double dfc,
-                            double *pm, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
+                            const double *tx, int T, bool own_tx, const double *rx, int R,
+                            double f0c, double dfc, uint2 *xt, uint2 *yt, float *amp, int32_t *src,
                             hipStream_t s);
+// the X table keeps one row per chirp (each path's own transmitter) for a
+// per-element launch on the sample split with transmitter groups, else one
+// per (chirp, transmitter); entries (8 bytes each) of both tables
+bool freq_own_tx(int tile, bool per_element, bool has_groups);
+int64_t freq_table_entries(int T, int R, int M, int64_t Ppad, bool own_tx);
 // exact product engine layouts: Tx x Rx tile 16, 32, 48, 64 or 96, or 1 (one
 // channel per wavefront, samples split); the layout of least modelled time,
 // the modelled time (relative) of one, and the path splits of a launch
-int freq_tile(int T, int R, int K);
-double freq_tile_cost(int T, int R, int K, int tile);
+int freq_tile(int T, int R, int K, bool per_element);
+double freq_tile_cost(int T, int R, int K, int tile, bool per_element);
 void freq_splits(int tile, int T, int R, int M, int K, int64_t Ppad, int &n_split, int64_t &split_len);
 // the exact model's AUTO rule: the best product layout is modelled at least
 // 1.5x the direct engine's throughput
-bool freq_pays(int T, int R, int K);
+bool freq_pays(int T, int R, int K, bool per_element);
 // rng_lo / rng_hi (may be NULL): the path count read on the device, as for
-// launch_freq_prep; the splits then divide that count evenly
+// launch_freq_prep; the splits then divide that count evenly.  groups (may be
+// NULL; per-element launch, tile 1): [T + 1] path range of each transmitter
+// in the list the tables were built from (offset by groups[0])
 hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, const int32_t *src,
                             int T, int R, int M, int K, int64_t Ppad, int n_split, int64_t split_len,
                             int per_element, int tile, const int64_t *rng_lo, const int64_t *rng_hi,
-                            float2 *partial, float2 *cube, hipStream_t s);
+                            const int64_t *groups, float2 *partial, float2 *cube, hipStream_t s);
 hipError_t launch_refit(float4 *nodes, float *ubox, const int32_t *order,
                         const int64_t *level_start, int n_levels, float4 *ltris, int64_t n_tris,
                         const int32_t *tris, const float *verts, double pad, hipStream_t s);

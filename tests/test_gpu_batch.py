@@ -187,7 +187,9 @@ def test_batch_autotune(gpu):
     eng, pt = B.plan()
     for e, t, tl, w in zip(eng, pt, tiles, ws):
         if e == rr.GEMM_EXACT:
-            assert w.array.mode == sg.MODE_SHARED and t in (1, 16, 32, 48, 64, 96)
+            # a per-element launch takes the product engine only as the
+            # sample split (tiles would multiply every path into all Tx rows)
+            assert t in ((1, 16, 32, 48, 64, 96) if w.array.mode == sg.MODE_SHARED else (1,))
         else:
             assert e == rr.DIRECT_FP32 and t == tl
     counts = B.launch(cubes)
@@ -199,9 +201,11 @@ def test_batch_autotune(gpu):
 
 
 def test_batch_autotune_picks_product_engine(gpu):
-    """Two shared 48 x 64 street scenes (3072 channels) beside a small one:
-    the tuner runs them on the product engine, the small one on the direct
-    engine; the cubes agree with the single-scene launches."""
+    """Two shared 48 x 64 street scenes (3072 channels) beside a small
+    per-element one: the tuner runs the large ones on the product engine (64
+    or 48 tiles: 48 rows pad to 64 either way), the small one on whichever
+    engine its timing favours; every cube agrees with the single-scene
+    launch."""
     import paper_2307_15412_amd as rr
     street = sg.scene_street(3, scale=0.1, n_cars=8, n_poles=10)
     big = [sg.Workload(f"big{i}", street, sg.array_sparse_grid(48, 64, 30 + i),
@@ -215,7 +219,7 @@ def test_batch_autotune_picks_product_engine(gpu):
     cubes = B.alloc_cubes()
     B.tune(cubes)
     eng, tiles = B.plan()
-    assert list(eng) == [rr.GEMM_EXACT, rr.DIRECT_FP32, rr.GEMM_EXACT], (eng, tiles)
+    assert eng[0] == eng[2] == rr.GEMM_EXACT and tiles[1] in (1, 4, 8, 16, 32), (eng, tiles)
     counts = B.launch(cubes)
     for i, w in enumerate(ws):
         n, ref = _single(gpu, w)
