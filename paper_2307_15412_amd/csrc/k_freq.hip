@@ -455,10 +455,11 @@ void k_freq_gemm(FreqArgs A)
 // lane loads its 8 paths' leg words straight from the tables (the 16 lanes of
 // a row group read the same words).
 // the shared-launch 1 x 1 variant fits three wavefronts per SIMD without
-// spilling (3-7 % faster than two); the others spill there and stay at the
-// compiler's choice
+// spilling (3-7 % faster than two); the others spill at three and run two
+// (asked for explicitly: left to itself the compiler parks registers in the
+// accumulator file and moves them back and forth every step)
 template <bool PER_EL, int QB, int SB>
-__global__ __launch_bounds__(FQ_G * 64, (!PER_EL && QB * SB == 1) ? 3 : 1) void k_freq_ks(FreqArgs A)
+__global__ __launch_bounds__(FQ_G * 64, (!PER_EL && QB * SB == 1) ? 3 : 2) void k_freq_ks(FreqArgs A)
 {
     typedef f32x4 acc;
     const int lane = threadIdx.x & 63;
