@@ -9,8 +9,8 @@ at 1 to 1024 samples (ragged S), several chirps of a moving scene, the
 per-element launch (paths feed only their own Tx; the sample split reads only
 each transmitter's path group), path counts around the
 path steps and the split boundaries, an empty path list; the hand set-up
-against the direct FP32 engine and sampled oracle entries; invalid requests
-refused."""
+and the full-size street (per-element) against the direct FP32 engine and
+sampled oracle entries; invalid requests refused."""
 import math
 
 import numpy as np
@@ -102,6 +102,35 @@ def test_per_element_sample_split(gpu, orc, n_tx, n_rx, K):
     ref = orc.synth(op, w.scene, w.array, w.chirp, model=0, idx=idx)
     got = prod.reshape(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
     assert rel_err(got, ref) < TOL
+
+
+def test_street_full_size_per_element(gpu, orc):
+    """The street configuration at full size, in the launch the benchmark
+    times: 1e7 rays, 12 Tx x 16 Rx per-element launch, 128 chirps x 256
+    samples, every path kept.  AUTO takes the product engine (the sample split
+    over each transmitter's path group, one X word per path and chirp) and
+    returns its cube bit for bit; the whole cube against the direct FP32
+    engine, and 4096 seeded entries against the oracle's own trace of the
+    same rays."""
+    import paper_2307_15412_amd as rr
+    w = sg.workload_street(0)
+    gpu.setup(w)
+    n = gpu.trace_workload(w, record_hits=False)
+    prod = gpu.synthesize(model=rr.EXACT, engine=rr.GEMM_EXACT).clone()
+    auto = gpu.synthesize(model=rr.EXACT, engine=rr.ENGINE_AUTO)
+    assert torch.equal(auto, prod)
+    del auto
+    direct = gpu.synthesize(model=rr.EXACT, engine=rr.DIRECT_FP32)
+    assert rel_err(prod.cpu().numpy(), direct.cpu().numpy()) < TOL
+    del direct
+    _, op = orc.trace(w.scene, w.array, w.trace, want_hits=False)
+    assert len(op) == n
+    idx = np.random.default_rng(23).choice(prod.numel(), 4096, replace=False)
+    ref = orc.synth(op, w.scene, w.array, w.chirp, model=0, idx=idx)
+    got = prod.reshape(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    err = rel_err(got, ref)
+    print(f"street full size: {n} paths, sampled error vs oracle {err:.2e}")
+    assert err < TOL
 
 
 @pytest.mark.parametrize("n_keep", [1, 15, 16, 17, 4097])
