@@ -333,21 +333,15 @@ __device__ void trace_tri(const TraceArgs &A, int64_t g, int64_t t, int64_t i, i
                     A.piece_parent[f], cn);
 }
 
-template <bool CNT = false>
-__device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk, TraceCount *cn = nullptr)
+// The first direction of ray i of source t as a point (fa, fs) of the unit
+// square (azimuth fraction, sine of elevation fraction) and its weight:
+// uniform, or a proposal bin drawn from the table and a point inside it.
+__device__ __forceinline__ void primary_draw(const TraceArgs &A, int64_t t, int64_t i, double &fa,
+                                             double &fs, double &w)
 {
-    int64_t t = g / A.n_per_src;
-    int64_t i = g - t * A.n_per_src;
-    int64_t v = A.vbase + t * A.n_virt_per_src + i;
-    d3 src = A.shared ? mk3(A.oT[0], A.oT[1], A.oT[2])
-                      : mk3(A.tx[3 * t], A.tx[3 * t + 1], A.tx[3 * t + 2]);
-    if (A.sampler == RR_PER_TRIANGLE) {
-        trace_tri<CNT>(A, g, t, i, v, src, stk, cn);
-        return;
-    }
     uint64_t r[4];
     philox((uint64_t)i, (uint64_t)t, 0, A.seed, r);
-    double fa, fs, w = 1.0;
+    w = 1.0;
     if (A.sampler == RR_PROPOSAL) {
         int nb = A.n_az * A.n_el;
         int b = cdf_bin(A.cdf, nb, u01(r[0]));
@@ -360,6 +354,22 @@ __device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk, TraceCount *c
         fa = u01(r[0]);
         fs = u01(r[1]);
     }
+}
+
+template <bool CNT = false>
+__device__ void trace_ray(const TraceArgs &A, int64_t g, int *stk, TraceCount *cn = nullptr)
+{
+    int64_t t = g / A.n_per_src;
+    int64_t i = g - t * A.n_per_src;
+    int64_t v = A.vbase + t * A.n_virt_per_src + i;
+    d3 src = A.shared ? mk3(A.oT[0], A.oT[1], A.oT[2])
+                      : mk3(A.tx[3 * t], A.tx[3 * t + 1], A.tx[3 * t + 2]);
+    if (A.sampler == RR_PER_TRIANGLE) {
+        trace_tri<CNT>(A, g, t, i, v, src, stk, cn);
+        return;
+    }
+    double fa, fs, w;
+    primary_draw(A, t, i, fa, fs, w);
     double turn = A.at + fa * (A.bt - A.at);
     double sz = A.slo + fs * (A.shi - A.slo);
     double ce = sqrt(1.0 - sz * sz);
@@ -509,11 +519,12 @@ __device__ void trace_point(const TraceArgs &A, int64_t g, int *stk)
 // wavefronts and no spills; five wavefronts spill ~145 registers and lose).
 #define RR_TRACE_WAVES 4
 
+// lane g traces ray order[g] when a coherent order is given, else ray g
 __global__ __launch_bounds__(RR_TRACE_BLOCK, RR_TRACE_WAVES) void k_trace(TraceArgs A, int64_t n_traced)
 {
     __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
     const int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
-    if (g < n_traced) trace_ray(A, g, lds_stack + threadIdx.x);
+    if (g < n_traced) trace_ray(A, A.order ? (int64_t)A.order[g] : g, lds_stack + threadIdx.x);
 }
 
 // k_trace with work counters: the same rays, hits and paths, plus the sums
@@ -525,7 +536,7 @@ __global__ __launch_bounds__(RR_TRACE_BLOCK) void k_trace_count(TraceArgs A, int
     __shared__ int lds_stack[RR_STACK * RR_TRACE_BLOCK];
     const int64_t g = (int64_t)blockIdx.x * RR_TRACE_BLOCK + threadIdx.x;
     TraceCount cn = {0u, 0u, 0u};
-    if (g < n_traced) trace_ray<true>(A, g, lds_stack + threadIdx.x, &cn);
+    if (g < n_traced) trace_ray<true>(A, A.order ? (int64_t)A.order[g] : g, lds_stack + threadIdx.x, &cn);
     unsigned long long a = cn.nodes, b = cn.tris, q = cn.queries;
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off);
@@ -788,6 +799,116 @@ __global__ void k_set_alpha(float *ltris, int64_t n, const float *tri_alpha, con
     T[11] = tri_alpha ? tri_alpha[id] : obj_alpha[obj];
 }
 
+// Coherent ray order.  The rays of one source are sorted by the cell of their
+// first direction: 2^b x 2^b cells of the unit square that direction is drawn
+// from, in Morton order, so that a wavefront's rays leave their source
+// together and walk the same BVH nodes.  A counting sort over chunks of one
+// source's rays (four rays a cell per chunk): a workgroup counts its chunk's
+// cells in LDS and adds the non-zero counts to the global ones; after the
+// scan it reserves each cell's range with one atomic and places its rays
+// inside it (the order inside a cell is whatever the atomics give).  Nothing
+// a ray computes depends on the lane that takes it: its random numbers follow
+// its index, and its hit row, count and path records are written there.
+__device__ __forceinline__ unsigned spread_bits(unsigned x)
+{
+    x &= 0xffu;
+    x = (x | (x << 4)) & 0x0f0fu;
+    x = (x | (x << 2)) & 0x3333u;
+    x = (x | (x << 1)) & 0x5555u;
+    return x;
+}
+
+// cell of ray i of source t within its source's 4^bits cells
+__device__ __forceinline__ unsigned ray_cell(const TraceArgs &A, int64_t t, int64_t i, int bits)
+{
+    double fa, fs, w;
+    primary_draw(A, t, i, fa, fs, w);
+    const int n = 1 << bits;
+    const unsigned ca = (unsigned)min((int)(fa * n), n - 1);
+    const unsigned cs = (unsigned)min((int)(fs * n), n - 1);
+    return spread_bits(ca) | (spread_bits(cs) << 1);
+}
+
+// workgroup blockIdx.x: chunk c of source t, rays [lo, hi)
+__device__ __forceinline__ void order_chunk(const TraceArgs &A, int64_t chunk, int64_t &t,
+                                            int64_t &lo, int64_t &hi)
+{
+    const int64_t per = (A.n_per_src + chunk - 1) / chunk;
+    t = blockIdx.x / per;
+    lo = (int64_t)(blockIdx.x - t * per) * chunk;
+    hi = min(lo + chunk, A.n_per_src);
+}
+
+#define RR_ORDER_T 512
+
+__global__ __launch_bounds__(RR_ORDER_T) void k_order_count(TraceArgs A, int bits, int64_t chunk,
+                                                            uint16_t *cells, unsigned *cnt)
+{
+    extern __shared__ unsigned hist[];
+    const int nb = 1 << (2 * bits);
+    int64_t t, lo, hi;
+    order_chunk(A, chunk, t, lo, hi);
+    for (int b = threadIdx.x; b < nb; b += RR_ORDER_T) hist[b] = 0u;
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RR_ORDER_T) {
+        const unsigned c = ray_cell(A, t, i, bits);
+        cells[t * A.n_per_src + i] = (uint16_t)c;
+        atomicAdd(&hist[c], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += RR_ORDER_T)
+        if (hist[b]) atomicAdd(cnt + t * nb + b, hist[b]);
+}
+
+// exclusive scan of nk counts in place, one workgroup of 1024 threads, each
+// over a contiguous run
+__global__ __launch_bounds__(1024) void k_order_scan(unsigned *c, int64_t nk)
+{
+    __shared__ unsigned part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (nk + 1023) / 1024;
+    const int64_t lo = min(nk, (int64_t)tid * per), hi = min(nk, lo + per);
+    unsigned s = 0;
+    for (int64_t k = lo; k < hi; k++) s += c[k];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    unsigned run = tid ? part[tid - 1] : 0u;
+    for (int64_t k = lo; k < hi; k++) {
+        const unsigned x = c[k];
+        c[k] = run;
+        run += x;
+    }
+}
+
+__global__ __launch_bounds__(RR_ORDER_T) void k_order_place(TraceArgs A, int bits, int64_t chunk,
+                                                            const uint16_t *cells, unsigned *cur,
+                                                            int32_t *order)
+{
+    extern __shared__ unsigned hist[];
+    const int nb = 1 << (2 * bits);
+    int64_t t, lo, hi;
+    order_chunk(A, chunk, t, lo, hi);
+    const uint16_t *cl = cells + t * A.n_per_src;
+    for (int b = threadIdx.x; b < nb; b += RR_ORDER_T) hist[b] = 0u;
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RR_ORDER_T) atomicAdd(&hist[cl[i]], 1u);
+    __syncthreads();
+    // this chunk's range of every cell it holds
+    for (int b = threadIdx.x; b < nb; b += RR_ORDER_T) {
+        const unsigned v = hist[b];
+        hist[b] = v ? atomicAdd(cur + t * nb + b, v) : 0u;
+    }
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RR_ORDER_T)
+        order[atomicAdd(&hist[cl[i]], 1u)] = (int32_t)(t * A.n_per_src + i);
+}
+
 }  // namespace
 
 hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alpha,
@@ -798,6 +919,38 @@ hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alph
     const unsigned blocks = (unsigned)((n_tris + 255) / 256);
     hipLaunchKernelGGL(k_set_alpha, dim3(blocks), dim3(256), 0, s, reinterpret_cast<float *>(ltris),
                        n_tris, tri_alpha, obj_alpha);
+    return hipGetLastError();
+}
+
+#ifndef RR_ORDER_MAXBITS
+#define RR_ORDER_MAXBITS 7   // at most 128 x 128 cells per source
+#endif
+#ifndef RR_ORDER_CELL
+#define RR_ORDER_CELL 128    // rays a cell, about
+#endif
+int trace_order_bits(int64_t n_per_src)
+{
+    int bits = 0;
+    while (bits < RR_ORDER_MAXBITS && (n_per_src >> (2 * bits + 2)) >= RR_ORDER_CELL) bits++;
+    return bits;
+}
+
+hipError_t launch_trace_order(const TraceArgs &a, int64_t n_traced, int bits, unsigned *cells,
+                              uint16_t *ray_cells, int32_t *order, hipStream_t s)
+{
+    if (n_traced <= 0) return hipSuccess;
+    if (bits > RR_ORDER_MAXBITS || n_traced != a.n_src * a.n_per_src) return hipErrorInvalidValue;
+    const int64_t nb = (int64_t)1 << (2 * bits), nk = a.n_src * nb;
+    hipError_t e = hipMemsetAsync(cells, 0, (size_t)nk * 4, s);
+    if (e != hipSuccess) return e;
+    const int64_t chunk = 4 * nb;
+    const int64_t blocks = a.n_src * ((a.n_per_src + chunk - 1) / chunk);
+    const size_t lds = (size_t)nb * 4;
+    hipLaunchKernelGGL(k_order_count, dim3((unsigned)blocks), dim3(RR_ORDER_T), lds, s, a, bits, chunk,
+                       ray_cells, cells);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, cells, nk);
+    hipLaunchKernelGGL(k_order_place, dim3((unsigned)blocks), dim3(RR_ORDER_T), lds, s, a, bits, chunk,
+                       ray_cells, cells, order);
     return hipGetLastError();
 }
 

@@ -197,6 +197,7 @@ struct rr_ctx {
     // refit of the BVH to moved vertices (rr_scene_update_vertices)
     DevBuf tris_dev, verts_dev, refit_order, ubox;
     DevBuf fq_xt, fq_yt, fq_amp, fq_src, fq_part;   // exact-model GEMM engine
+    DevBuf order_cells, order_rc, order_idx;   // coherent ray order of a trace
     DevBuf bp_sf;              // cube slices in fragment layout (MFMA back-projection)
     std::vector<double> h_tx, h_rx;
     std::vector<int64_t> refit_levels;   // starts of the levels in refit_order, deepest first
@@ -364,7 +365,7 @@ void rr_destroy(rr_ctx *c)
                       &c->mlp_acts, &c->mlp_z, &c->mlp_dz, &c->mlp_d, &c->mlp_loss, &c->mlp_part,
                       &c->tr_codes, &c->tr_hist, &c->tr_loss, &c->bp_peak, &c->trace_stats, &c->tri_alpha, &c->pieces_v, &c->pieces_p, &c->tris_dev, &c->verts_dev,
                       &c->refit_order, &c->ubox,
-                      &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part, &c->bp_sf};
+                      &c->order_cells, &c->order_rc, &c->order_idx, &c->fq_xt, &c->fq_yt, &c->fq_amp, &c->fq_src, &c->fq_part, &c->bp_sf};
     for (DevBuf *b : bufs) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -749,6 +750,15 @@ static int trace_impl(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out
     }
     if (c->tmp_cap == 0) c->tmp_cap = std::max<int64_t>(65536, V / 32);
     if ((rc = c->tmp.alloc(c->tmp_cap))) return rc;
+    // uniform and proposal launches trace their rays in a coherent order
+    // (sorted by source and first-direction cell; results do not depend on it)
+    const bool coherent = !tri_g && n_per_src >= 4096 && n_traced < ((int64_t)1 << 31);
+    const int obits = coherent ? trace_order_bits(n_per_src) : 0;
+    if (coherent) {
+        if ((rc = c->order_idx.ensure((size_t)n_traced * 4))) return rc;
+        if ((rc = c->order_rc.ensure((size_t)n_traced * 2))) return rc;
+        if ((rc = c->order_cells.ensure((size_t)(n_src << (2 * obits)) * 4))) return rc;
+    }
 
     TraceArgs A{};
     A.nodes = c->nodes.as<const float4>();
@@ -793,12 +803,19 @@ static int trace_impl(rr_ctx *c, const rr_trace_params *tp, int64_t *n_paths_out
     A.err_flag = c->err_flag.as<int>();
 
     auto kernels = [&](const TraceArgs &a) -> hipError_t {
-        hipError_t e;
-        if (stats) {
+        hipError_t e = hipSuccess;
+        TraceArgs b = a;
+        if (coherent) {
+            e = launch_trace_order(a, n_traced, obits, c->order_cells.as<unsigned>(),
+                                   c->order_rc.as<uint16_t>(), c->order_idx.as<int32_t>(),
+                                   c->stream);
+            b.order = c->order_idx.as<const int32_t>();
+        }
+        if (e == hipSuccess && stats) {
             e = hipMemsetAsync(stats, 0, 3 * sizeof(unsigned long long), c->stream);
-            if (e == hipSuccess) e = launch_trace_count(a, n_traced, stats, c->stream);
-        } else {
-            e = launch_trace(a, n_traced, c->stream);
+            if (e == hipSuccess) e = launch_trace_count(b, n_traced, stats, c->stream);
+        } else if (e == hipSuccess) {
+            e = launch_trace(b, n_traced, c->stream);
         }
         return e == hipSuccess ? launch_points(a, c->stream) : e;
     };

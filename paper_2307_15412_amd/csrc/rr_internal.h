@@ -85,6 +85,7 @@ struct TraceArgs {
     int tri_g;                // g: g^2 rays per piece and source
     double fov_c0, fov_s0, fov_c1, fov_s1;   // cos, sin of the azimuth bounds
     int64_t vbase;            // first virtual ray of this scene in the (batched) ray space
+    const int32_t *order;     // [n_traced] ray of each lane (coherent order) or null
     // outputs
     int32_t *hits;            // [n_src*n_per_src][bmax+1] or null
     uint8_t *counts;          // indexed by vbase + virtual ray
@@ -170,6 +171,12 @@ struct BatchRangeInfo {
 
 // launchers (defined in the .hip files)
 hipError_t launch_trace(const TraceArgs &a, int64_t n_traced, hipStream_t s);
+// coherent ray order of a uniform or proposal launch: rays sorted by source
+// and the 2^bits x 2^bits cell of their first direction (cells: n_src 4^bits
+// counters, ray_cells: n_traced cell numbers, order: n_traced ray indices)
+int trace_order_bits(int64_t n_per_src);
+hipError_t launch_trace_order(const TraceArgs &a, int64_t n_traced, int bits, unsigned *cells,
+                              uint16_t *ray_cells, int32_t *order, hipStream_t s);
 hipError_t launch_points(const TraceArgs &a, hipStream_t s);
 // k_trace plus exact work counters: stats[0] BVH nodes fetched, stats[1] leaf
 // triangle records fetched, stats[2] closest-hit queries (summed, not cleared)
