@@ -579,8 +579,10 @@ def street_trace(ctx, scene, args, reps=None):
             "traffic": profiled_traffic("paper_2307_15412_amd/csrc/k_trace.hip",
                                         "profiles/k_trace_street.md"),
             "algorithmic_bytes": alg,
-            "note": "the 30 MB BVH of nodes and leaf triangles stays in L2/MALL, so algorithmic "
-                    "bytes (every node and triangle fetch counted) can exceed what HBM delivers"}
+            "note": "algorithmic bytes count every lane's node and triangle fetch; the rays of a "
+                    "wavefront are traced in a coherent order and share those fetches, and the "
+                    "30 MB BVH stays in L2/MALL, so they can exceed what HBM delivers (the kernel "
+                    "is bound by the latency of dependent node fetches, not by HBM)"}
     # the configuration's cube (exact model, FP32 bar): AUTO's engine (the
     # product engine's per-element sample split) and the direct engine; a
     # path of the per-element launch feeds its own transmitter's 16 channels
