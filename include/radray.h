@@ -186,6 +186,10 @@ typedef struct {
  * rr_synthesize, rr_proposal_histogram) reads it back with one
  * synchronisation; if the paths overflowed the current temporary buffer, that
  * call returns RR_EOVERFLOW, the buffer grows and the trace must be repeated.
+ * Uniform and proposal launches of at least 4096 rays per source trace their
+ * rays in a coherent order (sorted by source and first-direction cell, which
+ * costs n_rays x 6 bytes of device memory); hits, counts and paths are the
+ * same as in ray order, bit for bit.
  * Errors: RR_ESTATE (no scene or array), RR_EINVAL, RR_ENOMEM, RR_EHIP,
  * RR_EUNSUPPORTED (a BVH deeper than the traversal stack; the builder keeps
  * depth <= 31, so this is not expected). */
@@ -564,8 +568,8 @@ int rr_max_projection(rr_ctx *ctx, const void *image_dev, const rr_volume *vol, 
  * in milliseconds, measured with HIP events on the context stream
  * (synchronises).  which: 0 = trace (all trace kernels, scan and scatter
  * included), 1 = synthesis main kernel, 2 = back-projection, 3 = the tracing
- * kernels of the last trace alone (rays and point reflectors, before the
- * scan). */
+ * kernels of the last trace alone (the coherent ray order, rays and point
+ * reflectors, before the scan). */
 int rr_last_kernel_ms(rr_ctx *ctx, int32_t which, double *ms_out);
 
 #ifdef __cplusplus
