@@ -211,6 +211,29 @@ struct Raw {           // one lane's table words of one step: 8 (beta, gamma) pa
 
 // the 8 path slots of one fragment lane at sample k, times a (when given),
 // split into the four bf16 planes
+// one operand fragment from the lane's 8 phases (32-bit fixed-point turns):
+// the phasors, times the amplitudes a (if given), split into bf16 hi/lo
+__device__ __forceinline__ Frag phase_frag(const unsigned *ph, const float *a)
+{
+    float re[8], im[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        phasor(ph[e], re[e], im[e]);
+        if (a) {
+            re[e] *= a[e];
+            im[e] *= a[e];
+        }
+    }
+    Frag f;
+    unsigned *rh = &f.rh.x, *rl = &f.rl.x, *ih = &f.ih.x, *il = &f.il.x;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        split_bf16(re[2 * q], re[2 * q + 1], rh[q], rl[q]);
+        split_bf16(im[2 * q], im[2 * q + 1], ih[q], il[q]);
+    }
+    return f;
+}
+
 __device__ __forceinline__ Frag leg_frag(const Raw &raw, unsigned k, const float *a)
 {
     const unsigned *wv = reinterpret_cast<const unsigned *>(raw.w);
@@ -253,8 +276,8 @@ struct FreqArgs {
     // with rng_lo: the path count is *rng_hi - *rng_lo (at most Ppad), read
     // on the device, and the splits divide its padded count evenly
     const int64_t *rng_lo, *rng_hi;
-    // sample split (one channel per wavefront): k = k1 S + k2
-    int S;
+    // sample split (one channel per wavefront): k = k1 S + k2, S = 2^S_log2
+    int S, S_log2;
     int64_t n_waves;
     // per-element launch, sample split: groups[t] .. groups[t + 1] are the
     // paths of transmitter t (path indices of the list the tables were built
@@ -463,7 +486,8 @@ __global__ __launch_bounds__(FQ_G * 64, (!PER_EL && QB * SB == 1) ? 3 : 2) void 
 {
     typedef f32x4 acc;
     const int lane = threadIdx.x & 63;
-    const int64_t wv = (int64_t)blockIdx.x * FQ_G + (threadIdx.x >> 6);
+    // wavefront index, uniform by construction (kept in scalar registers)
+    const int64_t wv = (int64_t)blockIdx.x * FQ_G + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wv >= A.n_waves) return;
     // wave -> (split, chirp, channel), channel fastest
     const int C = A.T * A.R;
@@ -483,10 +507,15 @@ __global__ __launch_bounds__(FQ_G * 64, (!PER_EL && QB * SB == 1) ? 3 : 2) void 
     // group widened to whole 32-path steps (the paths of neighbouring groups
     // in the edge steps are masked by their source below)
     int64_t plo = 0, phi = used;
+    // [glo, ghi): the group itself; steps inside it hold only paths of this
+    // transmitter and need no masking
+    int64_t glo = 0, ghi = -1;
     if (PER_EL && A.groups) {
         const int64_t g0 = A.groups[0];
-        plo = min(max(A.groups[t] - g0, (int64_t)0), used) / 32 * 32;
-        phi = min((max(A.groups[t + 1] - g0, (int64_t)0) + 31) / 32 * 32, used);
+        glo = min(max(A.groups[t] - g0, (int64_t)0), used);
+        ghi = min(max(A.groups[t + 1] - g0, (int64_t)0), used);
+        plo = glo / 32 * 32;
+        phi = min((ghi + 31) / 32 * 32, used);
         phi = max(phi, plo);
         split_len = ((phi - plo + A.n_split - 1) / A.n_split + 31) / 32 * 32;
     }
@@ -502,11 +531,11 @@ __global__ __launch_bounds__(FQ_G * 64, (!PER_EL && QB * SB == 1) ? 3 : 2) void 
     const u32x4 *yp = reinterpret_cast<const u32x4 *>(A.yt + ((int64_t)m * A.R + r) * A.Ppad + p0);
     const u32x4 *apn = reinterpret_cast<const u32x4 *>(A.amp + p0);
     const u32x4 *spn = reinterpret_cast<const u32x4 *>(A.src + p0);
-    unsigned kq[QB], k2[SB];
-#pragma unroll
-    for (int q = 0; q < QB; q++) kq[q] = (unsigned)((16 * q + lrow) * A.S);
-#pragma unroll
-    for (int b = 0; b < SB; b++) k2[b] = (unsigned)(16 * b + lrow);
+    // sample k1 S + k2 of the lane's U row k1 = 16 q + lrow and V column
+    // k2 = 16 b + lrow: with t = lrow gamma (mod 2^32) the V phase is
+    // t + 16 b gamma and the U phase beta + ((t + 16 q gamma) << S_log2)
+    const unsigned lr = (unsigned)lrow;
+    const int ssh = A.S_log2;
     f32x4 sr[QB][SB], si[QB][SB];
 #pragma unroll
     for (int i = 0; i < QB; i++)
@@ -537,35 +566,41 @@ __global__ __launch_bounds__(FQ_G * 64, (!PER_EL && QB * SB == 1) ? 3 : 2) void 
     // one step: U (beta, gamma) and V (0, gamma) words of the channel, the
     // amplitudes (in a per-element launch a path feeds its own Tx only), the
     // fragments and the products
-#define KS_STEP(X, Y, AM, SR)                                                                     \
+#define KS_STEP(X, Y, AM, SR, ST)                                                                 \
     do {                                                                                          \
-        Raw ru_, rv_;                                                                             \
+        unsigned bt_[8], gm_[8], t_[8], ph_[8];                                                   \
         float a_[8];                                                                              \
-        unsigned *wu_ = reinterpret_cast<unsigned *>(ru_.w);                                      \
-        unsigned *wv_ = reinterpret_cast<unsigned *>(rv_.w);                                      \
         _Pragma("unroll") for (int q_ = 0; q_ < 4; q_++) {                                        \
-            wu_[4 * q_] = X[q_].x + Y[q_].x;                                                      \
-            wu_[4 * q_ + 1] = X[q_].y + Y[q_].y;                                                  \
-            wu_[4 * q_ + 2] = X[q_].z + Y[q_].z;                                                  \
-            wu_[4 * q_ + 3] = X[q_].w + Y[q_].w;                                                  \
+            bt_[2 * q_] = X[q_].x + Y[q_].x;                                                      \
+            gm_[2 * q_] = X[q_].y + Y[q_].y;                                                      \
+            bt_[2 * q_ + 1] = X[q_].z + Y[q_].z;                                                  \
+            gm_[2 * q_ + 1] = X[q_].w + Y[q_].w;                                                  \
         }                                                                                         \
-        _Pragma("unroll") for (int e_ = 0; e_ < 8; e_++) {                                        \
-            wv_[2 * e_] = 0u;                                                                     \
-            wv_[2 * e_ + 1] = wu_[2 * e_ + 1];                                                    \
-        }                                                                                         \
+        _Pragma("unroll") for (int e_ = 0; e_ < 8; e_++) t_[e_] = lr * gm_[e_];                   \
         _Pragma("unroll") for (int e_ = 0; e_ < 4; e_++) {                                        \
             a_[e_] = __uint_as_float(AM[0][e_]);                                                  \
             a_[4 + e_] = __uint_as_float(AM[1][e_]);                                              \
-            if (PER_EL) {                                                                         \
-                const int s0_ = (int)SR[0][e_], s1_ = (int)SR[1][e_];                             \
-                if (s0_ >= 0 && s0_ != t) a_[e_] = 0.0f;                                          \
-                if (s1_ >= 0 && s1_ != t) a_[4 + e_] = 0.0f;                                      \
+        }                                                                                         \
+        if (PER_EL) {                                                                             \
+            const int64_t ps_ = pstart + 32 * (int64_t)(ST);                                      \
+            if (ghi < 0 || ps_ < glo || ps_ + 32 > ghi) {                                         \
+                _Pragma("unroll") for (int e_ = 0; e_ < 4; e_++) {                                \
+                    const int s0_ = (int)SR[0][e_], s1_ = (int)SR[1][e_];                         \
+                    if (s0_ >= 0 && s0_ != t) a_[e_] = 0.0f;                                      \
+                    if (s1_ >= 0 && s1_ != t) a_[4 + e_] = 0.0f;                                  \
+                }                                                                                 \
             }                                                                                     \
         }                                                                                         \
         Frag v_[SB];                                                                              \
-        _Pragma("unroll") for (int j_ = 0; j_ < SB; j_++) v_[j_] = leg_frag(rv_, k2[j_], nullptr); \
+        _Pragma("unroll") for (int j_ = 0; j_ < SB; j_++) {                                       \
+            _Pragma("unroll") for (int e_ = 0; e_ < 8; e_++)                                      \
+                ph_[e_] = j_ ? t_[e_] + (unsigned)j_ * (gm_[e_] << 4) : t_[e_];                   \
+            v_[j_] = phase_frag(ph_, nullptr);                                                    \
+        }                                                                                         \
         _Pragma("unroll") for (int i_ = 0; i_ < QB; i_++) {                                       \
-            const Frag x_ = leg_frag(ru_, kq[i_], a_);                                            \
+            _Pragma("unroll") for (int e_ = 0; e_ < 8; e_++)                                      \
+                ph_[e_] = bt_[e_] + ((i_ ? t_[e_] + (unsigned)i_ * (gm_[e_] << 4) : t_[e_]) << ssh); \
+            const Frag x_ = phase_frag(ph_, a_);                                                  \
             const uint4 nih_ = neg(x_.ih), nil_ = neg(x_.il);                                     \
             _Pragma("unroll") for (int j_ = 0; j_ < SB; j_++) {                                   \
                 acc &R_ = sr[i_][j_], &I_ = si[i_][j_];                                           \
@@ -587,10 +622,10 @@ __global__ __launch_bounds__(FQ_G * 64, (!PER_EL && QB * SB == 1) ? 3 : 2) void 
     if (nsteps > 0) KS_LOAD(0, X0, Y0, AM0, SR0);
     for (int64_t st = 0; st < nsteps; st += 2) {
         if (st + 1 < nsteps) KS_LOAD(st + 1, X1, Y1, AM1, SR1);
-        KS_STEP(X0, Y0, AM0, SR0);
+        KS_STEP(X0, Y0, AM0, SR0, st);
         if (st + 1 >= nsteps) break;
         if (st + 2 < nsteps) KS_LOAD(st + 2, X0, Y0, AM0, SR0);
-        KS_STEP(X1, Y1, AM1, SR1);
+        KS_STEP(X1, Y1, AM1, SR1, st + 1);
     }
 #undef KS_LOAD
 #undef KS_STEP
@@ -677,19 +712,16 @@ static const int FQ_TILES[5] = {16, 32, 48, 64, 96};
 static const double FQ_TILE_RATE[5] = {17.8, 30.0, 38.0, 43.0, 42.0};
 
 // sample split of K samples: QB x SB blocks of 16 x 16, S samples a row
-static void ks_shape(int K, int &qb, int &sb, int &S)
+// blocks of the sample split and S = 2^s, the least power of two with
+// Q S >= K (Q = 16 qb rows); S <= 16 sb always holds
+static void ks_shape(int K, int &qb, int &sb, int &S, int &s)
 {
-    if (K <= 256) {
-        qb = sb = 1;
-        S = (K + 15) / 16;
-    } else if (K <= 512) {
-        qb = 1;
-        sb = 2;
-        S = (K + 15) / 16;
-    } else {
-        qb = sb = 2;
-        S = (K + 31) / 32;
-    }
+    qb = K <= 512 ? 1 : 2;
+    sb = K <= 256 ? 1 : 2;
+    const int need = (K + 16 * qb - 1) / (16 * qb);
+    s = 0;
+    while ((1 << s) < need) s++;
+    S = 1 << s;
 }
 
 int freq_tile(int T, int R, int K, bool per_element);
@@ -698,8 +730,8 @@ int freq_tile(int T, int R, int K, bool per_element);
 // the rest of the blocks' products unused
 static double ks_rate(int K)
 {
-    int qb, sb, S;
-    ks_shape(K, qb, sb, S);
+    int qb, sb, S, sl;
+    ks_shape(K, qb, sb, S, sl);
     const double full = qb * sb == 1 ? 17.0 : qb * sb == 2 ? 23.0 : 25.0;
     return full * K / (256.0 * qb * sb);
 }
@@ -802,7 +834,7 @@ hipError_t launch_freq_gemm(const uint2 *xt, const uint2 *yt, const float *amp, 
     A.rng_hi = rng_hi;
     A.groups = tile == 1 && per_element ? groups : nullptr;
     int qb = 1, sb = 1;
-    ks_shape(K, qb, sb, A.S);
+    ks_shape(K, qb, sb, A.S, A.S_log2);
     A.n_waves = (int64_t)n_split * M * T * R;
     const int64_t blocks = tile == 1 ? (A.n_waves + FQ_G - 1) / FQ_G
                                      : (int64_t)n_split * M * A.tt * A.rt * A.kg;
