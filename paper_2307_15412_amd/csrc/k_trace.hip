@@ -860,14 +860,16 @@ __global__ __launch_bounds__(RR_ORDER_T) void k_order_count(TraceArgs A, int bit
         if (hist[b]) atomicAdd(cnt + t * nb + b, hist[b]);
 }
 
-// exclusive scan of nk counts in place, one workgroup of 1024 threads, each
-// over a contiguous run
-__global__ __launch_bounds__(1024) void k_order_scan(unsigned *c, int64_t nk)
+// exclusive scan in place of source blockIdx.x's nb cell counts, offset by
+// the source's first position (every source has n_per_src rays): one
+// workgroup of 1024 threads a source, each over a contiguous run
+__global__ __launch_bounds__(1024) void k_order_scan(unsigned *cells, int64_t nb, int64_t n_per_src)
 {
     __shared__ unsigned part[1024];
+    unsigned *c = cells + (int64_t)blockIdx.x * nb;
     const int tid = threadIdx.x;
-    const int64_t per = (nk + 1023) / 1024;
-    const int64_t lo = min(nk, (int64_t)tid * per), hi = min(nk, lo + per);
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t lo = min(nb, (int64_t)tid * per), hi = min(nb, lo + per);
     unsigned s = 0;
     for (int64_t k = lo; k < hi; k++) s += c[k];
     part[tid] = s;
@@ -878,7 +880,7 @@ __global__ __launch_bounds__(1024) void k_order_scan(unsigned *c, int64_t nk)
         part[tid] += v;
         __syncthreads();
     }
-    unsigned run = tid ? part[tid - 1] : 0u;
+    unsigned run = (unsigned)((int64_t)blockIdx.x * n_per_src) + (tid ? part[tid - 1] : 0u);
     for (int64_t k = lo; k < hi; k++) {
         const unsigned x = c[k];
         c[k] = run;
@@ -948,7 +950,7 @@ hipError_t launch_trace_order(const TraceArgs &a, int64_t n_traced, int bits, un
     const size_t lds = (size_t)nb * 4;
     hipLaunchKernelGGL(k_order_count, dim3((unsigned)blocks), dim3(RR_ORDER_T), lds, s, a, bits, chunk,
                        ray_cells, cells);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, cells, nk);
+    hipLaunchKernelGGL(k_order_scan, dim3((unsigned)a.n_src), dim3(1024), 0, s, cells, nb, a.n_per_src);
     hipLaunchKernelGGL(k_order_place, dim3((unsigned)blocks), dim3(RR_ORDER_T), lds, s, a, bits, chunk,
                        ray_cells, cells, order);
     return hipGetLastError();
