@@ -129,11 +129,26 @@ __global__ void k_prep_a(const float2 *T, const float2 *R, int nrx, int C, int R
     const int row = rb * 32 + (lane & 31);
     const int64_t p0 = (int64_t)kb * GM_KS + (lane >> 5) * 8;
     unsigned short h[GM_PL][8];
+    // the lane's 8 paths of its Tx and Rx rows as four 16-byte loads each
+    // (rows are Ppad = 96 k entries long, so every load is aligned)
+    float4 ta[4], rb4[4];
+    if (row < C) {
+        const int t = row / nrx, r = row - t * nrx;
+        const float4 *tp = reinterpret_cast<const float4 *>(T + (int64_t)t * Ppad + p0);
+        const float4 *rp = reinterpret_cast<const float4 *>(R + (int64_t)r * Ppad + p0);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            ta[q] = tp[q];
+            rb4[q] = rp[q];
+        }
+    }
+#pragma unroll
     for (int e = 0; e < 8; e++) {
         float re = 0.0f, im = 0.0f;
         if (row < C) {
-            const int t = row / nrx, r = row - (row / nrx) * nrx;
-            float2 a = T[(int64_t)t * Ppad + p0 + e], b = R[(int64_t)r * Ppad + p0 + e];
+            const float4 av = ta[e >> 1], bv = rb4[e >> 1];
+            const float2 a = (e & 1) ? make_float2(av.z, av.w) : make_float2(av.x, av.y);
+            const float2 b = (e & 1) ? make_float2(bv.z, bv.w) : make_float2(bv.x, bv.y);
             re = a.x * b.x - a.y * b.y;
             im = a.x * b.y + a.y * b.x;
         }
