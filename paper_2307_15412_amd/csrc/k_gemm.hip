@@ -42,7 +42,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #define GM_PL 6            // operand planes: re hi, re lo, im hi, im lo, (re+im) hi, (re+im) lo
 #define GM_NBUF 3          // B tiles in LDS: read one step ahead, generated two ahead
 static_assert((GM_TM / 32 / GM_WR) == GM_THREADS / 64, "wavefront grid");
-#define BFRAG_U4 72        // one B fragment in LDS: 64 lanes + 8 padding (uint4 units)
+#define GM_BPAD 4          // padding after lane 31 of a B fragment in LDS (uint4 units)
+#define BFRAG_U4 (64 + GM_BPAD)   // one B fragment in LDS (uint4 units)
 #ifndef GM_VPM
 #define GM_VPM 2           // vector instructions scheduled beside each MFMA
 #endif
@@ -245,8 +246,9 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
                                                         int n_col_tiles, float2 *__restrict__ cube)
 {
     // B: three buffers x 6 planes x column blocks, each fragment 64 lanes x
-    // 16 B with 128 B of padding after lane 31, so that the generator's
-    // 32-bit writes of both lane halves land in distinct banks.
+    // 16 B with 64 B of padding after lane 31, so that the generator's
+    // 32-bit writes of both lane halves land in distinct banks (no bank
+    // conflicts; with 128 B of padding a quarter of the LDS cycles were).
     __shared__ uint4 Bs[GM_NBUF][GM_PL * GM_NCB * BFRAG_U4];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -275,7 +277,7 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
     const int p0 = 2 * pp;
     const int flane = (p0 >> 3) * 32 + nb;
     // 32-bit word index of (fragment 0, this lane, slots p0 & 7 and +1)
-    const int wofs = (flane * 16 + (flane >= 32 ? 128 : 0) + (p0 & 7) * 2) / 4;
+    const int wofs = (flane * 16 + (flane >= 32 ? 16 * GM_BPAD : 0) + (p0 & 7) * 2) / 4;
     const uint4 *bprow = Bp + (int64_t)m * Ppad;   // + p0 per lane
     // words per plane (all column blocks)
     constexpr int PS = GM_NCB * BFRAG_U4 * 4;
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(GM_THREADS, 1) void k_gemm(const uint4 *__restrict_
         for (int p = 0; p < GM_PL; p++) a.q[p] = src[p * 64 + lane];
         return a;
     };
-    const int lofs = lane + (lane >= 32 ? 8 : 0);
+    const int lofs = lane + (lane >= 32 ? GM_BPAD : 0);
     auto load_b = [&](const uint4 *B) -> BCols {
         BCols b;
 #pragma unroll
