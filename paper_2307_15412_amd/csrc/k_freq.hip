@@ -211,6 +211,21 @@ struct Raw {           // one lane's table words of one step: 8 (beta, gamma) pa
 
 // the 8 path slots of one fragment lane at sample k, times a (when given),
 // split into the four bf16 planes
+// hi = bf16(x, y); lo = bf16(x - hi.x, y - hi.y) with each difference formed
+// exactly by one dot product, hi . (-1, -0) + x and hi . (0, -1) + y: one
+// vector instruction instead of a shift or mask and a subtraction.  Used
+// where the matrix cores are mostly idle (the sample split): the dot products
+// do not overlap the MFMAs, which costs the Tx x Rx tiles more than it saves.
+// The (-1, -0) word must be a literal: as the inline constant -1.0 the
+// hardware reads it as the 32-bit float, i.e. (0, -1).
+__device__ __forceinline__ void split_bf16_dot(float x, float y, unsigned &hi, unsigned &lo)
+{
+    hi = pack_bf16(x, y);
+    const bf16x2 h = __builtin_bit_cast(bf16x2, hi);
+    lo = pack_bf16(__builtin_amdgcn_fdot2_f32_bf16(h, __builtin_bit_cast(bf16x2, 0x8000bf80u), x, false),
+                   __builtin_amdgcn_fdot2_f32_bf16(h, __builtin_bit_cast(bf16x2, 0xbf800000u), y, false));
+}
+
 // one operand fragment from the lane's 8 phases (32-bit fixed-point turns):
 // the phasors, times the amplitudes a (if given), split into bf16 hi/lo
 __device__ __forceinline__ Frag phase_frag(const unsigned *ph, const float *a)
@@ -228,8 +243,8 @@ __device__ __forceinline__ Frag phase_frag(const unsigned *ph, const float *a)
     unsigned *rh = &f.rh.x, *rl = &f.rl.x, *ih = &f.ih.x, *il = &f.il.x;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        split_bf16(re[2 * q], re[2 * q + 1], rh[q], rl[q]);
-        split_bf16(im[2 * q], im[2 * q + 1], ih[q], il[q]);
+        split_bf16_dot(re[2 * q], re[2 * q + 1], rh[q], rl[q]);
+        split_bf16_dot(im[2 * q], im[2 * q + 1], ih[q], il[q]);
     }
     return f;
 }
