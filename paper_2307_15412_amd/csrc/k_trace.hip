@@ -924,12 +924,12 @@ hipError_t launch_set_alpha(float4 *ltris, int64_t n_tris, const float *tri_alph
     return hipGetLastError();
 }
 
-#ifndef RR_ORDER_MAXBITS
-#define RR_ORDER_MAXBITS 7   // at most 128 x 128 cells per source
-#endif
-#ifndef RR_ORDER_CELL
-#define RR_ORDER_CELL 128    // rays a cell, about
-#endif
+// cells per source: 4^b with about 128-512 rays a cell (a sweep of cell sizes
+// found ~200 best for 8e5 and 4e6 rays per source), at most 128 x 128 (the
+// LDS counts of a workgroup, 64 KiB; cell numbers fit 16 bits)
+#define RR_ORDER_MAXBITS 7
+#define RR_ORDER_CELL 128
+static_assert(RR_ORDER_MAXBITS <= 7, "cell counts must fit 64 KiB of LDS");
 int trace_order_bits(int64_t n_per_src)
 {
     int bits = 0;
