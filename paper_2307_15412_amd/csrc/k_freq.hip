@@ -488,7 +488,7 @@ void k_freq_gemm(FreqArgs A)
 //     U[k1, p] = a_p exp(-j 2 pi (beta + k1 S gamma)),  V[p, k2] = exp(-j 2 pi k2 gamma),
 // a (Q x paths) by (paths x S) complex product in QB x SB blocks of 16 x 16
 // (v_mfma_f32_16x16x32_bf16, 32 paths a step, split bf16 as the tile
-// kernels).  Per path and channel it evaluates Q + S phasors instead of the
+// kernels, the low parts by one dot product each).  Per path and channel it evaluates Q + S phasors instead of the
 // Tx x Rx tiles' (T + R) K / (T R): the better choice for small arrays.  Each
 // lane loads its 8 paths' leg words straight from the tables (the 16 lanes of
 // a row group read the same words).
@@ -578,8 +578,10 @@ __global__ __launch_bounds__(FQ_G * 64, (!PER_EL && QB * SB == 1) ? 3 : 2) void 
             SR[1] = spn[(st_) * 8 + 1];                                                           \
         }                                                                                         \
     } while (0)
-    // one step: U (beta, gamma) and V (0, gamma) words of the channel, the
-    // amplitudes (in a per-element launch a path feeds its own Tx only), the
+    // one step: the channel's (beta, gamma) per path (sums of its Tx and Rx
+    // leg words), the U and V phases from one product t = lrow gamma, the
+    // amplitudes (in a per-element launch a path feeds its own Tx only: other
+    // transmitters' paths, present only in a group's edge steps, get 0), the
     // fragments and the products
 #define KS_STEP(X, Y, AM, SR, ST)                                                                 \
     do {                                                                                          \
