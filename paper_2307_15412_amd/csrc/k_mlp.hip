@@ -4,9 +4,11 @@
 // then its CDF) that the tracer's importance sampler reads.
 //
 // Weights and activations are stored in FP16; every product is formed and
-// accumulated in FP32 (an FP16 x FP16 product is exact in FP32).  The network
-// is small (9 601 parameters, ~1.6e6 rows per epoch of 200 scenes) so each lane
-// evaluates one row with the weights broadcast from LDS.
+// accumulated in FP32 (an FP16 x FP16 product is exact in FP32).  The forward
+// pass runs its hidden layers on the matrix cores (FP16 MFMA, 32 rows per
+// wavefront); the backward pass keeps its gradients in FP32 (they fall below
+// FP16's normal range) and runs one row per lane with the weights broadcast
+// from LDS, the weight gradients as ordered outer-product reductions.
 #include <hip/hip_fp16.h>
 
 #include "rr_internal.h"
@@ -50,54 +52,127 @@ __device__ __forceinline__ void row_input(const float *codes, int64_t r, float x
     for (int k = 0; k < 16; k++) x[2 + k] = h16(codes[s * 16 + k]);
 }
 
-// forward: logits z[r]; activations h1..h3 kept in FP16 for the backward pass
+// input k of row r (as row_input)
+__device__ __forceinline__ float row_input_k(const float *codes, int64_t r, int k)
+{
+    const int64_t s = r / NBINS;
+    const int b = (int)(r - s * NBINS);
+    if (k == 0) return h16(2.0f * ((float)(b % NAZ) + 0.5f) / (float)NAZ - 1.0f);
+    if (k == 1) return h16(2.0f * ((float)(b / NAZ) + 0.5f) / (float)NEL - 1.0f);
+    return h16(codes[s * 16 + k - 2]);
+}
+
+// forward on the matrix cores (v_mfma_f32_32x32x16_f16: FP16 operands, FP32
+// accumulation; an FP16 x FP16 product is exact in FP32).  A wavefront takes
+// 32 rows: per hidden layer the activations (32 x 64, FP16) are the A operand
+// and the weights the B operand (in x out, 16 inputs a step; layer 1's 18
+// inputs padded to 32 with zeros), then bias, ReLU and the FP16 rounding in
+// FP32 on the accumulators; the activations go through LDS (row-major) to
+// become the next layer's A fragments.  Logit: each of lanes 0..31 takes its
+// row's dot product with W4 in input order.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+#define MF_RS (NH + 8)              // LDS row stride of an activation tile (halves)
+#define MF_FRAGS (2 * 2 + 2 * 4 * 2)  // B fragments: layer 1 (2 column blocks x 2 input steps), layers 2, 3 (2 x 4 each)
+
+// B fragment (column block cb, input step kc) of a layer with weights
+// w[out][in] (in-width nin): lane l holds output 32 cb + l % 32, inputs
+// 16 kc + 8 (l / 32) .. + 7, rounded to FP16 (zero beyond nin)
+__device__ __forceinline__ uint4 wfrag(const float *w, int nin, int cb, int kc, int l)
+{
+    const int j = 32 * cb + (l & 31), i0 = 16 * kc + 8 * (l >> 5);
+    f16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; e++) v[e] = (_Float16)(i0 + e < nin ? w[j * nin + i0 + e] : 0.0f);
+    return __builtin_bit_cast(uint4, v);
+}
+
 __global__ __launch_bounds__(256) void k_mlp_fwd(const float *P, const float *codes, int64_t n,
                                                  __half *acts, float *z)
 {
-    __shared__ float W[NPARAMS];
-    load_params(P, W);
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    float x[NIN];
-    row_input(codes, r, x);
-    float h[NH], g[NH];
-#pragma unroll
-    for (int j = 0; j < NH; j++) {
-        float a = W[OFF_B1 + j];
-#pragma unroll
-        for (int i = 0; i < NIN; i++) a = fmaf(W[OFF_W1 + j * NIN + i], x[i], a);
-        h[j] = h16(fmaxf(a, 0.0f));
+    __shared__ uint4 Wf[MF_FRAGS][64];
+    __shared__ float Bs[3][NH], W4s[NH + 1];
+    __shared__ _Float16 Hs[4][32][MF_RS];
+    for (int q = threadIdx.x; q < MF_FRAGS * 64; q += blockDim.x) {
+        const int f = q >> 6, l = q & 63;
+        uint4 v;
+        if (f < 4) v = wfrag(P + OFF_W1, NIN, f >> 1, f & 1, l);
+        else if (f < 12) v = wfrag(P + OFF_W2, NH, (f - 4) >> 2, (f - 4) & 3, l);
+        else v = wfrag(P + OFF_W3, NH, (f - 12) >> 2, (f - 12) & 3, l);
+        Wf[f][l] = v;
     }
-    if (acts) {
+    for (int q = threadIdx.x; q < NH; q += blockDim.x) {
+        Bs[0][q] = h16(P[OFF_B1 + q]);
+        Bs[1][q] = h16(P[OFF_B2 + q]);
+        Bs[2][q] = h16(P[OFF_B3 + q]);
+        W4s[q] = h16(P[OFF_W4 + q]);
+    }
+    if (threadIdx.x == 0) W4s[NH] = h16(P[OFF_B4]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 32;
+    if (r0 >= n) return;
+    const int row = lane & 31, half = lane >> 5;
+    const int64_t r = r0 + row;
+    const bool live = r < n;
+    _Float16(*H)[MF_RS] = Hs[w];
+
+    // layer-1 A fragments: inputs 8 half .. + 7 (step 0) and 16 + 8 half .. (step 1)
+    uint4 A[4];
+    {
+        f16x8 a0, a1;
 #pragma unroll
-        for (int j = 0; j < NH; j++) acts[(0 * n + r) * NH + j] = __float2half(h[j]);
+        for (int e = 0; e < 8; e++) {
+            a0[e] = (_Float16)row_input_k(codes, live ? r : n - 1, 8 * half + e);
+            a1[e] = (_Float16)(!half && e < NIN - 16 ? row_input_k(codes, live ? r : n - 1, 16 + e) : 0.0f);
+        }
+        A[0] = __builtin_bit_cast(uint4, a0);
+        A[1] = __builtin_bit_cast(uint4, a1);
     }
 #pragma unroll
-    for (int j = 0; j < NH; j++) {
-        float a = W[OFF_B2 + j];
+    for (int L = 0; L < 3; L++) {
+        const int nk = L == 0 ? 2 : 4;                   // input steps of the layer
+        const int fb = L == 0 ? 0 : (L == 1 ? 4 : 12);   // its first B fragment
+        f32x16 acc[2];
 #pragma unroll
-        for (int i = 0; i < NH; i++) a = fmaf(W[OFF_W2 + j * NH + i], h[i], a);
-        g[j] = h16(fmaxf(a, 0.0f));
+        for (int cb = 0; cb < 2; cb++) {
+#pragma unroll
+            for (int e = 0; e < 16; e++) acc[cb][e] = 0.0f;
+#pragma unroll
+            for (int kc = 0; kc < 4; kc++)
+                if (kc < nk)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, A[kc]),
+                        __builtin_bit_cast(f16x8, Wf[fb + cb * nk + kc][lane]), acc[cb], 0, 0, 0);
+        }
+        // D layout: register e of lane l is row 8 (e / 4) + 4 (l / 32) + e % 4,
+        // column l % 32 of the block
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) {
+            const int j = 32 * cb + (lane & 31);
+            const float bj = Bs[L][j];
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                const int rr = 8 * (e >> 2) + 4 * half + (e & 3);
+                H[rr][j] = (_Float16)fmaxf(acc[cb][e] + bj, 0.0f);
+            }
+        }
+        // the wavefront's own tile: its LDS operations run in order
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int kc = 0; kc < 4; kc++) A[kc] = *reinterpret_cast<const uint4 *>(&H[row][16 * kc + 8 * half]);
+        if (acts && live) {
+#pragma unroll
+            for (int kc = 0; kc < 4; kc++)
+                *reinterpret_cast<uint4 *>(acts + ((int64_t)L * n + r) * NH + 16 * kc + 8 * half) = A[kc];
+        }
     }
-    if (acts) {
+    if (half == 0 && live) {
+        float a = W4s[NH];
 #pragma unroll
-        for (int j = 0; j < NH; j++) acts[(1 * n + r) * NH + j] = __float2half(g[j]);
+        for (int i = 0; i < NH; i++) a = fmaf(W4s[i], (float)H[row][i], a);
+        z[r] = a;
     }
-#pragma unroll
-    for (int j = 0; j < NH; j++) {
-        float a = W[OFF_B3 + j];
-#pragma unroll
-        for (int i = 0; i < NH; i++) a = fmaf(W[OFF_W3 + j * NH + i], g[i], a);
-        h[j] = h16(fmaxf(a, 0.0f));
-    }
-    if (acts) {
-#pragma unroll
-        for (int j = 0; j < NH; j++) acts[(2 * n + r) * NH + j] = __float2half(h[j]);
-    }
-    float a = W[OFF_B4];
-#pragma unroll
-    for (int i = 0; i < NH; i++) a = fmaf(W[OFF_W4 + i], h[i], a);
-    z[r] = a;
 }
 
 // per scene: softmax of the logits; loss -sum H log q / sum H and its
@@ -371,7 +446,7 @@ hipError_t launch_mlp_forward(const float *P, const float *codes, int64_t n, __h
                               hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, codes, n,
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, s, P, codes, n,
                        acts, z);
     return hipGetLastError();
 }
