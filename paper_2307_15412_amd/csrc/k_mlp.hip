@@ -4,11 +4,11 @@
 // then its CDF) that the tracer's importance sampler reads.
 //
 // Weights and activations are stored in FP16; every product is formed and
-// accumulated in FP32 (an FP16 x FP16 product is exact in FP32).  The forward
-// pass runs its hidden layers on the matrix cores (FP16 MFMA, 32 rows per
-// wavefront); the backward pass keeps its gradients in FP32 (they fall below
-// FP16's normal range) and runs one row per lane with the weights broadcast
-// from LDS, the weight gradients as ordered outer-product reductions.
+// accumulated in FP32 (an FP16 x FP16 product is exact in FP32).  Every layer
+// runs on the matrix cores: the forward pass in FP16 MFMA, the backward pass
+// and the weight gradients in FP32 MFMA (the gradients fall below FP16's
+// normal range), 32 rows per wavefront; the weight gradients are reduced in
+// a fixed order.
 #include <hip/hip_fp16.h>
 
 #include "rr_internal.h"
@@ -34,25 +34,8 @@ static_assert(NPARAMS == RR_MLP_PARAMS, "parameter count");
 
 __device__ __forceinline__ float h16(float x) { return __half2float(__float2half(x)); }
 
-// load the parameters into LDS rounded to FP16
-__device__ __forceinline__ void load_params(const float *P, float *W)
-{
-    for (int i = threadIdx.x; i < NPARAMS; i += blockDim.x) W[i] = h16(P[i]);
-    __syncthreads();
-}
-
-__device__ __forceinline__ void row_input(const float *codes, int64_t r, float x[NIN])
-{
-    const int64_t s = r / NBINS;
-    const int b = (int)(r - s * NBINS);
-    const int ia = b % NAZ, ie = b / NAZ;
-    x[0] = h16(2.0f * ((float)ia + 0.5f) / (float)NAZ - 1.0f);
-    x[1] = h16(2.0f * ((float)ie + 0.5f) / (float)NEL - 1.0f);
-#pragma unroll
-    for (int k = 0; k < 16; k++) x[2 + k] = h16(codes[s * 16 + k]);
-}
-
-// input k of row r (as row_input)
+// input k of row r: k = 0, 1 the bin's azimuth and elevation centre mapped
+// to [-1, 1], k = 2 .. 17 the scene code (all rounded to FP16)
 __device__ __forceinline__ float row_input_k(const float *codes, int64_t r, int k)
 {
     const int64_t s = r / NBINS;
@@ -234,114 +217,199 @@ __global__ __launch_bounds__(1024) void k_softmax_grad(const float *z, const flo
     if (threadIdx.x == 0) loss[s] = Hs > 0.0f ? red[0] / Hs / (float)n_scenes : 0.0f;
 }
 
-// backward through the layers for each row: d3, d2, d1 (pre-activation grads)
+// Backward pass on the matrix cores in FP32 (v_mfma_f32_32x32x2f32): the
+// gradients fall below FP16's normal range, so they stay FP32 throughout.
+// A wavefront takes 32 rows: d3 = [h3 > 0] dz W4 (vector units), then
+// d2 = [h2 > 0] (d3 W3) and d1 = [h1 > 0] (d2 W2) as (32 x 64) by (64 x 64)
+// products, the weights (FP16-rounded) as the B operand from LDS and the
+// previous gradient tile as the A operand from LDS (row-major, one float a
+// lane and step); every gradient tile is also written out for the weight
+// gradients.
+#define BW_RS (NH + 1)
 __global__ __launch_bounds__(256) void k_mlp_bwd(const float *P, const float *dz, int64_t n,
                                                  const __half *acts, float *d1, float *d2, float *d3)
 {
-    __shared__ float W[NPARAMS];
-    load_params(P, W);
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const float g = dz[r];
-    float a[NH], b[NH];
-    const __half *h3 = acts + (2 * n + r) * NH;
-    const __half *h2 = acts + (1 * n + r) * NH;
-    const __half *h1 = acts + (0 * n + r) * NH;
-#pragma unroll
-    for (int j = 0; j < NH; j++) {
-        a[j] = __half2float(h3[j]) > 0.0f ? g * W[OFF_W4 + j] : 0.0f;
-        d3[r * NH + j] = a[j];
+    __shared__ float Ws[2][NH][NH];        // W3, W2 as [out j][in i]
+    __shared__ float W4s[NH];
+    __shared__ float Dt[4][32][BW_RS];
+    for (int q = threadIdx.x; q < NH * NH; q += blockDim.x) {
+        Ws[0][q / NH][q % NH] = h16(P[OFF_W3 + q]);
+        Ws[1][q / NH][q % NH] = h16(P[OFF_W2 + q]);
     }
-#pragma unroll
-    for (int i = 0; i < NH; i++) {
-        float s = 0.0f;
-#pragma unroll
-        for (int j = 0; j < NH; j++) s = fmaf(W[OFF_W3 + j * NH + i], a[j], s);
-        b[i] = __half2float(h2[i]) > 0.0f ? s : 0.0f;
-        d2[r * NH + i] = b[i];
+    for (int q = threadIdx.x; q < NH; q += blockDim.x) W4s[q] = h16(P[OFF_W4 + q]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 32;
+    if (r0 >= n) return;
+    const int rows = (int)min((int64_t)32, n - r0);
+    float(*D)[BW_RS] = Dt[w];
+    // d3: lane j over the tile's rows (coalesced)
+    {
+        const int j = lane;
+#pragma unroll 8
+        for (int rr = 0; rr < 32; rr++) {
+            float v = 0.0f;
+            if (rr < rows) {
+                const int64_t r = r0 + rr;
+                v = __half2float(acts[(2 * n + r) * NH + j]) > 0.0f ? dz[r] * W4s[j] : 0.0f;
+                d3[r * NH + j] = v;
+            }
+            D[rr][j] = v;
+        }
     }
+    __builtin_amdgcn_wave_barrier();
+    const int col = lane & 31, kk = lane >> 5;
 #pragma unroll
-    for (int i = 0; i < NH; i++) {
-        float s = 0.0f;
+    for (int L = 0; L < 2; L++) {
+        // out[r][i] = sum_j D[r][j] W[j][i]: A[r][k = j] = D, B[k = j][i] = W
+        f32x16 acc[2];
 #pragma unroll
-        for (int j = 0; j < NH; j++) s = fmaf(W[OFF_W2 + j * NH + i], b[j], s);
-        d1[r * NH + i] = __half2float(h1[i]) > 0.0f ? s : 0.0f;
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) acc[cb][e] = 0.0f;
+#pragma unroll 8
+        for (int ks = 0; ks < NH / 2; ks++) {
+            const int k = 2 * ks + kk;
+            const float av = D[col][k];
+#pragma unroll
+            for (int cb = 0; cb < 2; cb++)
+                acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, Ws[L][k][32 * cb + col], acc[cb], 0, 0, 0);
+        }
+        const __half *h = acts + (int64_t)(1 - L) * n * NH;
+        float *dout = L == 0 ? d2 : d1;
+        __builtin_amdgcn_wave_barrier();
+        // D layout: register e of lane l is row 8 (e / 4) + 4 (l / 32) + e % 4,
+        // column l % 32 of the block
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) {
+            const int i = 32 * cb + col;
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                const int rr = 8 * (e >> 2) + 4 * kk + (e & 3);
+                float v = 0.0f;
+                if (rr < rows) {
+                    const int64_t r = r0 + rr;
+                    v = __half2float(h[r * NH + i]) > 0.0f ? acc[cb][e] : 0.0f;
+                    dout[r * NH + i] = v;
+                }
+                D[rr][i] = v;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// weight gradients as outer-product reductions over rows:
+// Weight gradients on the matrix cores in FP32 (v_mfma_f32_32x32x2f32):
 //   G[a][c] = sum_r D[r][a] V[r][c],  Gb[a] = sum_r D[r][a]
-// V is either the FP16 activation (mode 0, width 64) or the layer-1 input
-// (mode 1, width 18, rebuilt from the bin and the scene code).
-// Block b sums its own rows in row order and writes its partial sums to row b
-// of the partial table (stride NPARAMS, at the layer's parameter offsets);
-// k_wgrad_sum then adds the rows of that table in block order, so the
-// gradient is the same bits on every run.
-// 256 threads: thread t owns output row a = t / 4, 16 columns from (t % 4) * 16.
-#define WG_ROWS 64
-__global__ __launch_bounds__(256) void k_wgrad(const float *D, int da, const __half *V,
-                                               const float *codes, int vc, int64_t n,
-                                               int64_t rows_per_block, float *part, int off_g,
-                                               int off_b)
+// as (da x rows) by (rows x vc) products, two rows a step: lane l takes
+// D[r + l / 32][a] and V[r + l / 32][c] for a, c = l % 32 (+ 32) straight from
+// memory (coalesced).  V is the FP16 activation (width 64) or, without it,
+// the layer-1 input (width 18, rebuilt from the bin and the scene code).
+// Block b sums its rows in order and writes its partial sums to row b of the
+// partial table (stride NPARAMS, at the layer's parameter offsets); two
+// passes then add the rows in a fixed order, so the gradient is the same
+// bits on every run.
+#define WG_MAXB 4096      // most blocks (partial-table rows) per layer
+#define WG_RUN 32         // rows of the partial table added per first-pass run
+#define WG_STEPS 8        // two-row steps loaded together
+__global__ __launch_bounds__(64) void k_wgrad(const float *D, int da, const __half *V,
+                                              const float *codes, int vc, int64_t n,
+                                              int64_t rows_per_block, float *part, int off_g,
+                                              int off_b)
 {
     float *G = part + (int64_t)blockIdx.x * NPARAMS + off_g;
     float *Gb = part + (int64_t)blockIdx.x * NPARAMS + off_b;
-    __shared__ float sD[WG_ROWS][NH + 1];
-    __shared__ float sV[WG_ROWS][NH + 1];
-    const int t = threadIdx.x;
-    const int a = t >> 2;
-    const int c0 = (t & 3) * 16;
-    float acc[16];
+    const int lane = threadIdx.x, col = lane & 31, kk = lane >> 5;
+    const int nab = da > 32 ? 2 : 1, ncb = vc > 32 ? 2 : 1;
+    f32x16 acc[2][2];
 #pragma unroll
-    for (int k = 0; k < 16; k++) acc[k] = 0.0f;
-    float accb = 0.0f;
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+    float bs[2] = {0.0f, 0.0f};
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = min(n, r0 + rows_per_block);
-    for (int64_t base = r0; base < r1; base += WG_ROWS) {
-        const int cnt = (int)min((int64_t)WG_ROWS, r1 - base);
-        __syncthreads();
-        for (int e = t; e < WG_ROWS * NH; e += 256) {
-            const int rr = e / NH, cc = e % NH;
-            float dv = 0.0f, vv = 0.0f;
-            if (rr < cnt) {
-                const int64_t row = base + rr;
-                if (cc < da) dv = D[row * da + cc];
-                if (V) {
-                    if (cc < vc) vv = __half2float(V[row * vc + cc]);
-                } else if (cc < vc) {
-                    float x[NIN];
-                    row_input(codes, row, x);
-                    vv = x[cc];
-                }
-            }
-            sD[rr][cc] = dv;
-            sV[rr][cc] = vv;
-        }
-        __syncthreads();
-        if (a < da) {
-            for (int rr = 0; rr < cnt; rr++) {
-                const float d = sD[rr][a];
-                accb += d;
+    // WG_STEPS steps (two rows each) at a time, the next group's values
+    // loaded while this group's products run
+    float ca[WG_STEPS][2], cv[WG_STEPS][2], na[WG_STEPS][2], nv[WG_STEPS][2];
+    auto load = [&](int64_t rbase, float (&xa)[WG_STEPS][2], float (&xv)[WG_STEPS][2]) {
 #pragma unroll
-                for (int k = 0; k < 16; k++) acc[k] = fmaf(d, sV[rr][c0 + k], acc[k]);
+        for (int q = 0; q < WG_STEPS; q++) {
+            const int64_t row = rbase + 2 * q + kk;
+            const bool ok = row < r1;
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                const int a = 32 * i + col;
+                xa[q][i] = ok && i < nab && a < da ? D[row * da + a] : 0.0f;
+                const int c = 32 * i + col;
+                xv[q][i] = 0.0f;
+                if (ok && i < ncb && c < vc)
+                    xv[q][i] = V ? __half2float(V[row * vc + c]) : row_input_k(codes, row, c);
             }
         }
+    };
+    load(r0, ca, cv);
+    for (int64_t rb = r0; rb < r1; rb += 2 * WG_STEPS) {
+        if (rb + 2 * WG_STEPS < r1) load(rb + 2 * WG_STEPS, na, nv);
+#pragma unroll
+        for (int q = 0; q < WG_STEPS; q++)
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                bs[i] += ca[q][i];
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    if (i < nab && j < ncb)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[q][i], cv[q][j], acc[i][j], 0, 0, 0);
+            }
+#pragma unroll
+        for (int q = 0; q < WG_STEPS; q++)
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                ca[q][i] = na[q][i];
+                cv[q][i] = nv[q][i];
+            }
     }
-    if (a < da) {
+    // D layout: register e of lane l is row (a) 8 (e / 4) + 4 (l / 32) + e % 4,
+    // column (c) l % 32 of the block
 #pragma unroll
-        for (int k = 0; k < 16; k++)
-            if (c0 + k < vc) G[a * vc + c0 + k] = acc[k];
-        if ((t & 3) == 0) Gb[a] = accb;
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                const int a = 32 * i + 8 * (e >> 2) + 4 * kk + (e & 3), c = 32 * j + col;
+                if (i < nab && j < ncb && a < da && c < vc) G[a * vc + c] = acc[i][j][e];
+            }
+    // bias: the even rows' sum (lanes 0..31) plus the odd rows' (lanes 32..63)
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const float other = __shfl_down(bs[i], 32, 64);
+        const int a = 32 * i + col;
+        if (kk == 0 && i < nab && a < da) Gb[a] = bs[i] + other;
     }
 }
 
-// G[i] = sum over blocks b = 0, 1, ... of part[b][i], in that order
-__global__ __launch_bounds__(256) void k_wgrad_sum(const float *part, int nb, float *G)
+// first pass: run y of the partial table (rows y WG_RUN .. + WG_RUN - 1, in
+// order) into row nb + y; second pass: those runs in order into G
+__global__ __launch_bounds__(256) void k_wgrad_sum(float *part, int nb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAMS) return;
+    const int y = blockIdx.y;
+    const int b0 = y * WG_RUN, b1 = min(nb, b0 + WG_RUN);
+    float s = 0.0f;
+    for (int b = b0; b < b1; b++) s += part[(int64_t)b * NPARAMS + i];
+    part[(int64_t)(nb + y) * NPARAMS + i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_wgrad_sum2(const float *part, int nb, int runs, float *G)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPARAMS) return;
     float s = 0.0f;
-    for (int b = 0; b < nb; b++) s += part[(int64_t)b * NPARAMS + i];
+    for (int y = 0; y < runs; y++) s += part[(int64_t)(nb + y) * NPARAMS + i];
     G[i] = s;
 }
 
@@ -459,27 +527,44 @@ hipError_t launch_softmax_grad(const float *z, const float *H, int n_scenes, flo
     return hipGetLastError();
 }
 
-int64_t mlp_wgrad_blocks(int64_t n) { return (n + MLP_WGRAD_ROWS - 1) / MLP_WGRAD_ROWS; }
+// blocks of the weight-gradient kernels: an even number of rows each, at
+// most WG_MAXB
+static int wgrad_blocks(int64_t n, int64_t &rows_per_block)
+{
+    int64_t rpb = (n + WG_MAXB - 1) / WG_MAXB;
+    rpb = std::max<int64_t>(2, (rpb + 1) / 2 * 2);
+    rows_per_block = rpb;
+    return (int)((n + rpb - 1) / rpb);
+}
+
+int64_t mlp_part_rows(int64_t n)
+{
+    int64_t rpb;
+    const int nb = wgrad_blocks(std::max<int64_t>(n, 1), rpb);
+    return nb + (nb + WG_RUN - 1) / WG_RUN;
+}
 
 hipError_t launch_mlp_backward(const float *P, const float *dz, int64_t n, const __half *acts,
                                float *d1, float *d2, float *d3, const float *codes, float *part,
                                float *grad, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, dz, n, acts,
+    hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, s, P, dz, n, acts,
                        d1, d2, d3);
-    const int64_t rpb = MLP_WGRAD_ROWS;
-    const int nb = (int)mlp_wgrad_blocks(n);
+    int64_t rpb;
+    const int nb = wgrad_blocks(n, rpb);
     // layer 4: dz (width 1) x h3; layer 3: d3 x h2; layer 2: d2 x h1; layer 1: d1 x input
-    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, dz, 1, acts + 2 * n * NH, codes, NH, n, rpb,
+    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(64), 0, s, dz, 1, acts + 2 * n * NH, codes, NH, n, rpb,
                        part, OFF_W4, OFF_B4);
-    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d3, NH, acts + 1 * n * NH, codes, NH, n, rpb,
+    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(64), 0, s, d3, NH, acts + 1 * n * NH, codes, NH, n, rpb,
                        part, OFF_W3, OFF_B3);
-    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d2, NH, acts + 0 * n * NH, codes, NH, n, rpb,
+    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(64), 0, s, d2, NH, acts + 0 * n * NH, codes, NH, n, rpb,
                        part, OFF_W2, OFF_B2);
-    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(256), 0, s, d1, NH, (const __half *)nullptr, codes, NIN,
+    hipLaunchKernelGGL(k_wgrad, dim3(nb), dim3(64), 0, s, d1, NH, (const __half *)nullptr, codes, NIN,
                        n, rpb, part, OFF_W1, OFF_B1);
-    hipLaunchKernelGGL(k_wgrad_sum, dim3((NPARAMS + 255) / 256), dim3(256), 0, s, part, nb, grad);
+    const int runs = (nb + WG_RUN - 1) / WG_RUN;
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((NPARAMS + 255) / 256, runs), dim3(256), 0, s, part, nb);
+    hipLaunchKernelGGL(k_wgrad_sum2, dim3((NPARAMS + 255) / 256), dim3(256), 0, s, part, nb, runs, grad);
     return hipGetLastError();
 }
 

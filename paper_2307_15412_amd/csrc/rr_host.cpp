@@ -1532,7 +1532,7 @@ static int mlp_buffers(rr_ctx *c, int64_t rows, int n_scenes)
     if ((rc = c->mlp_dz.ensure((size_t)rows * 4))) return rc;
     if ((rc = c->mlp_d.ensure((size_t)rows * 3 * 64 * 4))) return rc;
     if ((rc = c->mlp_loss.ensure((size_t)n_scenes * 4 + 4))) return rc;
-    if ((rc = c->mlp_part.ensure((size_t)mlp_wgrad_blocks(rows) * RR_MLP_PARAMS * 4))) return rc;
+    if ((rc = c->mlp_part.ensure((size_t)mlp_part_rows(rows) * RR_MLP_PARAMS * 4))) return rc;
     return RR_OK;
 }
 

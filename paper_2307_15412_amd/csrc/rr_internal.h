@@ -266,11 +266,11 @@ hipError_t launch_mlp_forward(const float *P, const float *codes, int64_t n, __h
                               hipStream_t s);
 hipError_t launch_softmax_grad(const float *z, const float *H, int n_scenes, float *dz, float *loss,
                                hipStream_t s);
-// weight gradients: blocks of MLP_WGRAD_ROWS rows write partial sums into
-// part ([mlp_wgrad_blocks(n)][RR_MLP_PARAMS] floats), then one pass adds them
-// in block order into grad (every entry written)
-#define MLP_WGRAD_ROWS 4096
-int64_t mlp_wgrad_blocks(int64_t n);
+// weight gradients: the rows are split over at most 4 096 blocks, each
+// writing its partial sums into part; two passes then add them in a fixed
+// order (runs of consecutive blocks, then the runs) into grad (every entry
+// written).  part holds mlp_part_rows(n) rows of RR_MLP_PARAMS floats.
+int64_t mlp_part_rows(int64_t n);
 hipError_t launch_mlp_backward(const float *P, const float *dz, int64_t n, const __half *acts,
                                float *d1, float *d2, float *d3, const float *codes, float *part,
                                float *grad, hipStream_t s);
