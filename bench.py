@@ -49,14 +49,15 @@ def parse():
                     help="only time vendor-library bf16 and fp32 GEMMs (reachable matrix peak)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--workload", choices=["large_mimo", "batch", "proposal", "hand", "alpha_sweep",
-                                           "tri_cast", "hand_motion", "street_trace"],
+                                           "tri_cast", "hand_motion", "street_trace", "mlp"],
                     default="large_mimo",
                     help="large_mimo (default): the benchmarked step; batch: 64 uneven scenes in "
                          "one captured launch; proposal: learned-proposal training and gain; "
                          "hand: SFCW hand imaging (trace, synthesis, back-projection, projection); "
                          "alpha_sweep: the hand imaged at alpha = 0, 0.1, ..., 1; tri_cast: "
                          "per-triangle casting vs the uniform launch at equal rays; hand_motion: "
-                         "32 frames of a moving hand (refit, trace, synthesis per frame)")
+                         "32 frames of a moving hand (refit, trace, synthesis per frame); mlp: "
+                         "the proposal network's forward rate and training-step time")
     return ap.parse_args()
 
 
@@ -199,6 +200,57 @@ def run_proposal(args):
                                "beta 0.1"},
         "results": out,
         "equal_error": {k: v for k, v in eq.items() if k != "per_scene"}}))
+
+
+def run_mlp(args):
+    """The proposal network alone: logits for every bin of 128 scenes (1.05e6
+    evaluations) and one training step (forward, softmax gradient, backward,
+    weight gradients, Adam) at 16 scenes (the training batch) and at 128;
+    seeded synthetic scene codes and histograms, wall time around synchronised
+    repetitions."""
+    import torch
+    import paper_2307_15412_amd as rr
+    ctx = rr.Context(0)
+    g = torch.Generator().manual_seed(5)
+    nbins = 128 * 64
+    macs = 18 * 64 + 64 * 64 + 64 * 64 + 64          # per evaluation (forward)
+    out = {}
+    ctx.mlp_init(3)
+    for ns in (16, 128):
+        codes = torch.rand((ns, 16), generator=g).to("cuda:0")
+        hists = torch.rand((ns, nbins), generator=g).to("cuda:0")
+        for _ in range(args.warmup + 1):
+            ctx.mlp_forward(codes)
+            ctx.mlp_train_step(codes, hists, 1e-3)
+        torch.cuda.synchronize()
+        reps = max(args.steps, 1) * 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.mlp_forward(codes)
+        torch.cuda.synchronize()
+        t_fwd = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.mlp_train_step(codes, hists, 1e-3)
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / reps
+        out[f"scenes_{ns}"] = {"rows": ns * nbins, "forward_ms": t_fwd * 1e3,
+                               "train_step_ms": t_step * 1e3,
+                               "evaluations_per_s": ns * nbins / t_fwd}
+    big = out["scenes_128"]
+    achieved = 2.0 * macs * big["evaluations_per_s"] / 1e12
+    print(json.dumps({
+        "metric": "proposal-network evaluations/s (forward, all bins of 128 scenes)",
+        "value": big["evaluations_per_s"], "unit": "evaluations/s", "higher_is_better": True,
+        "n_gpus": 1, "dtype": "fp16 forward / fp32 backward, fp32 accumulation",
+        "data": "synthetic (seeded codes and histograms)",
+        "config": {"workload": "MLP 18-64-64-64-1, 128 x 64 bins a scene; training step at 16 "
+                               "and 128 scenes"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "kernel": "k_mlp_fwd",
+                     "note": "wall time of the forward call (launch included), "
+                             "2 x 9 408 flops per evaluation"},
+        "results": out}))
 
 
 def run_hand(args, sweep=False):
@@ -672,6 +724,9 @@ def main():
         return
     if args.workload == "street_trace":
         run_street_trace(args)
+        return
+    if args.workload == "mlp":
+        run_mlp(args)
         return
     if args.workload in ("hand", "alpha_sweep"):
         run_hand(args, sweep=args.workload == "alpha_sweep")
