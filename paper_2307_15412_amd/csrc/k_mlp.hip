@@ -310,6 +310,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const float *P, const float *dz
 // passes then add the rows in a fixed order, so the gradient is the same
 // bits on every run.
 #define WG_MAXB 4096      // most blocks (partial-table rows) per layer
+#define WG_MINR 64        // fewest rows per block
 #define WG_RUN 32         // rows of the partial table added per first-pass run
 #define WG_STEPS 8        // two-row steps loaded together
 __global__ __launch_bounds__(64) void k_wgrad(const float *D, int da, const __half *V,
@@ -528,11 +529,12 @@ hipError_t launch_softmax_grad(const float *z, const float *H, int n_scenes, flo
 }
 
 // blocks of the weight-gradient kernels: an even number of rows each, at
-// most WG_MAXB
+// least WG_MINR (small batches keep a small partial table), at most WG_MAXB
+// blocks
 static int wgrad_blocks(int64_t n, int64_t &rows_per_block)
 {
     int64_t rpb = (n + WG_MAXB - 1) / WG_MAXB;
-    rpb = std::max<int64_t>(2, (rpb + 1) / 2 * 2);
+    rpb = std::max<int64_t>(WG_MINR, (rpb + 1) / 2 * 2);
     rows_per_block = rpb;
     return (int)((n + rpb - 1) / rpb);
 }
