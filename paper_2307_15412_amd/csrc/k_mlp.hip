@@ -229,12 +229,12 @@ __global__ __launch_bounds__(1024) void k_softmax_grad(const float *z, const flo
 __global__ __launch_bounds__(256) void k_mlp_bwd(const float *P, const float *dz, int64_t n,
                                                  const __half *acts, float *d1, float *d2, float *d3)
 {
-    __shared__ float Ws[2][NH][NH];        // W3, W2 as [out j][in i]
+    __shared__ _Float16 Ws[2][NH][NH];     // W3, W2 as [out j][in i] (FP16 values: exact)
     __shared__ float W4s[NH];
     __shared__ float Dt[4][32][BW_RS];
     for (int q = threadIdx.x; q < NH * NH; q += blockDim.x) {
-        Ws[0][q / NH][q % NH] = h16(P[OFF_W3 + q]);
-        Ws[1][q / NH][q % NH] = h16(P[OFF_W2 + q]);
+        Ws[0][q / NH][q % NH] = (_Float16)P[OFF_W3 + q];
+        Ws[1][q / NH][q % NH] = (_Float16)P[OFF_W2 + q];
     }
     for (int q = threadIdx.x; q < NH; q += blockDim.x) W4s[q] = h16(P[OFF_W4 + q]);
     __syncthreads();
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const float *P, const float *dz
             const float av = D[col][k];
 #pragma unroll
             for (int cb = 0; cb < 2; cb++)
-                acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, Ws[L][k][32 * cb + col], acc[cb], 0, 0, 0);
+                acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, (float)Ws[L][k][32 * cb + col], acc[cb], 0, 0, 0);
         }
         const __half *h = acts + (int64_t)(1 - L) * n * NH;
         float *dout = L == 0 ? d2 : d1;
